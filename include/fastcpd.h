@@ -1,0 +1,192 @@
+/*
+ * fastcpd.h -- C ABI of libfastcpd.so, a gfx950 (MI355X) implementation of the
+ * EM iteration of Fast Coherent Point Drift (Feng, Feng & Zhu, "Fast Coherent
+ * Point Drift", arXiv 2006.06281) and of the original CPD M-step it replaces.
+ *
+ * Problem statement (Section I and Section II): a model set X in R^{M x D}
+ * moves onto a scene set Y in R^{N x D} through f(X) = X + Phi W (eq. 9-10),
+ * Phi_ij = exp(-|x_i - x_j|^2 / (2 beta^2)) (eq. 11).  One EM iteration:
+ *   E-step  posterior p_mn with a uniform outlier term of weight w (eq. 4),
+ *           rows renormalised to sum to 1 (the corresponding constraint, eq. 5);
+ *   M-step  Fast CPD: W = U (Lam + lambda sigma^2 I)^-1 U^T (Yt - X) (eq. 17),
+ *           optionally with the top-K eigenpairs only (eq. 20);
+ *           original CPD: W = (Phi + lambda sigma^2 d(P1)^-1)^-1
+ *                             (d(P1)^-1 P Y - X)                    (eq. 21);
+ *   sigma^2 update (eq. 18).
+ *
+ * Conventions for every entry point:
+ *   - All arrays are row-major and contiguous.  Point arrays are M x D or
+ *     N x D.  "device" means a pointer into memory of the current HIP device.
+ *   - Floating-point point arrays are double when precision == CPD_PREC_FP64
+ *     and float otherwise.
+ *   - The library never allocates device memory.  The caller allocates one
+ *     workspace of cpd_workspace_size() bytes (256-byte aligned) and keeps it
+ *     alive until cpd_destroy().  The handle itself is host memory.
+ *   - All device work is enqueued on the stream given to cpd_init.  Calls
+ *     that return host scalars synchronise that stream.
+ *   - Errors are reported through the return code only; arguments are
+ *     validated before any device work is enqueued.  cpd_last_error() holds a
+ *     message for the last failing call on a handle.  A handle is not
+ *     thread-safe; distinct handles are independent.
+ */
+#ifndef FASTCPD_H
+#define FASTCPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPD_ABI_VERSION 1
+
+typedef enum {
+  CPD_OK = 0,
+  CPD_NOT_CONVERGED = 1,   /* max_iter reached before |dsigma^2| < tol       */
+  CPD_E_ARG = -1,          /* invalid argument (nothing was enqueued)         */
+  CPD_E_STATE = -2,        /* call out of order (e.g. step before prepare)    */
+  CPD_E_WORKSPACE = -3,    /* workspace missing, misaligned or too small      */
+  CPD_E_DEVICE = -4,       /* no usable gfx950 device, or a HIP runtime error */
+  CPD_E_NUMERIC = -5,      /* non-finite sigma^2, failed factorisation, ...   */
+  CPD_E_UNSUPPORTED = -6   /* valid but not implemented combination           */
+} cpd_status;
+
+typedef enum {
+  CPD_METHOD_ORIGINAL = 0, /* eq. 21: M x M SPD solve every iteration          */
+  CPD_METHOD_FAST = 1      /* eq. 5 + eq. 17 (eq. 20 when K < M)               */
+} cpd_method;
+
+typedef enum {
+  CPD_PREC_FP64 = 0,       /* everything in double                             */
+  CPD_PREC_FP32 = 1,       /* E-step and M-step in float; eig and sigma^2 FP64 */
+  CPD_PREC_BF16X = 2       /* E-step squared distances from bf16 products on
+                              the matrix cores, fp32 accumulate and exp        */
+} cpd_precision;
+
+typedef enum {
+  CPD_EIG_FULL = 0,        /* all eigenpairs of Phi that are not round-off     */
+  CPD_EIG_TOPK = 1,        /* the K largest eigenpairs (eq. 19), randomized    */
+  CPD_EIG_IMPORT = 2       /* caller supplies U (M x K) and Lam (K)            */
+} cpd_eig_mode;
+
+typedef struct {
+  int32_t abi_version;     /* must be CPD_ABI_VERSION                          */
+  int32_t M, N, D;         /* 1 <= M, N <= 2^26; 1 <= D <= 3                   */
+  double beta;             /* kernel width, > 0 (eq. 10-11)                    */
+  double lambda;           /* regularisation weight, > 0 (eq. 7, eq. 11)       */
+  double w;                /* outlier weight, 0 <= w < 1 (eq. 2)               */
+  double sigma2_init;      /* <= 0: sum_mn |y_n - x_m|^2 / (D M N)             */
+  int32_t method;          /* cpd_method                                       */
+  int32_t precision;       /* cpd_precision                                    */
+  int32_t eig_mode;        /* cpd_eig_mode (Fast only)                         */
+  int32_t K;               /* TOPK / IMPORT: number of eigenpairs, 1 <= K <= M */
+  int32_t oversample;      /* TOPK: extra columns p (default 20 when <= 0)     */
+  int32_t power_iters;     /* TOPK: subspace iterations q (default 2 when < 0) */
+  uint64_t seed;           /* TOPK: seed of the Gaussian test matrix           */
+  double tol;              /* stop when |sigma2_new - sigma2| < tol            */
+  int32_t max_iter;        /* iteration cap of cpd_register (> 0)              */
+  int32_t reserved;        /* must be 0                                        */
+} cpd_params;
+
+typedef struct {
+  int32_t iter;            /* iterations completed on this handle              */
+  int32_t converged;       /* |dsigma2| < tol after this step                  */
+  double sigma2;           /* sigma^2 after the step                           */
+  double dsigma2;          /* |sigma^2 after - sigma^2 before|                 */
+  double loglik;           /* eq. 3 at the state the E-step saw                */
+} cpd_step_info;
+
+typedef struct {
+  int32_t iters, converged;
+  double sigma2;
+  double t_c;              /* E-step time (s), as the paper's t_c              */
+  double t_eig;            /* eigendecomposition time (s) (t_eig)              */
+  double t_iter;           /* M-step time (s) (t_iter)                         */
+  double t_o;              /* everything else (s) (t_o)                        */
+} cpd_result;
+
+typedef struct cpd_ctx* cpd_handle;
+
+/* Bytes of device workspace needed for these parameters (no device call). */
+cpd_status cpd_workspace_size(const cpd_params* p, size_t* bytes);
+
+/* Create a handle.  X (M x D) and Y (N x D) are device arrays of the working
+ * precision; they are copied into the workspace, so the caller may reuse them
+ * after this call returns.  Sets Xt = X and sigma^2 to sigma2_init (or the
+ * standard start, computed on the device).  hip_stream may be NULL (the null
+ * stream).  On failure *h is set to NULL. */
+cpd_status cpd_init(cpd_handle* h, const cpd_params* p, const void* X,
+                    const void* Y, void* workspace, size_t workspace_bytes,
+                    void* hip_stream);
+
+/* One-time preparation before the iterations (Section III, eq. 16 and 19).
+ *   FAST + FULL   all eigenpairs of Phi (Jacobi on the dense Phi up to 1024
+ *                 points; above that, randomized subspace iteration whose width
+ *                 grows until the trailing Ritz value is round-off of lam_1).
+ *   FAST + TOPK   the K largest eigenpairs: randomized range finder with
+ *                 power_iters subspace iterations and a Rayleigh-Ritz step on
+ *                 K + oversample columns.  omega (device, M x (K+oversample)
+ *                 doubles) is the Gaussian test matrix; NULL draws it on the
+ *                 device from `seed`.
+ *   FAST + IMPORT U_import (device, M x K doubles, orthonormal columns) and
+ *                 lam_import (device, K doubles), e.g. from cpd_eig_export.
+ *   ORIGINAL      builds the M x M Gram matrix Phi.
+ * Arguments not used by the mode must be NULL. */
+cpd_status cpd_eig_prepare(cpd_handle h, const double* U_import,
+                           const double* lam_import, const double* omega);
+
+/* Number of eigenpairs held after cpd_eig_prepare (K, or the adaptive count
+ * of FULL mode). */
+cpd_status cpd_eig_count(cpd_handle h, int32_t* K_out);
+
+/* Copy the eigenpairs out (device, M x K and K doubles, descending order;
+ * eigenvalues are reported as computed, before clamping at 0). */
+cpd_status cpd_eig_export(cpd_handle h, double* U_out, double* lam_out);
+
+/* One EM iteration from the current state (E-step at (Xt, sigma^2), M-step
+ * with lambda sigma^2, Xt <- X + Phi W, then the sigma^2 update).  With
+ * info == NULL the call only enqueues work; otherwise it waits and fills
+ * info.  Returns CPD_E_NUMERIC if sigma^2 became non-finite. */
+cpd_status cpd_step(cpd_handle h, cpd_step_info* info);
+
+/* Iterate from the current state until |dsigma^2| < tol or max_iter steps.
+ * W0 (device, M x D, nullable) sets Xt = X + Phi W0 and resets sigma^2 to its
+ * start value first (warm start).  X_out (device, M x D) receives Xt; W_out
+ * (nullable) receives W.  res (host, nullable) gets counts and the timing
+ * split of the paper's runtime protocol (Section IV).  Returns
+ * CPD_NOT_CONVERGED when the cap was hit. */
+cpd_status cpd_register(cpd_handle h, const void* W0, void* X_out,
+                        void* W_out, cpd_result* res);
+
+/* Overwrite the iterate: Xt (device, M x D) and sigma^2 (> 0). */
+cpd_status cpd_set_state(cpd_handle h, const void* Xt, double sigma2);
+
+/* Read the iterate: Xt and W (device, M x D, nullable) and sigma^2 (host,
+ * nullable).  Synchronises the stream. */
+cpd_status cpd_get_state(cpd_handle h, void* Xt_out, void* W_out,
+                         double* sigma2_out);
+
+/* E-step alone at the current state (eq. 4-5), results to device arrays of
+ * the working precision, each nullable:
+ *   logd (N)   natural log of eq. 4's denominator sum_k exp(-|y_n-xt_k|^2/2s2) + c
+ *   P1 (M)     row sums of the eq. 4 posterior
+ *   Yt (M x D) P'Y with P' the row-normalised posterior (eq. 5)
+ *   tbar (M)   sum_n p'_mn |y_n - xt_m|^2
+ * The iterate is not changed. */
+cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+cpd_status cpd_destroy(cpd_handle h);
+
+const char* cpd_status_str(cpd_status s);
+const char* cpd_last_error(cpd_handle h);   /* h may be NULL: global message */
+
+/* Library build information: ABI version and the offload target. */
+int32_t cpd_abi_version(void);
+const char* cpd_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTCPD_H */

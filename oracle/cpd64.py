@@ -252,6 +252,8 @@ def rel_rms(A, B) -> float:
     """|A - B|_F / |B - mean_rows(B)|_F: the parity measure on point sets."""
     B = np.asarray(B, np.float64)
     den = np.linalg.norm(B - B.mean(0, keepdims=True))
+    if den == 0.0:                       # a single point: uncentred norm
+        den = np.linalg.norm(B) or 1.0
     return float(np.linalg.norm(np.asarray(A, np.float64) - B) / den)
 
 

@@ -1,0 +1,310 @@
+"""Python binding of libfastcpd, the gfx950 Fast Coherent Point Drift library.
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+libfastcpd.so.  PyTorch supplies device memory (tensors) and the HIP stream.
+The functions keep the names of the C ABI declared in include/fastcpd.h;
+``Registration`` bundles one handle with its workspace.
+
+The library is built in-tree by ``paper_2006_06281_amd.build.build()``.
+Importing this package when it is missing raises at once: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfastcpd.so")
+
+CPD_ABI_VERSION = 1
+
+CPD_OK, CPD_NOT_CONVERGED = 0, 1
+CPD_E_ARG, CPD_E_STATE, CPD_E_WORKSPACE = -1, -2, -3
+CPD_E_DEVICE, CPD_E_NUMERIC, CPD_E_UNSUPPORTED = -4, -5, -6
+
+CPD_METHOD_ORIGINAL, CPD_METHOD_FAST = 0, 1
+CPD_PREC_FP64, CPD_PREC_FP32, CPD_PREC_BF16X = 0, 1, 2
+CPD_EIG_FULL, CPD_EIG_TOPK, CPD_EIG_IMPORT = 0, 1, 2
+
+METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST}
+PRECISIONS = {"fp64": CPD_PREC_FP64, "fp32": CPD_PREC_FP32, "bf16x": CPD_PREC_BF16X}
+EIG_MODES = {"full": CPD_EIG_FULL, "topk": CPD_EIG_TOPK, "import": CPD_EIG_IMPORT}
+
+EXPORTED = [
+    "cpd_workspace_size", "cpd_init", "cpd_eig_prepare", "cpd_eig_count",
+    "cpd_eig_export", "cpd_step", "cpd_register", "cpd_set_state",
+    "cpd_get_state", "cpd_estep", "cpd_destroy", "cpd_status_str",
+    "cpd_last_error", "cpd_abi_version", "cpd_build_info",
+]
+
+
+class cpd_params(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32), ("M", ctypes.c_int32), ("N", ctypes.c_int32),
+        ("D", ctypes.c_int32), ("beta", ctypes.c_double), ("lambda_", ctypes.c_double),
+        ("w", ctypes.c_double), ("sigma2_init", ctypes.c_double),
+        ("method", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("eig_mode", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class cpd_step_info(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("sigma2", ctypes.c_double), ("dsigma2", ctypes.c_double),
+                ("loglik", ctypes.c_double)]
+
+
+class cpd_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("sigma2", ctypes.c_double), ("t_c", ctypes.c_double),
+                ("t_eig", ctypes.c_double), ("t_iter", ctypes.c_double),
+                ("t_o", ctypes.c_double)]
+
+
+class FastCPDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status_name(status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfastcpd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2006_06281_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "cpd_workspace_size": ([P(cpd_params), P(sz)], ctypes.c_int),
+        "cpd_init": ([P(vp), P(cpd_params), vp, vp, vp, sz, vp], ctypes.c_int),
+        "cpd_eig_prepare": ([vp, vp, vp, vp], ctypes.c_int),
+        "cpd_eig_count": ([vp, P(ctypes.c_int32)], ctypes.c_int),
+        "cpd_eig_export": ([vp, vp, vp], ctypes.c_int),
+        "cpd_step": ([vp, P(cpd_step_info)], ctypes.c_int),
+        "cpd_register": ([vp, vp, vp, vp, P(cpd_result)], ctypes.c_int),
+        "cpd_set_state": ([vp, vp, ctypes.c_double], ctypes.c_int),
+        "cpd_get_state": ([vp, vp, vp, P(ctypes.c_double)], ctypes.c_int),
+        "cpd_estep": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "cpd_destroy": ([vp], ctypes.c_int),
+        "cpd_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "cpd_last_error": ([vp], ctypes.c_char_p),
+        "cpd_abi_version": ([], ctypes.c_int32),
+        "cpd_build_info": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    if lib.cpd_abi_version() != CPD_ABI_VERSION:
+        raise ImportError("libfastcpd ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def status_name(s: int) -> str:
+    try:
+        return load_library().cpd_status_str(s).decode()
+    except ImportError:
+        return str(s)
+
+
+def last_error(h=None) -> str:
+    return load_library().cpd_last_error(h).decode()
+
+
+def _check(status: int, h=None, ok=(CPD_OK,)):
+    if status not in ok:
+        raise FastCPDError(status, last_error(h))
+    return status
+
+
+def require_device():
+    """Raise unless the library is built and a HIP device is visible."""
+    import torch
+    load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device visible to torch")
+
+
+def make_params(M, N, D=3, beta=2.0, lam=3.0, w=0.1, sigma2_init=0.0, method="fast",
+                precision="fp32", eig_mode="full", K=0, oversample=20, power_iters=2,
+                seed=0, tol=1e-8, max_iter=1000) -> cpd_params:
+    return cpd_params(CPD_ABI_VERSION, int(M), int(N), int(D), float(beta), float(lam),
+                      float(w), float(sigma2_init), METHODS.get(method, method),
+                      PRECISIONS.get(precision, precision), EIG_MODES.get(eig_mode, eig_mode),
+                      int(K), int(oversample), int(power_iters), int(seed), float(tol),
+                      int(max_iter), 0)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------- C ABI, 1:1
+def cpd_workspace_size(p: cpd_params) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().cpd_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def cpd_init(p: cpd_params, X, Y, workspace, stream=None):
+    h = ctypes.c_void_p()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(load_library().cpd_init(ctypes.byref(h), ctypes.byref(p), _ptr(X), _ptr(Y),
+                                   _ptr(workspace), nbytes, _stream_ptr(stream)))
+    return h
+
+
+def cpd_eig_prepare(h, U=None, lam=None, omega=None):
+    _check(load_library().cpd_eig_prepare(h, _ptr(U), _ptr(lam), _ptr(omega)), h)
+
+
+def cpd_eig_count(h) -> int:
+    k = ctypes.c_int32(0)
+    _check(load_library().cpd_eig_count(h, ctypes.byref(k)), h)
+    return k.value
+
+
+def cpd_eig_export(h, U_out, lam_out):
+    _check(load_library().cpd_eig_export(h, _ptr(U_out), _ptr(lam_out)), h)
+
+
+def cpd_step(h, want_info=True):
+    info = cpd_step_info()
+    _check(load_library().cpd_step(h, ctypes.byref(info) if want_info else None), h)
+    return info if want_info else None
+
+
+def cpd_register(h, W0=None, X_out=None, W_out=None):
+    res = cpd_result()
+    st = _check(load_library().cpd_register(h, _ptr(W0), _ptr(X_out), _ptr(W_out),
+                                            ctypes.byref(res)), h,
+                ok=(CPD_OK, CPD_NOT_CONVERGED))
+    return res, st
+
+
+def cpd_set_state(h, Xt, sigma2):
+    _check(load_library().cpd_set_state(h, _ptr(Xt), float(sigma2)), h)
+
+
+def cpd_get_state(h, Xt_out=None, W_out=None) -> float:
+    s2 = ctypes.c_double(0)
+    _check(load_library().cpd_get_state(h, _ptr(Xt_out), _ptr(W_out), ctypes.byref(s2)), h)
+    return s2.value
+
+
+def cpd_estep(h, logd=None, P1=None, Yt=None, tbar=None):
+    _check(load_library().cpd_estep(h, _ptr(logd), _ptr(P1), _ptr(Yt), _ptr(tbar)), h)
+
+
+def cpd_destroy(h):
+    if h:
+        load_library().cpd_destroy(h)
+
+
+# ------------------------------------------------------------- convenience
+@dataclass
+class RegistrationResult:
+    Xt: object
+    W: object
+    iters: int
+    converged: bool
+    sigma2: float
+    t_c: float
+    t_eig: float
+    t_iter: float
+    t_o: float
+
+
+class Registration:
+    """One handle plus its workspace.  X, Y: CUDA tensors (M x D, N x D) of
+    the working precision (float64 for 'fp64', float32 otherwise)."""
+
+    def __init__(self, X, Y, stream=None, **kw):
+        import torch
+        self.params = make_params(X.shape[0], Y.shape[0], X.shape[1], **kw)
+        self.dtype = torch.float64 if self.params.precision == CPD_PREC_FP64 else torch.float32
+        for t in (X, Y):
+            if not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
+                raise ValueError(f"X, Y must be contiguous {self.dtype} CUDA tensors")
+        nbytes = cpd_workspace_size(self.params)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=X.device)
+        self.stream = stream
+        self.h = cpd_init(self.params, X, Y, self.workspace, stream)
+        self.M, self.N, self.D = X.shape[0], Y.shape[0], X.shape[1]
+        self.device = X.device
+
+    def prepare(self, U=None, lam=None, omega=None):
+        cpd_eig_prepare(self.h, U, lam, omega)
+        return self
+
+    @property
+    def K(self) -> int:
+        return cpd_eig_count(self.h)
+
+    def export_eig(self):
+        import torch
+        K = self.K
+        U = torch.empty(self.M, K, dtype=torch.float64, device=self.device)
+        lam = torch.empty(K, dtype=torch.float64, device=self.device)
+        cpd_eig_export(self.h, U, lam)
+        return U, lam
+
+    def step(self):
+        return cpd_step(self.h)
+
+    def estep(self):
+        import torch
+        o = dict(logd=torch.empty(self.N, dtype=self.dtype, device=self.device),
+                 P1=torch.empty(self.M, dtype=self.dtype, device=self.device),
+                 Yt=torch.empty(self.M, self.D, dtype=self.dtype, device=self.device),
+                 tbar=torch.empty(self.M, dtype=self.dtype, device=self.device))
+        cpd_estep(self.h, **o)
+        return o
+
+    def set_state(self, Xt, sigma2):
+        cpd_set_state(self.h, Xt, sigma2)
+
+    def state(self):
+        import torch
+        Xt = torch.empty(self.M, self.D, dtype=self.dtype, device=self.device)
+        W = torch.empty_like(Xt)
+        s2 = cpd_get_state(self.h, Xt, W)
+        return Xt, W, s2
+
+    def register(self, W0=None) -> RegistrationResult:
+        import torch
+        Xt = torch.empty(self.M, self.D, dtype=self.dtype, device=self.device)
+        W = torch.empty_like(Xt)
+        res, st = cpd_register(self.h, W0, Xt, W)
+        return RegistrationResult(Xt, W, res.iters, bool(res.converged), res.sigma2,
+                                  res.t_c, res.t_eig, res.t_iter, res.t_o)
+
+    def close(self):
+        if getattr(self, "h", None):
+            cpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

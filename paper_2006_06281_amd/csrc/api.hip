@@ -1,0 +1,639 @@
+// Host runtime behind the C ABI of fastcpd.h: argument validation, the
+// workspace carve-up, the per-handle state machine and the order of kernel
+// launches inside one EM iteration.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fastcpd.h"
+#include "common.hpp"
+#include "eig.hpp"
+#include "kernels.hpp"
+#include "orig.hpp"
+
+using namespace fcpd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+enum class Stage { Init = 0, Prepared = 1 };
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+  size_t total = 0;
+  Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, badcols, badrows, llpart,
+      sigpart, initpart;
+  Region U, lam, U64, tpart, GT, HT;
+  EigLayout eig;
+  OrigLayout orig;
+  int splitsA = 1, chunkA = 1, splitsB = 1, chunkB = 1;
+  int mchunks = 1, mrows = 64;
+  int Kcap = 0;
+};
+
+size_t add(Layout& L, Region& r, size_t bytes) {
+  r.off = L.total;
+  r.bytes = bytes;
+  L.total += (bytes + 255) & ~(size_t)255;
+  return r.off;
+}
+
+int kcap_of(const cpd_params& p) {
+  if (p.method != CPD_METHOD_FAST) return 0;
+  if (p.eig_mode == CPD_EIG_FULL) return eig_full_capacity(p.M);
+  return p.K;
+}
+
+template <typename T>
+Layout make_layout(const cpd_params& p) {
+  Layout L;
+  const size_t M = (size_t)p.M, N = (size_t)p.N;
+  const size_t p4 = sizeof(P4<T>);
+  estep_splits<T>(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+  add(L, L.sc, sizeof(DevScalars));
+  add(L, L.X, M * p4);
+  add(L, L.Xt, M * p4);
+  add(L, L.Xnew, M * p4);
+  add(L, L.Y, N * p4);
+  add(L, L.W, M * p4);
+  add(L, L.xs, M * p4);
+  add(L, L.ys, N * p4);
+  add(L, L.Yt, M * p4);
+  add(L, L.P1, M * sizeof(T));
+  add(L, L.tbar, M * sizeof(T));
+  add(L, L.partA, (size_t)L.splitsA * N * sizeof(T));
+  add(L, L.partB, (size_t)L.splitsB * 5 * M * sizeof(T));
+  add(L, L.badcols, N * sizeof(int));
+  add(L, L.badrows, M * sizeof(int));
+  add(L, L.llpart, ((N + 255) / 256) * sizeof(double));
+  add(L, L.sigpart, 2 * (size_t)sigma2_blocks<T>(p.M) * sizeof(double));
+  add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
+  L.Kcap = kcap_of(p);
+  if (p.method == CPD_METHOD_FAST) {
+    const size_t K = (size_t)L.Kcap;
+    L.mchunks = fast_mstep_chunks<T>(p.M, &L.mrows);
+    add(L, L.U, M * K * sizeof(T));
+    add(L, L.lam, K * sizeof(double));
+    add(L, L.U64, M * K * sizeof(double));
+    add(L, L.tpart, (size_t)L.mchunks * K * 4 * sizeof(T));
+    add(L, L.GT, K * p4);
+    add(L, L.HT, K * p4);
+    if (p.eig_mode != CPD_EIG_IMPORT) {
+      L.eig = eig_layout(p.M, p.eig_mode, p.K, p.oversample, L.total);
+      L.total = L.eig.end;
+    }
+  } else {
+    L.orig = orig_layout(p.M, (int)sizeof(T), L.total);
+    L.total = L.orig.end;
+  }
+  return L;
+}
+
+Layout layout_for(const cpd_params& p) {
+  return p.precision == CPD_PREC_FP64 ? make_layout<double>(p) : make_layout<float>(p);
+}
+
+}  // namespace
+
+struct cpd_ctx {
+  cpd_params p{};
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t st = nullptr;
+  Stage stage = Stage::Init;
+  int K = 0;  // eigenpairs held
+  double t_eig = 0.0;
+  std::string err;
+  template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
+  DevScalars* sc() const { return at<DevScalars>(L.sc); }
+};
+
+namespace {
+
+cpd_status fail(cpd_ctx* h, cpd_status s, const std::string& msg) {
+  g_last_error = msg;
+  if (h) h->err = msg;
+  return s;
+}
+
+cpd_status hip_fail(cpd_ctx* h, hipError_t e, const char* what) {
+  return fail(h, CPD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                       \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call);    \
+  } while (0)
+
+cpd_status validate(const cpd_params* p) {
+  if (!p) return fail(nullptr, CPD_E_ARG, "params is NULL");
+  if (p->abi_version != CPD_ABI_VERSION) return fail(nullptr, CPD_E_ARG, "abi_version mismatch");
+  if (p->M < 1 || p->N < 1 || p->M > (1 << 26) || p->N > (1 << 26))
+    return fail(nullptr, CPD_E_ARG, "M and N must be in [1, 2^26]");
+  if (p->D < 1 || p->D > 3) return fail(nullptr, CPD_E_ARG, "D must be 1, 2 or 3");
+  if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(nullptr, CPD_E_ARG, "beta must be > 0");
+  if (!(p->lambda > 0.0) || !std::isfinite(p->lambda))
+    return fail(nullptr, CPD_E_ARG, "lambda must be > 0");
+  if (!(p->w >= 0.0 && p->w < 1.0)) return fail(nullptr, CPD_E_ARG, "w must satisfy 0 <= w < 1");
+  if (!std::isfinite(p->sigma2_init)) return fail(nullptr, CPD_E_ARG, "sigma2_init not finite");
+  if (p->method != CPD_METHOD_ORIGINAL && p->method != CPD_METHOD_FAST)
+    return fail(nullptr, CPD_E_ARG, "unknown method");
+  if (p->precision < CPD_PREC_FP64 || p->precision > CPD_PREC_BF16X)
+    return fail(nullptr, CPD_E_ARG, "unknown precision");
+  if (p->method == CPD_METHOD_FAST) {
+    if (p->eig_mode < CPD_EIG_FULL || p->eig_mode > CPD_EIG_IMPORT)
+      return fail(nullptr, CPD_E_ARG, "unknown eig_mode");
+    if (p->eig_mode != CPD_EIG_FULL && (p->K < 1 || p->K > p->M))
+      return fail(nullptr, CPD_E_ARG, "K must be in [1, M]");
+    if (p->eig_mode == CPD_EIG_TOPK) {
+      const int over = p->oversample > 0 ? p->oversample : 20;
+      if (p->K + over > eig_topk_max_cols())
+        return fail(nullptr, CPD_E_UNSUPPORTED, "K + oversample exceeds the randomized solver's width");
+      if (p->power_iters > 16) return fail(nullptr, CPD_E_ARG, "power_iters must be <= 16");
+    }
+  }
+  if (!(p->tol >= 0.0)) return fail(nullptr, CPD_E_ARG, "tol must be >= 0");
+  if (p->max_iter < 1) return fail(nullptr, CPD_E_ARG, "max_iter must be >= 1");
+  if (p->reserved != 0) return fail(nullptr, CPD_E_ARG, "reserved must be 0");
+  if (p->precision == CPD_PREC_BF16X && p->method != CPD_METHOD_FAST)
+    return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X precision is implemented for the Fast method");
+  return CPD_OK;
+}
+
+cpd_status check_device(cpd_ctx* h) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) return fail(h, CPD_E_DEVICE, "no HIP device available");
+  int dev = 0;
+  HIPCHK(h, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(h, hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(h, CPD_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+  return CPD_OK;
+}
+
+// ------------------------------------------------------------- one step
+template <typename T>
+void enqueue_estep(cpd_ctx* h, int gate, T* logd_out) {
+  const Layout& L = h->L;
+  EStepArgs<T> a{};
+  a.Xt = h->at<P4<T>>(L.Xt);
+  a.Y = h->at<P4<T>>(L.Y);
+  a.xs = h->at<P4<T>>(L.xs);
+  a.ys = h->at<P4<T>>(L.ys);
+  a.M = h->p.M;
+  a.N = h->p.N;
+  a.D = h->p.D;
+  a.w = h->p.w;
+  a.sc = h->sc();
+  a.gate = gate;
+  a.splitsA = L.splitsA;
+  a.chunkA = L.chunkA;
+  a.splitsB = L.splitsB;
+  a.chunkB = L.chunkB;
+  a.partA = h->at<T>(L.partA);
+  a.partB = h->at<T>(L.partB);
+  a.badcols = h->at<int>(L.badcols);
+  a.badrows = h->at<int>(L.badrows);
+  a.llpart = h->at<double>(L.llpart);
+  a.logd_out = logd_out;
+  a.Yt = h->at<P4<T>>(L.Yt);
+  a.P1 = h->at<T>(L.P1);
+  a.tbar = h->at<T>(L.tbar);
+  if (h->p.precision == CPD_PREC_BF16X)
+    estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
+  else
+    estep_launch<T>(a, h->st);
+}
+
+template <typename T>
+void enqueue_mstep(cpd_ctx* h, int gate) {
+  const Layout& L = h->L;
+  if (h->p.method == CPD_METHOD_FAST) {
+    FastMArgs<T> a{};
+    a.X = h->at<P4<T>>(L.X);
+    a.Yt = h->at<P4<T>>(L.Yt);
+    a.U = h->at<T>(L.U);
+    a.lam = h->at<double>(L.lam);
+    a.M = h->p.M;
+    a.K = h->K;
+    a.D = h->p.D;
+    a.lmbda = h->p.lambda;
+    a.sc = h->sc();
+    a.gate = gate;
+    a.rows_per_chunk = L.mrows;
+    a.chunks = L.mchunks;
+    a.tpart = h->at<T>(L.tpart);
+    a.GT = h->at<P4<T>>(L.GT);
+    a.HT = h->at<P4<T>>(L.HT);
+    a.Xnew = h->at<P4<T>>(L.Xnew);
+    a.W = h->at<P4<T>>(L.W);
+    fast_mstep_launch<T>(a, h->st);
+  } else {
+    OrigArgs<T> a{};
+    a.X = h->at<P4<T>>(L.X);
+    a.Yt = h->at<P4<T>>(L.Yt);
+    a.P1 = h->at<T>(L.P1);
+    a.M = h->p.M;
+    a.D = h->p.D;
+    a.lmbda = h->p.lambda;
+    a.sc = h->sc();
+    a.gate = gate;
+    a.ws = h->ws;
+    a.L = &L.orig;
+    a.Xnew = h->at<P4<T>>(L.Xnew);
+    a.W = h->at<P4<T>>(L.W);
+    orig_mstep_launch<T>(a, h->st);
+  }
+}
+
+template <typename T>
+void enqueue_sigma2(cpd_ctx* h, int gate) {
+  const Layout& L = h->L;
+  Sigma2Args<T> a{};
+  a.Xt = h->at<P4<T>>(L.Xt);
+  a.Xnew = h->at<P4<T>>(L.Xnew);
+  a.Yt = h->at<P4<T>>(L.Yt);
+  a.tbar = h->at<T>(L.tbar);
+  a.P1 = h->p.method == CPD_METHOD_ORIGINAL ? h->at<T>(L.P1) : nullptr;
+  a.M = h->p.M;
+  a.N = h->p.N;
+  a.D = h->p.D;
+  a.w = h->p.w;
+  a.sc = h->sc();
+  a.gate = gate;
+  a.part = h->at<double>(L.sigpart);
+  a.blocks = sigma2_blocks<T>(h->p.M);
+  a.llpart = h->at<double>(L.llpart);
+  a.llblocks = (h->p.N + 255) / 256;
+  sigma2_launch<T>(a, h->st);
+}
+
+struct PhaseEvents {
+  hipEvent_t e[4];
+};
+
+template <typename T>
+void enqueue_step(cpd_ctx* h, int gate, PhaseEvents* ev) {
+  if (ev) (void)hipEventRecord(ev->e[0], h->st);
+  enqueue_estep<T>(h, gate, nullptr);
+  if (ev) (void)hipEventRecord(ev->e[1], h->st);
+  enqueue_mstep<T>(h, gate);
+  if (ev) (void)hipEventRecord(ev->e[2], h->st);
+  enqueue_sigma2<T>(h, gate);
+  if (ev) (void)hipEventRecord(ev->e[3], h->st);
+}
+
+__global__ void k_arm(DevScalars* sc, int reset_iter) {
+  if (threadIdx.x == 0) {
+    sc->done = 0;
+    sc->converged = 0;
+    if (reset_iter) sc->iter = 0;
+  }
+}
+
+cpd_status ready_for_steps(cpd_ctx* h) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  if (h->stage != Stage::Prepared)
+    return fail(h, CPD_E_STATE, "cpd_eig_prepare must run before stepping");
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status step_impl(cpd_ctx* h, cpd_step_info* info) {
+  hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 0);
+  enqueue_step<T>(h, 0, nullptr);
+  HIPCHK(h, hipGetLastError());
+  if (!info) return CPD_OK;
+  DevScalars s;
+  HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  info->iter = s.iter;
+  info->converged = s.converged;
+  info->sigma2 = s.sigma2;
+  info->dsigma2 = s.dsigma2;
+  info->loglik = s.loglik;
+  if (s.nonfinite) return fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, cpd_result* res) {
+  const Layout& L = h->L;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (W0) {
+    phi_apply_launch<T>(h->at<P4<T>>(L.X), static_cast<const T*>(W0), h->at<P4<T>>(L.Xt), h->p.M,
+                        h->p.D, h->p.beta, h->st);
+    if (!(h->p.sigma2_init > 0.0))
+      reset_sigma2_launch<T>(h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D,
+                             h->sc(), h->at<double>(L.initpart), h->st);
+  }
+  hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 1);
+  HIPCHK(h, hipGetLastError());
+  // Iterations are enqueued in batches; after convergence the remaining
+  // launches of a batch see sc->done and return at once.
+  const int batch = 8;
+  std::vector<PhaseEvents> evs;
+  if (res) {
+    evs.resize(batch);
+    for (auto& pe : evs)
+      for (auto& e : pe.e) HIPCHK(h, hipEventCreate(&e));
+  }
+  double t_c = 0, t_it = 0;
+  DevScalars s{};
+  cpd_status status = CPD_OK;
+  for (int done_iters = 0; done_iters < h->p.max_iter;) {
+    const int nb = std::min(batch, h->p.max_iter - done_iters);
+    for (int i = 0; i < nb; ++i) enqueue_step<T>(h, 1, res ? &evs[i] : nullptr);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (res) {
+      for (int i = 0; i < nb; ++i) {
+        float a = 0, b = 0;
+        (void)hipEventElapsedTime(&a, evs[i].e[0], evs[i].e[1]);
+        (void)hipEventElapsedTime(&b, evs[i].e[1], evs[i].e[2]);
+        t_c += a * 1e-3;
+        t_it += b * 1e-3;
+      }
+    }
+    done_iters += nb;
+    if (s.done) break;
+  }
+  for (auto& pe : evs)
+    for (auto& e : pe.e) (void)hipEventDestroy(e);
+  if (s.nonfinite) status = fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
+  if (X_out) unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(X_out), h->p.M, h->p.D, h->st);
+  if (W_out) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W_out), h->p.M, h->p.D, h->st);
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  const double total =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (res) {
+    res->iters = s.iter;
+    res->converged = s.converged;
+    res->sigma2 = s.sigma2;
+    res->t_c = t_c;
+    res->t_iter = t_it;
+    res->t_eig = h->t_eig;
+    res->t_o = std::max(0.0, total - t_c - t_it);
+  }
+  if (status != CPD_OK) return status;
+  return s.converged ? CPD_OK : CPD_NOT_CONVERGED;
+}
+
+template <typename T>
+cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
+  const Layout& L = h->L;
+  init_launch<T>(static_cast<const T*>(X), static_cast<const T*>(Y), h->at<P4<T>>(L.X),
+                 h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D, h->p.sigma2_init,
+                 h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st);
+  // W starts at 0 (so Xt = X)
+  HIPCHK(h, hipMemsetAsync(h->ws + L.W.off, 0, L.W.bytes, h->st));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_import,
+                        const double* omega) {
+  const Layout& L = h->L;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (h->p.method == CPD_METHOD_ORIGINAL) {
+    if (U_import || lam_import || omega)
+      return fail(h, CPD_E_ARG, "the original method takes no eigen-prep arguments");
+    orig_prepare<T>(h->at<P4<T>>(L.X), h->p.M, h->p.beta, h->ws, L.orig, h->st);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->stage = Stage::Prepared;
+    h->t_eig = 0.0;
+    return CPD_OK;
+  }
+  if (h->p.eig_mode == CPD_EIG_IMPORT) {
+    if (!U_import || !lam_import) return fail(h, CPD_E_ARG, "IMPORT needs U_import and lam_import");
+    if (omega) return fail(h, CPD_E_ARG, "omega is only used by TOPK");
+    import_eig_launch<T>(U_import, lam_import, h->at<T>(L.U), h->at<double>(L.lam),
+                         h->at<double>(L.U64), h->p.M, h->p.K, h->st);
+    h->K = h->p.K;
+  } else {
+    if (U_import || lam_import) return fail(h, CPD_E_ARG, "U_import/lam_import are for IMPORT only");
+    if (omega && h->p.eig_mode != CPD_EIG_TOPK) return fail(h, CPD_E_ARG, "omega is for TOPK only");
+    EigRun r{};
+    r.X = reinterpret_cast<const void*>(h->at<P4<T>>(L.X));
+    r.x_is_double = sizeof(T) == 8;
+    r.M = h->p.M;
+    r.beta = h->p.beta;
+    r.mode = h->p.eig_mode;
+    r.K = h->p.K;
+    r.oversample = h->p.oversample;
+    r.power_iters = h->p.power_iters;
+    r.seed = h->p.seed;
+    r.omega = omega;
+    r.ws = h->ws;
+    r.L = &L.eig;
+    r.U64 = h->at<double>(L.U64);
+    r.lam = h->at<double>(L.lam);
+    r.Kcap = L.Kcap;
+    r.st = h->st;
+    int K = 0;
+    std::string msg;
+    const int rc = eig_prepare_run(r, &K, &msg);
+    if (rc != 0) return fail(h, rc == 1 ? CPD_E_NUMERIC : CPD_E_DEVICE, msg);
+    h->K = K;
+    convert_u_launch<T>(h->at<double>(L.U64), h->at<T>(L.U), (size_t)h->p.M * K, h->st);
+  }
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  h->t_eig = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  h->stage = Stage::Prepared;
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status estep_impl(cpd_ctx* h, void* logd, void* P1, void* Yt, void* tbar) {
+  const Layout& L = h->L;
+  enqueue_estep<T>(h, 0, static_cast<T*>(logd));
+  if (P1) HIPCHK(h, hipMemcpyAsync(P1, h->ws + L.P1.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
+  if (tbar) HIPCHK(h, hipMemcpyAsync(tbar, h->ws + L.tbar.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
+  if (Yt) unpack_launch<T>(h->at<P4<T>>(L.Yt), static_cast<T*>(Yt), h->p.M, h->p.D, h->st);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
+}
+
+__global__ void k_set_sigma2(DevScalars* sc, double s2) {
+  if (threadIdx.x == 0) {
+    sc->sigma2 = s2;
+    sc->done = 0;
+    sc->converged = 0;
+  }
+}
+
+template <typename T>
+cpd_status set_state_impl(cpd_ctx* h, const void* Xt, double sigma2) {
+  const Layout& L = h->L;
+  pack_launch<T>(static_cast<const T*>(Xt), h->at<P4<T>>(L.Xt), h->p.M, h->p.D, h->st);
+  hipLaunchKernelGGL(k_set_sigma2, dim3(1), dim3(64), 0, h->st, h->sc(), sigma2);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status get_state_impl(cpd_ctx* h, void* Xt, void* W, double* sigma2) {
+  const Layout& L = h->L;
+  if (Xt) unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(Xt), h->p.M, h->p.D, h->st);
+  if (W) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W), h->p.M, h->p.D, h->st);
+  DevScalars s;
+  HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  if (sigma2) *sigma2 = s.sigma2;
+  return CPD_OK;
+}
+
+bool is_f64(const cpd_ctx* h) { return h->p.precision == CPD_PREC_FP64; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t cpd_abi_version(void) { return CPD_ABI_VERSION; }
+
+const char* cpd_build_info(void) { return "libfastcpd abi=1 target=gfx950"; }
+
+const char* cpd_status_str(cpd_status s) {
+  switch (s) {
+    case CPD_OK: return "CPD_OK";
+    case CPD_NOT_CONVERGED: return "CPD_NOT_CONVERGED";
+    case CPD_E_ARG: return "CPD_E_ARG";
+    case CPD_E_STATE: return "CPD_E_STATE";
+    case CPD_E_WORKSPACE: return "CPD_E_WORKSPACE";
+    case CPD_E_DEVICE: return "CPD_E_DEVICE";
+    case CPD_E_NUMERIC: return "CPD_E_NUMERIC";
+    case CPD_E_UNSUPPORTED: return "CPD_E_UNSUPPORTED";
+  }
+  return "unknown status";
+}
+
+const char* cpd_last_error(cpd_handle h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+cpd_status cpd_workspace_size(const cpd_params* p, size_t* bytes) {
+  if (!bytes) return fail(nullptr, CPD_E_ARG, "bytes is NULL");
+  const cpd_status v = validate(p);
+  if (v != CPD_OK) return v;
+  *bytes = layout_for(*p).total;
+  return CPD_OK;
+}
+
+cpd_status cpd_init(cpd_handle* out, const cpd_params* p, const void* X, const void* Y,
+                    void* workspace, size_t workspace_bytes, void* hip_stream) {
+  if (!out) return fail(nullptr, CPD_E_ARG, "handle pointer is NULL");
+  *out = nullptr;
+  const cpd_status v = validate(p);
+  if (v != CPD_OK) return v;
+  if (!X || !Y) return fail(nullptr, CPD_E_ARG, "X and Y must be device pointers");
+  const Layout L = layout_for(*p);
+  if (!workspace) return fail(nullptr, CPD_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(nullptr, CPD_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total) return fail(nullptr, CPD_E_WORKSPACE, "workspace too small");
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  cpd_ctx* h = new (std::nothrow) cpd_ctx();
+  if (!h) return fail(nullptr, CPD_E_DEVICE, "out of host memory");
+  h->p = *p;
+  h->L = L;
+  h->ws = static_cast<char*>(workspace);
+  h->st = static_cast<hipStream_t>(hip_stream);
+  const cpd_status s = is_f64(h) ? init_impl<double>(h, X, Y) : init_impl<float>(h, X, Y);
+  if (s != CPD_OK) {
+    g_last_error = h->err;
+    delete h;
+    return s;
+  }
+  *out = h;
+  return CPD_OK;
+}
+
+cpd_status cpd_eig_prepare(cpd_handle h, const double* U_import, const double* lam_import,
+                           const double* omega) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  return is_f64(h) ? prepare_impl<double>(h, U_import, lam_import, omega)
+                   : prepare_impl<float>(h, U_import, lam_import, omega);
+}
+
+cpd_status cpd_eig_count(cpd_handle h, int32_t* K_out) {
+  if (!h || !K_out) return fail(h, CPD_E_ARG, "NULL argument");
+  if (h->stage != Stage::Prepared || h->p.method != CPD_METHOD_FAST)
+    return fail(h, CPD_E_STATE, "no eigenpairs prepared");
+  *K_out = h->K;
+  return CPD_OK;
+}
+
+cpd_status cpd_eig_export(cpd_handle h, double* U_out, double* lam_out) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  if (h->stage != Stage::Prepared || h->p.method != CPD_METHOD_FAST)
+    return fail(h, CPD_E_STATE, "no eigenpairs prepared");
+  if (!U_out && !lam_out) return fail(h, CPD_E_ARG, "nothing to export");
+  if (U_out)
+    HIPCHK(h, hipMemcpyAsync(U_out, h->ws + h->L.U64.off, sizeof(double) * (size_t)h->p.M * h->K,
+                             hipMemcpyDeviceToDevice, h->st));
+  if (lam_out)
+    HIPCHK(h, hipMemcpyAsync(lam_out, h->ws + h->L.lam.off, sizeof(double) * h->K,
+                             hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
+}
+
+cpd_status cpd_step(cpd_handle h, cpd_step_info* info) {
+  const cpd_status r = ready_for_steps(h);
+  if (r != CPD_OK) return r;
+  return is_f64(h) ? step_impl<double>(h, info) : step_impl<float>(h, info);
+}
+
+cpd_status cpd_register(cpd_handle h, const void* W0, void* X_out, void* W_out, cpd_result* res) {
+  const cpd_status r = ready_for_steps(h);
+  if (r != CPD_OK) return r;
+  return is_f64(h) ? register_impl<double>(h, W0, X_out, W_out, res)
+                   : register_impl<float>(h, W0, X_out, W_out, res);
+}
+
+cpd_status cpd_set_state(cpd_handle h, const void* Xt, double sigma2) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  if (!Xt) return fail(h, CPD_E_ARG, "Xt is NULL");
+  if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(h, CPD_E_ARG, "sigma2 must be > 0");
+  return is_f64(h) ? set_state_impl<double>(h, Xt, sigma2) : set_state_impl<float>(h, Xt, sigma2);
+}
+
+cpd_status cpd_get_state(cpd_handle h, void* Xt_out, void* W_out, double* sigma2_out) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  return is_f64(h) ? get_state_impl<double>(h, Xt_out, W_out, sigma2_out)
+                   : get_state_impl<float>(h, Xt_out, W_out, sigma2_out);
+}
+
+cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  return is_f64(h) ? estep_impl<double>(h, logd, P1, Yt, tbar)
+                   : estep_impl<float>(h, logd, P1, Yt, tbar);
+}
+
+cpd_status cpd_destroy(cpd_handle h) {
+  delete h;
+  return CPD_OK;
+}
+
+}  // extern "C"

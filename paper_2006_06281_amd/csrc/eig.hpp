@@ -1,0 +1,45 @@
+// Eigen-prep of Fast CPD (Section III, eq. 16 and eq. 19): interfaces.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace fcpd {
+
+struct EigLayout {
+  size_t end = 0;
+  int n = 0;        // working width of the randomized solver (columns)
+  int Mdense = 0;   // dense Jacobi size (0 when not used)
+  size_t omega = 0, Z = 0, Q = 0, G = 0, R = 0, V = 0, ritz = 0, misc = 0, phi = 0;
+};
+
+// Columns the randomized solver can carry (K + oversample <= this).
+int eig_topk_max_cols();
+// Eigenpairs FULL mode may hold for M model points.
+int eig_full_capacity(int M);
+EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start);
+
+struct EigRun {
+  const void* X;       // P4<float> or P4<double> model points
+  bool x_is_double;
+  int M;
+  double beta;
+  int mode, K, oversample, power_iters;
+  uint64_t seed;
+  const double* omega; // nullable (TOPK)
+  char* ws;
+  const EigLayout* L;
+  double* U64;         // out: M x Kcap (row-major, M x K used)
+  double* lam;         // out: Kcap
+  int Kcap;
+  hipStream_t st;
+};
+// 0 ok, 1 numerical failure, 2 device error, 3 unsupported.
+int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg);
+
+template <typename T> void convert_u_launch(const double* U64, T* U, size_t n, hipStream_t st);
+
+}  // namespace fcpd

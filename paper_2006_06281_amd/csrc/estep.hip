@@ -1,0 +1,401 @@
+// E-step of (Fast) CPD on gfx950: the posterior of eq. 4 with the outlier
+// term, and the row normalisation of eq. 5, reduced to the per-row and
+// per-column quantities the M-step and the sigma^2 update need.  The M x N
+// posterior is never stored.
+//
+// Exponents are kept in base 2 on prescaled coordinates: with
+// kappa = log2(e)/(2 sigma^2) and x^ = sqrt(kappa) x, eq. 4's Gaussian is
+// 2^(-|y^_n - x^_m|^2), so each pair costs three differences, three
+// multiply-adds and one v_exp_f32.
+//
+// Pass A (columns): L_n = log2 d_n, d_n = sum_m 2^(-|y^_n - x^_m|^2) + c,
+//   measured from a fixed reference ref = max(log2 c, -100).  The outlier
+//   sink makes the fixed reference exact: every term is <= 2^(-ref) and a
+//   term that underflows is < 2^-126 * c <= 2^-126 * d_n.  Columns whose sum
+//   still falls below 2^-60 of the reference (only possible with w = 0 or an
+//   extreme c) are recomputed exactly by colfix with their own maximum.
+// Pass B (rows): p_mn = 2^(-|y^_n - x^_m|^2 - L_n) <= 1; per row m it sums
+//   r_m = sum_n p_mn (P1, eq. 21), sum_n p_mn (y^_n - x^_m) (gives P'Y of
+//   eq. 5 relative to the point itself) and sum_n p_mn |y^_n - x^_m|^2.
+//   Rows whose r_m underflows (a model point far from every scene point) are
+//   recomputed exactly by rowfix, which shifts by the row's own maximum --
+//   the constrained posterior p'_mn = p_mn / r_m is then still defined.
+//
+// Both passes split the long reduction axis over blockIdx.y so a launch has
+// thousands of workgroups; partial sums go to a [split][...] buffer and are
+// merged in a fixed order (deterministic, no float atomics).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fcpd {
+
+// ---------------------------------------------------------------- prescale
+template <typename T>
+__global__ __launch_bounds__(256) void k_prescale(const P4<T>* __restrict__ Xt,
+                                                  const P4<T>* __restrict__ Y,
+                                                  P4<T>* __restrict__ xs,
+                                                  P4<T>* __restrict__ ys, int M, int N,
+                                                  DevScalars* sc, int gate) {
+  if (gate && sc->done) return;
+  const double sk = sqrt(kappa_of(sc->sigma2));
+  const T s = (T)sk;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc->bad_cols = 0;
+    sc->bad_rows = 0;
+  }
+  if (i < M) {
+    P4<T> p = Xt[i];
+    xs[i] = P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
+  } else if (i < M + N) {
+    P4<T> p = Y[i - M];
+    ys[i - M] = P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
+  }
+}
+
+// ------------------------------------------------------------------ pass A
+template <typename T, int D>
+__device__ __forceinline__ T sq3(const P4<T>& a, T bx, T by, T bz, T init) {
+  T dx = a.x - bx;
+  T q = fma(dx, dx, init);
+  if (D > 1) {
+    T dy = a.y - by;
+    q = fma(dy, dy, q);
+  }
+  if (D > 2) {
+    T dz = a.z - bz;
+    q = fma(dz, dz, q);
+  }
+  return q;
+}
+
+// part[blockIdx.y * N + n] = sum over this split's model points of
+// 2^(-(|y^_n - x^_m|^2 + ref)).
+template <typename T, int D, int NB>
+__global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys, int M, int N,
+                                                int m_chunk, const DevScalars* __restrict__ sc,
+                                                double w, T* __restrict__ part, int gate) {
+  if (gate && sc->done) return;
+  const double l2c = log2_c(sc->sigma2, D, w, M, N);
+  const T ref = (T)fmax(l2c, kRefFloor);
+  const int n0 = blockIdx.x * (256 * NB) + threadIdx.x;
+  const int m0 = blockIdx.y * m_chunk;
+  const int m1 = min(M, m0 + m_chunk);
+  T yx[NB], yy[NB], yz[NB], s[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 256;
+    P4<T> p = n < N ? ys[n] : P4<T>{(T)0, (T)0, (T)0, (T)0};
+    yx[j] = p.x;
+    yy[j] = p.y;
+    yz[j] = p.z;
+    s[j] = (T)0;
+  }
+  int m = m0;
+  for (; m + 4 <= m1; m += 4) {
+    P4<T> a0 = xs[m], a1 = xs[m + 1], a2 = xs[m + 2], a3 = xs[m + 3];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      T e0 = fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+      T e1 = fexp2(-sq3<T, D>(a1, yx[j], yy[j], yz[j], ref));
+      T e2 = fexp2(-sq3<T, D>(a2, yx[j], yy[j], yz[j], ref));
+      T e3 = fexp2(-sq3<T, D>(a3, yx[j], yy[j], yz[j], ref));
+      s[j] += (e0 + e1) + (e2 + e3);
+    }
+  }
+  for (; m < m1; ++m) {
+    P4<T> a0 = xs[m];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) s[j] += fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = n0 + j * 256;
+    if (n < N) part[(size_t)blockIdx.y * N + n] = s[j];
+  }
+}
+
+// L_n = ref + log2(sum_splits part + 2^(log2 c - ref)) into ys[n].w; flags
+// columns that need the exact path; per-block partial of sum_n ln d_n.
+template <typename T>
+__global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, int splits,
+                                                  P4<T>* __restrict__ ys, T* __restrict__ logd_out,
+                                                  int M, int N, int D, DevScalars* sc, double w,
+                                                  int* __restrict__ badlist,
+                                                  double* __restrict__ llpart, int gate) {
+  __shared__ double sh[16];
+  if (gate && sc->done) return;
+  const double l2c = log2_c(sc->sigma2, D, w, M, N);
+  const double refd = fmax(l2c, kRefFloor);
+  const T ref = (T)refd;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  double ln_d = 0.0;
+  if (n < N) {
+    T s = (T)0;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * N + n];
+    s += (T)exp2(l2c - refd);  // the outlier sink c, relative to ref (0 if w = 0)
+    const T L = ref + flog2(s);
+    const bool bad = !(s >= (T)0x1p-60) || !isfinite(L);
+    if (bad) {
+      const int k = atomicAdd(&sc->bad_cols, 1);
+      badlist[k] = n;
+    }
+    ys[n].w = L;
+    if (logd_out) logd_out[n] = (T)((double)L * kLn2);
+    ln_d = (double)L * kLn2;
+  }
+  const double b = block_sum_d(ln_d, sh);
+  if (threadIdx.x == 0) llpart[blockIdx.x] = b;
+}
+
+// Exact pass A for the flagged columns: two sweeps over all model points,
+// the first for the column maximum, the second for the shifted sum.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
+                                                P4<T>* __restrict__ ys, T* __restrict__ logd_out,
+                                                int M, int N, DevScalars* sc, double w,
+                                                const int* __restrict__ badlist, int gate) {
+  if (gate && sc->done) return;
+  const int nbad = sc->bad_cols;
+  const int lane = threadIdx.x & 63;
+  const int wglobal = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const double l2c = log2_c(sc->sigma2, D, w, M, N);
+  for (int b = wglobal; b < nbad; b += nwaves) {
+    const int n = badlist[b];
+    const P4<T> y = ys[n];
+    double mx = l2c;
+    for (int m = lane; m < M; m += 64)
+      mx = fmax(mx, -(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0));
+    mx = wave_max(mx);
+    double s = 0.0;
+    for (int m = lane; m < M; m += 64)
+      s += exp2(-(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0) - mx);
+    s = wave_sum(s) + exp2(l2c - mx);
+    if (lane == 0) {
+      const double L = mx + log2(s);
+      ys[n].w = (T)L;
+      if (logd_out) logd_out[n] = (T)(L * kLn2);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ pass B
+// part layout: [split][5][M]: r, sum p dx, sum p dy, sum p dz, sum p d2
+// (prescaled differences y^_n - x^_m).
+template <typename T, int D, int NB>
+__global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys, int M, int N,
+                                                int n_chunk, const DevScalars* __restrict__ sc,
+                                                T* __restrict__ part, int gate) {
+  if (gate && sc->done) return;
+  const int m0 = blockIdx.x * (256 * NB) + threadIdx.x;
+  const int nb = blockIdx.y * n_chunk;
+  const int ne = min(N, nb + n_chunk);
+  T ax[NB], ay[NB], az[NB], r[NB], px[NB], py[NB], pz[NB], t[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int m = m0 + j * 256;
+    P4<T> p = m < M ? xs[m] : P4<T>{(T)0, (T)0, (T)0, (T)0};
+    ax[j] = p.x;
+    ay[j] = p.y;
+    az[j] = p.z;
+    r[j] = px[j] = py[j] = pz[j] = t[j] = (T)0;
+  }
+  for (int n = nb; n < ne; ++n) {
+    const P4<T> y = ys[n];  // (x^, y^, z^, L_n)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const T dx = y.x - ax[j];
+      T d2 = dx * dx;
+      T dy = (T)0, dz = (T)0;
+      if (D > 1) {
+        dy = y.y - ay[j];
+        d2 = fma(dy, dy, d2);
+      }
+      if (D > 2) {
+        dz = y.z - az[j];
+        d2 = fma(dz, dz, d2);
+      }
+      const T e = fexp2(-(d2 + y.w));
+      r[j] += e;
+      px[j] = fma(e, dx, px[j]);
+      if (D > 1) py[j] = fma(e, dy, py[j]);
+      if (D > 2) pz[j] = fma(e, dz, pz[j]);
+      t[j] = fma(e, d2, t[j]);
+    }
+  }
+  T* base = part + (size_t)blockIdx.y * 5 * M;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int m = m0 + j * 256;
+    if (m < M) {
+      base[m] = r[j];
+      base[(size_t)M + m] = px[j];
+      base[(size_t)2 * M + m] = py[j];
+      base[(size_t)3 * M + m] = pz[j];
+      base[(size_t)4 * M + m] = t[j];
+    }
+  }
+}
+
+// Row merge: P1_m = r_m, Yt_m = xt_m + (sum p (y - xt)) / r_m, tbar_m.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, int splits,
+                                                  const P4<T>* __restrict__ Xt,
+                                                  P4<T>* __restrict__ Yt, T* __restrict__ P1,
+                                                  T* __restrict__ tbar, int M,
+                                                  DevScalars* sc, int* __restrict__ badlist,
+                                                  int gate) {
+  if (gate && sc->done) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const double kap = kappa_of(sc->sigma2);
+  T r = 0, px = 0, py = 0, pz = 0, t = 0;
+  for (int k = 0; k < splits; ++k) {
+    const T* b = part + (size_t)k * 5 * M;
+    r += b[m];
+    px += b[(size_t)M + m];
+    py += b[(size_t)2 * M + m];
+    pz += b[(size_t)3 * M + m];
+    t += b[(size_t)4 * M + m];
+  }
+  const bool tiny = !(r >= (T)(sizeof(T) == 4 ? 0x1p-60 : 0x1p-900));
+  if (tiny) {
+    const int k = atomicAdd(&sc->bad_rows, 1);
+    badlist[k] = m;
+  }
+  const T inv = (T)1 / r;
+  const T isk = (T)(1.0 / sqrt(kap));
+  const P4<T> x = Xt[m];
+  Yt[m] = P4<T>{x.x + px * inv * isk, x.y + py * inv * isk, x.z + pz * inv * isk, (T)0};
+  P1[m] = r;
+  tbar[m] = t * inv * (T)(1.0 / kap);
+}
+
+// Exact pass B for flagged rows: shift by the row maximum of
+// -(|y^_n - x^_m|^2 + L_n), then the same sums.  P1 keeps its true (tiny or
+// zero) value; Yt and tbar come from the shifted, well-scaled sums.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys,
+                                                const P4<T>* __restrict__ Xt,
+                                                P4<T>* __restrict__ Yt, T* __restrict__ P1,
+                                                T* __restrict__ tbar, int M, int N,
+                                                DevScalars* sc, const int* __restrict__ badlist,
+                                                int gate) {
+  if (gate && sc->done) return;
+  const int nbad = sc->bad_rows;
+  const int lane = threadIdx.x & 63;
+  const int wglobal = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const double kap = kappa_of(sc->sigma2);
+  for (int b = wglobal; b < nbad; b += nwaves) {
+    const int m = badlist[b];
+    const P4<T> a = xs[m];
+    double mx = -__builtin_inf();
+    for (int n = lane; n < N; n += 64) {
+      const P4<T> y = ys[n];
+      mx = fmax(mx, -((double)sq3<T, D>(a, y.x, y.y, y.z, (T)0) + (double)y.w));
+    }
+    mx = wave_max(mx);
+    double r = 0, px = 0, py = 0, pz = 0, t = 0;
+    for (int n = lane; n < N; n += 64) {
+      const P4<T> y = ys[n];
+      const double dx = (double)y.x - a.x;
+      const double dy = D > 1 ? (double)y.y - a.y : 0.0;
+      const double dz = D > 2 ? (double)y.z - a.z : 0.0;
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      const double e = exp2(-(d2 + (double)y.w) - mx);
+      r += e;
+      px += e * dx;
+      py += e * dy;
+      pz += e * dz;
+      t += e * d2;
+    }
+    r = wave_sum(r);
+    px = wave_sum(px);
+    py = wave_sum(py);
+    pz = wave_sum(pz);
+    t = wave_sum(t);
+    if (lane == 0) {
+      const double isk = 1.0 / sqrt(kap);
+      const P4<T> x = Xt[m];
+      Yt[m] = P4<T>{(T)(x.x + px / r * isk), (T)(x.y + py / r * isk),
+                    (T)(x.z + pz / r * isk), (T)0};
+      P1[m] = (T)(r * exp2(mx));
+      tbar[m] = (T)(t / r / kap);
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+template <typename T>
+void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
+  constexpr int NB = sizeof(T) == 4 ? 4 : 2;
+  const int gate = a.gate;
+  const int nthr = a.M + a.N;
+  hipLaunchKernelGGL(k_prescale<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
+                     a.ys, a.M, a.N, a.sc, gate);
+  // pass A
+  {
+    const int tiles = (a.N + 256 * NB - 1) / (256 * NB);
+    dim3 grid(tiles, a.splitsA);
+    switch (a.D) {
+      case 1: hipLaunchKernelGGL((k_colsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
+      case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
+      default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
+    }
+    hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA,
+                       a.splitsA, a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols,
+                       a.llpart, gate);
+    switch (a.D) {
+      case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+      case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+      default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+    }
+  }
+  // pass B
+  {
+    const int tiles = (a.M + 256 * NB - 1) / (256 * NB);
+    dim3 grid(tiles, a.splitsB);
+    switch (a.D) {
+      case 1: hipLaunchKernelGGL((k_rowsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
+      case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
+      default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
+    }
+    hipLaunchKernelGGL(k_rowmerge<T>, dim3((a.M + 255) / 256), dim3(256), 0, st, a.partB,
+                       a.splitsB, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, a.badrows, gate);
+    switch (a.D) {
+      case 1: hipLaunchKernelGGL((k_rowfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+      case 2: hipLaunchKernelGGL((k_rowfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+      default: hipLaunchKernelGGL((k_rowfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+    }
+  }
+}
+
+template <typename T>
+void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
+  constexpr int NB = sizeof(T) == 4 ? 4 : 2;
+  const int target = 4096;
+  auto plan = [&](int cols, int len, int* splits, int* chunk) {
+    const int tiles = (cols + 256 * NB - 1) / (256 * NB);
+    int s = (target + tiles - 1) / tiles;
+    const int smax = (len + 63) / 64;  // at least 64 reduction steps per split
+    s = s < 1 ? 1 : (s > smax ? smax : s);
+    int c = (len + s - 1) / s;
+    c = (c + 3) & ~3;
+    *chunk = c;
+    *splits = (len + c - 1) / c;
+  };
+  plan(N, M, splitsA, chunkA);
+  plan(M, N, splitsB, chunkB);
+}
+
+template void estep_launch<float>(const EStepArgs<float>&, hipStream_t);
+template void estep_launch<double>(const EStepArgs<double>&, hipStream_t);
+template void estep_splits<float>(int, int, int*, int*, int*, int*);
+template void estep_splits<double>(int, int, int*, int*, int*, int*);
+
+}  // namespace fcpd

@@ -1,0 +1,407 @@
+// Fast CPD M-step (Section III, eq. 17 and its top-K form eq. 20), the
+// sigma^2 update (eq. 18 with the row-normalised posterior) and the small
+// set-up kernels.
+//
+// With U (M x K) and Lam precomputed, one M-step is
+//   T   = U^T (Yt - X)                         K x D, reduction over M
+//   g_k = 1 / (max(lam_k, 0) + lambda sigma^2),  h_k = max(lam_k, 0) g_k
+//   W   = U (g o T),   Xt_new = X + U (h o T)  ( = X + Phi W for exact U)
+// Both products stream U once; at D = 3 they run at ~2 flop/byte, so they are
+// bandwidth kernels: U is read with full-row coalesced loads and the K x D
+// factors are tiny.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fcpd {
+
+// ---------------------------------------------------------------- T = U^T R
+// Block (k-group, row chunk): thread k accumulates sum_m U[m][k] R_m over the
+// chunk; R_m = Yt_m - X_m is uniform across the block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
+                                               const P4<T>* __restrict__ Yt,
+                                               const T* __restrict__ U, int M, int K, int rows,
+                                               const DevScalars* __restrict__ sc,
+                                               T* __restrict__ tpart, int gate) {
+  if (gate && sc->done) return;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int m0 = blockIdx.y * rows;
+  const int m1 = min(M, m0 + rows);
+  T ax = 0, ay = 0, az = 0;
+  if (k < K) {
+    for (int m = m0; m < m1; ++m) {
+      const P4<T> y = Yt[m], x = X[m];
+      const T u = U[(size_t)m * K + k];
+      ax = fma(u, y.x - x.x, ax);
+      ay = fma(u, y.y - x.y, ay);
+      az = fma(u, y.z - x.z, az);
+    }
+    T* o = tpart + ((size_t)blockIdx.y * K + k) * 4;
+    o[0] = ax;
+    o[1] = ay;
+    o[2] = az;
+    o[3] = 0;
+  }
+}
+
+// T_k = sum over chunks; GT_k = g_k T_k, HT_k = h_k T_k.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tmerge(const T* __restrict__ tpart, int chunks,
+                                                const double* __restrict__ lam, int K,
+                                                double lmbda, const DevScalars* __restrict__ sc,
+                                                P4<T>* __restrict__ GT, P4<T>* __restrict__ HT,
+                                                int gate) {
+  if (gate && sc->done) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  T tx = 0, ty = 0, tz = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const T* p = tpart + ((size_t)c * K + k) * 4;
+    tx += p[0];
+    ty += p[1];
+    tz += p[2];
+  }
+  const double lp = fmax(lam[k], 0.0);
+  const double g = 1.0 / (lp + lmbda * sc->sigma2);
+  const double h = lp * g;
+  GT[k] = P4<T>{(T)(g * tx), (T)(g * ty), (T)(g * tz), (T)0};
+  HT[k] = P4<T>{(T)(h * tx), (T)(h * ty), (T)(h * tz), (T)0};
+}
+
+// One wave per model row: Xnew_m = X_m + U_m . HT, W_m = U_m . GT.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
+                                               const T* __restrict__ U,
+                                               const P4<T>* __restrict__ GT,
+                                               const P4<T>* __restrict__ HT, int M, int K,
+                                               const DevScalars* __restrict__ sc,
+                                               P4<T>* __restrict__ Xnew, P4<T>* __restrict__ W,
+                                               int gate) {
+  if (gate && sc->done) return;
+  const int lane = threadIdx.x & 63;
+  const int m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (m >= M) return;
+  const T* u = U + (size_t)m * K;
+  T hx = 0, hy = 0, hz = 0, gx = 0, gy = 0, gz = 0;
+  for (int k = lane; k < K; k += 64) {
+    const T uk = u[k];
+    const P4<T> h = HT[k], g = GT[k];
+    hx = fma(uk, h.x, hx);
+    hy = fma(uk, h.y, hy);
+    hz = fma(uk, h.z, hz);
+    gx = fma(uk, g.x, gx);
+    gy = fma(uk, g.y, gy);
+    gz = fma(uk, g.z, gz);
+  }
+  hx = wave_sum(hx);
+  hy = wave_sum(hy);
+  hz = wave_sum(hz);
+  gx = wave_sum(gx);
+  gy = wave_sum(gy);
+  gz = wave_sum(gz);
+  if (lane == 0) {
+    const P4<T> x = X[m];
+    Xnew[m] = P4<T>{x.x + hx, x.y + hy, x.z + hz, (T)0};
+    W[m] = P4<T>{gx, gy, gz, (T)0};
+  }
+}
+
+template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk) {
+  const int rows = 64;
+  *rows_per_chunk = rows;
+  return (M + rows - 1) / rows;
+}
+
+template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st) {
+  dim3 g1((a.K + 255) / 256, a.chunks);
+  hipLaunchKernelGGL(k_tpart<T>, g1, dim3(256), 0, st, a.X, a.Yt, a.U, a.M, a.K,
+                     a.rows_per_chunk, a.sc, a.tpart, a.gate);
+  hipLaunchKernelGGL(k_tmerge<T>, dim3((a.K + 255) / 256), dim3(256), 0, st, a.tpart, a.chunks,
+                     a.lam, a.K, a.lmbda, a.sc, a.GT, a.HT, a.gate);
+  hipLaunchKernelGGL(k_apply<T>, dim3((a.M + 3) / 4), dim3(256), 0, st, a.X, a.U, a.GT, a.HT,
+                     a.M, a.K, a.sc, a.Xnew, a.W, a.gate);
+}
+
+// ------------------------------------------------------------------ sigma^2
+// Per row, with b = xt_old, a = xt_new and sum_n p'_mn = 1:
+//   sum_n p'_mn |y_n - a|^2 = tbar_m + 2 (yt_m - b).(b - a) + |b - a|^2
+// (no cancellation of large terms, unlike the trace form of eq. 18).  For the
+// original method the row carries its weight P1_m and sigma^2 divides by
+// N_P = sum_m P1_m instead of M.  The kernel also retires the old iterate.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sig_part(P4<T>* __restrict__ Xt,
+                                                  const P4<T>* __restrict__ Xnew,
+                                                  const P4<T>* __restrict__ Yt,
+                                                  const T* __restrict__ tbar,
+                                                  const T* __restrict__ P1, int M,
+                                                  const DevScalars* __restrict__ sc,
+                                                  double* __restrict__ part, int gate) {
+  __shared__ double sh[16];
+  if (gate && sc->done) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0, wsum = 0.0;
+  if (m < M) {
+    const P4<T> b = Xt[m], a = Xnew[m], y = Yt[m];
+    const double bx = b.x, by = b.y, bz = b.z;
+    const double ex = bx - a.x, ey = by - a.y, ez = bz - a.z;
+    const double cross = ((double)y.x - bx) * ex + ((double)y.y - by) * ey + ((double)y.z - bz) * ez;
+    v = (double)tbar[m] + 2.0 * cross + ex * ex + ey * ey + ez * ez;
+    if (P1) {
+      wsum = (double)P1[m];
+      v *= wsum;
+    }
+    Xt[m] = a;
+  }
+  const double s1 = block_sum_d(v, sh);
+  const double s2 = block_sum_d(wsum, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s1;
+    part[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ part, int blocks,
+                                                   const double* __restrict__ llpart,
+                                                   int llblocks, int M, int N, int D, double w,
+                                                   int weighted, DevScalars* sc, int gate) {
+  __shared__ double sh[16];
+  if (gate && sc->done) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < blocks; i += blockDim.x) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  for (int i = threadIdx.x; i < llblocks; i += blockDim.x) c += llpart[i];
+  a = block_sum_d(a, sh);
+  b = block_sum_d(b, sh);
+  c = block_sum_d(c, sh);
+  if (threadIdx.x == 0) {
+    const double s2old = sc->sigma2;
+    const double denom = weighted ? (double)D * b : (double)D * (double)M;
+    double s2 = a / denom;
+    const bool finite = isfinite(s2);
+    if (finite) s2 = fmax(s2, sc->sigma2_floor);
+    const double ds = fabs(s2 - s2old);
+    // eq. 3: sum_n ln[w/N + (1-w)/M (2 pi s2)^(-D/2) sum_m exp(.)]
+    //      = sum_n ln d_n + N (ln((1-w)/M) - D/2 ln(2 pi s2))
+    sc->loglik = c + (double)N * (log1p(-w) - log((double)M) -
+                                  0.5 * D * log(2.0 * 3.14159265358979323846 * s2old));
+    sc->iter += 1;
+    if (!finite) {
+      sc->nonfinite = 1;
+      sc->done = 1;
+      return;
+    }
+    sc->sigma2 = s2;
+    sc->dsigma2 = ds;
+    sc->converged = ds < sc->tol;
+    if (sc->converged || sc->iter >= sc->max_iter) sc->done = 1;
+  }
+}
+
+template <typename T> int sigma2_blocks(int M) { return (M + 255) / 256; }
+
+template <typename T> void sigma2_launch(const Sigma2Args<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_sig_part<T>, dim3(a.blocks), dim3(256), 0, st, a.Xt, a.Xnew, a.Yt, a.tbar,
+                     a.P1, a.M, a.sc, a.part, a.gate);
+  hipLaunchKernelGGL(k_sig_final<T>, dim3(1), dim3(256), 0, st, a.part, a.blocks, a.llpart,
+                     a.llblocks, a.M, a.N, a.D, a.w, a.P1 != nullptr ? 1 : 0, a.sc, a.gate);
+}
+
+// -------------------------------------------------------------------- init
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack(const T* __restrict__ src, P4<T>* __restrict__ dst,
+                                              P4<T>* __restrict__ dst2, int M, int D) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const T* s = src + (size_t)i * D;
+  P4<T> p{s[0], D > 1 ? s[1] : (T)0, D > 2 ? s[2] : (T)0, (T)0};
+  dst[i] = p;
+  if (dst2) dst2[i] = p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(const P4<T>* __restrict__ src, T* __restrict__ dst,
+                                                int M, int D) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const P4<T> p = src[i];
+  T* d = dst + (size_t)i * D;
+  d[0] = p.x;
+  if (D > 1) d[1] = p.y;
+  if (D > 2) d[2] = p.z;
+}
+
+// Partial sums of (u, |u|^2) over both sets with u = p - X[0] (shift keeps
+// the double sums well scaled): part[blk * 8 + ...].
+template <typename T>
+__global__ __launch_bounds__(256) void k_s2init_part(const P4<T>* __restrict__ X,
+                                                     const P4<T>* __restrict__ Y, int M, int N,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const P4<T> o = X[0];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < M + N) {
+    const P4<T> p = i < M ? X[i] : Y[i - M];
+    const double ux = (double)p.x - o.x, uy = (double)p.y - o.y, uz = (double)p.z - o.z;
+    const int b = i < M ? 0 : 4;
+    v[b] = ux;
+    v[b + 1] = uy;
+    v[b + 2] = uz;
+    v[b + 3] = ux * ux + uy * uy + uz * uz;
+  }
+  for (int j = 0; j < 8; ++j) {
+    const double s = block_sum_d(v[j], sh);
+    if (threadIdx.x == 0) part[blockIdx.x * 8 + j] = s;
+  }
+}
+
+// sigma^2_0 = sum_mn |y_n - x_m|^2 / (D M N)
+//          = (N sum|u|^2 + M sum|v|^2 - 2 (sum u).(sum v)) / (D M N)
+__global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__ part, int blocks,
+                                                      int M, int N, int D, double given,
+                                                      double tol, int max_iter, int set_all,
+                                                      DevScalars* sc) {
+  __shared__ double sh[16];
+  double v[8];
+  for (int j = 0; j < 8; ++j) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += blockDim.x) a += part[i * 8 + j];
+    v[j] = block_sum_d(a, sh);
+  }
+  if (threadIdx.x == 0) {
+    double s2 = given;
+    if (!(given > 0.0)) {
+      const double cross = v[0] * v[4] + v[1] * v[5] + v[2] * v[6];
+      s2 = ((double)N * v[3] + (double)M * v[7] - 2.0 * cross) / ((double)D * M * N);
+    }
+    sc->sigma2 = s2;
+    sc->sigma2_start = s2;
+    sc->sigma2_floor = 1e-10 * s2;
+    sc->dsigma2 = 0.0;
+    sc->done = 0;
+    sc->converged = 0;
+    sc->nonfinite = 0;
+    if (set_all) {
+      sc->loglik = 0.0;
+      sc->tol = tol;
+      sc->iter = 0;
+      sc->max_iter = max_iter;
+      sc->bad_cols = 0;
+      sc->bad_rows = 0;
+    }
+  }
+}
+
+int init_blocks(int M, int N) { return (M + N + 255) / 256; }
+
+template <typename T>
+void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int M, int N, int D,
+                 double sigma2_init, double tol, int max_iter, DevScalars* sc, double* part,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, Xin, X, Xt, M, D);
+  hipLaunchKernelGGL(k_pack<T>, dim3((N + 255) / 256), dim3(256), 0, st, Yin, Y, (P4<T>*)nullptr,
+                     N, D);
+  const int blocks = init_blocks(M, N);
+  hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
+  hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D,
+                     sigma2_init, tol, max_iter, 1, sc);
+}
+
+template <typename T>
+void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
+                         double* part, hipStream_t st) {
+  const int blocks = init_blocks(M, N);
+  hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
+  hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D, -1.0, 0.0,
+                     0, 0, sc);
+}
+
+template <typename T> void unpack_launch(const P4<T>* src, T* dst, int M, int D, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack<T>, dim3((M + 255) / 256), dim3(256), 0, st, src, dst, M, D);
+}
+template <typename T> void pack_launch(const T* src, P4<T>* dst, int M, int D, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, src, dst,
+                     (P4<T>*)nullptr, M, D);
+}
+
+// --------------------------------------------------------- Xt = X + Phi W
+// One wave per row m; Phi_mj = exp(-|x_m - x_j|^2 / (2 beta^2)) is formed on
+// the fly (eq. 11).  Sums in double.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phi_apply(const P4<T>* __restrict__ X,
+                                                   const T* __restrict__ W, P4<T>* __restrict__ Xt,
+                                                   int M, int D, double beta) {
+  const int lane = threadIdx.x & 63;
+  const int m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (m >= M) return;
+  const double inv = 1.0 / (2.0 * beta * beta);
+  const P4<T> a = X[m];
+  double sx = 0, sy = 0, sz = 0;
+  for (int j = lane; j < M; j += 64) {
+    const P4<T> b = X[j];
+    const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
+    const double p = exp(-(dx * dx + dy * dy + dz * dz) * inv);
+    const T* wj = W + (size_t)j * D;
+    sx += p * (double)wj[0];
+    if (D > 1) sy += p * (double)wj[1];
+    if (D > 2) sz += p * (double)wj[2];
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  sz = wave_sum(sz);
+  if (lane == 0) Xt[m] = P4<T>{(T)(a.x + sx), (T)(a.y + sy), (T)(a.z + sz), (T)0};
+}
+
+template <typename T>
+void phi_apply_launch(const P4<T>* X, const T* Wrm, P4<T>* Xt, int M, int D, double beta,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_phi_apply<T>, dim3((M + 3) / 4), dim3(256), 0, st, X, Wrm, Xt, M, D, beta);
+}
+
+// ---------------------------------------------------------- eig import
+template <typename T>
+__global__ __launch_bounds__(256) void k_import_eig(const double* __restrict__ Uin,
+                                                    const double* __restrict__ lamin,
+                                                    T* __restrict__ U, double* __restrict__ lam,
+                                                    double* __restrict__ U64, int M, int K) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)M * K;
+  if (i < n) {
+    const double v = Uin[i];
+    U[i] = (T)v;
+    if (U64) U64[i] = v;
+  }
+  if (i < (size_t)K) lam[i] = lamin[i];
+}
+
+template <typename T>
+void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam, double* U64,
+                       int M, int K, hipStream_t st) {
+  const size_t n = (size_t)M * K;
+  const size_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_import_eig<T>, dim3((unsigned)blocks), dim3(256), 0, st, Uin, lamin, U,
+                     lam, U64, M, K);
+}
+
+#define FCPD_INST(T)                                                                          \
+  template void fast_mstep_launch<T>(const FastMArgs<T>&, hipStream_t);                      \
+  template int fast_mstep_chunks<T>(int, int*);                                              \
+  template void sigma2_launch<T>(const Sigma2Args<T>&, hipStream_t);                         \
+  template int sigma2_blocks<T>(int);                                                        \
+  template void init_launch<T>(const T*, const T*, P4<T>*, P4<T>*, P4<T>*, int, int, int,     \
+                               double, double, int, DevScalars*, double*, hipStream_t);      \
+  template void reset_sigma2_launch<T>(const P4<T>*, const P4<T>*, int, int, int, DevScalars*, \
+                                       double*, hipStream_t);                                 \
+  template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t);                   \
+  template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t);                    \
+  template void phi_apply_launch<T>(const P4<T>*, const T*, P4<T>*, int, int, double,         \
+                                    hipStream_t);                                             \
+  template void import_eig_launch<T>(const double*, const double*, T*, double*, double*, int,  \
+                                     int, hipStream_t);
+FCPD_INST(float)
+FCPD_INST(double)
+
+}  // namespace fcpd
