@@ -159,6 +159,7 @@ cpd_status validate(const cpd_params* p) {
       return fail(nullptr, CPD_E_ARG, "K must be in [1, M]");
     if (p->eig_mode == CPD_EIG_TOPK) {
       const int over = p->oversample > 0 ? p->oversample : 20;
+      if (p->K + over > p->M) return fail(nullptr, CPD_E_ARG, "K + oversample must not exceed M");
       if (p->K + over > eig_topk_max_cols())
         return fail(nullptr, CPD_E_UNSUPPORTED, "K + oversample exceeds the randomized solver's width");
       if (p->power_iters > 16) return fail(nullptr, CPD_E_ARG, "power_iters must be <= 16");
@@ -169,6 +170,10 @@ cpd_status validate(const cpd_params* p) {
   if (p->reserved != 0) return fail(nullptr, CPD_E_ARG, "reserved must be 0");
   if (p->precision == CPD_PREC_BF16X && p->method != CPD_METHOD_FAST)
     return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X precision is implemented for the Fast method");
+  if (p->method == CPD_METHOD_ORIGINAL)
+    return fail(nullptr, CPD_E_UNSUPPORTED, "the original method is not built yet");
+  if (p->precision == CPD_PREC_BF16X)
+    return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X is not built yet");
   return CPD_OK;
 }
 
@@ -451,7 +456,8 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     int K = 0;
     std::string msg;
     const int rc = eig_prepare_run(r, &K, &msg);
-    if (rc != 0) return fail(h, rc == 1 ? CPD_E_NUMERIC : CPD_E_DEVICE, msg);
+    if (rc != 0)
+      return fail(h, rc == 1 ? CPD_E_NUMERIC : (rc == 3 ? CPD_E_UNSUPPORTED : CPD_E_DEVICE), msg);
     h->K = K;
     convert_u_launch<T>(h->at<double>(L.U64), h->at<T>(L.U), (size_t)h->p.M * K, h->st);
   }

@@ -1,0 +1,745 @@
+// One-time eigen-prep of Fast CPD on gfx950, all in FP64.
+//
+// The paper decomposes the Gram matrix once, Phi = U Lam U^T (Section III,
+// eq. 16), or keeps its K largest pairs (eq. 19).  Here:
+//   * dense Jacobi: Phi is formed explicitly and diagonalised by cyclic
+//     two-sided Jacobi rotations in one workgroup (M <= 1024);
+//   * randomized: the K + p dimensional dominant subspace of Phi is found by a
+//     Gaussian range finder with subspace iteration and a Rayleigh-Ritz step
+//     (Halko, Martinsson & Tropp, SIAM Review 53(2), 2011).  Every product
+//     with Phi forms Phi's tiles on the fly from the points (Phi is never
+//     stored), orthonormalisation is shifted CholeskyQR followed by two plain
+//     CholeskyQR passes (Fukaya, Kannan, Nakatsukasa, Zhang & Yamamoto, SIAM J.
+//     Sci. Comput. 42(1), 2020), and the small projected matrix is diagonalised
+//     by the same Jacobi kernel.  FULL mode above 1024 points widens the
+//     subspace until the trailing Ritz value is round-off of the largest.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "eig.hpp"
+
+namespace fcpd {
+
+namespace {
+constexpr int kTopKMaxCols = 2048;
+constexpr int kDenseMax = 1024;
+constexpr int kFullOversample = 32;
+constexpr int kGramMaxChunks = 64;
+constexpr int kJacobiMax = kTopKMaxCols;
+// Graded spectra (Gaussian Gram matrices reach round-off within a few
+// hundred eigenvalues) need 20-30 sweeps before no rotation is left.
+constexpr int kJacobiSweeps = 100;
+
+int full_widths_max(int M) { return std::min(M, kTopKMaxCols); }
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
+int eig_topk_max_cols() { return kTopKMaxCols; }
+
+int eig_full_capacity(int M) {
+  if (M <= kDenseMax) return M;
+  return full_widths_max(M) - std::min(kFullOversample, full_widths_max(M) / 4);
+}
+
+static int gram_chunks(int M, int n) {
+  const size_t per = (size_t)n * n * sizeof(double);
+  int c = (int)std::max<size_t>(1, std::min<size_t>(kGramMaxChunks, (size_t)(256u << 20) / per));
+  c = std::min(c, std::max(1, M / 64));
+  return c;
+}
+
+EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
+  EigLayout L;
+  size_t off = start;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += al(bytes);
+    return o;
+  };
+  if (mode == 0 /*FULL*/ && M <= kDenseMax) {
+    L.Mdense = M;
+    L.n = M;
+    L.phi = take((size_t)M * M * sizeof(double));
+    L.V = take((size_t)M * M * sizeof(double));
+    L.ritz = take((size_t)M * sizeof(double));
+    L.misc = take(((size_t)M * sizeof(int) + 64) + 4 * sizeof(double));
+  } else {
+    int n;
+    if (mode == 0)
+      n = full_widths_max(M);
+    else
+      n = K + (oversample > 0 ? oversample : 20);
+    L.n = n;
+    const size_t Mn = (size_t)M * n * sizeof(double);
+    const size_t nn = (size_t)n * n * sizeof(double);
+    L.omega = take(Mn);
+    L.Z = take(Mn);
+    L.Q = take(Mn);
+    L.G = take(nn * (size_t)gram_chunks(M, n));
+    L.R = take(nn);
+    L.V = take(nn);
+    L.phi = take(nn);  // the n x n Rayleigh-Ritz / Gram matrix
+    L.ritz = take((size_t)n * sizeof(double));
+    L.misc = take(((size_t)n * sizeof(int) + 64) + 4 * sizeof(double));
+  }
+  L.end = off;
+  return L;
+}
+
+// -------------------------------------------------------------- RNG
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11), counter-based: the
+// normal at index i depends only on (seed, i), so the draw does not depend on
+// the launch shape.  Box-Muller turns two uniforms into two normals.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gauss(double* __restrict__ out, size_t n, uint64_t seed) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // one counter -> 4 normals
+  if (4 * i >= n) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)(i >> 32), 0x5CA1AB1Eu, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double inv = 1.0 / 4294967296.0;
+  double z[4];
+  for (int j = 0; j < 2; ++j) {
+    const double u1 = ((double)c[2 * j] + 0.5) * inv;  // (0, 1)
+    const double u2 = ((double)c[2 * j + 1] + 0.5) * inv;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, co;
+    sincospi(2.0 * u2, &s, &co);
+    z[2 * j] = r * co;
+    z[2 * j + 1] = r * s;
+  }
+  for (int j = 0; j < 4; ++j)
+    if (4 * i + j < n) out[4 * i + j] = z[j];
+}
+
+// ---------------------------------------------------- 64 x 64 FP64 tiles
+// C[i][c] = sum_j A[i][j] B[j][c] for a 64 x 64 output tile per block, 4 x 4
+// per thread, contraction in steps of 32 staged through LDS.  A is either a
+// row-major matrix (lda) or the Gram matrix of the points, formed on the fly:
+// A[i][j] = exp(-|x_i - x_j|^2 / (2 beta^2)) (eq. 11).
+constexpr int TI = 64, TC = 64, TJ = 32;
+
+template <typename PT, bool PHI>
+__global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A, int lda,
+                                                   const P4<PT>* __restrict__ pts, double inv2b2,
+                                                   const double* __restrict__ B, int ldb,
+                                                   double* __restrict__ C, int ldc, int rows,
+                                                   int inner, int cols) {
+  __shared__ double sA[TJ][TI + 2];
+  __shared__ double sB[TJ][TC + 2];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * TI, c0 = blockIdx.x * TC;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  // the 8 (i, jj) elements of A this thread fills: i = tid & 63, jj = (tid >> 6) + 4 k
+  const int fi = tid & 63;
+  double xi0 = 0, xi1 = 0, xi2 = 0;
+  if (PHI && i0 + fi < rows) {
+    const P4<PT> p = pts[i0 + fi];
+    xi0 = p.x;
+    xi1 = p.y;
+    xi2 = p.z;
+  }
+  for (int j0 = 0; j0 < inner; j0 += TJ) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int jj = (tid >> 6) + 4 * k;
+      const int i = i0 + fi, j = j0 + jj;
+      double v = 0.0;
+      if (i < rows && j < inner) {
+        if (PHI) {
+          const P4<PT> q = pts[j];
+          const double dx = xi0 - (double)q.x, dy = xi1 - (double)q.y, dz = xi2 - (double)q.z;
+          v = exp(-(dx * dx + dy * dy + dz * dz) * inv2b2);
+        } else {
+          v = A[(size_t)i * lda + j];
+        }
+      }
+      sA[jj][fi] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = tid + 256 * k;
+      const int jj = e >> 6, c = e & 63;
+      const int j = j0 + jj, cc = c0 + c;
+      sB[jj][c] = (j < inner && cc < cols) ? B[(size_t)j * ldb + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int jj = 0; jj < TJ; ++jj) {
+      double a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = sA[jj][ty * 4 + t];
+        b[t] = sB[jj][tx * 4 + t];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = i0 + ty * 4 + x;
+    if (i >= rows) continue;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int c = c0 + tx * 4 + y;
+      if (c < cols) C[(size_t)i * ldc + c] = acc[x][y];
+    }
+  }
+}
+
+// Partial A^T B over a chunk of rows: P[chunk][a][b] = sum_{m in chunk}
+// A[m][a] B[m][b]; A, B are M x n row-major.
+__global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
+                                                   const double* __restrict__ B, int M, int n,
+                                                   int rows_per_chunk, double* __restrict__ P) {
+  __shared__ double sA[TJ][TI + 2];
+  __shared__ double sB[TJ][TC + 2];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int a0 = blockIdx.y * TI, b0 = blockIdx.x * TC;
+  const int m0 = blockIdx.z * rows_per_chunk;
+  const int m1 = min(M, m0 + rows_per_chunk);
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int mb = m0; mb < m1; mb += TJ) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = tid + 256 * k;
+      const int r = e >> 6, c = e & 63;
+      const int m = mb + r;
+      sA[r][c] = (m < m1 && a0 + c < n) ? A[(size_t)m * n + a0 + c] : 0.0;
+      sB[r][c] = (m < m1 && b0 + c < n) ? B[(size_t)m * n + b0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < TJ; ++r) {
+      double a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = sA[r][ty * 4 + t];
+        b[t] = sB[r][tx * 4 + t];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+    }
+    __syncthreads();
+  }
+  double* out = P + (size_t)blockIdx.z * n * n;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int a = a0 + ty * 4 + x;
+    if (a >= n) continue;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int b = b0 + tx * 4 + y;
+      if (b < n) out[(size_t)a * n + b] = acc[x][y];
+    }
+  }
+}
+
+// G = sum of chunk partials, symmetrised: G = (S + S^T)/2.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ P, int chunks,
+                                                     int n, double* __restrict__ G) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int a = (int)(idx / n), b = (int)(idx % n);
+  double s = 0.0, t = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    s += P[(size_t)c * n * n + (size_t)a * n + b];
+    t += P[(size_t)c * n * n + (size_t)b * n + a];
+  }
+  G[idx] = 0.5 * (s + t);
+}
+
+// In-place lower Cholesky of G + shift*I (n x n, row-major), one workgroup,
+// then Linv = L^-1 written (lower) into R.  info[0] = 0 ok, k+1 if pivot k
+// was not positive.
+__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ G, double* __restrict__ R,
+                                                   int n, const double* __restrict__ shift_rel,
+                                                   int* __restrict__ info) {
+  __shared__ double sh_shift;
+  __shared__ int sh_fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += G[(size_t)i * n + i];
+    sh_shift = shift_rel ? shift_rel[0] * tr : 0.0;
+    sh_fail = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) G[(size_t)i * n + i] += sh_shift;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = G[(size_t)k * n + k];
+      if (!(d > 0.0) || !isfinite(d)) {
+        sh_fail = k + 1;
+        G[(size_t)k * n + k] = 1.0;
+      } else {
+        G[(size_t)k * n + k] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (sh_fail) break;
+    const double piv = G[(size_t)k * n + k];
+    for (int i = k + 1 + tid; i < n; i += nt) G[(size_t)i * n + k] /= piv;
+    __syncthreads();
+    // trailing update of the lower triangle
+    const int len = n - k - 1;
+    const size_t work = (size_t)len * (len + 1) / 2;
+    for (size_t e = tid; e < work; e += nt) {
+      // e -> (i, j) with j <= i, both in [k+1, n)
+      int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while ((size_t)(i + 1) * (i + 2) / 2 <= e) ++i;
+      while ((size_t)i * (i + 1) / 2 > e) --i;
+      const int j = (int)(e - (size_t)i * (i + 1) / 2);
+      const int ii = k + 1 + i, jj = k + 1 + j;
+      G[(size_t)ii * n + jj] -= G[(size_t)ii * n + k] * G[(size_t)jj * n + k];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[0] = sh_fail;
+  if (sh_fail) return;
+  // Linv: solve L X = I column by column (each thread owns columns)
+  for (int c = tid; c < n; c += nt) {
+    for (int i = 0; i < n; ++i) {
+      if (i < c) {
+        R[(size_t)i * n + c] = 0.0;
+        continue;
+      }
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= G[(size_t)i * n + k] * R[(size_t)k * n + c];
+      R[(size_t)i * n + c] = s / G[(size_t)i * n + i];
+    }
+  }
+}
+
+// T = Linv^T (upper), as the right factor of Q = Z Linv^T.
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ A,
+                                                   double* __restrict__ B, int n) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int a = (int)(idx / n), b = (int)(idx % n);
+  B[(size_t)b * n + a] = A[idx];
+}
+
+// ------------------------------------------------------------ Jacobi
+// Cyclic two-sided Jacobi on a symmetric n x n matrix A (row-major, global),
+// one workgroup.  Round-robin ordering: n/2 disjoint rotations per step, rows
+// then columns updated with barriers between.  V accumulates the rotations
+// (columns are eigenvectors); on exit diag(A) holds the eigenvalues.
+__global__ __launch_bounds__(1024) void k_jacobi(double* __restrict__ A, double* __restrict__ V,
+                                                 int n, int max_sweeps, int* __restrict__ sweeps_out) {
+  __shared__ double cs_c[kJacobiMax / 2 + 1], cs_s[kJacobiMax / 2 + 1];
+  __shared__ double dg_p[kJacobiMax / 2 + 1], dg_q[kJacobiMax / 2 + 1];
+  __shared__ int pp[kJacobiMax / 2 + 1], qq[kJacobiMax / 2 + 1];
+  __shared__ int any_rot;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int np = (n + 1) & ~1;  // even number of players (one dummy when n is odd)
+  const int half = np / 2;
+  for (size_t e = tid; e < (size_t)n * n; e += nt) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  const double eps = 1.1102230246251565e-16;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    __syncthreads();  // every thread has read any_rot of the previous sweep
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int step = 0; step < np - 1; ++step) {
+      for (int k = tid; k < half; k += nt) {
+        auto pos = [&](int t) { return t == 0 ? 0 : ((t - 1 + step) % (np - 1)) + 1; };
+        int p = pos(k), q = pos(np - 1 - k);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
+        if (q < n) {
+          const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+          const double apq = A[(size_t)p * n + q];
+          const double aa = fabs(apq);
+          // relative test: rotate unless apq is round-off of both diagonals
+          if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-300) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            dp = app - t * apq;  // the 2 x 2 block after the rotation, exactly
+            dq = aqq + t * apq;
+            any_rot = 1;
+          }
+        }
+        pp[k] = p;
+        qq[k] = q < n ? q : -1;
+        cs_c[k] = c;
+        cs_s[k] = s;
+        dg_p[k] = dp;
+        dg_q[k] = dq;
+      }
+      __syncthreads();
+      // rows p, q of A  (J^T A)
+      for (int e = tid; e < half * n; e += nt) {
+        const int k = e / n, j = e % n;
+        const int q = qq[k];
+        if (q < 0 || cs_s[k] == 0.0) continue;
+        const int p = pp[k];
+        const double c = cs_c[k], s = cs_s[k];
+        const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
+        A[(size_t)p * n + j] = c * ap - s * aq;
+        A[(size_t)q * n + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of A and V  (A J, V J)
+      for (int e = tid; e < half * n; e += nt) {
+        const int k = e / n, i = e % n;
+        const int q = qq[k];
+        if (q < 0 || cs_s[k] == 0.0) continue;
+        const int p = pp[k];
+        const double c = cs_c[k], s = cs_s[k];
+        const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
+        if (i == p) {
+          A[(size_t)p * n + p] = dg_p[k];
+          A[(size_t)p * n + q] = 0.0;
+        } else if (i == q) {
+          A[(size_t)q * n + p] = 0.0;
+          A[(size_t)q * n + q] = dg_q[k];
+        } else {
+          A[(size_t)i * n + p] = c * ap - s * aq;
+          A[(size_t)i * n + q] = s * ap + c * aq;
+        }
+        const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
+        V[(size_t)i * n + p] = c * vp - s * vq;
+        V[(size_t)i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    const int rotated = any_rot;  // uniform: nobody writes it before the next barrier
+    if (!rotated) break;
+  }
+  if (tid == 0) sweeps_out[0] = sweep;
+}
+
+// Eigenvalues (diag of the converged A) sorted descending: perm and values.
+__global__ __launch_bounds__(1024) void k_sort_desc(const double* __restrict__ A, int n,
+                                                    int* __restrict__ perm,
+                                                    double* __restrict__ vals) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double vi = A[(size_t)i * n + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double vj = A[(size_t)j * n + j];
+      rank += (vj > vi) || (vj == vi && j < i);
+    }
+    perm[rank] = i;
+    vals[rank] = vi;
+  }
+}
+
+// S (n x K) = columns perm[0..K) of V (n x n).
+__global__ __launch_bounds__(256) void k_gather_cols(const double* __restrict__ V, int n,
+                                                     const int* __restrict__ perm, int K,
+                                                     double* __restrict__ S) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * K) return;
+  const int r = (int)(idx / K), k = (int)(idx % K);
+  int p = perm[k];
+  p = (p >= 0 && p < n) ? p : 0;  // a NaN eigenvalue can leave a rank unset
+  S[idx] = V[(size_t)r * n + p];
+}
+
+__global__ __launch_bounds__(256) void k_copy_lam(const double* __restrict__ v, int K,
+                                                  double* __restrict__ lam) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) lam[i] = v[i];
+}
+
+template <typename T>
+__global__ void k_conv(const double* __restrict__ a, T* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (T)a[i];
+}
+
+template <typename T> void convert_u_launch(const double* U64, T* U, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_conv<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U64, U, n);
+}
+template void convert_u_launch<float>(const double*, float*, size_t, hipStream_t);
+template void convert_u_launch<double>(const double*, double*, size_t, hipStream_t);
+
+// --------------------------------------------------------------- host side
+namespace {
+
+struct Ctx {
+  const EigRun& r;
+  char* ws;
+  const EigLayout& L;
+  hipStream_t st;
+  double* at(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+};
+
+unsigned blocks_for(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <typename PT>
+void phi_times(const Ctx& c, const double* B, double* C, int n) {
+  const int M = c.r.M;
+  dim3 grid((n + TC - 1) / TC, (M + TI - 1) / TI);
+  const double inv2b2 = 1.0 / (2.0 * c.r.beta * c.r.beta);
+  hipLaunchKernelGGL((k_gemm_tile<PT, true>), grid, dim3(256), 0, c.st, (const double*)nullptr, 0,
+                     static_cast<const P4<PT>*>(c.r.X), inv2b2, B, n, C, n, M, M, n);
+}
+
+void gemm_nn(const Ctx& c, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+             int rows, int inner, int cols) {
+  dim3 grid((cols + TC - 1) / TC, (rows + TI - 1) / TI);
+  hipLaunchKernelGGL((k_gemm_tile<double, false>), grid, dim3(256), 0, c.st, A, lda,
+                     (const P4<double>*)nullptr, 0.0, B, ldb, C, ldc, rows, inner, cols);
+}
+
+void gram(const Ctx& c, const double* A, const double* B, int n, double* G) {
+  const int M = c.r.M;
+  const int chunks = gram_chunks(M, n);
+  const int rows = (M + chunks - 1) / chunks;
+  const int nch = (M + rows - 1) / rows;
+  dim3 grid((n + TC - 1) / TC, (n + TI - 1) / TI, nch);
+  double* P = c.at(c.L.G);
+  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, c.st, A, B, M, n, rows, P);
+  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks_for((size_t)n * n)), dim3(256), 0, c.st, P, nch,
+                     n, G);
+}
+
+int* misc_int(const Ctx& c) { return reinterpret_cast<int*>(c.ws + c.L.misc); }
+double* misc_dbl(const Ctx& c, int n) {
+  return reinterpret_cast<double*>(c.ws + c.L.misc + (((size_t)n * sizeof(int) + 64 + 7) & ~(size_t)7));
+}
+
+// Q <- orth(Z) by repeated CholeskyQR.  A shifted pass (Gram + s I) is always
+// factorisable and lifts the smallest singular values by ~1/sqrt(s); Z = Phi B
+// is numerically rank deficient (the Gram spectrum reaches round-off within a
+// few hundred eigenvalues), so three shifted passes bring it to a condition
+// number that plain passes handle, and two clean plain passes finish.  A plain
+// pass that breaks down is redone with the shift.  Returns 0 or 1.
+int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg) {
+  const int M = c.r.M;
+  double* G = c.at(c.L.phi);
+  double* Linv = c.at(c.L.R);
+  double* Tt = c.at(c.L.V);
+  int* info = misc_int(c) + n;  // after perm
+  double* shift = misc_dbl(c, n);
+  // shift / trace(G) from the bound 11 (M n + n (n + 1)) u |Z|_2^2, |Z|_2^2 <= trace
+  const double u = 1.1102230246251565e-16;
+  const double srel = 11.0 * ((double)M * n + (double)n * (n + 1)) * u;
+  (void)hipMemcpyAsync(shift, &srel, sizeof(double), hipMemcpyHostToDevice, c.st);
+  const double* src = Z;
+  int plain_ok = 0, pass = 0;
+  const int max_passes = 10;
+  for (; pass < max_passes && plain_ok < 2; ++pass) {
+    const bool shifted = pass < 3;
+    gram(c, src, src, n, G);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, c.st, G, Linv, n,
+                       shifted ? (const double*)shift : (const double*)nullptr, info);
+    int h_info = 0;
+    (void)hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    if (h_info != 0) {
+      if (shifted) {
+        *msg = "shifted CholeskyQR broke down at pivot " + std::to_string(h_info);
+        return 1;
+      }
+      // redo this step with the shift
+      gram(c, src, src, n, G);
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, c.st, G, Linv, n,
+                         (const double*)shift, info);
+      (void)hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, c.st);
+      (void)hipStreamSynchronize(c.st);
+      if (h_info != 0) {
+        *msg = "CholeskyQR broke down at pivot " + std::to_string(h_info);
+        return 1;
+      }
+      plain_ok = 0;
+    } else if (!shifted) {
+      ++plain_ok;
+    }
+    hipLaunchKernelGGL(k_transpose, dim3(blocks_for((size_t)n * n)), dim3(256), 0, c.st, Linv, Tt,
+                       n);
+    // next = src * Linv^T ; ping-pong through Z/Q so source and destination differ
+    double* dst = (src == Q) ? Z : Q;
+    gemm_nn(c, src, n, Tt, n, dst, n, M, n, n);
+    src = dst;
+  }
+  if (plain_ok < 2) {
+    *msg = "CholeskyQR did not reach orthonormality";
+    return 1;
+  }
+  if (src != Q)
+    (void)hipMemcpyAsync(Q, src, sizeof(double) * (size_t)M * n, hipMemcpyDeviceToDevice, c.st);
+  return 0;
+}
+
+// Jacobi on the n x n symmetric matrix in A (destroyed), V gets eigenvectors;
+// eigenvalues sorted descending into vals, permutation into perm.
+int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::string* msg) {
+  if (n > kJacobiMax) {
+    *msg = "Jacobi size exceeds its limit";
+    return 3;
+  }
+  int* perm = misc_int(c);
+  int* sweeps = misc_int(c) + n + 1;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, c.st, A, V, n, kJacobiSweeps, sweeps);
+  hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);
+  int hs = 0;
+  (void)hipMemcpyAsync(&hs, sweeps, sizeof(int), hipMemcpyDeviceToHost, c.st);
+  (void)hipStreamSynchronize(c.st);
+  if (hs >= kJacobiSweeps) {
+    *msg = "Jacobi did not converge";
+    return 1;
+  }
+  return 0;
+}
+
+template <typename PT>
+int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64_t seed,
+               std::string* msg) {
+  const int M = c.r.M;
+  double* Om = c.at(c.L.omega);
+  double* Z = c.at(c.L.Z);
+  double* Q = c.at(c.L.Q);
+  double* B = c.at(c.L.phi);
+  double* V = c.at(c.L.V);
+  double* S = c.at(c.L.R);
+  double* vals = c.at(c.L.ritz);
+  const double* O = omega_in;
+  if (!O) {
+    const size_t cnt = (size_t)M * n;
+    hipLaunchKernelGGL(k_gauss, dim3(blocks_for((cnt + 3) / 4)), dim3(256), 0, c.st, Om, cnt, seed);
+    O = Om;
+  }
+  phi_times<PT>(c, O, Z, n);
+  if (orth(c, Z, Q, n, msg)) return 1;
+  for (int it = 0; it < q; ++it) {
+    phi_times<PT>(c, Q, Z, n);
+    if (orth(c, Z, Q, n, msg)) return 1;
+  }
+  phi_times<PT>(c, Q, Z, n);  // Z = Phi Q
+  gram(c, Q, Z, n, B);        // B = Q^T Phi Q (symmetrised)
+  if (jacobi_sorted(c, B, V, n, vals, msg)) return 1;
+  hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)n * K)), dim3(256), 0, c.st, V, n,
+                     misc_int(c), K, S);
+  gemm_nn(c, Q, n, S, K, c.r.U64, K, M, n, K);
+  hipLaunchKernelGGL(k_copy_lam, dim3(blocks_for(K)), dim3(256), 0, c.st, vals, K, c.r.lam);
+  return 0;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_phi_dense(const P4<PT>* __restrict__ X, int M,
+                                                   double inv2b2, double* __restrict__ Phi) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)M * M) return;
+  const int i = (int)(idx / M), j = (int)(idx % M);
+  const P4<PT> a = X[i], b = X[j];
+  const double dx = (double)a.x - b.x, dy = (double)a.y - b.y, dz = (double)a.z - b.z;
+  Phi[idx] = exp(-(dx * dx + dy * dy + dz * dz) * inv2b2);
+}
+
+template <typename PT>
+int dense_full(const Ctx& c, int* K_out, std::string* msg) {
+  const int M = c.r.M;
+  double* Phi = c.at(c.L.phi);
+  double* V = c.at(c.L.V);
+  double* vals = c.at(c.L.ritz);
+  hipLaunchKernelGGL(k_phi_dense<PT>, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st,
+                     static_cast<const P4<PT>*>(c.r.X), M, 1.0 / (2.0 * c.r.beta * c.r.beta), Phi);
+  if (jacobi_sorted(c, Phi, V, M, vals, msg)) return 1;
+  hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st, V, M,
+                     misc_int(c), M, c.r.U64);
+  hipLaunchKernelGGL(k_copy_lam, dim3(blocks_for(M)), dim3(256), 0, c.st, vals, M, c.r.lam);
+  *K_out = M;
+  return 0;
+}
+
+template <typename PT>
+int run(const EigRun& r, int* K_out, std::string* msg) {
+  Ctx c{r, r.ws, *r.L, r.st};
+  const int q = r.power_iters >= 0 ? r.power_iters : 2;
+  if (r.mode == 0 /*FULL*/) {
+    if (r.M <= kDenseMax) return dense_full<PT>(c, K_out, msg);
+    // widen until the trailing Ritz value is round-off of the largest
+    const int nmax = c.L.n;
+    int n = std::min(nmax, 512);
+    for (;;) {
+      const int p = std::min(kFullOversample, n / 4);
+      const int K = n - p;
+      if (randomized<PT>(c, n, K, q, nullptr, r.seed, msg)) return 1;
+      double v[2] = {0, 0};
+      (void)hipMemcpyAsync(&v[0], c.r.lam, sizeof(double), hipMemcpyDeviceToHost, c.st);
+      (void)hipMemcpyAsync(&v[1], c.r.lam + (K - 1), sizeof(double), hipMemcpyDeviceToHost, c.st);
+      (void)hipStreamSynchronize(c.st);
+      *K_out = K;
+      if (std::fabs(v[1]) <= 1e-14 * std::fabs(v[0]) || n >= nmax) return 0;
+      n = std::min(nmax, 2 * n);
+    }
+  }
+  const int p = r.oversample > 0 ? r.oversample : 20;
+  const int n = r.K + p;
+  if (n > c.L.n) {
+    *msg = "layout too small";
+    return 2;
+  }
+  if (n > r.M) {
+    *msg = "K + oversample exceeds M";
+    return 3;
+  }
+  if (randomized<PT>(c, n, r.K, q, r.omega, r.seed, msg)) return 1;
+  *K_out = r.K;
+  return 0;
+}
+
+}  // namespace
+
+int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg) {
+  const int rc = r.x_is_double ? run<double>(r, K_out, msg) : run<float>(r, K_out, msg);
+  if (rc) return rc;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    *msg = std::string("eigen-prep launch failed: ") + hipGetErrorString(e);
+    return 2;
+  }
+  return 0;
+}
+
+}  // namespace fcpd
