@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Fast CPD on one MI355X: EM iterations/s and time-to-converge at M=N=50k, D=3.
+
+Workload (synthetic, seeded): the 50 000-point random spherical-harmonic
+surface, scene = model pushed through a Gaussian-RBF field (beta = 1.5),
+N(0, 0.02^2) noise, 20% of scene rows replaced by uniform outliers; Fast CPD
+with the top K = 300 eigenpairs (randomized, p = 20, q = 2), lambda = 2,
+w = 0.2, stop at |dsigma^2| < 1e-8.
+
+A "step" is one full EM iteration (E-step passes A and B, the Fast M-step,
+the sigma^2 update) on inputs already resident in HBM.  Warm-up steps run
+first, then exactly --steps steps are timed between two synchronisations.
+The eigen-prep (t_eig) and a full time-to-converge run are timed separately.
+
+Prints one JSON line.  --gpus above 1 is refused: this path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-converge (s) & EM iters/s at M=N=50k, 3D; vs plain CPD same GPU"
+
+# Algorithmic work per model-scene pair and pass (D = 3), exp counted as one
+# operation: pass A 8 (|y-x|^2) + 1 (scale) + 1 (sum) + exp; pass B the same
+# squared distance + 2 (scale, minus log d_n) + exp + 1 (P1) + 6 (PY) + 2
+# (the weighted squared distance).
+FLOP_PASS_A = 11
+FLOP_PASS_B = 20
+PEAK_VALU_FP32_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pair, K, rows=20000):
+    """The FP64 oracle as it stands, timed on this host on a bounded sample:
+    the E-step and the sigma^2 pass on `rows` model rows against all scene
+    points, scaled to M x N pairs, plus one full Fast M-step (K columns)."""
+    from oracle import cpd64
+    M, N = pair.M, pair.N
+    Xs = pair.X[:rows]
+    s2 = 0.01
+    t0 = time.perf_counter()
+    es = cpd64.estep(Xs, pair.Y, s2, pair.w)
+    cpd64.sigma2_fast(Xs, pair.Y, s2, es, Xs)
+    t_pairs = (time.perf_counter() - t0) * (M / rows)
+    rng = np.random.default_rng(0)
+    U, _ = np.linalg.qr(rng.standard_normal((M, K)))
+    lam = np.sort(rng.random(K))[::-1]
+    Yt = pair.X + 0.01
+    t0 = time.perf_counter()
+    cpd64.fast_mstep(pair.X, Yt, U, lam, pair.lam, s2)
+    t_m = time.perf_counter() - t0
+    per_iter = t_pairs + t_m
+    return {"value": 1.0 / per_iter, "unit": "EM iters/s", "cores": cpd64.threads(),
+            "kind": "oracle",
+            "sample": f"E-step + sigma^2 pass on {rows} of {M} model rows x {N} scene "
+                      f"points scaled to M x N, plus one full Fast M-step (K={K}); "
+                      f"{per_iter:.2f} s per iteration extrapolated"}
+
+
+def converge_run(reg, pair, t_eig):
+    """cpd_register from the handle's current state to |dsigma^2| < tol."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = reg.register()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    rmse = float(np.sqrt(((out.Xt.double().cpu().numpy() - pair.Y_hat) ** 2).sum(1).mean()))
+    return {"iters": out.iters, "converged": out.converged, "sigma2": out.sigma2,
+            "time_to_converge_s": t_eig + t if out.converged else None,
+            "time_to_converge_no_eig_s": t if out.converged else None,
+            "run_s": t, "t_eig_s": t_eig, "t_c_s": out.t_c, "t_iter_s": out.t_iter,
+            "t_o_s": out.t_o, "rmse_eq22": rmse}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-converge", action="store_true", help="skip time-to-converge")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(each GPU would register its own instances).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2006_06281_amd as fc
+    fc.require_device()
+
+    t0 = time.perf_counter()
+    pair = synth.workload("surface50k")
+    log(f"inputs generated in {time.perf_counter() - t0:.1f}s  M={pair.M} N={pair.N}")
+    K, over, q = 300, 20, 2
+    X = torch.as_tensor(pair.X, dtype=torch.float32).cuda().contiguous()
+    Y = torch.as_tensor(pair.Y, dtype=torch.float32).cuda().contiguous()
+    kw = dict(precision=args.precision, beta=pair.beta, lam=pair.lam, w=pair.w,
+              eig_mode="topk", K=K, oversample=over, power_iters=q, seed=0, tol=1e-8,
+              max_iter=1000)
+    reg = fc.Registration(X, Y, **kw)
+    _, _, s2_0 = reg.state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reg.prepare()
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    log(f"eigen-prep {t_eig:.3f}s  K={reg.K}")
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        fc.cpd_step(reg.h, want_info=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        fc.cpd_step(reg.h, want_info=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    log(f"{args.steps} steps: {ms_step:.3f} ms/step")
+
+    kern = reg.time_kernels(reps=10)
+    log("stage ms: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
+
+    conv = None
+    if not args.no_converge:
+        conv = {}
+        # As configured (w = 0.2), from the same start.
+        reg.set_state(X, s2_0)
+        conv["w=0.2"] = converge_run(reg, pair, t_eig)
+        log(f"w=0.2: {conv['w=0.2']}")
+        # The same inputs with the paper's own outlier weight (Section IV,
+        # w = 0.7): at w = 0.2 the uniform term does not absorb 20% outliers
+        # at this size and the run stalls at sigma^2 ~ 0.05.
+        reg7 = fc.Registration(X, Y, **dict(kw, w=0.7))
+        t0 = time.perf_counter()
+        reg7.prepare()
+        torch.cuda.synchronize()
+        t_eig7 = time.perf_counter() - t0
+        conv["w=0.7"] = converge_run(reg7, pair, t_eig7)
+        log(f"w=0.7: {conv['w=0.7']}")
+        reg7.close()
+
+    pairs = pair.M * pair.N
+    tB = kern["passB"] * 1e-3
+    achieved = pairs * FLOP_PASS_B / tB / 1e12
+    roofline = {"bound": "alu", "kernel": "k_rowsum (E-step pass B)", "achieved": achieved,
+                "peak": PEAK_VALU_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_VALU_FP32_TFLOPS, "traffic": None,
+                "passA_TFLOPs": pairs * FLOP_PASS_A / (kern["passA"] * 1e-3) / 1e12}
+
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(pair, K)
+        log(f"cpu baseline {cpu['value']:.4f} it/s ({time.perf_counter() - t0:.1f}s)")
+
+    rec = {
+        "metric": METRIC, "value": 1000.0 / ms_step, "unit": "EM iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16x": "bf16x-f32"}[args.precision], "data": "synthetic",
+        "config": {"workload": "surface50k: M=N=50000, D=3, spherical-harmonic surface, "
+                               "GRBF field beta=1.5, 20% outliers, N(0,0.02^2) noise; Fast CPD "
+                               "top-K=300 (p=20, q=2), lambda=2, w=0.2, tol 1e-8",
+                   "M": pair.M, "N": pair.N, "D": 3, "K": K, "method": "fast-topk",
+                   "precision": args.precision, "parallelism": "single-gpu"},
+        "converge": conv, "kernels_ms": kern, "roofline": roofline, "cpu_baseline": cpu,
+        "plain_cpd": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,17 @@ cpd_status cpd_get_state(cpd_handle h, void* Xt_out, void* W_out,
  * The iterate is not changed. */
 cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar);
 
+/* Kernel timing for benchmarks and tuning: runs `reps` full iterations from
+ * the current state (the iterate advances) and reports the average device
+ * time in milliseconds of each stage, measured with HIP events on the
+ * handle's stream, into out_ms[8]:
+ *   [0] E-step pass A, column sums        [1] pass A merge and exact fix-up
+ *   [2] E-step pass B, row sums           [3] pass B merge and exact fix-up
+ *   [4] M-step                            [5] sigma^2 update
+ *   [6] prescale                          [7] whole iteration
+ * Synchronises the stream. */
+cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms);
+
 /* Release the handle (host memory only; the workspace stays the caller's). */
 cpd_status cpd_destroy(cpd_handle h);
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "cpd_workspace_size", "cpd_init", "cpd_eig_prepare", "cpd_eig_count",
     "cpd_eig_export", "cpd_step", "cpd_register", "cpd_set_state",
     "cpd_get_state", "cpd_estep", "cpd_destroy", "cpd_status_str",
-    "cpd_last_error", "cpd_abi_version", "cpd_build_info",
+    "cpd_last_error", "cpd_abi_version", "cpd_build_info", "cpd_time_kernels",
 ]
 
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "cpd_get_state": ([vp, vp, vp, P(ctypes.c_double)], ctypes.c_int),
         "cpd_estep": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "cpd_destroy": ([vp], ctypes.c_int),
+        "cpd_time_kernels": ([vp, ctypes.c_int32, P(ctypes.c_double)], ctypes.c_int),
         "cpd_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "cpd_last_error": ([vp], ctypes.c_char_p),
         "cpd_abi_version": ([], ctypes.c_int32),
@@ -215,6 +216,16 @@ def cpd_estep(h, logd=None, P1=None, Yt=None, tbar=None):
     _check(load_library().cpd_estep(h, _ptr(logd), _ptr(P1), _ptr(Yt), _ptr(tbar)), h)
 
 
+KERNEL_STAGES = ("passA", "passA_merge", "passB", "passB_merge", "mstep", "sigma2",
+                 "prescale", "iteration")
+
+
+def cpd_time_kernels(h, reps=10) -> dict:
+    out = (ctypes.c_double * 8)()
+    _check(load_library().cpd_time_kernels(h, int(reps), out), h)
+    return dict(zip(KERNEL_STAGES, list(out)))
+
+
 def cpd_destroy(h):
     if h:
         load_library().cpd_destroy(h)
@@ -279,6 +290,9 @@ class Registration:
                  tbar=torch.empty(self.M, dtype=self.dtype, device=self.device))
         cpd_estep(self.h, **o)
         return o
+
+    def time_kernels(self, reps=10) -> dict:
+        return cpd_time_kernels(self.h, reps)
 
     def set_state(self, Xt, sigma2):
         cpd_set_state(self.h, Xt, sigma2)

@@ -192,7 +192,7 @@ cpd_status check_device(cpd_ctx* h) {
 
 // ------------------------------------------------------------- one step
 template <typename T>
-void enqueue_estep(cpd_ctx* h, int gate, T* logd_out) {
+void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) {
   const Layout& L = h->L;
   EStepArgs<T> a{};
   a.Xt = h->at<P4<T>>(L.Xt);
@@ -218,6 +218,7 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out) {
   a.Yt = h->at<P4<T>>(L.Yt);
   a.P1 = h->at<T>(L.P1);
   a.tbar = h->at<T>(L.tbar);
+  a.ev = ev;
   if (h->p.precision == CPD_PREC_BF16X)
     estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
   else
@@ -511,6 +512,44 @@ cpd_status get_state_impl(cpd_ctx* h, void* Xt, void* W, double* sigma2) {
   return CPD_OK;
 }
 
+template <typename T>
+cpd_status time_impl(cpd_ctx* h, int reps, double* out) {
+  hipEvent_t e[8];
+  for (auto& x : e) HIPCHK(h, hipEventCreate(&x));
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 0);
+  cpd_status s = CPD_OK;
+  for (int r = 0; r < reps && s == CPD_OK; ++r) {
+    (void)hipEventRecord(e[0], h->st);
+    enqueue_estep<T>(h, 0, nullptr, &e[1]);  // e[1..5]
+    enqueue_mstep<T>(h, 0);
+    (void)hipEventRecord(e[6], h->st);
+    enqueue_sigma2<T>(h, 0);
+    (void)hipEventRecord(e[7], h->st);
+    hipError_t err = hipEventSynchronize(e[7]);
+    if (err != hipSuccess) {
+      s = hip_fail(h, err, "hipEventSynchronize");
+      break;
+    }
+    float ms[7];
+    for (int i = 0; i < 7; ++i) (void)hipEventElapsedTime(&ms[i], e[i], e[i + 1]);
+    float tot = 0;
+    (void)hipEventElapsedTime(&tot, e[0], e[7]);
+    acc[6] += ms[0];                // prescale
+    acc[0] += ms[1];                // pass A
+    acc[1] += ms[2];                // pass A merge + fix-up
+    acc[2] += ms[3];                // pass B
+    acc[3] += ms[4];                // pass B merge + fix-up
+    acc[4] += ms[5];                // M-step
+    acc[5] += ms[6];                // sigma^2
+    acc[7] += tot;
+  }
+  for (auto& x : e) (void)hipEventDestroy(x);
+  if (s != CPD_OK) return s;
+  for (int i = 0; i < 8; ++i) out[i] = acc[i] / reps;
+  return CPD_OK;
+}
+
 bool is_f64(const cpd_ctx* h) { return h->p.precision == CPD_PREC_FP64; }
 
 }  // namespace
@@ -635,6 +674,13 @@ cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar) {
   if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
   return is_f64(h) ? estep_impl<double>(h, logd, P1, Yt, tbar)
                    : estep_impl<float>(h, logd, P1, Yt, tbar);
+}
+
+cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms) {
+  const cpd_status r = ready_for_steps(h);
+  if (r != CPD_OK) return r;
+  if (reps < 1 || !out_ms) return fail(h, CPD_E_ARG, "reps must be >= 1 and out_ms non-NULL");
+  return is_f64(h) ? time_impl<double>(h, reps, out_ms) : time_impl<float>(h, reps, out_ms);
 }
 
 cpd_status cpd_destroy(cpd_handle h) {

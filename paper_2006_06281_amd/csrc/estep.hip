@@ -338,6 +338,7 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
   const int nthr = a.M + a.N;
   hipLaunchKernelGGL(k_prescale<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
                      a.ys, a.M, a.N, a.sc, gate);
+  if (a.ev) (void)hipEventRecord(a.ev[0], st);
   // pass A
   {
     const int tiles = (a.N + 256 * NB - 1) / (256 * NB);
@@ -347,6 +348,7 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
       default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
     }
+    if (a.ev) (void)hipEventRecord(a.ev[1], st);
     hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA,
                        a.splitsA, a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols,
                        a.llpart, gate);
@@ -356,6 +358,7 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
     }
   }
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
   // pass B
   {
     const int tiles = (a.M + 256 * NB - 1) / (256 * NB);
@@ -365,6 +368,7 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
       default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
     }
+    if (a.ev) (void)hipEventRecord(a.ev[3], st);
     hipLaunchKernelGGL(k_rowmerge<T>, dim3((a.M + 255) / 256), dim3(256), 0, st, a.partB,
                        a.splitsB, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, a.badrows, gate);
     switch (a.D) {
@@ -373,6 +377,7 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       default: hipLaunchKernelGGL((k_rowfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
     }
   }
+  if (a.ev) (void)hipEventRecord(a.ev[4], st);
 }
 
 template <typename T>

@@ -23,6 +23,7 @@ template <typename T> struct EStepArgs {
   P4<T>* Yt;         // out (M)
   T* P1;             // out (M)
   T* tbar;           // out (M)
+  hipEvent_t* ev;    // nullable: 5 events recorded between the stages
 };
 
 template <typename T> void estep_launch(const EStepArgs<T>& a, hipStream_t st);

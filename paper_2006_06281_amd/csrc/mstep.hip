@@ -15,111 +15,166 @@
 namespace fcpd {
 
 // ---------------------------------------------------------------- T = U^T R
-// Block (k-group, row chunk): thread k accumulates sum_m U[m][k] R_m over the
-// chunk; R_m = Yt_m - X_m is uniform across the block.
-template <typename T>
+// Block (row chunk, k-group of 256*KT): thread t accumulates
+// sum_m U[m][k] R_m for k = k0 + t + 256 j, j < KT; R_m = Yt_m - X_m is uniform
+// across the block (scalar loads).  U rows are read with coalesced loads.
+template <typename T, int KT>
 __global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
                                                const P4<T>* __restrict__ Yt,
                                                const T* __restrict__ U, int M, int K, int rows,
                                                const DevScalars* __restrict__ sc,
                                                T* __restrict__ tpart, int gate) {
   if (gate && sc->done) return;
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  const int m0 = blockIdx.y * rows;
+  const int k0 = blockIdx.y * 256 * KT + threadIdx.x;
+  const int m0 = blockIdx.x * rows;
   const int m1 = min(M, m0 + rows);
-  T ax = 0, ay = 0, az = 0;
-  if (k < K) {
-    for (int m = m0; m < m1; ++m) {
-      const P4<T> y = Yt[m], x = X[m];
-      const T u = U[(size_t)m * K + k];
-      ax = fma(u, y.x - x.x, ax);
-      ay = fma(u, y.y - x.y, ay);
-      az = fma(u, y.z - x.z, az);
+  T ax[KT], ay[KT], az[KT];
+#pragma unroll
+  for (int j = 0; j < KT; ++j) ax[j] = ay[j] = az[j] = (T)0;
+#pragma unroll 4
+  for (int m = m0; m < m1; ++m) {
+    const P4<T> y = Yt[m], x = X[m];
+    const T rx = y.x - x.x, ry = y.y - x.y, rz = y.z - x.z;
+    const T* u = U + (size_t)m * K;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) {
+      const int k = k0 + 256 * j;
+      const T uk = k < K ? u[k] : (T)0;
+      ax[j] = fma(uk, rx, ax[j]);
+      ay[j] = fma(uk, ry, ay[j]);
+      az[j] = fma(uk, rz, az[j]);
     }
-    T* o = tpart + ((size_t)blockIdx.y * K + k) * 4;
-    o[0] = ax;
-    o[1] = ay;
-    o[2] = az;
-    o[3] = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < KT; ++j) {
+    const int k = k0 + 256 * j;
+    if (k < K) {
+      T* o = tpart + ((size_t)blockIdx.x * K + k) * 4;
+      o[0] = ax[j];
+      o[1] = ay[j];
+      o[2] = az[j];
+      o[3] = (T)0;
+    }
   }
 }
 
-// T_k = sum over chunks; GT_k = g_k T_k, HT_k = h_k T_k.
+// One wave per eigenpair k: T_k = sum over row chunks (fixed order: lane
+// strides, then a fixed butterfly), GT_k = g_k T_k, HT_k = h_k T_k with
+// g_k = 1/(max(lam_k, 0) + lambda sigma^2) and h_k = max(lam_k, 0) g_k.
 template <typename T>
-__global__ __launch_bounds__(256) void k_tmerge(const T* __restrict__ tpart, int chunks,
-                                                const double* __restrict__ lam, int K,
-                                                double lmbda, const DevScalars* __restrict__ sc,
-                                                P4<T>* __restrict__ GT, P4<T>* __restrict__ HT,
-                                                int gate) {
+__global__ __launch_bounds__(64) void k_tmerge(const T* __restrict__ tpart, int chunks,
+                                               const double* __restrict__ lam, int K,
+                                               double lmbda, const DevScalars* __restrict__ sc,
+                                               P4<T>* __restrict__ GT, P4<T>* __restrict__ HT,
+                                               int gate) {
   if (gate && sc->done) return;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
   T tx = 0, ty = 0, tz = 0;
-  for (int c = 0; c < chunks; ++c) {
+  for (int c = lane; c < chunks; c += 64) {
     const T* p = tpart + ((size_t)c * K + k) * 4;
     tx += p[0];
     ty += p[1];
     tz += p[2];
   }
-  const double lp = fmax(lam[k], 0.0);
-  const double g = 1.0 / (lp + lmbda * sc->sigma2);
-  const double h = lp * g;
-  GT[k] = P4<T>{(T)(g * tx), (T)(g * ty), (T)(g * tz), (T)0};
-  HT[k] = P4<T>{(T)(h * tx), (T)(h * ty), (T)(h * tz), (T)0};
+  tx = wave_sum(tx);
+  ty = wave_sum(ty);
+  tz = wave_sum(tz);
+  if (lane == 0) {
+    const double lp = fmax(lam[k], 0.0);
+    const double g = 1.0 / (lp + lmbda * sc->sigma2);
+    const double h = lp * g;
+    GT[k] = P4<T>{(T)(g * tx), (T)(g * ty), (T)(g * tz), (T)0};
+    HT[k] = P4<T>{(T)(h * tx), (T)(h * ty), (T)(h * tz), (T)0};
+  }
 }
 
-// One wave per model row: Xnew_m = X_m + U_m . HT, W_m = U_m . GT.
-template <typename T>
+// Xnew_m = X_m + U_m . HT, W_m = U_m . GT.  Sixteen lanes per row (four rows
+// per wave), 64 rows per block; GT and HT staged in LDS when they fit.
+template <typename T, bool LDS>
 __global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
                                                const T* __restrict__ U,
-                                               const P4<T>* __restrict__ GT,
-                                               const P4<T>* __restrict__ HT, int M, int K,
+                                               const P4<T>* __restrict__ GTg,
+                                               const P4<T>* __restrict__ HTg, int M, int K,
                                                const DevScalars* __restrict__ sc,
                                                P4<T>* __restrict__ Xnew, P4<T>* __restrict__ W,
                                                int gate) {
+  extern __shared__ __align__(16) unsigned char smem[];
   if (gate && sc->done) return;
-  const int lane = threadIdx.x & 63;
-  const int m = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (m >= M) return;
-  const T* u = U + (size_t)m * K;
-  T hx = 0, hy = 0, hz = 0, gx = 0, gy = 0, gz = 0;
-  for (int k = lane; k < K; k += 64) {
-    const T uk = u[k];
-    const P4<T> h = HT[k], g = GT[k];
-    hx = fma(uk, h.x, hx);
-    hy = fma(uk, h.y, hy);
-    hz = fma(uk, h.z, hz);
-    gx = fma(uk, g.x, gx);
-    gy = fma(uk, g.y, gy);
-    gz = fma(uk, g.z, gz);
+  const P4<T>* GT = GTg;
+  const P4<T>* HT = HTg;
+  if (LDS) {
+    P4<T>* sG = reinterpret_cast<P4<T>*>(smem);
+    P4<T>* sH = sG + K;
+    for (int k = threadIdx.x; k < K; k += 256) {
+      sG[k] = GTg[k];
+      sH[k] = HTg[k];
+    }
+    __syncthreads();
+    GT = sG;
+    HT = sH;
   }
-  hx = wave_sum(hx);
-  hy = wave_sum(hy);
-  hz = wave_sum(hz);
-  gx = wave_sum(gx);
-  gy = wave_sum(gy);
-  gz = wave_sum(gz);
-  if (lane == 0) {
-    const P4<T> x = X[m];
-    Xnew[m] = P4<T>{x.x + hx, x.y + hy, x.z + hz, (T)0};
-    W[m] = P4<T>{gx, gy, gz, (T)0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane >> 4, l16 = lane & 15;
+  for (int it = 0; it < 4; ++it) {
+    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+    T hx = 0, hy = 0, hz = 0, gx = 0, gy = 0, gz = 0;
+    if (m < M) {
+      const T* u = U + (size_t)m * K;
+      for (int k = l16; k < K; k += 16) {
+        const T uk = u[k];
+        const P4<T> h = HT[k], g = GT[k];
+        hx = fma(uk, h.x, hx);
+        hy = fma(uk, h.y, hy);
+        hz = fma(uk, h.z, hz);
+        gx = fma(uk, g.x, gx);
+        gy = fma(uk, g.y, gy);
+        gz = fma(uk, g.z, gz);
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      hx += __shfl_xor(hx, o, 16);
+      hy += __shfl_xor(hy, o, 16);
+      hz += __shfl_xor(hz, o, 16);
+      gx += __shfl_xor(gx, o, 16);
+      gy += __shfl_xor(gy, o, 16);
+      gz += __shfl_xor(gz, o, 16);
+    }
+    if (l16 == 0 && m < M) {
+      const P4<T> x = X[m];
+      Xnew[m] = P4<T>{x.x + hx, x.y + hy, x.z + hz, (T)0};
+      W[m] = P4<T>{gx, gy, gz, (T)0};
+    }
   }
 }
 
+constexpr int kTRows = 128;
+constexpr size_t kApplyLdsBytes = 65536;
+
 template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk) {
-  const int rows = 64;
-  *rows_per_chunk = rows;
-  return (M + rows - 1) / rows;
+  *rows_per_chunk = kTRows;
+  return (M + kTRows - 1) / kTRows;
 }
 
 template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st) {
-  dim3 g1((a.K + 255) / 256, a.chunks);
-  hipLaunchKernelGGL(k_tpart<T>, g1, dim3(256), 0, st, a.X, a.Yt, a.U, a.M, a.K,
-                     a.rows_per_chunk, a.sc, a.tpart, a.gate);
-  hipLaunchKernelGGL(k_tmerge<T>, dim3((a.K + 255) / 256), dim3(256), 0, st, a.tpart, a.chunks,
-                     a.lam, a.K, a.lmbda, a.sc, a.GT, a.HT, a.gate);
-  hipLaunchKernelGGL(k_apply<T>, dim3((a.M + 3) / 4), dim3(256), 0, st, a.X, a.U, a.GT, a.HT,
-                     a.M, a.K, a.sc, a.Xnew, a.W, a.gate);
+  const int kt = a.K <= 256 ? 1 : (a.K <= 512 ? 2 : 4);
+  dim3 g1(a.chunks, (a.K + 256 * kt - 1) / (256 * kt));
+  if (kt == 1)
+    hipLaunchKernelGGL((k_tpart<T, 1>), g1, dim3(256), 0, st, a.X, a.Yt, a.U, a.M, a.K, a.rows_per_chunk, a.sc, a.tpart, a.gate);
+  else if (kt == 2)
+    hipLaunchKernelGGL((k_tpart<T, 2>), g1, dim3(256), 0, st, a.X, a.Yt, a.U, a.M, a.K, a.rows_per_chunk, a.sc, a.tpart, a.gate);
+  else
+    hipLaunchKernelGGL((k_tpart<T, 4>), g1, dim3(256), 0, st, a.X, a.Yt, a.U, a.M, a.K, a.rows_per_chunk, a.sc, a.tpart, a.gate);
+  hipLaunchKernelGGL(k_tmerge<T>, dim3(a.K), dim3(64), 0, st, a.tpart, a.chunks, a.lam, a.K,
+                     a.lmbda, a.sc, a.GT, a.HT, a.gate);
+  const dim3 g3((a.M + 63) / 64);
+  if (2 * (size_t)a.K * sizeof(P4<T>) <= kApplyLdsBytes)
+    hipLaunchKernelGGL((k_apply<T, true>), g3, dim3(256), 2 * a.K * sizeof(P4<T>), st, a.X, a.U,
+                       a.GT, a.HT, a.M, a.K, a.sc, a.Xnew, a.W, a.gate);
+  else
+    hipLaunchKernelGGL((k_apply<T, false>), g3, dim3(256), 0, st, a.X, a.U, a.GT, a.HT, a.M,
+                       a.K, a.sc, a.Xnew, a.W, a.gate);
 }
 
 // ------------------------------------------------------------------ sigma^2

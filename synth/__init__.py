@@ -61,16 +61,20 @@ def _threads() -> int:
 
 
 def _rbf_field(P: np.ndarray, C: np.ndarray, Wc: np.ndarray, beta: float,
-               chunk: int = 2048) -> np.ndarray:
+               chunk: int = 4096) -> np.ndarray:
     """v(p) = sum_j Wc_j exp(-|p - C_j|^2/(2 beta^2)) for every row p of P."""
     out = np.empty((P.shape[0], Wc.shape[1]))
     inv = 1.0 / (2.0 * beta * beta)
+    c2 = (C * C).sum(1)
     starts = list(range(0, P.shape[0], chunk))
 
     def one(s):
         p = P[s:s + chunk]
-        d2 = ((p[:, None, :] - C[None, :, :]) ** 2).sum(-1)
-        out[s:s + chunk] = np.exp(-d2 * inv) @ Wc
+        d2 = (p * p).sum(1)[:, None] + c2[None, :] - 2.0 * (p @ C.T)
+        np.maximum(d2, 0.0, out=d2)
+        d2 *= -inv
+        np.exp(d2, out=d2)
+        out[s:s + chunk] = d2 @ Wc
 
     with ThreadPoolExecutor(_threads()) as ex:
         list(ex.map(one, starts))
@@ -123,18 +127,26 @@ class _Surface:
         return u * r[:, None]
 
 
-def _finish(rng, X, P, Yclean_src_centres, Wc, beta, outlier_frac, noise,
-            keep_gt=True):
+def _finish(rng, X, P, centres, Wc, beta, outlier_frac, noise, field_rms=None,
+            outlier_box=1.5):
     """Deform P with the field centred at the model points, add noise and
-    outliers, shuffle.  Returns (Y, Y_hat)."""
-    Y = P + _rbf_field(P, Yclean_src_centres, Wc, beta)
-    Y_hat = X + _rbf_field(X, Yclean_src_centres, Wc, beta) if keep_gt else None
+    outliers, shuffle.  With field_rms the coefficients are rescaled so the
+    displacement of the model points has that RMS per coordinate.
+    Returns (Y, Y_hat)."""
+    vX = _rbf_field(X, centres, Wc, beta)
+    scale = 1.0
+    if field_rms is not None:
+        scale = field_rms / np.sqrt(np.mean(vX ** 2))
+    vX *= scale
+    vP = vX if P is X else scale * _rbf_field(P, centres, Wc, beta)
+    Y = P + vP
+    Y_hat = X + vX
     if noise > 0:
         Y = Y + rng.normal(0.0, noise, Y.shape)
     n_out = int(round(outlier_frac * Y.shape[0]))
     if n_out > 0:
         idx = rng.choice(Y.shape[0], n_out, replace=False)
-        Y[idx] = rng.uniform(-1.5, 1.5, (n_out, Y.shape[1]))
+        Y[idx] = rng.uniform(-outlier_box, outlier_box, (n_out, Y.shape[1]))
     perm = rng.permutation(Y.shape[0])
     return np.ascontiguousarray(Y[perm]), Y_hat
 
@@ -159,21 +171,25 @@ def sphere_pair(M=500, N=None, seed=0, beta=2.0, lam=3.0, w=0.1,
 
 
 def surface_pair(M=10000, N=None, seed=1, beta=2.0, lam=3.0, w=0.1,
-                 coef=None, outlier_frac=0.05, noise=0.0, radial_noise=0.02):
+                 field_rms=0.2, outlier_frac=0.05, noise=0.0, radial_noise=0.02,
+                 outlier_box=1.5):
     """Model on a random spherical-harmonic surface; scene drawn from the same
     surface (the model itself when N == M, fresh samples otherwise), pushed
-    through the RBF field centred at the model points."""
+    through the RBF field centred at the model points.  The field's
+    coefficients are N(0, s^2) with s set so that the displacement of the
+    model points has RMS `field_rms` per coordinate (20% of the unit radius by
+    default): a smooth non-rigid deformation that keeps the deformed scene
+    inside the outlier box."""
     rng = np.random.default_rng(seed)
     N = M if N is None else N
-    coef = coef_std(M) if coef is None else coef
     surf = _Surface(rng)
     X = surf.sample(rng, M, radial_noise)
-    Wc = rng.normal(0.0, coef, (M, 3))
+    Wc = rng.normal(0.0, 1.0, (M, 3))
     P = X if N == M else surf.sample(rng, N, radial_noise)
-    Y, Y_hat = _finish(rng, X, P, X, Wc, beta, outlier_frac, noise)
+    Y, Y_hat = _finish(rng, X, P, X, Wc, beta, outlier_frac, noise, field_rms, outlier_box)
     return PointPair(np.ascontiguousarray(X), Y, Y_hat, beta, lam, w, seed,
-                     {"kind": "surface", "coef": coef, "outliers": outlier_frac,
-                      "noise": noise, "harmonics": surf.terms})
+                     {"kind": "surface", "field_rms": field_rms, "outliers": outlier_frac,
+                      "noise": noise, "outlier_box": outlier_box, "harmonics": surf.terms})
 
 
 def batch_pairs(B=256, m_range=(500, 8000), seed0=1000, w=0.1,
