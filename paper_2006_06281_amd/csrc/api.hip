@@ -170,8 +170,6 @@ cpd_status validate(const cpd_params* p) {
   if (p->reserved != 0) return fail(nullptr, CPD_E_ARG, "reserved must be 0");
   if (p->precision == CPD_PREC_BF16X && p->method != CPD_METHOD_FAST)
     return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X precision is implemented for the Fast method");
-  if (p->method == CPD_METHOD_ORIGINAL)
-    return fail(nullptr, CPD_E_UNSUPPORTED, "the original method is not built yet");
   if (p->precision == CPD_PREC_BF16X)
     return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X is not built yet");
   return CPD_OK;
@@ -332,6 +330,7 @@ cpd_status step_impl(cpd_ctx* h, cpd_step_info* info) {
   info->sigma2 = s.sigma2;
   info->dsigma2 = s.dsigma2;
   info->loglik = s.loglik;
+  if (s.nonfinite == 2) return fail(h, CPD_E_NUMERIC, "Cholesky factorisation broke down");
   if (s.nonfinite) return fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
   return CPD_OK;
 }
@@ -381,7 +380,8 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
   }
   for (auto& pe : evs)
     for (auto& e : pe.e) (void)hipEventDestroy(e);
-  if (s.nonfinite) status = fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
+  if (s.nonfinite == 2) status = fail(h, CPD_E_NUMERIC, "Cholesky factorisation broke down");
+  else if (s.nonfinite) status = fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
   if (X_out) unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(X_out), h->p.M, h->p.D, h->st);
   if (W_out) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W_out), h->p.M, h->p.D, h->st);
   HIPCHK(h, hipStreamSynchronize(h->st));

@@ -26,8 +26,8 @@ struct DevScalars {
   int32_t converged;
   int32_t bad_cols;     // columns that need the exact (rescaled) pass A
   int32_t bad_rows;     // rows that need the exact (rescaled) pass B
-  int32_t nonfinite;    // sigma^2 became NaN/Inf
-  int32_t pad_;
+  int32_t nonfinite;    // 1: sigma^2 became NaN/Inf, 2: Cholesky breakdown
+  int32_t chol_fail;    // the original method's factorisation broke down
 };
 
 __device__ __forceinline__ float fexp2(float v) { return __builtin_amdgcn_exp2f(v); }

@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_sig_part(P4<T>* __restrict__ Xt,
                                                   double* __restrict__ part, int gate) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
+  if (sc->nonfinite) return;  // a failed M-step leaves the iterate as it was
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   double v = 0.0, wsum = 0.0;
   if (m < M) {
@@ -232,6 +233,11 @@ __global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ pa
   b = block_sum_d(b, sh);
   c = block_sum_d(c, sh);
   if (threadIdx.x == 0) {
+    if (sc->nonfinite) {
+      sc->iter += 1;
+      sc->done = 1;
+      return;
+    }
     const double s2old = sc->sigma2;
     const double denom = weighted ? (double)D * b : (double)D * (double)M;
     double s2 = a / denom;
@@ -339,6 +345,7 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
     sc->done = 0;
     sc->converged = 0;
     sc->nonfinite = 0;
+    sc->chol_fail = 0;
     if (set_all) {
       sc->loglik = 0.0;
       sc->tol = tol;
