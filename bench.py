@@ -85,6 +85,51 @@ def converge_run(reg, pair, t_eig):
             "t_o_s": out.t_o, "rmse_eq22": rmse}
 
 
+def plain_cpd_legs(fc, torch, X, Y, pair, kw, fast_ms_step):
+    """The original CPD M-step (eq. 21) on the same GPU.
+
+    50k: per-iteration time of original CPD on the same inputs (two timed
+    iterations; a full run to convergence would take minutes per 100
+    iterations).  10k: the 10 000-point surface workload (beta = 2,
+    lambda = 3, w = 0.1, 5% outliers) run to |dsigma^2| < 1e-8 by original CPD
+    and by Fast CPD with the full eigendecomposition, both in FP32 mode."""
+    import synth
+    out = {}
+    reg = fc.Registration(X, Y, **dict(kw, method="original", eig_mode="full", K=0))
+    reg.prepare()
+    k = reg.time_kernels(reps=2)
+    out["surface50k_ms_per_iter"] = k["iteration"]
+    out["surface50k_mstep_ms"] = k["mstep"]
+    out["surface50k_em_iters_per_s"] = 1000.0 / k["iteration"]
+    out["fast_over_plain_iter_rate"] = k["iteration"] / fast_ms_step
+    reg.close()
+    del reg
+    torch.cuda.empty_cache()
+    log(f"plain CPD 50k: {k['iteration']:.1f} ms/iter (M-step {k['mstep']:.1f} ms)")
+    p = synth.workload("surface10k")
+    X10 = torch.as_tensor(p.X, dtype=torch.float32).cuda().contiguous()
+    Y10 = torch.as_tensor(p.Y, dtype=torch.float32).cuda().contiguous()
+    base = dict(precision="fp32", beta=p.beta, lam=p.lam, w=p.w, tol=1e-8, max_iter=1000)
+    for name, extra in (("original", dict(method="original")),
+                        ("fast_full", dict(method="fast", eig_mode="full"))):
+        r = fc.Registration(X10, Y10, **base, **extra)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.prepare()
+        torch.cuda.synchronize()
+        t_eig = time.perf_counter() - t0
+        res = converge_run(r, p, t_eig)
+        if name == "fast_full":
+            res["K"] = r.K
+        out[f"surface10k_{name}"] = res
+        log(f"surface10k {name}: {res}")
+        r.close()
+    o, f = out["surface10k_original"], out["surface10k_fast_full"]
+    if o["time_to_converge_s"] and f["time_to_converge_s"]:
+        out["surface10k_speedup_time_to_converge"] = o["time_to_converge_s"] / f["time_to_converge_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +138,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converge")
+    ap.add_argument("--no-plain", action="store_true", help="skip the original-CPD comparator")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -158,6 +204,10 @@ def main():
         log(f"w=0.7: {conv['w=0.7']}")
         reg7.close()
 
+    plain = None
+    if not args.no_plain:
+        plain = plain_cpd_legs(fc, torch, X, Y, pair, kw, ms_step)
+
     pairs = pair.M * pair.N
     tB = kern["passB"] * 1e-3
     achieved = pairs * FLOP_PASS_B / tB / 1e12
@@ -183,7 +233,7 @@ def main():
                    "M": pair.M, "N": pair.N, "D": 3, "K": K, "method": "fast-topk",
                    "precision": args.precision, "parallelism": "single-gpu"},
         "converge": conv, "kernels_ms": kern, "roofline": roofline, "cpu_baseline": cpu,
-        "plain_cpd": None,
+        "plain_cpd": plain,
     }
     print(json.dumps(rec), flush=True)
 

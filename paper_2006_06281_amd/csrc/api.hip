@@ -33,7 +33,7 @@ struct Region {
 struct Layout {
   size_t total = 0;
   Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, badcols, badrows, llpart,
-      sigpart, initpart;
+      sigpart, initpart, featX, featY;
   Region U, lam, U64, tpart, GT, HT;
   EigLayout eig;
   OrigLayout orig;
@@ -60,15 +60,23 @@ Layout make_layout(const cpd_params& p) {
   Layout L;
   const size_t M = (size_t)p.M, N = (size_t)p.N;
   const size_t p4 = sizeof(P4<T>);
-  estep_splits<T>(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+  if (p.precision == CPD_PREC_BF16X)
+    bfx_splits(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+  else
+    estep_splits<T>(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+  const size_t M256 = (size_t)pad256(p.M), N256 = (size_t)pad256(p.N);
   add(L, L.sc, sizeof(DevScalars));
   add(L, L.X, M * p4);
   add(L, L.Xt, M * p4);
   add(L, L.Xnew, M * p4);
   add(L, L.Y, N * p4);
   add(L, L.W, M * p4);
-  add(L, L.xs, M * p4);
-  add(L, L.ys, N * p4);
+  add(L, L.xs, M256 * p4);
+  add(L, L.ys, N256 * p4);
+  if (p.precision == CPD_PREC_BF16X) {
+    add(L, L.featX, M256 * 64);
+    add(L, L.featY, N256 * 64);
+  }
   add(L, L.Yt, M * p4);
   add(L, L.P1, M * sizeof(T));
   add(L, L.tbar, M * sizeof(T));
@@ -170,8 +178,8 @@ cpd_status validate(const cpd_params* p) {
   if (p->reserved != 0) return fail(nullptr, CPD_E_ARG, "reserved must be 0");
   if (p->precision == CPD_PREC_BF16X && p->method != CPD_METHOD_FAST)
     return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X precision is implemented for the Fast method");
-  if (p->precision == CPD_PREC_BF16X)
-    return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X is not built yet");
+  if (p->precision == CPD_PREC_BF16X && p->D != 3)
+    return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X is implemented for D = 3");
   return CPD_OK;
 }
 
@@ -217,6 +225,8 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.P1 = h->at<T>(L.P1);
   a.tbar = h->at<T>(L.tbar);
   a.ev = ev;
+  a.featX = h->at<__bf16>(L.featX);
+  a.featY = h->at<__bf16>(L.featY);
   if (h->p.precision == CPD_PREC_BF16X)
     estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
   else
@@ -406,8 +416,10 @@ cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
   init_launch<T>(static_cast<const T*>(X), static_cast<const T*>(Y), h->at<P4<T>>(L.X),
                  h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D, h->p.sigma2_init,
                  h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st);
-  // W starts at 0 (so Xt = X)
+  // W starts at 0 (so Xt = X); the padding of the prescaled copies stays 0
   HIPCHK(h, hipMemsetAsync(h->ws + L.W.off, 0, L.W.bytes, h->st));
+  HIPCHK(h, hipMemsetAsync(h->ws + L.xs.off, 0, L.xs.bytes, h->st));
+  HIPCHK(h, hipMemsetAsync(h->ws + L.ys.off, 0, L.ys.bytes, h->st));
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->st));
   return CPD_OK;

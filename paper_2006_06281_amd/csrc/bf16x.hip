@@ -1,0 +1,280 @@
+// BF16X precision mode of the E-step: the squared distances of eq. 4 come
+// from the matrix cores (bf16 operands, fp32 accumulation), the exponentials
+// and sums stay in fp32 on the VALU.
+//
+// |u - v|^2 = |u|^2 + |v|^2 - 2 u.v is one dot product of two 32-slot feature
+// vectors per point.  Each fp32 coordinate is split into three bf16 pieces
+// u = u1 + u2 + u3 (u1 = bf16(u), u2 = bf16(u - u1), u3 = bf16(u - u1 - u2),
+// 24 significant bits in total), and the cross term keeps the six products
+// u1v1, u1v2, u2v1, u1v3, u2v2, u3v1, dropping terms below 2^-24 relative
+// (the split-precision scheme of Henry, Tang & Heinecke, "Leveraging the
+// bfloat16 artificial intelligence datatype for higher-precision
+// computations", ARITH 2019).  Norms (and the per-column offset: the pass-A
+// reference, or L_n = log2 d_n in pass B) enter as three bf16 pieces times 1.
+//   model   F(u) = [u1 u1 u2 u1 u2 u3]xyz, |u|^2 (3 pieces), 1 1 1, 0...
+//   scene   G(v) = -2[v1 v2 v1 v3 v2 v1]xyz, 1 1 1, |v|^2 + extra (3 pieces), 0...
+// so F(u).G(v) = |u - v|^2 + extra in prescaled units (base-2 exponent).
+// The remaining error is the fp32 accumulation of terms of size ~kappa |x|^2,
+// about 2^-23 * 3 kappa max|x|^2 in the exponent.
+//
+// v_mfma_f32_16x16x32_bf16 layout (checked on the device): A lane l holds
+// row l%16, k = 8(l/16)..+7; B lane l holds column l%16, the same k slice;
+// D lane l holds rows 4(l/16)..+3 of column l%16.  A feature vector is 64
+// bytes, so a lane's operand is the 16-byte slice (l/16) of point l%16.
+//
+// Pass A: a wave keeps four 16-column scene tiles (B operands) in registers
+// and streams 16-point model tiles (A); per pair: one v_exp_f32 and one add.
+// Pass B: a wave keeps four 16-point model tiles (B) and streams scene tiles
+// (A, extra = L_n); per pair: exp, and the sums of p, p*v, p*|u - v|^2.
+// Padded points carry a 3e30 offset so their exponentials are exactly 0.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fcpd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kPadOffset = 3.0e30f;
+
+__device__ __forceinline__ void split3(float u, __bf16& a, __bf16& b, __bf16& c) {
+  a = (__bf16)u;
+  const float r1 = u - (float)a;
+  b = (__bf16)r1;
+  const float r2 = r1 - (float)b;
+  c = (__bf16)r2;
+}
+
+// Model features from the prescaled model xs (P4, M valid of Mpad).
+__global__ __launch_bounds__(256) void k_feat_model(const P4<float>* __restrict__ xs, int M,
+                                                    int Mpad, __bf16* __restrict__ F,
+                                                    const DevScalars* __restrict__ sc, int gate) {
+  if (gate && sc->done) return;
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= Mpad) return;
+  __bf16 f[32];
+  for (int k = 0; k < 32; ++k) f[k] = (__bf16)0.0f;
+  if (m < M) {
+    const P4<float> p = xs[m];
+    const float c[3] = {p.x, p.y, p.z};
+    for (int d = 0; d < 3; ++d) {
+      __bf16 a, b, e;
+      split3(c[d], a, b, e);
+      f[6 * d + 0] = a;
+      f[6 * d + 1] = a;
+      f[6 * d + 2] = b;
+      f[6 * d + 3] = a;
+      f[6 * d + 4] = b;
+      f[6 * d + 5] = e;
+    }
+    const float n = p.x * p.x + p.y * p.y + p.z * p.z;
+    split3(n, f[18], f[19], f[20]);
+  } else {
+    f[18] = (__bf16)kPadOffset;
+  }
+  f[21] = f[22] = f[23] = (__bf16)1.0f;
+  bf16x8* out = reinterpret_cast<bf16x8*>(F + (size_t)m * 32);
+  for (int q = 0; q < 4; ++q) {
+    bf16x8 v;
+    for (int t = 0; t < 8; ++t) v[t] = f[8 * q + t];
+    out[q] = v;
+  }
+}
+
+// Scene features; extra = the pass-A reference (use_L = 0) or L_n = ys[n].w.
+__global__ __launch_bounds__(256) void k_feat_scene(const P4<float>* __restrict__ ys, int N,
+                                                    int Npad, int use_L, double w, int M, int D,
+                                                    __bf16* __restrict__ G,
+                                                    const DevScalars* __restrict__ sc, int gate) {
+  if (gate && sc->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Npad) return;
+  __bf16 g[32];
+  for (int k = 0; k < 32; ++k) g[k] = (__bf16)0.0f;
+  g[18] = g[19] = g[20] = (__bf16)1.0f;
+  if (n < N) {
+    const P4<float> p = ys[n];
+    const float c[3] = {p.x, p.y, p.z};
+    for (int d = 0; d < 3; ++d) {
+      __bf16 a, b, e;
+      split3(c[d], a, b, e);
+      const __bf16 a2 = (__bf16)(-2.0f * (float)a), b2 = (__bf16)(-2.0f * (float)b),
+                   e2 = (__bf16)(-2.0f * (float)e);
+      g[6 * d + 0] = a2;
+      g[6 * d + 1] = b2;
+      g[6 * d + 2] = a2;
+      g[6 * d + 3] = e2;
+      g[6 * d + 4] = b2;
+      g[6 * d + 5] = a2;
+    }
+    float extra;
+    if (use_L) {
+      extra = p.w;
+    } else {
+      const double l2c = log2_c(sc->sigma2, D, w, M, N);
+      extra = (float)fmax(l2c, kRefFloor);
+    }
+    const float m = p.x * p.x + p.y * p.y + p.z * p.z + extra;
+    split3(m, g[21], g[22], g[23]);
+  } else {
+    g[21] = (__bf16)kPadOffset;
+  }
+  bf16x8* out = reinterpret_cast<bf16x8*>(G + (size_t)n * 32);
+  for (int q = 0; q < 4; ++q) {
+    bf16x8 v;
+    for (int t = 0; t < 8; ++t) v[t] = g[8 * q + t];
+    out[q] = v;
+  }
+}
+
+__device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int point, int lane) {
+  return *reinterpret_cast<const bf16x8*>(feat + (size_t)point * 32 + 8 * (lane >> 4));
+}
+
+// Pass A partials: part[split][n] = sum over the split's model points of
+// 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.
+__global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
+                                                    const __bf16* __restrict__ G, int Mpad, int N,
+                                                    int m_chunk, const DevScalars* __restrict__ sc,
+                                                    float* __restrict__ part, int gate) {
+  if (gate && sc->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 scene columns
+  bf16x8 b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) b[s] = load_op(G, n0 + 16 * s + (lane & 15), lane);
+  const int m0 = blockIdx.y * m_chunk;
+  const int m1 = min(Mpad, m0 + m_chunk);
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  for (int mt = m0; mt < m1; mt += 16) {
+    const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+      acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    acc[s] += __shfl_xor(acc[s], 16, 64);
+    acc[s] += __shfl_xor(acc[s], 32, 64);
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int n = n0 + 16 * s + lane;
+      if (n < N) part[(size_t)blockIdx.y * N + n] = acc[s];
+    }
+  }
+}
+
+// Pass B partials: part[split][5][M] = sum over the split's scene points of
+// p, p*v (prescaled, absolute), p*|u - v|^2 with p = 2^-(|u - v|^2 + L_n).
+__global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F,
+                                                    const __bf16* __restrict__ G,
+                                                    const P4<float>* __restrict__ ys, int M,
+                                                    int Npad, int n_chunk,
+                                                    const DevScalars* __restrict__ sc,
+                                                    float* __restrict__ part, int gate) {
+  if (gate && sc->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 model columns
+  bf16x8 b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
+  const int nb = blockIdx.y * n_chunk;
+  const int ne = min(Npad, nb + n_chunk);
+  float r[4], px[4], py[4], pz[4], t[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
+  for (int nt = nb; nt < ne; nt += 16) {
+    const bf16x8 a = load_op(G, nt + (lane & 15), lane);
+    P4<float> yv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float p = fexp2(-d[q]);
+        const float d2 = d[q] - yv[q].w;
+        r[s] += p;
+        px[s] = fmaf(p, yv[q].x, px[s]);
+        py[s] = fmaf(p, yv[q].y, py[s]);
+        pz[s] = fmaf(p, yv[q].z, pz[s]);
+        t[s] = fmaf(p, d2, t[s]);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      r[s] += __shfl_xor(r[s], o, 64);
+      px[s] += __shfl_xor(px[s], o, 64);
+      py[s] += __shfl_xor(py[s], o, 64);
+      pz[s] += __shfl_xor(pz[s], o, 64);
+      t[s] += __shfl_xor(t[s], o, 64);
+    }
+  }
+  if (lane < 16) {
+    float* base = part + (size_t)blockIdx.y * 5 * M;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int m = m0 + 16 * s + lane;
+      if (m < M) {
+        base[m] = r[s];
+        base[(size_t)M + m] = px[s];
+        base[(size_t)2 * M + m] = py[s];
+        base[(size_t)3 * M + m] = pz[s];
+        base[(size_t)4 * M + m] = t[s];
+      }
+    }
+  }
+}
+
+void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
+  const int target = 4096;
+  auto plan = [&](int cols, int len, int* splits, int* chunk) {
+    const int lenp = (len + 15) & ~15;
+    const int tiles = (cols + 255) / 256;
+    int s = (target + tiles - 1) / tiles;
+    const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
+    s = s < 1 ? 1 : (s > smax ? smax : s);
+    int c = (lenp + s - 1) / s;
+    c = (c + 15) & ~15;
+    *chunk = c;
+    *splits = (lenp + c - 1) / c;
+  };
+  plan(N, M, splitsA, chunkA);
+  plan(M, N, splitsB, chunkB);
+}
+
+void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
+  const int Mpad = (a.M + 15) & ~15, Npad = (a.N + 15) & ~15;
+  const int gate = a.gate;
+  prescale_launch<float>(a, st);
+  hipLaunchKernelGGL(k_feat_model, dim3((Mpad + 255) / 256), dim3(256), 0, st, a.xs, a.M, Mpad,
+                     a.featX, a.sc, gate);
+  hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 0,
+                     a.w, a.M, a.D, a.featY, a.sc, gate);
+  if (a.ev) (void)hipEventRecord(a.ev[0], st);
+  hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
+                     a.featY, Mpad, a.N, a.chunkA, a.sc, a.partA, gate);
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  colmerge_fix_launch<float>(a, st);
+  hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 1,
+                     a.w, a.M, a.D, a.featY, a.sc, gate);
+  if (a.ev) (void)hipEventRecord(a.ev[2], st);
+  hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
+                     a.featY, a.ys, a.M, Npad, a.chunkB, a.sc, a.partB, gate);
+  if (a.ev) (void)hipEventRecord(a.ev[3], st);
+  rowmerge_fix_launch<float>(a, st, /*relative=*/0);
+  if (a.ev) (void)hipEventRecord(a.ev[4], st);
+}
+
+}  // namespace fcpd

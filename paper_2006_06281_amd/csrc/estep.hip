@@ -241,13 +241,15 @@ __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
 }
 
 // Row merge: P1_m = r_m, Yt_m = xt_m + (sum p (y - xt)) / r_m, tbar_m.
+// relative = 1: the sums hold p (y^ - x^) (direct-difference pass B);
+// relative = 0: they hold p y^ (absolute, the matrix-core pass B).
 template <typename T>
 __global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, int splits,
                                                   const P4<T>* __restrict__ Xt,
                                                   P4<T>* __restrict__ Yt, T* __restrict__ P1,
                                                   T* __restrict__ tbar, int M,
                                                   DevScalars* sc, int* __restrict__ badlist,
-                                                  int gate) {
+                                                  int relative, int gate) {
   if (gate && sc->done) return;
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
@@ -268,7 +270,8 @@ __global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, in
   }
   const T inv = (T)1 / r;
   const T isk = (T)(1.0 / sqrt(kap));
-  const P4<T> x = Xt[m];
+  P4<T> x = Xt[m];
+  if (!relative) x = P4<T>{(T)0, (T)0, (T)0, (T)0};
   Yt[m] = P4<T>{x.x + px * inv * isk, x.y + py * inv * isk, x.z + pz * inv * isk, (T)0};
   P1[m] = r;
   tbar[m] = t * inv * (T)(1.0 / kap);
@@ -331,15 +334,41 @@ __global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
 }
 
 // ------------------------------------------------------------- launchers
+template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st) {
+  const int nthr = a.M + a.N;
+  hipLaunchKernelGGL(k_prescale<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
+                     a.ys, a.M, a.N, a.sc, a.gate);
+}
+
+template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st) {
+  const int gate = a.gate;
+  hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA, a.splitsA,
+                     a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, gate);
+  switch (a.D) {
+    case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+    case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+    default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+  }
+}
+
+template <typename T>
+void rowmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st, int relative) {
+  const int gate = a.gate;
+  hipLaunchKernelGGL(k_rowmerge<T>, dim3((a.M + 255) / 256), dim3(256), 0, st, a.partB, a.splitsB,
+                     a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, a.badrows, relative, gate);
+  switch (a.D) {
+    case 1: hipLaunchKernelGGL((k_rowfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+    case 2: hipLaunchKernelGGL((k_rowfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+    default: hipLaunchKernelGGL((k_rowfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
+  }
+}
+
 template <typename T>
 void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
   constexpr int NB = sizeof(T) == 4 ? 4 : 2;
   const int gate = a.gate;
-  const int nthr = a.M + a.N;
-  hipLaunchKernelGGL(k_prescale<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
-                     a.ys, a.M, a.N, a.sc, gate);
+  prescale_launch<T>(a, st);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
-  // pass A
   {
     const int tiles = (a.N + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsA);
@@ -348,18 +377,10 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
       default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
     }
-    if (a.ev) (void)hipEventRecord(a.ev[1], st);
-    hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA,
-                       a.splitsA, a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols,
-                       a.llpart, gate);
-    switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
-      case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
-      default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
-    }
   }
+  if (a.ev) (void)hipEventRecord(a.ev[1], st);
+  colmerge_fix_launch<T>(a, st);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
-  // pass B
   {
     const int tiles = (a.M + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsB);
@@ -368,15 +389,9 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
       case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
       default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
     }
-    if (a.ev) (void)hipEventRecord(a.ev[3], st);
-    hipLaunchKernelGGL(k_rowmerge<T>, dim3((a.M + 255) / 256), dim3(256), 0, st, a.partB,
-                       a.splitsB, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, a.badrows, gate);
-    switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_rowfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-      case 2: hipLaunchKernelGGL((k_rowfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-      default: hipLaunchKernelGGL((k_rowfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-    }
   }
+  if (a.ev) (void)hipEventRecord(a.ev[3], st);
+  rowmerge_fix_launch<T>(a, st, 1);
   if (a.ev) (void)hipEventRecord(a.ev[4], st);
 }
 
@@ -400,6 +415,9 @@ void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* ch
 
 template void estep_launch<float>(const EStepArgs<float>&, hipStream_t);
 template void estep_launch<double>(const EStepArgs<double>&, hipStream_t);
+template void prescale_launch<float>(const EStepArgs<float>&, hipStream_t);
+template void colmerge_fix_launch<float>(const EStepArgs<float>&, hipStream_t);
+template void rowmerge_fix_launch<float>(const EStepArgs<float>&, hipStream_t, int);
 template void estep_splits<float>(int, int, int*, int*, int*, int*);
 template void estep_splits<double>(int, int, int*, int*, int*, int*);
 

@@ -24,9 +24,17 @@ template <typename T> struct EStepArgs {
   T* P1;             // out (M)
   T* tbar;           // out (M)
   hipEvent_t* ev;    // nullable: 5 events recorded between the stages
+  __bf16* featX;     // BF16X: model feature vectors (32 bf16 per point, padded)
+  __bf16* featY;     // BF16X: scene feature vectors
 };
 
 template <typename T> void estep_launch(const EStepArgs<T>& a, hipStream_t st);
+// pieces shared with the BF16X E-step
+template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st);
+template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st);
+template <typename T> void rowmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st, int relative);
+void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
+inline int pad256(int n) { return (n + 255) & ~255; }
 template <typename T>
 void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
 
