@@ -67,7 +67,7 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.phi = take((size_t)M * M * sizeof(double));
     L.V = take((size_t)M * M * sizeof(double));
     L.ritz = take((size_t)M * sizeof(double));
-    L.misc = take(((size_t)M * sizeof(int) + 64) + 4 * sizeof(double));
+    L.misc = take(((size_t)M * sizeof(int) + 64) + (64 + 4 * (size_t)(M / 2 + 1)) * sizeof(double));
   } else {
     int n;
     if (mode == 0)
@@ -85,7 +85,7 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.V = take(nn);
     L.phi = take(nn);  // the n x n Rayleigh-Ritz / Gram matrix
     L.ritz = take((size_t)n * sizeof(double));
-    L.misc = take(((size_t)n * sizeof(int) + 64) + 4 * sizeof(double));
+    L.misc = take(((size_t)n * sizeof(int) + 64) + (64 + 4 * (size_t)(n / 2 + 1)) * sizeof(double));
   }
   L.end = off;
   return L;
@@ -361,99 +361,116 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ A,
 }
 
 // ------------------------------------------------------------ Jacobi
-// Cyclic two-sided Jacobi on a symmetric n x n matrix A (row-major, global),
-// one workgroup.  Round-robin ordering: n/2 disjoint rotations per step, rows
-// then columns updated with barriers between.  V accumulates the rotations
-// (columns are eigenvectors); on exit diag(A) holds the eigenvalues.
-__global__ __launch_bounds__(1024) void k_jacobi(double* __restrict__ A, double* __restrict__ V,
-                                                 int n, int max_sweeps, int* __restrict__ sweeps_out) {
-  __shared__ double cs_c[kJacobiMax / 2 + 1], cs_s[kJacobiMax / 2 + 1];
-  __shared__ double dg_p[kJacobiMax / 2 + 1], dg_q[kJacobiMax / 2 + 1];
-  __shared__ int pp[kJacobiMax / 2 + 1], qq[kJacobiMax / 2 + 1];
-  __shared__ int any_rot;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int np = (n + 1) & ~1;  // even number of players (one dummy when n is odd)
-  const int half = np / 2;
-  for (size_t e = tid; e < (size_t)n * n; e += nt) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
-  const double eps = 1.1102230246251565e-16;
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    __syncthreads();  // every thread has read any_rot of the previous sweep
-    if (tid == 0) any_rot = 0;
-    __syncthreads();
-    for (int step = 0; step < np - 1; ++step) {
-      for (int k = tid; k < half; k += nt) {
-        auto pos = [&](int t) { return t == 0 ? 0 : ((t - 1 + step) % (np - 1)) + 1; };
-        int p = pos(k), q = pos(np - 1 - k);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
-        if (q < n) {
-          const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-          const double apq = A[(size_t)p * n + q];
-          const double aa = fabs(apq);
-          // relative test: rotate unless apq is round-off of both diagonals
-          if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-300) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            dp = app - t * apq;  // the 2 x 2 block after the rotation, exactly
-            dq = aqq + t * apq;
-            any_rot = 1;
-          }
-        }
-        pp[k] = p;
-        qq[k] = q < n ? q : -1;
-        cs_c[k] = c;
-        cs_s[k] = s;
-        dg_p[k] = dp;
-        dg_q[k] = dq;
-      }
-      __syncthreads();
-      // rows p, q of A  (J^T A)
-      for (int e = tid; e < half * n; e += nt) {
-        const int k = e / n, j = e % n;
-        const int q = qq[k];
-        if (q < 0 || cs_s[k] == 0.0) continue;
-        const int p = pp[k];
-        const double c = cs_c[k], s = cs_s[k];
-        const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
-        A[(size_t)p * n + j] = c * ap - s * aq;
-        A[(size_t)q * n + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      // columns p, q of A and V  (A J, V J)
-      for (int e = tid; e < half * n; e += nt) {
-        const int k = e / n, i = e % n;
-        const int q = qq[k];
-        if (q < 0 || cs_s[k] == 0.0) continue;
-        const int p = pp[k];
-        const double c = cs_c[k], s = cs_s[k];
-        const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
-        if (i == p) {
-          A[(size_t)p * n + p] = dg_p[k];
-          A[(size_t)p * n + q] = 0.0;
-        } else if (i == q) {
-          A[(size_t)q * n + p] = 0.0;
-          A[(size_t)q * n + q] = dg_q[k];
-        } else {
-          A[(size_t)i * n + p] = c * ap - s * aq;
-          A[(size_t)i * n + q] = s * ap + c * aq;
-        }
-        const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
-        V[(size_t)i * n + p] = c * vp - s * vq;
-        V[(size_t)i * n + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-    const int rotated = any_rot;  // uniform: nobody writes it before the next barrier
-    if (!rotated) break;
+// Cyclic two-sided Jacobi on a symmetric n x n matrix A (row-major, global).
+// Round-robin ordering: in each of the n-1 steps of a sweep the n/2 pairs are
+// disjoint, so their rotations commute.  A step is two launches over the
+// whole GPU: k_jac_rows (one block per pair: rotation from the pair's 2 x 2
+// block, then rows p, q of J^T A) and k_jac_cols (columns p, q of A J and of
+// V J, the 2 x 2 block set to its exact rotated values so round-off cannot
+// keep re-opening it).  A pair is rotated while |a_pq| exceeds both
+// eps sqrt(|a_pp a_qq|) (relative accuracy) and 1e-16 |A|_F (entries below
+// are round-off of the largest eigenvalues).  V accumulates the rotations;
+// on exit diag(A) holds the eigenvalues.
+__device__ __forceinline__ void rr_pair(int k, int step, int n, int* p, int* q) {
+  const int np = (n + 1) & ~1;
+  auto pos = [&](int t) { return t == 0 ? 0 : ((t - 1 + step) % (np - 1)) + 1; };
+  int a = pos(k), b = pos(np - 1 - k);
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
   }
-  if (tid == 0) sweeps_out[0] = sweep;
+  *p = a;
+  *q = b;  // q >= n: the dummy player (n odd)
+}
+
+__global__ __launch_bounds__(256) void k_jac_init(const double* __restrict__ A,
+                                                  double* __restrict__ V, int n,
+                                                  double* __restrict__ normsq) {
+  __shared__ double sh[16];
+  double part = 0.0;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < (size_t)n * n;
+       e += (size_t)gridDim.x * 256) {
+    V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+    part += A[e] * A[e];
+  }
+  part = block_sum_d(part, sh);
+  if (threadIdx.x == 0) normsq[blockIdx.x] = part;
+}
+
+__global__ __launch_bounds__(256) void k_jac_rows(double* __restrict__ A, int n, int step,
+                                                  const double* __restrict__ normsq, int nparts,
+                                                  double* __restrict__ prm,
+                                                  int* __restrict__ rotated) {
+  __shared__ double sc_[4];
+  const int k = blockIdx.x;
+  int p, q;
+  rr_pair(k, step, n, &p, &q);
+  if (threadIdx.x == 0) {
+    double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
+    if (q < n) {
+      double nsq = 0.0;
+      for (int i = 0; i < nparts; ++i) nsq += normsq[i];
+      const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+      const double apq = A[(size_t)p * n + q];
+      const double aa = fabs(apq);
+      const double eps = 1.1102230246251565e-16;
+      if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-16 * sqrt(nsq)) {
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + t * t);
+        s = t * c;
+        dp = app - t * apq;
+        dq = aqq + t * apq;
+        rotated[0] = 1;
+      }
+    }
+    sc_[0] = c;
+    sc_[1] = s;
+    prm[4 * k + 0] = c;
+    prm[4 * k + 1] = s;
+    prm[4 * k + 2] = dp;
+    prm[4 * k + 3] = dq;
+  }
+  __syncthreads();
+  const double c = sc_[0], s = sc_[1];
+  if (q >= n || s == 0.0) return;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
+    A[(size_t)p * n + j] = c * ap - s * aq;
+    A[(size_t)q * n + j] = s * ap + c * aq;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jac_cols(double* __restrict__ A, double* __restrict__ V,
+                                                  int n, int step,
+                                                  const double* __restrict__ prm) {
+  const int k = blockIdx.x;
+  int p, q;
+  rr_pair(k, step, n, &p, &q);
+  if (q >= n) return;
+  const double c = prm[4 * k + 0], s = prm[4 * k + 1];
+  if (s == 0.0) return;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
+  if (i == p) {
+    A[(size_t)p * n + p] = prm[4 * k + 2];
+    A[(size_t)p * n + q] = 0.0;
+  } else if (i == q) {
+    A[(size_t)q * n + p] = 0.0;
+    A[(size_t)q * n + q] = prm[4 * k + 3];
+  } else {
+    A[(size_t)i * n + p] = c * ap - s * aq;
+    A[(size_t)i * n + q] = s * ap + c * aq;
+  }
+  const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
+  V[(size_t)i * n + p] = c * vp - s * vq;
+  V[(size_t)i * n + q] = s * vp + c * vq;
+}
+
+__global__ void k_flag_clear(int* f) {
+  if (threadIdx.x == 0) f[0] = 0;
 }
 
 // Eigenvalues (diag of the converged A) sorted descending: perm and values.
@@ -619,13 +636,28 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
     return 3;
   }
   int* perm = misc_int(c);
-  int* sweeps = misc_int(c) + n + 1;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, c.st, A, V, n, kJacobiSweeps, sweeps);
+  int* flag = misc_int(c) + n + 1;
+  double* scratch = misc_dbl(c, n);  // [0..64): norm partials, then 4 per pair
+  double* normsq = scratch;
+  double* prm = scratch + 64;
+  const int half = ((n + 1) & ~1) / 2;
+  hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
+  int sweep = 0;
+  for (; sweep < kJacobiSweeps; ++sweep) {
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c.st, flag);
+    for (int step = 0; step < 2 * half - 1; ++step) {
+      hipLaunchKernelGGL(k_jac_rows, dim3(half), dim3(256), 0, c.st, A, n, step, normsq, 64, prm,
+                         flag);
+      hipLaunchKernelGGL(k_jac_cols, dim3(half, (n + 255) / 256), dim3(256), 0, c.st, A, V, n,
+                         step, prm);
+    }
+    int h = 0;
+    (void)hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    if (!h) break;
+  }
   hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);
-  int hs = 0;
-  (void)hipMemcpyAsync(&hs, sweeps, sizeof(int), hipMemcpyDeviceToHost, c.st);
-  (void)hipStreamSynchronize(c.st);
-  if (hs >= kJacobiSweeps) {
+  if (sweep >= kJacobiSweeps) {
     *msg = "Jacobi did not converge";
     return 1;
   }
