@@ -190,6 +190,45 @@ cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms);
 /* Release the handle (host memory only; the workspace stays the caller's). */
 cpd_status cpd_destroy(cpd_handle h);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent registrations of uneven sizes advanced together: every
+ * stage of an EM iteration (E-step passes, Fast M-step, sigma^2) runs as one
+ * launch whose workgroups walk a work list over all instances' tiles, the
+ * whole iteration is captured once as a HIP graph and replayed, and an
+ * instance that has converged (or hit its max_iter) drops out: its work items
+ * return at once.  Per-instance parameters follow cpd_params (Fast method,
+ * FP32, D = 3, FULL or TOPK eigen-prep).  Points are packed: instance i owns
+ * rows x_off[i] .. x_off[i+1]-1 of X_packed (float, device, sum M_i x 3) and
+ * likewise for Y with y_off (host arrays of B + 1 offsets).  One caller
+ * workspace of cpd_batch_workspace_size() bytes holds everything. */
+typedef struct cpd_batch_ctx* cpd_batch;
+
+cpd_status cpd_batch_workspace_size(int32_t B, const cpd_params* p, size_t* bytes);
+
+cpd_status cpd_batch_init(cpd_batch* hb, int32_t B, const cpd_params* p,
+                          const float* X_packed, const float* Y_packed,
+                          const int64_t* x_off, const int64_t* y_off,
+                          void* workspace, size_t workspace_bytes,
+                          void* hip_stream);
+
+/* Eigen-prep of every instance (Section III, eq. 16/19; host threads drive up
+ * to four streams), then, with tune != 0, a choice of the E-step split length
+ * among {512, 1024, 2048, 4096} points by timing two batched iterations of
+ * each, then the graph capture.  Leaves every instance at its start state. */
+cpd_status cpd_batch_prepare(cpd_batch hb, int32_t tune);
+
+/* Iterate all instances from their start state until each has converged or
+ * reached its max_iter.  X_out_packed (device, nullable) receives every Xt;
+ * res (host, nullable, B entries) gets per-instance iterations, convergence
+ * and sigma^2, with t_eig per instance and t_o = the whole batched run. */
+cpd_status cpd_batch_register(cpd_batch hb, float* X_out_packed, cpd_result* res);
+
+/* The split length the tuner chose and the per-candidate iteration times
+ * (ms, candidates 1024, 2048, 512, 4096; 0 when not tuned). */
+cpd_status cpd_batch_info(cpd_batch hb, int32_t* chunk, double* tune_ms);
+
+cpd_status cpd_batch_destroy(cpd_batch hb);
+
 const char* cpd_status_str(cpd_status s);
 const char* cpd_last_error(cpd_handle h);   /* h may be NULL: global message */
 

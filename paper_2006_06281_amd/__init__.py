@@ -37,6 +37,8 @@ EXPORTED = [
     "cpd_eig_export", "cpd_step", "cpd_register", "cpd_set_state",
     "cpd_get_state", "cpd_estep", "cpd_destroy", "cpd_status_str",
     "cpd_last_error", "cpd_abi_version", "cpd_build_info", "cpd_time_kernels",
+    "cpd_batch_workspace_size", "cpd_batch_init", "cpd_batch_prepare", "cpd_batch_register",
+    "cpd_batch_info", "cpd_batch_destroy",
 ]
 
 
@@ -99,6 +101,13 @@ def load_library(path: str = LIB_PATH):
         "cpd_estep": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "cpd_destroy": ([vp], ctypes.c_int),
         "cpd_time_kernels": ([vp, ctypes.c_int32, P(ctypes.c_double)], ctypes.c_int),
+        "cpd_batch_workspace_size": ([ctypes.c_int32, P(cpd_params), P(sz)], ctypes.c_int),
+        "cpd_batch_init": ([P(vp), ctypes.c_int32, P(cpd_params), vp, vp, P(ctypes.c_int64),
+                            P(ctypes.c_int64), vp, sz, vp], ctypes.c_int),
+        "cpd_batch_prepare": ([vp, ctypes.c_int32], ctypes.c_int),
+        "cpd_batch_register": ([vp, vp, P(cpd_result)], ctypes.c_int),
+        "cpd_batch_info": ([vp, P(ctypes.c_int32), P(ctypes.c_double)], ctypes.c_int),
+        "cpd_batch_destroy": ([vp], ctypes.c_int),
         "cpd_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "cpd_last_error": ([vp], ctypes.c_char_p),
         "cpd_abi_version": ([], ctypes.c_int32),
@@ -229,6 +238,80 @@ def cpd_time_kernels(h, reps=10) -> dict:
 def cpd_destroy(h):
     if h:
         load_library().cpd_destroy(h)
+
+
+# ------------------------------------------------------------------ batch
+def cpd_batch_workspace_size(params) -> int:
+    arr = (cpd_params * len(params))(*params)
+    out = ctypes.c_size_t(0)
+    _check(load_library().cpd_batch_workspace_size(len(params), arr, ctypes.byref(out)))
+    return out.value
+
+
+class BatchRegistration:
+    """Many independent Fast CPD registrations advanced together (FP32, D=3).
+
+    Xs, Ys: lists of CUDA float32 tensors (M_i x 3, N_i x 3); per-instance
+    keyword lists (beta, lam, w, ...) or scalars shared by all instances."""
+
+    def __init__(self, Xs, Ys, stream=None, **kw):
+        import torch
+        B = len(Xs)
+        self.B = B
+        per = []
+        for i in range(B):
+            a = {k: (v[i] if isinstance(v, (list, tuple)) else v) for k, v in kw.items()}
+            a.setdefault("precision", "fp32")
+            per.append(make_params(Xs[i].shape[0], Ys[i].shape[0], 3, **a))
+        self.params = per
+        self.Xp = torch.cat([x.float().reshape(-1, 3) for x in Xs]).contiguous()
+        self.Yp = torch.cat([y.float().reshape(-1, 3) for y in Ys]).contiguous()
+        xo = [0]
+        yo = [0]
+        for x, y in zip(Xs, Ys):
+            xo.append(xo[-1] + x.shape[0])
+            yo.append(yo[-1] + y.shape[0])
+        self.x_off = (ctypes.c_int64 * (B + 1))(*xo)
+        self.y_off = (ctypes.c_int64 * (B + 1))(*yo)
+        self._xo = xo
+        arr = (cpd_params * B)(*per)
+        self._arr = arr
+        n = cpd_batch_workspace_size(per)
+        self.workspace = torch.empty(max(n, 256), dtype=torch.uint8, device=self.Xp.device)
+        self.h = ctypes.c_void_p()
+        _check(load_library().cpd_batch_init(
+            ctypes.byref(self.h), B, arr, _ptr(self.Xp), _ptr(self.Yp), self.x_off, self.y_off,
+            _ptr(self.workspace), self.workspace.numel(), _stream_ptr(stream)))
+
+    def prepare(self, tune=True):
+        _check(load_library().cpd_batch_prepare(self.h, int(bool(tune))))
+        return self
+
+    def info(self):
+        c = ctypes.c_int32(0)
+        t = (ctypes.c_double * 4)()
+        _check(load_library().cpd_batch_info(self.h, ctypes.byref(c), t))
+        return c.value, dict(zip((1024, 2048, 512, 4096), list(t)))
+
+    def register(self):
+        import torch
+        out = torch.empty_like(self.Xp)
+        res = (cpd_result * self.B)()
+        _check(load_library().cpd_batch_register(self.h, _ptr(out), res),
+               ok=(CPD_OK, CPD_NOT_CONVERGED))
+        Xt = [out[self._xo[i]:self._xo[i + 1]] for i in range(self.B)]
+        return Xt, list(res)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().cpd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------- convenience

@@ -3,7 +3,9 @@
 // launches inside one EM iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -55,12 +57,23 @@ int kcap_of(const cpd_params& p) {
   return p.K;
 }
 
+// A batch member sizes its E-step partials for a fixed split length
+// (batch_chunk points per split) instead of the single-instance plan.
+void chunk_plan(int M, int N, int chunk, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
+  *chunkA = std::min(chunk, (M + 3) & ~3);
+  *splitsA = (M + *chunkA - 1) / *chunkA;
+  *chunkB = std::min(chunk, (N + 3) & ~3);
+  *splitsB = (N + *chunkB - 1) / *chunkB;
+}
+
 template <typename T>
-Layout make_layout(const cpd_params& p) {
+Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   Layout L;
   const size_t M = (size_t)p.M, N = (size_t)p.N;
   const size_t p4 = sizeof(P4<T>);
-  if (p.precision == CPD_PREC_BF16X)
+  if (batch_chunk > 0)
+    chunk_plan(p.M, p.N, batch_chunk, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+  else if (p.precision == CPD_PREC_BF16X)
     bfx_splits(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
   else
     estep_splits<T>(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
@@ -108,8 +121,9 @@ Layout make_layout(const cpd_params& p) {
   return L;
 }
 
-Layout layout_for(const cpd_params& p) {
-  return p.precision == CPD_PREC_FP64 ? make_layout<double>(p) : make_layout<float>(p);
+Layout layout_for(const cpd_params& p, int batch_chunk = 0) {
+  return p.precision == CPD_PREC_FP64 ? make_layout<double>(p, batch_chunk)
+                                      : make_layout<float>(p, batch_chunk);
 }
 
 }  // namespace
@@ -693,6 +707,434 @@ cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms) {
   if (r != CPD_OK) return r;
   if (reps < 1 || !out_ms) return fail(h, CPD_E_ARG, "reps must be >= 1 and out_ms non-NULL");
   return is_f64(h) ? time_impl<double>(h, reps, out_ms) : time_impl<float>(h, reps, out_ms);
+}
+
+// ---------------------------------------------------------------- batched
+}  // extern "C"
+
+namespace {
+constexpr int kBatchChunks[] = {1024, 2048, 512, 4096};  // candidates; [0] sizes the partials
+constexpr int kBatchSmallestChunk = 512;
+
+struct BatchHeader {
+  size_t desc = 0, items = 0, done = 0, end = 0;
+  size_t item_cap = 0;
+};
+
+size_t batch_item_capacity(int B, const cpd_params* p) {
+  // the largest item count of any candidate plan (the smallest split length)
+  size_t n = 0;
+  for (int i = 0; i < B; ++i) {
+    const int M = p[i].M, N = p[i].N;
+    const int c = kBatchSmallestChunk;
+    const size_t sA = (M + c - 1) / c, sB = (N + c - 1) / c;
+    const size_t tA = (N + 1023) / 1024, tB = (M + 1023) / 1024;
+    n += (M + N + 255) / 256;                        // prescale
+    n += tA * sA + tB * sB;                          // colsum, rowsum
+    n += (N + 255) / 256 + (M + 255) / 256;          // merges
+    n += 4;                                          // fix-up
+    n += (size_t)((M + 127) / 128) * 8;              // tpart (chunks x k groups)
+    n += (size_t)eig_topk_max_cols();                // tmerge
+    n += (M + 63) / 64 + (M + 255) / 256 + 1;        // apply, sigpart, final
+  }
+  return n;
+}
+
+BatchHeader batch_header(int B, const cpd_params* p) {
+  BatchHeader h;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += (b + 255) & ~(size_t)255;
+    return o;
+  };
+  h.desc = take((size_t)B * sizeof(InstDesc));
+  h.item_cap = batch_item_capacity(B, p);
+  h.items = take(h.item_cap * sizeof(int4));
+  h.done = take(256);
+  h.end = off;
+  return h;
+}
+
+cpd_status validate_batch(int B, const cpd_params* p) {
+  if (B < 1 || !p) return fail(nullptr, CPD_E_ARG, "B must be >= 1 and params non-NULL");
+  for (int i = 0; i < B; ++i) {
+    const cpd_status v = validate(&p[i]);
+    if (v != CPD_OK) return v;
+    if (p[i].method != CPD_METHOD_FAST || p[i].precision != CPD_PREC_FP32 || p[i].D != 3 ||
+        p[i].eig_mode == CPD_EIG_IMPORT)
+      return fail(nullptr, CPD_E_UNSUPPORTED,
+                  "batched registration runs Fast CPD, FP32, D = 3, FULL or TOPK eigen-prep");
+  }
+  return CPD_OK;
+}
+
+}  // namespace
+
+struct cpd_batch_ctx {
+  int B = 0;
+  std::vector<cpd_params> p;
+  std::vector<cpd_ctx*> inst;
+  std::vector<size_t> inst_off;
+  std::vector<int64_t> x_off, y_off;
+  BatchHeader hd;
+  char* ws = nullptr;
+  hipStream_t user_st = nullptr, st = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  BatchItems items{};
+  int chunk = kBatchChunks[0];
+  bool prepared = false;
+  std::string err;
+  double tune_ms[4] = {0, 0, 0, 0};
+  ~cpd_batch_ctx() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto* h : inst) delete h;
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+cpd_status bfail(cpd_batch_ctx* b, cpd_status s, const std::string& m) {
+  g_last_error = m;
+  if (b) b->err = m;
+  return s;
+}
+
+// Descriptors and work lists for split length `chunk`; uploads both.
+cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
+  std::vector<InstDesc> d(b->B);
+  std::vector<int4> pre, cs, cm, fx, rs, rm, tp, tm, ap, sp, in;
+  int maxK = 1;
+  for (int i = 0; i < b->B; ++i) maxK = std::max(maxK, b->inst[i]->K);
+  const int kt = maxK <= 256 ? 1 : (maxK <= 512 ? 2 : 4);
+  for (int i = 0; i < b->B; ++i) {
+    cpd_ctx* h = b->inst[i];
+    const Layout& L = h->L;
+    InstDesc& D = d[i];
+    D.X = h->at<P4<float>>(L.X);
+    D.Xt = h->at<P4<float>>(L.Xt);
+    D.Xnew = h->at<P4<float>>(L.Xnew);
+    D.Y = h->at<P4<float>>(L.Y);
+    D.W = h->at<P4<float>>(L.W);
+    D.xs = h->at<P4<float>>(L.xs);
+    D.ys = h->at<P4<float>>(L.ys);
+    D.Yt = h->at<P4<float>>(L.Yt);
+    D.P1 = h->at<float>(L.P1);
+    D.tbar = h->at<float>(L.tbar);
+    D.partA = h->at<float>(L.partA);
+    D.partB = h->at<float>(L.partB);
+    D.badcols = h->at<int>(L.badcols);
+    D.badrows = h->at<int>(L.badrows);
+    D.llpart = h->at<double>(L.llpart);
+    D.sigpart = h->at<double>(L.sigpart);
+    D.U = h->at<float>(L.U);
+    D.lam = h->at<double>(L.lam);
+    D.tpart = h->at<float>(L.tpart);
+    D.GT = h->at<P4<float>>(L.GT);
+    D.HT = h->at<P4<float>>(L.HT);
+    D.sc = h->sc();
+    D.M = h->p.M;
+    D.N = h->p.N;
+    D.K = h->K;
+    chunk_plan(D.M, D.N, chunk, &D.splitsA, &D.chunkA, &D.splitsB, &D.chunkB);
+    if (D.splitsA > L.splitsA || D.splitsB > L.splitsB)
+      return bfail(b, CPD_E_WORKSPACE, "batch split plan exceeds the partial buffers");
+    D.mrows = L.mrows;
+    D.mchunks = L.mchunks;
+    D.sigblocks = sigma2_blocks<float>(D.M);
+    D.llblocks = (D.N + 255) / 256;
+    D.w = h->p.w;
+    D.lmbda = h->p.lambda;
+    for (int x = 0; x < (D.M + D.N + 255) / 256; ++x) pre.push_back(make_int4(i, x, 0, 0));
+    for (int t = 0; t < (D.N + 1023) / 1024; ++t)
+      for (int s = 0; s < D.splitsA; ++s) cs.push_back(make_int4(i, t, s, 0));
+    for (int x = 0; x < (D.N + 255) / 256; ++x) cm.push_back(make_int4(i, x, 0, 0));
+    for (int x = 0; x < 4; ++x) fx.push_back(make_int4(i, x, 4, 0));
+    for (int t = 0; t < (D.M + 1023) / 1024; ++t)
+      for (int s = 0; s < D.splitsB; ++s) rs.push_back(make_int4(i, t, s, 0));
+    for (int x = 0; x < (D.M + 255) / 256; ++x) rm.push_back(make_int4(i, x, 0, 0));
+    for (int c = 0; c < D.mchunks; ++c)
+      for (int g = 0; g < (D.K + 256 * kt - 1) / (256 * kt); ++g) tp.push_back(make_int4(i, c, g, 0));
+    for (int k = 0; k < D.K; ++k) tm.push_back(make_int4(i, k, 0, 0));
+    for (int x = 0; x < (D.M + 63) / 64; ++x) ap.push_back(make_int4(i, x, 0, 0));
+    for (int x = 0; x < D.sigblocks; ++x) sp.push_back(make_int4(i, x, 0, 0));
+    in.push_back(make_int4(i, 0, 0, 0));
+  }
+  std::vector<int4> all;
+  std::vector<const std::vector<int4>*> lists = {&pre, &cs, &cm, &fx, &rs, &rm, &tp, &tm, &ap, &sp, &in};
+  for (auto* l : lists) all.insert(all.end(), l->begin(), l->end());
+  if (all.size() > b->hd.item_cap) return bfail(b, CPD_E_WORKSPACE, "batch work list too large");
+  int4* dev = reinterpret_cast<int4*>(b->ws + b->hd.items);
+  size_t o = 0;
+  const int4** ptrs[] = {&b->items.prescale, &b->items.colsum, &b->items.colmerge, &b->items.fix,
+                         &b->items.rowsum, &b->items.rowmerge, &b->items.tpart, &b->items.tmerge,
+                         &b->items.apply, &b->items.sigpart, &b->items.inst};
+  int* counts[] = {&b->items.n_prescale, &b->items.n_colsum, &b->items.n_colmerge, &b->items.n_fix,
+                   &b->items.n_rowsum, &b->items.n_rowmerge, &b->items.n_tpart, &b->items.n_tmerge,
+                   &b->items.n_apply, &b->items.n_sigpart, &b->items.n_inst};
+  for (size_t q = 0; q < lists.size(); ++q) {
+    *ptrs[q] = dev + o;
+    *counts[q] = (int)lists[q]->size();
+    o += lists[q]->size();
+  }
+  b->items.kt = kt;
+  b->items.maxK = maxK;
+  b->items.done_count = reinterpret_cast<int*>(b->ws + b->hd.done);
+  InstDesc* dd = reinterpret_cast<InstDesc*>(b->ws + b->hd.desc);
+  HIPCHK(nullptr, hipMemcpyAsync(dd, d.data(), sizeof(InstDesc) * d.size(), hipMemcpyHostToDevice, b->st));
+  HIPCHK(nullptr, hipMemcpyAsync(dev, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice, b->st));
+  HIPCHK(nullptr, hipStreamSynchronize(b->st));
+  b->chunk = chunk;
+  return CPD_OK;
+}
+
+const InstDesc* batch_desc(const cpd_batch_ctx* b) {
+  return reinterpret_cast<const InstDesc*>(b->ws + b->hd.desc);
+}
+
+__global__ void kb_reset(const InstDesc* __restrict__ d, int B, int restart) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  DevScalars* sc = d[i].sc;
+  if (restart) {
+    sc->sigma2 = sc->sigma2_start;
+    sc->nonfinite = 0;
+  }
+  sc->iter = 0;
+  sc->done = 0;
+  sc->converged = 0;
+}
+
+// Back to the start state (Xt = X, sigma^2 = sigma^2_0) for every instance.
+cpd_status batch_restart(cpd_batch_ctx* b) {
+  for (int i = 0; i < b->B; ++i) {
+    cpd_ctx* h = b->inst[i];
+    HIPCHK(nullptr, hipMemcpyAsync(h->ws + h->L.Xt.off, h->ws + h->L.X.off, h->L.X.bytes,
+                                   hipMemcpyDeviceToDevice, b->st));
+  }
+  hipLaunchKernelGGL(kb_reset, dim3((b->B + 255) / 256), dim3(256), 0, b->st, batch_desc(b), b->B, 1);
+  HIPCHK(nullptr, hipGetLastError());
+  return CPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpd_status cpd_batch_workspace_size(int32_t B, const cpd_params* p, size_t* bytes) {
+  if (!bytes) return fail(nullptr, CPD_E_ARG, "bytes is NULL");
+  const cpd_status v = validate_batch(B, p);
+  if (v != CPD_OK) return v;
+  size_t total = batch_header(B, p).end;
+  for (int i = 0; i < B; ++i) total += (layout_for(p[i], kBatchSmallestChunk).total + 255) & ~(size_t)255;
+  *bytes = total;
+  return CPD_OK;
+}
+
+cpd_status cpd_batch_init(cpd_batch* out, int32_t B, const cpd_params* p, const float* X_packed,
+                          const float* Y_packed, const int64_t* x_off, const int64_t* y_off,
+                          void* workspace, size_t bytes, void* hip_stream) {
+  if (!out) return fail(nullptr, CPD_E_ARG, "batch handle pointer is NULL");
+  *out = nullptr;
+  const cpd_status v = validate_batch(B, p);
+  if (v != CPD_OK) return v;
+  if (!X_packed || !Y_packed || !x_off || !y_off)
+    return fail(nullptr, CPD_E_ARG, "packed points and offsets are required");
+  for (int i = 0; i < B; ++i) {
+    if (x_off[i + 1] - x_off[i] != p[i].M || y_off[i + 1] - y_off[i] != p[i].N || x_off[i] < 0 ||
+        y_off[i] < 0)
+      return fail(nullptr, CPD_E_ARG, "offsets do not match M and N of instance " + std::to_string(i));
+  }
+  size_t need = 0;
+  const cpd_status sz = cpd_batch_workspace_size(B, p, &need);
+  if (sz != CPD_OK) return sz;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 256 || bytes < need)
+    return fail(nullptr, CPD_E_WORKSPACE, "batch workspace missing, misaligned or too small");
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  auto* b = new (std::nothrow) cpd_batch_ctx();
+  if (!b) return fail(nullptr, CPD_E_DEVICE, "out of host memory");
+  b->B = B;
+  b->p.assign(p, p + B);
+  b->x_off.assign(x_off, x_off + B + 1);
+  b->y_off.assign(y_off, y_off + B + 1);
+  b->ws = static_cast<char*>(workspace);
+  b->user_st = static_cast<hipStream_t>(hip_stream);
+  b->hd = batch_header(B, p);
+  hipError_t e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(nullptr, e, "hipStreamCreateWithFlags");
+  }
+  size_t off = b->hd.end;
+  for (int i = 0; i < B; ++i) {
+    auto* h = new (std::nothrow) cpd_ctx();
+    if (!h) {
+      delete b;
+      return fail(nullptr, CPD_E_DEVICE, "out of host memory");
+    }
+    h->p = p[i];
+    h->L = layout_for(p[i], kBatchSmallestChunk);
+    h->ws = b->ws + off;
+    h->st = b->st;
+    b->inst.push_back(h);
+    b->inst_off.push_back(off);
+    off += (h->L.total + 255) & ~(size_t)255;
+    const cpd_status s = init_impl<float>(h, X_packed + 3 * x_off[i], Y_packed + 3 * y_off[i]);
+    if (s != CPD_OK) {
+      const std::string m = h->err;
+      delete b;
+      return fail(nullptr, s, m);
+    }
+  }
+  *out = b;
+  return CPD_OK;
+}
+
+cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
+  if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
+  // per-instance eigen-prep, four host threads on streams of their own
+  const int nt = std::min(4, b->B);
+  std::vector<hipStream_t> sts(nt, nullptr);
+  for (auto& s : sts) HIPCHK(nullptr, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  std::vector<cpd_status> rc(b->B, CPD_OK);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      for (int i = t; i < b->B; i += nt) {
+        cpd_ctx* h = b->inst[i];
+        h->st = sts[t];
+        rc[i] = prepare_impl<float>(h, nullptr, nullptr, nullptr);
+        h->st = b->st;
+        if (rc[i] != CPD_OK) break;
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (auto& s : sts) (void)hipStreamDestroy(s);
+  for (int i = 0; i < b->B; ++i)
+    if (rc[i] != CPD_OK) return bfail(b, rc[i], "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+  // pick the split length: time two batched iterations per candidate
+  int best = kBatchChunks[0];
+  if (tune) {
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIPCHK(nullptr, hipEventCreate(&e0));
+    HIPCHK(nullptr, hipEventCreate(&e1));
+    for (int c = 0; c < 4; ++c) {
+      const cpd_status s = batch_build(b, kBatchChunks[c]);
+      if (s != CPD_OK) return s;
+      hipLaunchKernelGGL(kb_reset, dim3((b->B + 255) / 256), dim3(256), 0, b->st, batch_desc(b), b->B, 0);
+      batch_iteration_launch(batch_desc(b), b->items, b->st);  // warm
+      (void)hipEventRecord(e0, b->st);
+      for (int r = 0; r < 2; ++r) batch_iteration_launch(batch_desc(b), b->items, b->st);
+      (void)hipEventRecord(e1, b->st);
+      HIPCHK(nullptr, hipEventSynchronize(e1));
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      b->tune_ms[c] = ms / 2;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = kBatchChunks[c];
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  cpd_status s = batch_build(b, best);
+  if (s != CPD_OK) return s;
+  s = batch_restart(b);
+  if (s != CPD_OK) return s;
+  // capture one batched iteration (every stage, every instance) as a graph
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  HIPCHK(nullptr, hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+  batch_iteration_launch(batch_desc(b), b->items, b->st);
+  HIPCHK(nullptr, hipStreamEndCapture(b->st, &b->graph));
+  HIPCHK(nullptr, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  HIPCHK(nullptr, hipStreamSynchronize(b->st));
+  b->prepared = true;
+  return CPD_OK;
+}
+
+cpd_status cpd_batch_register(cpd_batch b, float* X_out_packed, cpd_result* res) {
+  if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
+  if (!b->prepared) return bfail(b, CPD_E_STATE, "cpd_batch_prepare must run first");
+  // order after the caller's stream
+  hipEvent_t ev0, ev1;
+  HIPCHK(nullptr, hipEventCreate(&ev0));
+  HIPCHK(nullptr, hipEventCreate(&ev1));
+  (void)hipEventRecord(ev0, b->user_st);
+  HIPCHK(nullptr, hipStreamWaitEvent(b->st, ev0, 0));
+  const cpd_status rs = batch_restart(b);
+  if (rs != CPD_OK) return rs;
+  int max_iter = 1;
+  for (auto& q : b->p) max_iter = std::max(max_iter, q.max_iter);
+  hipEvent_t t0, t1;
+  HIPCHK(nullptr, hipEventCreate(&t0));
+  HIPCHK(nullptr, hipEventCreate(&t1));
+  (void)hipEventRecord(t0, b->st);
+  int done = 0, iters = 0;
+  while (iters < max_iter && done < b->B) {
+    const int r = std::min(8, max_iter - iters);
+    for (int k = 0; k < r; ++k) HIPCHK(nullptr, hipGraphLaunch(b->exec, b->st));
+    iters += r;
+    HIPCHK(nullptr, hipMemcpyAsync(&done, b->items.done_count, sizeof(int), hipMemcpyDeviceToHost, b->st));
+    HIPCHK(nullptr, hipStreamSynchronize(b->st));
+  }
+  (void)hipEventRecord(t1, b->st);
+  HIPCHK(nullptr, hipEventSynchronize(t1));
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, t0, t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  std::vector<DevScalars> s(b->B);
+  for (int i = 0; i < b->B; ++i) {
+    cpd_ctx* h = b->inst[i];
+    HIPCHK(nullptr, hipMemcpyAsync(&s[i], h->sc(), sizeof(DevScalars), hipMemcpyDeviceToHost, b->st));
+    if (X_out_packed)
+      unpack_launch<float>(h->at<P4<float>>(h->L.Xt), X_out_packed + 3 * b->x_off[i], h->p.M, 3, b->st);
+  }
+  HIPCHK(nullptr, hipGetLastError());
+  (void)hipEventRecord(ev1, b->st);
+  HIPCHK(nullptr, hipStreamWaitEvent(b->user_st, ev1, 0));
+  HIPCHK(nullptr, hipStreamSynchronize(b->st));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  bool all = true, bad = false;
+  for (int i = 0; i < b->B; ++i) {
+    if (res) {
+      res[i].iters = s[i].iter;
+      res[i].converged = s[i].converged;
+      res[i].sigma2 = s[i].sigma2;
+      res[i].t_c = 0.0;
+      res[i].t_iter = 0.0;
+      res[i].t_eig = b->inst[i]->t_eig;
+      res[i].t_o = ms * 1e-3;  // the whole batched run
+    }
+    all = all && s[i].converged;
+    bad = bad || s[i].nonfinite;
+  }
+  if (bad) return bfail(b, CPD_E_NUMERIC, "an instance's sigma^2 became non-finite");
+  return all ? CPD_OK : CPD_NOT_CONVERGED;
+}
+
+cpd_status cpd_batch_info(cpd_batch b, int32_t* chunk, double* tune_ms) {
+  if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
+  if (chunk) *chunk = b->chunk;
+  if (tune_ms)
+    for (int c = 0; c < 4; ++c) tune_ms[c] = b->tune_ms[c];
+  return CPD_OK;
+}
+
+cpd_status cpd_batch_destroy(cpd_batch b) {
+  delete b;
+  return CPD_OK;
 }
 
 cpd_status cpd_destroy(cpd_handle h) {

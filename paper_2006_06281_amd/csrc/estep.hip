@@ -31,15 +31,15 @@ namespace fcpd {
 
 // ---------------------------------------------------------------- prescale
 template <typename T>
-__global__ __launch_bounds__(256) void k_prescale(const P4<T>* __restrict__ Xt,
+__device__ __forceinline__ void prescale_body(const P4<T>* __restrict__ Xt,
                                                   const P4<T>* __restrict__ Y,
                                                   P4<T>* __restrict__ xs,
                                                   P4<T>* __restrict__ ys, int M, int N,
-                                                  DevScalars* sc, int gate) {
+                                                  DevScalars* sc, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const double sk = sqrt(kappa_of(sc->sigma2));
   const T s = (T)sk;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx_ * blockDim.x + threadIdx.x;
   if (i == 0) {
     sc->bad_cols = 0;
     sc->bad_rows = 0;
@@ -51,6 +51,15 @@ __global__ __launch_bounds__(256) void k_prescale(const P4<T>* __restrict__ Xt,
     P4<T> p = Y[i - M];
     ys[i - M] = P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prescale(const P4<T>* __restrict__ Xt,
+                                                  const P4<T>* __restrict__ Y,
+                                                  P4<T>* __restrict__ xs,
+                                                  P4<T>* __restrict__ ys, int M, int N,
+                                                  DevScalars* sc, int gate) {
+  prescale_body<T>(Xt, Y, xs, ys, M, N, sc, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ------------------------------------------------------------------ pass A
@@ -72,15 +81,15 @@ __device__ __forceinline__ T sq3(const P4<T>& a, T bx, T by, T bz, T init) {
 // part[blockIdx.y * N + n] = sum over this split's model points of
 // 2^(-(|y^_n - x^_m|^2 + ref)).
 template <typename T, int D, int NB>
-__global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
+__device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int m_chunk, const DevScalars* __restrict__ sc,
-                                                double w, T* __restrict__ part, int gate) {
+                                                double w, T* __restrict__ part, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
   const T ref = (T)fmax(l2c, kRefFloor);
-  const int n0 = blockIdx.x * (256 * NB) + threadIdx.x;
-  const int m0 = blockIdx.y * m_chunk;
+  const int n0 = bx_ * (256 * NB) + threadIdx.x;
+  const int m0 = by_ * m_chunk;
   const int m1 = min(M, m0 + m_chunk);
   T yx[NB], yy[NB], yz[NB], s[NB];
 #pragma unroll
@@ -112,24 +121,32 @@ __global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int n = n0 + j * 256;
-    if (n < N) part[(size_t)blockIdx.y * N + n] = s[j];
+    if (n < N) part[(size_t)by_ * N + n] = s[j];
   }
+}
+
+template <typename T, int D, int NB>
+__global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys, int M, int N,
+                                                int m_chunk, const DevScalars* __restrict__ sc,
+                                                double w, T* __restrict__ part, int gate) {
+  colsum_body<T, D, NB>(xs, ys, M, N, m_chunk, sc, w, part, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // L_n = ref + log2(sum_splits part + 2^(log2 c - ref)) into ys[n].w; flags
 // columns that need the exact path; per-block partial of sum_n ln d_n.
 template <typename T>
-__global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, int splits,
+__device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int splits,
                                                   P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
-                                                  double* __restrict__ llpart, int gate) {
+                                                  double* __restrict__ llpart, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
   const double refd = fmax(l2c, kRefFloor);
   const T ref = (T)refd;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = bx_ * blockDim.x + threadIdx.x;
   double ln_d = 0.0;
   if (n < N) {
     T s = (T)0;
@@ -146,21 +163,30 @@ __global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, in
     ln_d = (double)L * kLn2;
   }
   const double b = block_sum_d(ln_d, sh);
-  if (threadIdx.x == 0) llpart[blockIdx.x] = b;
+  if (threadIdx.x == 0) llpart[bx_] = b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, int splits,
+                                                  P4<T>* __restrict__ ys, T* __restrict__ logd_out,
+                                                  int M, int N, int D, DevScalars* sc, double w,
+                                                  int* __restrict__ badlist,
+                                                  double* __restrict__ llpart, int gate) {
+  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Exact pass A for the flagged columns: two sweeps over all model points,
 // the first for the column maximum, the second for the shifted sum.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
+__device__ __forceinline__ void colfix_body(const P4<T>* __restrict__ xs,
                                                 P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                 int M, int N, DevScalars* sc, double w,
-                                                const int* __restrict__ badlist, int gate) {
+                                                const int* __restrict__ badlist, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const int nbad = sc->bad_cols;
   const int lane = threadIdx.x & 63;
-  const int wglobal = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int wglobal = (bx_ * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gx_ * blockDim.x) >> 6;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
   for (int b = wglobal; b < nbad; b += nwaves) {
     const int n = badlist[b];
@@ -181,17 +207,25 @@ __global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
   }
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
+                                                P4<T>* __restrict__ ys, T* __restrict__ logd_out,
+                                                int M, int N, DevScalars* sc, double w,
+                                                const int* __restrict__ badlist, int gate) {
+  colfix_body<T, D>(xs, ys, logd_out, M, N, sc, w, badlist, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // ------------------------------------------------------------------ pass B
 // part layout: [split][5][M]: r, sum p dx, sum p dy, sum p dz, sum p d2
 // (prescaled differences y^_n - x^_m).
 template <typename T, int D, int NB>
-__global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
+__device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int n_chunk, const DevScalars* __restrict__ sc,
-                                                T* __restrict__ part, int gate) {
+                                                T* __restrict__ part, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const int m0 = blockIdx.x * (256 * NB) + threadIdx.x;
-  const int nb = blockIdx.y * n_chunk;
+  const int m0 = bx_ * (256 * NB) + threadIdx.x;
+  const int nb = by_ * n_chunk;
   const int ne = min(N, nb + n_chunk);
   T ax[NB], ay[NB], az[NB], r[NB], px[NB], py[NB], pz[NB], t[NB];
 #pragma unroll
@@ -226,7 +260,7 @@ __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
       t[j] = fma(e, d2, t[j]);
     }
   }
-  T* base = part + (size_t)blockIdx.y * 5 * M;
+  T* base = part + (size_t)by_ * 5 * M;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int m = m0 + j * 256;
@@ -240,18 +274,26 @@ __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
   }
 }
 
+template <typename T, int D, int NB>
+__global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys, int M, int N,
+                                                int n_chunk, const DevScalars* __restrict__ sc,
+                                                T* __restrict__ part, int gate) {
+  rowsum_body<T, D, NB>(xs, ys, M, N, n_chunk, sc, part, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Row merge: P1_m = r_m, Yt_m = xt_m + (sum p (y - xt)) / r_m, tbar_m.
 // relative = 1: the sums hold p (y^ - x^) (direct-difference pass B);
 // relative = 0: they hold p y^ (absolute, the matrix-core pass B).
 template <typename T>
-__global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, int splits,
+__device__ __forceinline__ void rowmerge_body(const T* __restrict__ part, int splits,
                                                   const P4<T>* __restrict__ Xt,
                                                   P4<T>* __restrict__ Yt, T* __restrict__ P1,
                                                   T* __restrict__ tbar, int M,
                                                   DevScalars* sc, int* __restrict__ badlist,
-                                                  int relative, int gate) {
+                                                  int relative, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = bx_ * blockDim.x + threadIdx.x;
   if (m >= M) return;
   const double kap = kappa_of(sc->sigma2);
   T r = 0, px = 0, py = 0, pz = 0, t = 0;
@@ -277,22 +319,32 @@ __global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, in
   tbar[m] = t * inv * (T)(1.0 / kap);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, int splits,
+                                                  const P4<T>* __restrict__ Xt,
+                                                  P4<T>* __restrict__ Yt, T* __restrict__ P1,
+                                                  T* __restrict__ tbar, int M,
+                                                  DevScalars* sc, int* __restrict__ badlist,
+                                                  int relative, int gate) {
+  rowmerge_body<T>(part, splits, Xt, Yt, P1, tbar, M, sc, badlist, relative, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Exact pass B for flagged rows: shift by the row maximum of
 // -(|y^_n - x^_m|^2 + L_n), then the same sums.  P1 keeps its true (tiny or
 // zero) value; Yt and tbar come from the shifted, well-scaled sums.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
+__device__ __forceinline__ void rowfix_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys,
                                                 const P4<T>* __restrict__ Xt,
                                                 P4<T>* __restrict__ Yt, T* __restrict__ P1,
                                                 T* __restrict__ tbar, int M, int N,
                                                 DevScalars* sc, const int* __restrict__ badlist,
-                                                int gate) {
+                                                int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const int nbad = sc->bad_rows;
   const int lane = threadIdx.x & 63;
-  const int wglobal = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int wglobal = (bx_ * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gx_ * blockDim.x) >> 6;
   const double kap = kappa_of(sc->sigma2);
   for (int b = wglobal; b < nbad; b += nwaves) {
     const int m = badlist[b];
@@ -331,6 +383,17 @@ __global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
       tbar[m] = (T)(t / r / kap);
     }
   }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
+                                                const P4<T>* __restrict__ ys,
+                                                const P4<T>* __restrict__ Xt,
+                                                P4<T>* __restrict__ Yt, T* __restrict__ P1,
+                                                T* __restrict__ tbar, int M, int N,
+                                                DevScalars* sc, const int* __restrict__ badlist,
+                                                int gate) {
+  rowfix_body<T, D>(xs, ys, Xt, Yt, P1, tbar, M, N, sc, badlist, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ------------------------------------------------------------- launchers
@@ -411,6 +474,65 @@ void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* ch
   };
   plan(N, M, splitsA, chunkA);
   plan(M, N, splitsB, chunkB);
+}
+
+// ------------------------------------------------------------ batched
+// The same bodies driven by a work list over every instance of a batch.
+__global__ __launch_bounds__(256) void kb_prescale(const InstDesc* __restrict__ d,
+                                                   const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  prescale_body<float>(D.Xt, D.Y, D.xs, D.ys, D.M, D.N, D.sc, 1, it.y, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_colsum(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkA, D.sc, D.w, D.partA, 1, it.y, it.z, 0);
+}
+__global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ d,
+                                                   const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
+                       D.badcols, D.llpart, 1, it.y, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_colfix(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  colfix_body<float, 3>(D.xs, D.ys, (float*)nullptr, D.M, D.N, D.sc, D.w, D.badcols, 1, it.y, 0,
+                        it.z);
+}
+__global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkB, D.sc, D.partB, 1, it.y, it.z, 0);
+}
+__global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ d,
+                                                   const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  rowmerge_body<float>(D.partB, D.splitsB, D.Xt, D.Yt, D.P1, D.tbar, D.M, D.sc, D.badrows, 1, 1,
+                       it.y, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_rowfix(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  rowfix_body<float, 3>(D.xs, D.ys, D.Xt, D.Yt, D.P1, D.tbar, D.M, D.N, D.sc, D.badrows, 1, it.y,
+                        0, it.z);
+}
+
+void batch_estep_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
+  hipLaunchKernelGGL(kb_prescale, dim3(it.n_prescale), dim3(256), 0, st, d, it.prescale);
+  hipLaunchKernelGGL(kb_colsum, dim3(it.n_colsum), dim3(256), 0, st, d, it.colsum);
+  hipLaunchKernelGGL(kb_colmerge, dim3(it.n_colmerge), dim3(256), 0, st, d, it.colmerge);
+  hipLaunchKernelGGL(kb_colfix, dim3(it.n_fix), dim3(256), 0, st, d, it.fix);
+  hipLaunchKernelGGL(kb_rowsum, dim3(it.n_rowsum), dim3(256), 0, st, d, it.rowsum);
+  hipLaunchKernelGGL(kb_rowmerge, dim3(it.n_rowmerge), dim3(256), 0, st, d, it.rowmerge);
+  hipLaunchKernelGGL(kb_rowfix, dim3(it.n_fix), dim3(256), 0, st, d, it.fix);
 }
 
 template void estep_launch<float>(const EStepArgs<float>&, hipStream_t);

@@ -105,3 +105,51 @@ namespace fcpd {
 // E-step with squared distances from bf16 matrix-core products.
 void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st);
 }  // namespace fcpd
+
+namespace fcpd {
+// ------------------------------------------------------------------ batched
+// One registration of a batch, as the batched kernels see it (FP32, D = 3).
+struct InstDesc {
+  const P4<float>* X;
+  P4<float>* Xt;
+  P4<float>* Xnew;
+  const P4<float>* Y;
+  P4<float>* W;
+  P4<float>* xs;
+  P4<float>* ys;
+  P4<float>* Yt;
+  float* P1;
+  float* tbar;
+  float* partA;
+  float* partB;
+  int* badcols;
+  int* badrows;
+  double* llpart;
+  double* sigpart;
+  const float* U;
+  const double* lam;
+  float* tpart;
+  P4<float>* GT;
+  P4<float>* HT;
+  DevScalars* sc;
+  int M, N, K;
+  int splitsA, chunkA, splitsB, chunkB;
+  int mchunks, mrows, sigblocks, llblocks;
+  double w, lmbda;
+};
+
+// Work items: (instance, block index x, block index y, unused), one per
+// workgroup of the corresponding stage.
+struct BatchItems {
+  const int4 *prescale, *colsum, *colmerge, *fix, *rowsum, *rowmerge, *tpart, *tmerge, *apply,
+      *sigpart, *inst;
+  int n_prescale, n_colsum, n_colmerge, n_fix, n_rowsum, n_rowmerge, n_tpart, n_tmerge, n_apply,
+      n_sigpart, n_inst;
+  int kt;             // eigenpairs per thread in k_tpart (from the largest K)
+  int maxK;
+  int* done_count;    // device counter of finished instances
+};
+void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t st);
+void batch_estep_launch(const InstDesc* d, const BatchItems& it, hipStream_t st);
+void batch_mstep_sigma_launch(const InstDesc* d, const BatchItems& it, hipStream_t st);
+}  // namespace fcpd

@@ -19,14 +19,14 @@ namespace fcpd {
 // sum_m U[m][k] R_m for k = k0 + t + 256 j, j < KT; R_m = Yt_m - X_m is uniform
 // across the block (scalar loads).  U rows are read with coalesced loads.
 template <typename T, int KT>
-__global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
+__device__ __forceinline__ void tpart_body(const P4<T>* __restrict__ X,
                                                const P4<T>* __restrict__ Yt,
                                                const T* __restrict__ U, int M, int K, int rows,
                                                const DevScalars* __restrict__ sc,
-                                               T* __restrict__ tpart, int gate) {
+                                               T* __restrict__ tpart, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const int k0 = blockIdx.y * 256 * KT + threadIdx.x;
-  const int m0 = blockIdx.x * rows;
+  const int k0 = by_ * 256 * KT + threadIdx.x;
+  const int m0 = bx_ * rows;
   const int m1 = min(M, m0 + rows);
   T ax[KT], ay[KT], az[KT];
 #pragma unroll
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
   for (int j = 0; j < KT; ++j) {
     const int k = k0 + 256 * j;
     if (k < K) {
-      T* o = tpart + ((size_t)blockIdx.x * K + k) * 4;
+      T* o = tpart + ((size_t)bx_ * K + k) * 4;
       o[0] = ax[j];
       o[1] = ay[j];
       o[2] = az[j];
@@ -58,17 +58,26 @@ __global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
   }
 }
 
+template <typename T, int KT>
+__global__ __launch_bounds__(256) void k_tpart(const P4<T>* __restrict__ X,
+                                               const P4<T>* __restrict__ Yt,
+                                               const T* __restrict__ U, int M, int K, int rows,
+                                               const DevScalars* __restrict__ sc,
+                                               T* __restrict__ tpart, int gate) {
+  tpart_body<T, KT>(X, Yt, U, M, K, rows, sc, tpart, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // One wave per eigenpair k: T_k = sum over row chunks (fixed order: lane
 // strides, then a fixed butterfly), GT_k = g_k T_k, HT_k = h_k T_k with
 // g_k = 1/(max(lam_k, 0) + lambda sigma^2) and h_k = max(lam_k, 0) g_k.
 template <typename T>
-__global__ __launch_bounds__(64) void k_tmerge(const T* __restrict__ tpart, int chunks,
+__device__ __forceinline__ void tmerge_body(const T* __restrict__ tpart, int chunks,
                                                const double* __restrict__ lam, int K,
                                                double lmbda, const DevScalars* __restrict__ sc,
                                                P4<T>* __restrict__ GT, P4<T>* __restrict__ HT,
-                                               int gate) {
+                                               int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const int k = blockIdx.x;
+  const int k = bx_;
   const int lane = threadIdx.x;
   T tx = 0, ty = 0, tz = 0;
   for (int c = lane; c < chunks; c += 64) {
@@ -89,16 +98,25 @@ __global__ __launch_bounds__(64) void k_tmerge(const T* __restrict__ tpart, int 
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(64) void k_tmerge(const T* __restrict__ tpart, int chunks,
+                                               const double* __restrict__ lam, int K,
+                                               double lmbda, const DevScalars* __restrict__ sc,
+                                               P4<T>* __restrict__ GT, P4<T>* __restrict__ HT,
+                                               int gate) {
+  tmerge_body<T>(tpart, chunks, lam, K, lmbda, sc, GT, HT, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // Xnew_m = X_m + U_m . HT, W_m = U_m . GT.  Sixteen lanes per row (four rows
 // per wave), 64 rows per block; GT and HT staged in LDS when they fit.
 template <typename T, bool LDS>
-__global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
+__device__ __forceinline__ void apply_body(const P4<T>* __restrict__ X,
                                                const T* __restrict__ U,
                                                const P4<T>* __restrict__ GTg,
                                                const P4<T>* __restrict__ HTg, int M, int K,
                                                const DevScalars* __restrict__ sc,
                                                P4<T>* __restrict__ Xnew, P4<T>* __restrict__ W,
-                                               int gate) {
+                                               int gate, int bx_, int by_, int gx_) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (gate && sc->done) return;
   const P4<T>* GT = GTg;
@@ -117,7 +135,7 @@ __global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane >> 4, l16 = lane & 15;
   for (int it = 0; it < 4; ++it) {
-    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+    const int m = bx_ * 64 + wave * 16 + it * 4 + sub;
     T hx = 0, hy = 0, hz = 0, gx = 0, gy = 0, gz = 0;
     if (m < M) {
       const T* u = U + (size_t)m * K;
@@ -147,6 +165,17 @@ __global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
       W[m] = P4<T>{gx, gy, gz, (T)0};
     }
   }
+}
+
+template <typename T, bool LDS>
+__global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
+                                               const T* __restrict__ U,
+                                               const P4<T>* __restrict__ GTg,
+                                               const P4<T>* __restrict__ HTg, int M, int K,
+                                               const DevScalars* __restrict__ sc,
+                                               P4<T>* __restrict__ Xnew, P4<T>* __restrict__ W,
+                                               int gate) {
+  apply_body<T, LDS>(X, U, GTg, HTg, M, K, sc, Xnew, W, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 constexpr int kTRows = 128;
@@ -184,17 +213,17 @@ template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t 
 // original method the row carries its weight P1_m and sigma^2 divides by
 // N_P = sum_m P1_m instead of M.  The kernel also retires the old iterate.
 template <typename T>
-__global__ __launch_bounds__(256) void k_sig_part(P4<T>* __restrict__ Xt,
+__device__ __forceinline__ void sig_part_body(P4<T>* __restrict__ Xt,
                                                   const P4<T>* __restrict__ Xnew,
                                                   const P4<T>* __restrict__ Yt,
                                                   const T* __restrict__ tbar,
                                                   const T* __restrict__ P1, int M,
                                                   const DevScalars* __restrict__ sc,
-                                                  double* __restrict__ part, int gate) {
+                                                  double* __restrict__ part, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   if (sc->nonfinite) return;  // a failed M-step leaves the iterate as it was
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = bx_ * blockDim.x + threadIdx.x;
   double v = 0.0, wsum = 0.0;
   if (m < M) {
     const P4<T> b = Xt[m], a = Xnew[m], y = Yt[m];
@@ -211,16 +240,27 @@ __global__ __launch_bounds__(256) void k_sig_part(P4<T>* __restrict__ Xt,
   const double s1 = block_sum_d(v, sh);
   const double s2 = block_sum_d(wsum, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = s1;
-    part[2 * blockIdx.x + 1] = s2;
+    part[2 * bx_] = s1;
+    part[2 * bx_ + 1] = s2;
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ part, int blocks,
+__global__ __launch_bounds__(256) void k_sig_part(P4<T>* __restrict__ Xt,
+                                                  const P4<T>* __restrict__ Xnew,
+                                                  const P4<T>* __restrict__ Yt,
+                                                  const T* __restrict__ tbar,
+                                                  const T* __restrict__ P1, int M,
+                                                  const DevScalars* __restrict__ sc,
+                                                  double* __restrict__ part, int gate) {
+  sig_part_body<T>(Xt, Xnew, Yt, tbar, P1, M, sc, part, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void sig_final_body(const double* __restrict__ part, int blocks,
                                                    const double* __restrict__ llpart,
                                                    int llblocks, int M, int N, int D, double w,
-                                                   int weighted, DevScalars* sc, int gate) {
+                                                   int weighted, DevScalars* sc, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   double a = 0.0, b = 0.0, c = 0.0;
@@ -259,6 +299,14 @@ __global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ pa
     sc->converged = ds < sc->tol;
     if (sc->converged || sc->iter >= sc->max_iter) sc->done = 1;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ part, int blocks,
+                                                   const double* __restrict__ llpart,
+                                                   int llblocks, int M, int N, int D, double w,
+                                                   int weighted, DevScalars* sc, int gate) {
+  sig_final_body<T>(part, blocks, llpart, llblocks, M, N, D, w, weighted, sc, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <typename T> int sigma2_blocks(int M) { return (M + 255) / 256; }
@@ -446,6 +494,73 @@ void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam
   const size_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_import_eig<T>, dim3((unsigned)blocks), dim3(256), 0, st, Uin, lamin, U,
                      lam, U64, M, K);
+}
+
+// ------------------------------------------------------------ batched
+template <int KT>
+__global__ __launch_bounds__(256) void kb_tpart(const InstDesc* __restrict__ d,
+                                                const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  tpart_body<float, KT>(D.X, D.Yt, D.U, D.M, D.K, D.mrows, D.sc, D.tpart, 1, it.y, it.z, 0);
+}
+__global__ __launch_bounds__(64) void kb_tmerge(const InstDesc* __restrict__ d,
+                                                const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  tmerge_body<float>(D.tpart, D.mchunks, D.lam, D.K, D.lmbda, D.sc, D.GT, D.HT, 1, it.y, 0, 0);
+}
+template <bool LDS>
+__global__ __launch_bounds__(256) void kb_apply(const InstDesc* __restrict__ d,
+                                                const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  apply_body<float, LDS>(D.X, D.U, D.GT, D.HT, D.M, D.K, D.sc, D.Xnew, D.W, 1, it.y, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_sigpart(const InstDesc* __restrict__ d,
+                                                  const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  sig_part_body<float>(D.Xt, D.Xnew, D.Yt, D.tbar, (const float*)nullptr, D.M, D.sc, D.sigpart, 1,
+                       it.y, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_sigfinal(const InstDesc* __restrict__ d,
+                                                   const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  sig_final_body<float>(D.sigpart, D.sigblocks, D.llpart, D.llblocks, D.M, D.N, 3, D.w, 0, D.sc,
+                        1, 0, 0, 0);
+}
+__global__ __launch_bounds__(256) void kb_count_done(const InstDesc* __restrict__ d, int B,
+                                                     int* __restrict__ out) {
+  __shared__ double sh[16];
+  double c = 0.0;
+  for (int i = threadIdx.x; i < B; i += 256) c += d[i].sc->done ? 1.0 : 0.0;
+  c = block_sum_d(c, sh);
+  if (threadIdx.x == 0) out[0] = (int)c;
+}
+
+void batch_mstep_sigma_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
+  if (it.kt == 1)
+    hipLaunchKernelGGL(kb_tpart<1>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+  else if (it.kt == 2)
+    hipLaunchKernelGGL(kb_tpart<2>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+  else
+    hipLaunchKernelGGL(kb_tpart<4>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+  hipLaunchKernelGGL(kb_tmerge, dim3(it.n_tmerge), dim3(64), 0, st, d, it.tmerge);
+  const size_t lds = 2 * (size_t)it.maxK * sizeof(P4<float>);
+  if (lds <= kApplyLdsBytes)
+    hipLaunchKernelGGL(kb_apply<true>, dim3(it.n_apply), dim3(256), lds, st, d, it.apply);
+  else
+    hipLaunchKernelGGL(kb_apply<false>, dim3(it.n_apply), dim3(256), 0, st, d, it.apply);
+  hipLaunchKernelGGL(kb_sigpart, dim3(it.n_sigpart), dim3(256), 0, st, d, it.sigpart);
+  hipLaunchKernelGGL(kb_sigfinal, dim3(it.n_inst), dim3(256), 0, st, d, it.inst);
+  hipLaunchKernelGGL(kb_count_done, dim3(1), dim3(256), 0, st, d, it.n_inst, it.done_count);
+}
+
+void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
+  batch_estep_launch(d, it, st);
+  batch_mstep_sigma_launch(d, it, st);
 }
 
 #define FCPD_INST(T)                                                                          \
