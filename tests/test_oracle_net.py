@@ -65,3 +65,21 @@ def test_zero_output_layer_gives_zero_w0():
     W0, _ = net64.forward(np.random.default_rng(0).normal(size=(7, 3)),
                           np.random.default_rng(1).normal(size=(9, 3)), p)
     np.testing.assert_array_equal(W0, 0.0)
+
+
+def test_bf16_rounding_helper():
+    a = np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, -3.0e-3, 0.0, 65504.0])
+    r = net64.bf16(a)
+    np.testing.assert_array_equal(r[[0, 4]], [1.0, 0.0])
+    assert r[1] == 1.0                      # tie rounds to even
+    assert r[2] == 1.0 + 2 ** -7            # tie rounds to even (up)
+    assert abs(r[3] / a[3] - 1) < 2 ** -8
+    assert net64.bf16(np.array([1.0 + 2 ** -7]))[0] == 1.0 + 2 ** -7
+
+
+def test_bf16_mode_is_close_to_float64():
+    p = net64.init_params(1, out_scale=0.5)
+    batch = _batch()
+    L, G = net64.loss_grad(batch, p, 1.0)
+    Lb, Gb = net64.loss_grad(batch, p, 1.0, bf16_storage=True)
+    assert Lb == pytest.approx(L, rel=3e-2)
