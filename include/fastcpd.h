@@ -218,16 +218,56 @@ cpd_status cpd_batch_init(cpd_batch* hb, int32_t B, const cpd_params* p,
 cpd_status cpd_batch_prepare(cpd_batch hb, int32_t tune);
 
 /* Iterate all instances from their start state until each has converged or
- * reached its max_iter.  X_out_packed (device, nullable) receives every Xt;
+ * reached its max_iter.  W0_packed (device, nullable, sum M_i x 3) starts
+ * instance i at Xt = X + Phi W0_i with the standard sigma^2 start at that Xt
+ * (warm start); NULL starts at Xt = X.  X_out_packed (device, nullable)
+ * receives every Xt;
  * res (host, nullable, B entries) gets per-instance iterations, convergence
  * and sigma^2, with t_eig per instance and t_o = the whole batched run. */
-cpd_status cpd_batch_register(cpd_batch hb, float* X_out_packed, cpd_result* res);
+cpd_status cpd_batch_register(cpd_batch hb, const float* W0_packed, float* X_out_packed,
+                              cpd_result* res);
 
 /* The split length the tuner chose and the per-candidate iteration times
  * (ms, candidates 1024, 2048, 512, 4096; 0 when not tuned). */
 cpd_status cpd_batch_info(cpd_batch hb, int32_t* chunk, double* tune_ms);
 
 cpd_status cpd_batch_destroy(cpd_batch hb);
+
+/* --------------------------------------------------------- warm start net
+ * A point-set network predicting initial GRBF coefficients W0 (M x 3) from a
+ * model set X and a scene set Y, for f(X) = X + Phi W (Section III, eq. 9-11):
+ * a shared per-point MLP on [p, flag] (4 -> 256 -> 256 -> 256 -> 256, ReLU),
+ * max-pooled per set into g_X and g_Y, and a head per model point
+ * z = relu(f(x_m) Wa + g_X Wb + g_Y Wc + bh), W0_m = z Wo + bo.  The 256 x 256
+ * products run on the matrix cores in bf16 with fp32 accumulation; the
+ * parameters are one fp32 array (order W1 b1 W2 b2 W3 b3 W4 b4 Wa Wb Wc bh Wo
+ * bo, every W as [fan_in][fan_out]).  Training minimises the displacement
+ * error |Phi W0 - V*|^2 / M averaged over a batch (Phi formed on the fly).
+ * All arrays are device float arrays; a batch packs `batch` instances of M
+ * model and N scene points each, row-major x 3. */
+cpd_status cpdnet_param_count(size_t* count);
+cpd_status cpdnet_init(float* params, uint64_t seed, float out_scale, void* hip_stream);
+cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, size_t* bytes);
+cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, int32_t batch,
+                          int32_t M, int32_t N, float* W0_out, void* workspace,
+                          size_t workspace_bytes, void* hip_stream);
+/* Loss (host double, nullable) and its gradient (device, param_count floats). */
+cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y, const float* V,
+                            int32_t batch, int32_t M, int32_t N, double beta, float* grad_out,
+                            double* loss_out, void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the fp32 master; m, v
+ * are param_count floats each; step counts from 1. */
+cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                       float lr, void* hip_stream);
+/* Training pairs on the device from the 500-point sphere recipe at any M:
+ * X = unit-sphere directions + N(0, jitter^2), W* ~ N(0, coef^2),
+ * V* = Phi W* (displacement of every model point), Y = X + V* with a
+ * fraction outlier_frac of rows replaced by U[-1.5, 1.5]^3 (N = M).
+ * Instance b draws from counter-based stream seed0 + b.  W_scratch holds W*. */
+cpd_status cpdnet_synth(float* X, float* Y, float* V, float* W_scratch, int32_t batch, int32_t M,
+                        double beta, double coef, double jitter, double outlier_frac,
+                        uint64_t seed0, void* hip_stream);
 
 const char* cpd_status_str(cpd_status s);
 const char* cpd_last_error(cpd_handle h);   /* h may be NULL: global message */

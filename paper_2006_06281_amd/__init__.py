@@ -39,6 +39,8 @@ EXPORTED = [
     "cpd_last_error", "cpd_abi_version", "cpd_build_info", "cpd_time_kernels",
     "cpd_batch_workspace_size", "cpd_batch_init", "cpd_batch_prepare", "cpd_batch_register",
     "cpd_batch_info", "cpd_batch_destroy",
+    "cpdnet_param_count", "cpdnet_init", "cpdnet_workspace_size", "cpdnet_forward",
+    "cpdnet_loss_grad", "cpdnet_adam", "cpdnet_synth",
 ]
 
 
@@ -105,9 +107,20 @@ def load_library(path: str = LIB_PATH):
         "cpd_batch_init": ([P(vp), ctypes.c_int32, P(cpd_params), vp, vp, P(ctypes.c_int64),
                             P(ctypes.c_int64), vp, sz, vp], ctypes.c_int),
         "cpd_batch_prepare": ([vp, ctypes.c_int32], ctypes.c_int),
-        "cpd_batch_register": ([vp, vp, P(cpd_result)], ctypes.c_int),
+        "cpd_batch_register": ([vp, vp, vp, P(cpd_result)], ctypes.c_int),
         "cpd_batch_info": ([vp, P(ctypes.c_int32), P(ctypes.c_double)], ctypes.c_int),
         "cpd_batch_destroy": ([vp], ctypes.c_int),
+        "cpdnet_param_count": ([P(sz)], ctypes.c_int),
+        "cpdnet_init": ([vp, ctypes.c_uint64, ctypes.c_float, vp], ctypes.c_int),
+        "cpdnet_workspace_size": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(sz)], ctypes.c_int),
+        "cpdnet_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, sz,
+                            vp], ctypes.c_int),
+        "cpdnet_loss_grad": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_double, vp, P(ctypes.c_double), vp, sz, vp], ctypes.c_int),
+        "cpdnet_adam": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp], ctypes.c_int),
+        "cpdnet_synth": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp],
+                         ctypes.c_int),
         "cpd_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "cpd_last_error": ([vp], ctypes.c_char_p),
         "cpd_abi_version": ([], ctypes.c_int32),
@@ -293,11 +306,13 @@ class BatchRegistration:
         _check(load_library().cpd_batch_info(self.h, ctypes.byref(c), t))
         return c.value, dict(zip((1024, 2048, 512, 4096), list(t)))
 
-    def register(self):
+    def register(self, W0=None):
+        """W0: optional packed (sum M_i x 3) float32 CUDA tensor of warm-start
+        coefficients."""
         import torch
         out = torch.empty_like(self.Xp)
         res = (cpd_result * self.B)()
-        _check(load_library().cpd_batch_register(self.h, _ptr(out), res),
+        _check(load_library().cpd_batch_register(self.h, _ptr(W0), _ptr(out), res),
                ok=(CPD_OK, CPD_NOT_CONVERGED))
         Xt = [out[self._xo[i]:self._xo[i + 1]] for i in range(self.B)]
         return Xt, list(res)
@@ -312,6 +327,80 @@ class BatchRegistration:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ warm start
+class WarmStartNet:
+    """The warm-start point-set network: fp32 master parameters, Adam state
+    and a workspace sized for (batch, M, N)."""
+
+    def __init__(self, seed=0, out_scale=1e-3, device="cuda"):
+        import torch
+        n = ctypes.c_size_t(0)
+        _check(load_library().cpdnet_param_count(ctypes.byref(n)))
+        self.count = n.value
+        self.params = torch.empty(self.count, dtype=torch.float32, device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step_no = 0
+        self.device = device
+        self._ws = None
+        self._ws_key = None
+        _check(load_library().cpdnet_init(_ptr(self.params), int(seed), float(out_scale),
+                                          _stream_ptr()))
+
+    def _workspace(self, batch, M, N):
+        import torch
+        key = (batch, M, N)
+        if self._ws_key != key:
+            n = ctypes.c_size_t(0)
+            _check(load_library().cpdnet_workspace_size(batch, M, N, ctypes.byref(n)))
+            self._ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
+            self._ws_key = key
+        return self._ws
+
+    def forward(self, X, Y):
+        """X: (batch, M, 3), Y: (batch, N, 3) float32 -> W0 (batch, M, 3)."""
+        import torch
+        B, M, N = X.shape[0], X.shape[1], Y.shape[1]
+        W0 = torch.empty(B, M, 3, dtype=torch.float32, device=X.device)
+        ws = self._workspace(B, M, N)
+        _check(load_library().cpdnet_forward(_ptr(self.params), _ptr(X), _ptr(Y), B, M, N,
+                                             _ptr(W0), _ptr(ws), ws.numel(), _stream_ptr()))
+        return W0
+
+    def loss_grad(self, X, Y, V, beta):
+        B, M, N = X.shape[0], X.shape[1], Y.shape[1]
+        ws = self._workspace(B, M, N)
+        loss = ctypes.c_double(0)
+        _check(load_library().cpdnet_loss_grad(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(V), B,
+                                               M, N, float(beta), _ptr(self.grad),
+                                               ctypes.byref(loss), _ptr(ws), ws.numel(),
+                                               _stream_ptr()))
+        return loss.value
+
+    def train_step(self, X, Y, V, beta, lr=1e-3):
+        loss = self.loss_grad(X, Y, V, beta)
+        self.step_no += 1
+        _check(load_library().cpdnet_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                          _ptr(self.grad), self.step_no, float(lr),
+                                          _stream_ptr()))
+        return loss
+
+
+def synth_pairs(batch, M, beta=2.0, coef=0.15, jitter=0.01, outlier_frac=0.10, seed0=0,
+                device="cuda"):
+    """Training pairs drawn on the device (see cpdnet_synth): X, Y, V (batch, M, 3)."""
+    import torch
+    X = torch.empty(batch, M, 3, dtype=torch.float32, device=device)
+    Y = torch.empty_like(X)
+    V = torch.empty_like(X)
+    W = torch.empty_like(X)
+    _check(load_library().cpdnet_synth(_ptr(X), _ptr(Y), _ptr(V), _ptr(W), batch, M, float(beta),
+                                       float(coef), float(jitter), float(outlier_frac),
+                                       int(seed0), _stream_ptr()))
+    return X, Y, V
 
 
 # ------------------------------------------------------------- convenience

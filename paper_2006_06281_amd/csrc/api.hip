@@ -17,6 +17,7 @@
 #include "common.hpp"
 #include "eig.hpp"
 #include "kernels.hpp"
+#include "net.hpp"
 #include "orig.hpp"
 
 using namespace fcpd;
@@ -1062,7 +1063,8 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   return CPD_OK;
 }
 
-cpd_status cpd_batch_register(cpd_batch b, float* X_out_packed, cpd_result* res) {
+cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_packed,
+                              cpd_result* res) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
   if (!b->prepared) return bfail(b, CPD_E_STATE, "cpd_batch_prepare must run first");
   // order after the caller's stream
@@ -1073,6 +1075,17 @@ cpd_status cpd_batch_register(cpd_batch b, float* X_out_packed, cpd_result* res)
   HIPCHK(nullptr, hipStreamWaitEvent(b->st, ev0, 0));
   const cpd_status rs = batch_restart(b);
   if (rs != CPD_OK) return rs;
+  if (W0_packed) {
+    for (int i = 0; i < b->B; ++i) {
+      cpd_ctx* h = b->inst[i];
+      phi_apply_launch<float>(h->at<P4<float>>(h->L.X), W0_packed + 3 * b->x_off[i],
+                              h->at<P4<float>>(h->L.Xt), h->p.M, 3, h->p.beta, b->st);
+      if (!(h->p.sigma2_init > 0.0))
+        reset_sigma2_launch<float>(h->at<P4<float>>(h->L.Xt), h->at<P4<float>>(h->L.Y), h->p.M,
+                                   h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st);
+    }
+    HIPCHK(nullptr, hipGetLastError());
+  }
   int max_iter = 1;
   for (auto& q : b->p) max_iter = std::max(max_iter, q.max_iter);
   hipEvent_t t0, t1;
@@ -1134,6 +1147,99 @@ cpd_status cpd_batch_info(cpd_batch b, int32_t* chunk, double* tune_ms) {
 
 cpd_status cpd_batch_destroy(cpd_batch b) {
   delete b;
+  return CPD_OK;
+}
+
+// ---------------------------------------------------------------- network
+cpd_status cpdnet_param_count(size_t* count) {
+  if (!count) return fail(nullptr, CPD_E_ARG, "count is NULL");
+  *count = net_offsets().count;
+  return CPD_OK;
+}
+
+cpd_status cpdnet_init(float* params, uint64_t seed, float out_scale, void* stream) {
+  if (!params) return fail(nullptr, CPD_E_ARG, "params is NULL");
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  net_init_launch(params, seed, out_scale, static_cast<hipStream_t>(stream));
+  HIPCHK(nullptr, hipGetLastError());
+  return CPD_OK;
+}
+
+static cpd_status net_dims(int32_t batch, int32_t M, int32_t N) {
+  if (batch < 1 || M < 1 || N < 1 || (int64_t)batch * std::max(M, N) > (1 << 24))
+    return fail(nullptr, CPD_E_ARG, "batch, M, N must be >= 1 with batch * max(M, N) <= 2^24");
+  return CPD_OK;
+}
+
+cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, size_t* bytes) {
+  if (!bytes) return fail(nullptr, CPD_E_ARG, "bytes is NULL");
+  const cpd_status v = net_dims(batch, M, N);
+  if (v != CPD_OK) return v;
+  *bytes = net_ws_layout(batch, M, N).end;
+  return CPD_OK;
+}
+
+cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, int32_t batch,
+                          int32_t M, int32_t N, float* W0_out, void* ws, size_t bytes,
+                          void* stream) {
+  const cpd_status v = net_dims(batch, M, N);
+  if (v != CPD_OK) return v;
+  if (!params || !X || !Y || !W0_out) return fail(nullptr, CPD_E_ARG, "NULL array");
+  const NetWs L = net_ws_layout(batch, M, N);
+  if (!ws || bytes < L.end || reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(nullptr, CPD_E_WORKSPACE, "network workspace missing, misaligned or too small");
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L, st);
+  HIPCHK(nullptr, hipGetLastError());
+  return CPD_OK;
+}
+
+cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y, const float* V,
+                            int32_t batch, int32_t M, int32_t N, double beta, float* grad_out,
+                            double* loss_out, void* ws, size_t bytes, void* stream) {
+  const cpd_status v = net_dims(batch, M, N);
+  if (v != CPD_OK) return v;
+  if (!params || !X || !Y || !V || !grad_out) return fail(nullptr, CPD_E_ARG, "NULL array");
+  if (!(beta > 0.0)) return fail(nullptr, CPD_E_ARG, "beta must be > 0");
+  const NetWs L = net_ws_layout(batch, M, N);
+  if (!ws || bytes < L.end || reinterpret_cast<uintptr_t>(ws) % 256)
+    return fail(nullptr, CPD_E_WORKSPACE, "network workspace missing, misaligned or too small");
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  double* ldev = reinterpret_cast<double*>(w + L.loss);
+  net_loss_grad_launch(params, X, Y, V, batch, M, N, beta, grad_out, ldev, w, L, st);
+  HIPCHK(nullptr, hipGetLastError());
+  if (loss_out) {
+    HIPCHK(nullptr, hipMemcpyAsync(loss_out, ldev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(nullptr, hipStreamSynchronize(st));
+  }
+  return CPD_OK;
+}
+
+cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                       float lr, void* stream) {
+  if (!params || !m || !v || !grad || step < 1 || !(lr > 0.f))
+    return fail(nullptr, CPD_E_ARG, "bad Adam arguments");
+  net_adam_launch(params, m, v, grad, step, lr, static_cast<hipStream_t>(stream));
+  HIPCHK(nullptr, hipGetLastError());
+  return CPD_OK;
+}
+
+cpd_status cpdnet_synth(float* X, float* Y, float* V, float* Wsc, int32_t batch, int32_t M,
+                        double beta, double coef, double jitter, double outlier_frac,
+                        uint64_t seed0, void* stream) {
+  const cpd_status vd = net_dims(batch, M, M);
+  if (vd != CPD_OK) return vd;
+  if (!X || !Y || !V || !Wsc || !(beta > 0.0) || !(outlier_frac >= 0.0 && outlier_frac <= 1.0))
+    return fail(nullptr, CPD_E_ARG, "bad synth arguments");
+  net_synth_launch(X, Y, V, Wsc, batch, M, beta, coef, jitter, outlier_frac, seed0,
+                   static_cast<hipStream_t>(stream));
+  HIPCHK(nullptr, hipGetLastError());
   return CPD_OK;
 }
 

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "fastcpd.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(cpd_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(cpd(?:net)?_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_header_declarations_are_exported():
