@@ -172,6 +172,89 @@ def batch_leg(fc, torch, B=256, tune=True):
             "rmse_median": float(np.median(rmse)), "rmse_max": float(np.max(rmse))}
 
 
+def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=250,
+             beta=2.0, lam=3.0, w=0.1):
+    """Learned warm start at M = N = 2000: the network is trained on the GPU
+    on `triples` pairs of the sphere recipe (unit-sphere model + N(0, 0.01^2)
+    jitter, RBF field with coefficients N(0, s^2), s = 0.3 sqrt(500 / M) so
+    the field has the size it has at M = 500, 10% uniform outliers in
+    [-1.5, 1.5]^3), then `held_out` pairs from disjoint seeds are registered
+    twice by the batched path (FULL eigen-prep, FP32, tol 1e-8): from W = 0
+    and from the network's W0.  RMSE is against the true position x_m + v_m
+    of every model point."""
+    coef = 0.3 * np.sqrt(500.0 / M)
+    net = fc.WarmStartNet(seed=1)
+    steps = -(-triples // batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = float("nan")
+    for step in range(steps):
+        lr = 1e-3 if step < 0.6 * steps else (3e-4 if step < 0.85 * steps else 1e-4)
+        X, Y, V = fc.synth_pairs(batch, M, beta=beta, coef=coef, seed0=10_000_000 + batch * step)
+        loss = net.train_step(X, Y, V, beta=beta, lr=lr)
+        if step % 250 == 0 or step == steps - 1:
+            log(f"warm: train step {step}/{steps} loss {loss:.3f}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    acc = {k: [] for k in ("it0", "itw", "cv0", "cvw", "r0", "rw", "i0", "iw")}
+    t_run0 = t_runw = t_net = t_prep = 0.0
+    for c0 in range(0, held_out, chunk):
+        E = min(chunk, held_out - c0)
+        X, Y, V = fc.synth_pairs(E, M, beta=beta, coef=coef, seed0=1 + c0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W0 = net.forward(X, Y)
+        torch.cuda.synchronize()
+        t_net += time.perf_counter() - t0
+        br = fc.BatchRegistration([X[i] for i in range(E)], [Y[i] for i in range(E)], beta=beta,
+                                  lam=lam, w=w, eig_mode="full", tol=1e-8, max_iter=1000)
+        t0 = time.perf_counter()
+        br.prepare(tune=(c0 == 0))
+        torch.cuda.synchronize()
+        t_prep += time.perf_counter() - t0
+        gt = (X + V).double()
+        for tag, w0 in (("0", None), ("w", W0.reshape(-1, 3).contiguous())):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Xt, res = br.register(W0=w0)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if tag == "0":
+                t_run0 += dt
+            else:
+                t_runw += dt
+            acc["it" + tag] += [r.iters for r in res]
+            acc["cv" + tag] += [r.converged for r in res]
+            acc["r" + tag] += [float(((Xt[i].double() - gt[i]) ** 2).sum(1).mean().sqrt())
+                               for i in range(E)]
+        # RMSE of the starting positions: X (W = 0) and X + Phi W0
+        for i in range(E):
+            x = X[i].double()
+            Phi = torch.exp(-torch.cdist(x, x).square() / (2.0 * beta * beta))
+            acc["i0"].append(float((x - gt[i]).square().sum(1).mean().sqrt()))
+            acc["iw"].append(float((x + Phi @ W0[i].double() - gt[i]).square().sum(1).mean().sqrt()))
+        br.close()
+        log(f"warm: held-out {c0 + E}/{held_out} registered")
+    a = {k: np.asarray(v, dtype=np.float64) for k, v in acc.items()}
+    return {"workload": f"warm{M}: M=N={M}, D=3, unit sphere + N(0,0.01^2), RBF field beta={beta:g} "
+                        f"coef N(0,{coef:.4f}^2), 10% outliers; lambda={lam:g}, w={w:g}; "
+                        f"Fast CPD FULL eig, FP32, tol 1e-8",
+            "train_triples": steps * batch, "train_batch": batch, "train_s": t_train,
+            "train_loss_last": loss, "held_out": held_out,
+            "net_forward_s": t_net, "prepare_s": t_prep,
+            "iters_mean_w0": float(a["it0"].mean()), "iters_mean_net": float(a["itw"].mean()),
+            "iters_median_w0": float(np.median(a["it0"])),
+            "iters_median_net": float(np.median(a["itw"])),
+            "converged_w0": int(a["cv0"].sum()), "converged_net": int(a["cvw"].sum()),
+            "rmse_mean_w0": float(a["r0"].mean()), "rmse_mean_net": float(a["rw"].mean()),
+            "rmse_median_w0": float(np.median(a["r0"])),
+            "rmse_median_net": float(np.median(a["rw"])),
+            "net_worse_rmse_1pct": int((a["rw"] > 1.01 * a["r0"]).sum()),
+            "start_rmse_mean_w0": float(a["i0"].mean()),
+            "start_rmse_mean_net": float(a["iw"].mean()),
+            "run_s_w0": t_run0, "run_s_net": t_runw}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,8 +264,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converge")
     ap.add_argument("--no-plain", action="store_true", help="skip the original-CPD comparator")
-    ap.add_argument("--workload", default="surface50k", choices=["surface50k", "batch256"],
-                    help="batch256: the batched leg alone, one JSON line of its own")
+    ap.add_argument("--workload", default="surface50k",
+                    choices=["surface50k", "batch256", "warm2000"],
+                    help="batch256 / warm2000: that leg alone, one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -202,6 +286,17 @@ def main():
                           "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
                           "data": "synthetic", "config": {"workload": b["workload"]},
                           "batch": b}), flush=True)
+        return
+
+    if args.workload == "warm2000":
+        b = warm_leg(fc, torch)
+        log(f"warm: {b}")
+        print(json.dumps({"metric": "learned warm start: mean EM iterations to tolerance, "
+                                    "held-out pairs",
+                          "value": b["iters_mean_net"], "unit": "EM iterations",
+                          "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 net, f32 EM",
+                          "data": "synthetic", "config": {"workload": b["workload"]},
+                          "warm_start": b}), flush=True)
         return
 
     t0 = time.perf_counter()
