@@ -29,17 +29,69 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-converge (s) & EM iters/s at M=N=50k, 3D; vs plain CPD same GPU"
 
-# Algorithmic work per model-scene pair and pass (D = 3), exp counted as one
-# operation: pass A 8 (|y-x|^2) + 1 (scale) + 1 (sum) + exp; pass B the same
-# squared distance + 2 (scale, minus log d_n) + exp + 1 (P1) + 6 (PY) + 2
-# (the weighted squared distance).
-FLOP_PASS_A = 11
-FLOP_PASS_B = 20
+# Roofline of the E-step passes (ALU bound: O(M + N) bytes against O(M N)
+# arithmetic).  The algorithmic work per model-scene pair is counted in VALU
+# issue slots of the formulation each kernel implements (one slot = one
+# 64-lane instruction on a 16-lane SIMD = 4 cycles; v_exp_f32 takes two slots,
+# measured: 1.79e13 exp/s against 3.57e13 FMA/s on the chip), and expressed as
+# FP32 FMA-equivalent FLOP (2 per slot) so it compares with the non-packed
+# FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz = 78.6
+# TFLOP/s (this build disables packed FP32, so 157.3 is not reachable).
+#   FP32  pass A: 3 sub + 3 (mul, 2 fma) for |y - x|^2, exp, add        = 9
+#         pass B: the same 6, add L_n, exp, add (P1), 3 fma (PY), fma (t) = 14
+#   BF16X pass A: |y - x|^2 from the matrix cores; exp, add            = 3
+#         pass B: exp, sub L_n, add (P1), 3 fma (PY), fma (t)          = 8
+# BF16X also spends one v_mfma_f32_16x16x32_bf16 (16 cycles) per 256 pairs,
+# i.e. one slot-equivalent per pair, which does not overlap the VALU work of
+# the same tile (measured); the fraction that includes it is reported beside.
+SLOTS = {("fp32", "passA"): 9, ("fp32", "passB"): 14,
+         ("bf16x", "passA"): 3, ("bf16x", "passB"): 8}
+MFMA_SLOTS = {"fp32": 0, "bf16x": 1}
 PEAK_VALU_FP32_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_EXP_PER_S = 19.66e12      # v_exp_f32 at half the FMA issue rate
+KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
+               ("bf16x", "passA"): "k_bfx_colsum", ("bf16x", "passB"): "k_bfx_rowsum"}
+# HBM traffic of the dominant kernel per dispatch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
+# of known size; valid only while the kernel source is unchanged (sha256).
+TRAFFIC = {}
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def _source_hash(name):
+    import hashlib
+    p = os.path.join(ROOT, "paper_2006_06281_amd", "csrc", name)
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def roofline_of(kern, pairs, precision):
+    """Roofline entry for the dominant kernel (pass B), achieved from its
+    average launch time measured with HIP events on the handle's stream."""
+    out = {}
+    for stage in ("passA", "passB"):
+        t = kern[stage] * 1e-3
+        slots = SLOTS[(precision, stage)]
+        ach = pairs * slots * 2.0 / t / 1e12
+        out[stage] = {"kernel": KERNEL_NAME[(precision, stage)], "avg_us": kern[stage] * 1e3,
+                      "slots_per_pair": slots, "achieved": ach,
+                      "frac": ach / PEAK_VALU_FP32_TFLOPS,
+                      "frac_incl_mfma": pairs * (slots + MFMA_SLOTS[precision]) * 2.0 / t / 1e12
+                      / PEAK_VALU_FP32_TFLOPS,
+                      "exp_per_s": pairs / t, "exp_frac": pairs / t / PEAK_EXP_PER_S}
+    b = out["passB"]
+    traffic = None
+    tr = TRAFFIC.get(b["kernel"])
+    if tr and _source_hash(tr["source"]) == tr["sha256"]:
+        traffic = tr["bytes_per_dispatch"]
+    return {"bound": "alu", "kernel": b["kernel"] + " (E-step pass B)",
+            "achieved": b["achieved"], "peak": PEAK_VALU_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": b["frac"], "traffic": traffic,
+            "flop_model": "FMA-equivalent VALU issue slots per pair x pairs per launch",
+            "stages": out}
 
 
 def cpu_baseline(pair, K, rows=20000):
@@ -264,6 +316,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converge")
     ap.add_argument("--no-plain", action="store_true", help="skip the original-CPD comparator")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run two 256 MiB device-to-device copies first (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--workload", default="surface50k",
                     choices=["surface50k", "batch256", "warm2000"],
                     help="batch256 / warm2000: that leg alone, one JSON line of its own")
@@ -298,6 +353,15 @@ def main():
                           "data": "synthetic", "config": {"workload": b["workload"]},
                           "warm_start": b}), flush=True)
         return
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 2 x 268435456 bytes device to device")
+        del src, dst
 
     t0 = time.perf_counter()
     pair = synth.workload("surface50k")
@@ -358,12 +422,7 @@ def main():
         plain = plain_cpd_legs(fc, torch, X, Y, pair, kw, ms_step)
 
     pairs = pair.M * pair.N
-    tB = kern["passB"] * 1e-3
-    achieved = pairs * FLOP_PASS_B / tB / 1e12
-    roofline = {"bound": "alu", "kernel": "k_rowsum (E-step pass B)", "achieved": achieved,
-                "peak": PEAK_VALU_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_VALU_FP32_TFLOPS, "traffic": None,
-                "passA_TFLOPs": pairs * FLOP_PASS_A / (kern["passA"] * 1e-3) / 1e12}
+    roofline = roofline_of(kern, pairs, args.precision)
 
     cpu = None
     if not args.no_cpu:

@@ -21,11 +21,13 @@
 
 #include "common.hpp"
 #include "eig.hpp"
+#include "orig.hpp"
 
 namespace fcpd {
 
 namespace {
 constexpr int kTopKMaxCols = 2048;
+constexpr int kCholNB = kCholBlock;  // block width of the blocked Cholesky
 constexpr int kDenseMax = 1024;
 constexpr int kFullOversample = 32;
 constexpr int kGramMaxChunks = 64;
@@ -81,9 +83,11 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.Z = take(Mn);
     L.Q = take(Mn);
     L.G = take(nn * (size_t)gram_chunks(M, n));
-    L.R = take(nn);
+    const size_t nblk = (size_t)(n + kCholNB - 1) / kCholNB;
+    L.R = take(std::max(nn, nblk * kCholNB * kCholNB * sizeof(double)));
     L.V = take(nn);
     L.phi = take(nn);  // the n x n Rayleigh-Ritz / Gram matrix
+    L.chol = take((size_t)n * kCholNB * sizeof(double));
     L.ritz = take((size_t)n * sizeof(double));
     L.misc = take(((size_t)n * sizeof(int) + 64) + (64 + 4 * (size_t)(n / 2 + 1)) * sizeof(double));
   }
@@ -288,76 +292,67 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   G[idx] = 0.5 * (s + t);
 }
 
-// In-place lower Cholesky of G + shift*I (n x n, row-major), one workgroup,
-// then Linv = L^-1 written (lower) into R.  info[0] = 0 ok, k+1 if pivot k
-// was not positive.
-__global__ __launch_bounds__(1024) void k_chol_inv(double* __restrict__ G, double* __restrict__ R,
-                                                   int n, const double* __restrict__ shift_rel,
-                                                   int* __restrict__ info) {
-  __shared__ double sh_shift;
-  __shared__ int sh_fail;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < n; ++i) tr += G[(size_t)i * n + i];
-    sh_shift = shift_rel ? shift_rel[0] * tr : 0.0;
-    sh_fail = 0;
-  }
+// G += shift_rel * trace(G) * I (shift_rel NULL: no shift) and clears the
+// factorisation's failure flag.  One workgroup.
+__global__ __launch_bounds__(1024) void k_shift_diag(double* __restrict__ G, int n,
+                                                     const double* __restrict__ shift_rel,
+                                                     int* __restrict__ fail) {
+  __shared__ double sh[16];
+  const int tid = threadIdx.x;
+  if (tid == 0) *fail = 0;
+  if (!shift_rel) return;
+  double tr = 0.0;
+  for (int i = tid; i < n; i += 1024) tr += G[(size_t)i * n + i];
+  tr = block_sum_d(tr, sh);  // valid in thread 0
+  if (tid == 0) sh[0] = shift_rel[0] * tr;
   __syncthreads();
-  for (int i = tid; i < n; i += nt) G[(size_t)i * n + i] += sh_shift;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = G[(size_t)k * n + k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        sh_fail = k + 1;
-        G[(size_t)k * n + k] = 1.0;
-      } else {
-        G[(size_t)k * n + k] = sqrt(d);
-      }
-    }
-    __syncthreads();
-    if (sh_fail) break;
-    const double piv = G[(size_t)k * n + k];
-    for (int i = k + 1 + tid; i < n; i += nt) G[(size_t)i * n + k] /= piv;
-    __syncthreads();
-    // trailing update of the lower triangle
-    const int len = n - k - 1;
-    const size_t work = (size_t)len * (len + 1) / 2;
-    for (size_t e = tid; e < work; e += nt) {
-      // e -> (i, j) with j <= i, both in [k+1, n)
-      int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while ((size_t)(i + 1) * (i + 2) / 2 <= e) ++i;
-      while ((size_t)i * (i + 1) / 2 > e) --i;
-      const int j = (int)(e - (size_t)i * (i + 1) / 2);
-      const int ii = k + 1 + i, jj = k + 1 + j;
-      G[(size_t)ii * n + jj] -= G[(size_t)ii * n + k] * G[(size_t)jj * n + k];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) info[0] = sh_fail;
-  if (sh_fail) return;
-  // Linv: solve L X = I column by column (each thread owns columns)
-  for (int c = tid; c < n; c += nt) {
-    for (int i = 0; i < n; ++i) {
-      if (i < c) {
-        R[(size_t)i * n + c] = 0.0;
-        continue;
-      }
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) s -= G[(size_t)i * n + k] * R[(size_t)k * n + c];
-      R[(size_t)i * n + c] = s / G[(size_t)i * n + i];
-    }
-  }
+  const double add = sh[0];
+  for (int i = tid; i < n; i += 1024) G[(size_t)i * n + i] += add;
 }
 
-// T = Linv^T (upper), as the right factor of Q = Z Linv^T.
-__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ A,
-                                                   double* __restrict__ B, int n) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)n * n) return;
-  const int a = (int)(idx / n), b = (int)(idx % n);
-  B[(size_t)b * n + a] = A[idx];
+// T = (L^-1)^T from the blocked Cholesky factor L (lower triangle of G, n x n
+// row-major) and the inverses Linv of its diagonal blocks (width NB, stride
+// NB).  Workgroup c computes column c of L^-1 by block forward substitution,
+//   x_I = Linv_II (e_c[I] - L[I, <I] x[<I]),
+// and writes it as row c of T (upper triangular, zeros left of c).
+template <int NB>
+__global__ __launch_bounds__(256) void k_tri_inv_t(const double* __restrict__ G, int n,
+                                                   const double* __restrict__ Linv,
+                                                   double* __restrict__ T,
+                                                   const int* __restrict__ fail) {
+  __shared__ double x[kTopKMaxCols];
+  __shared__ double y[NB];
+  __shared__ double part[NB][2];
+  if (*fail) return;
+  const int c = blockIdx.x, tid = threadIdx.x;
+  for (int i = tid; i < n; i += 256) x[i] = 0.0;
+  __syncthreads();
+  const int nblk = (n + NB - 1) / NB;
+  for (int ib = c / NB; ib < nblk; ++ib) {
+    const int i0 = ib * NB, nbi = min(NB, n - i0);
+    // y_r = e_c[i0 + r] - sum_{k in [c, i0)} L[i0 + r][k] x[k]; two threads per row
+    {
+      const int r = tid >> 1, h = tid & 1;
+      double s = 0.0;
+      if (r < nbi) {
+        const double* row = G + (size_t)(i0 + r) * n;
+        for (int k = c + h; k < i0; k += 2) s = fma(row[k], x[k], s);
+      }
+      part[r][h] = s;
+    }
+    __syncthreads();
+    if (tid < nbi) y[tid] = (i0 + tid == c ? 1.0 : 0.0) - (part[tid][0] + part[tid][1]);
+    __syncthreads();
+    // x[i0 + r] = sum_{t <= r} Linv_II[r][t] y[t]
+    if (tid < nbi) {
+      const double* li = Linv + (size_t)ib * NB * NB + (size_t)tid * NB;
+      double v = 0.0;
+      for (int t = 0; t <= tid; ++t) v = fma(li[t], y[t], v);
+      x[i0 + tid] = v;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += 256) T[(size_t)c * n + i] = x[i];
 }
 
 // ------------------------------------------------------------ Jacobi
@@ -574,47 +569,48 @@ double* misc_dbl(const Ctx& c, int n) {
 int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg) {
   const int M = c.r.M;
   double* G = c.at(c.L.phi);
-  double* Linv = c.at(c.L.R);
   double* Tt = c.at(c.L.V);
-  int* info = misc_int(c) + n;  // after perm
+  double* Lblk = c.at(c.L.R);     // inverses of the diagonal blocks
+  double* Pan = c.at(c.L.chol);   // panel scratch
+  int* fail = misc_int(c) + n;    // after perm
   double* shift = misc_dbl(c, n);
   // shift / trace(G) from the bound 11 (M n + n (n + 1)) u |Z|_2^2, |Z|_2^2 <= trace
   const double u = 1.1102230246251565e-16;
   const double srel = 11.0 * ((double)M * n + (double)n * (n + 1)) * u;
   (void)hipMemcpyAsync(shift, &srel, sizeof(double), hipMemcpyHostToDevice, c.st);
+  // Gram, optional shift, blocked Cholesky, then T = L^-T; returns the
+  // failure flag (synchronises the stream).
+  auto factor = [&](const double* src, bool shifted) {
+    gram(c, src, src, n, G);
+    hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(1024), 0, c.st, G, n,
+                       shifted ? (const double*)shift : (const double*)nullptr, fail);
+    chol_blocked_launch(G, n, n, Lblk, Pan, fail, nullptr, c.st);
+    hipLaunchKernelGGL(k_tri_inv_t<kCholNB>, dim3(n), dim3(256), 0, c.st, G, n, Lblk, Tt, fail);
+    int h = 0;
+    (void)hipMemcpyAsync(&h, fail, sizeof(int), hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    return h;
+  };
   const double* src = Z;
   int plain_ok = 0, pass = 0;
   const int max_passes = 10;
   for (; pass < max_passes && plain_ok < 2; ++pass) {
     const bool shifted = pass < 3;
-    gram(c, src, src, n, G);
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, c.st, G, Linv, n,
-                       shifted ? (const double*)shift : (const double*)nullptr, info);
-    int h_info = 0;
-    (void)hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, c.st);
-    (void)hipStreamSynchronize(c.st);
-    if (h_info != 0) {
+    if (factor(src, shifted)) {
       if (shifted) {
-        *msg = "shifted CholeskyQR broke down at pivot " + std::to_string(h_info);
+        *msg = "shifted CholeskyQR broke down";
         return 1;
       }
       // redo this step with the shift
-      gram(c, src, src, n, G);
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, c.st, G, Linv, n,
-                         (const double*)shift, info);
-      (void)hipMemcpyAsync(&h_info, info, sizeof(int), hipMemcpyDeviceToHost, c.st);
-      (void)hipStreamSynchronize(c.st);
-      if (h_info != 0) {
-        *msg = "CholeskyQR broke down at pivot " + std::to_string(h_info);
+      if (factor(src, true)) {
+        *msg = "CholeskyQR broke down";
         return 1;
       }
       plain_ok = 0;
     } else if (!shifted) {
       ++plain_ok;
     }
-    hipLaunchKernelGGL(k_transpose, dim3(blocks_for((size_t)n * n)), dim3(256), 0, c.st, Linv, Tt,
-                       n);
-    // next = src * Linv^T ; ping-pong through Z/Q so source and destination differ
+    // next = src * L^-T ; ping-pong through Z/Q so source and destination differ
     double* dst = (src == Q) ? Z : Q;
     gemm_nn(c, src, n, Tt, n, dst, n, M, n, n);
     src = dst;

@@ -13,7 +13,7 @@ struct EigLayout {
   size_t end = 0;
   int n = 0;        // working width of the randomized solver (columns)
   int Mdense = 0;   // dense Jacobi size (0 when not used)
-  size_t omega = 0, Z = 0, Q = 0, G = 0, R = 0, V = 0, ritz = 0, misc = 0, phi = 0;
+  size_t omega = 0, Z = 0, Q = 0, G = 0, R = 0, V = 0, ritz = 0, misc = 0, phi = 0, chol = 0;
 };
 
 // Columns the randomized solver can carry (K + oversample <= this).

@@ -24,7 +24,7 @@
 namespace fcpd {
 
 namespace {
-constexpr int NB = 128;
+constexpr int NB = kCholBlock;
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
 
@@ -92,14 +92,14 @@ __global__ __launch_bounds__(256) void k_build_system(const double* __restrict__
 // ------------------------------------------------------------- diagonal
 // Cholesky of the nb x nb diagonal block at (k0, k0), in LDS; writes L_kk back
 // (lower; the strict upper part is left as is) and Linv = L_kk^-1 (lower,
-// nb x nb, row-major with stride NB).  Breakdown sets sc->chol_fail.
+// nb x nb, row-major with stride NB).  Breakdown sets *chol_fail.
 __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int lda, int k0,
                                                      int nb, double* __restrict__ Linv,
-                                                     DevScalars* sc, int gate) {
+                                                     int* chol_fail, const int* done) {
   __shared__ double s[NB][NB + 1];
   __shared__ int fail;
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < nb * nb; e += nt) {
     const int r = e / nb, c = e % nb;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
     __syncthreads();
   }
   if (fail) {
-    if (tid == 0) sc->chol_fail = 1;
+    if (tid == 0) *chol_fail = 1;
     return;
   }
   for (int e = tid; e < nb * nb; e += nt) {
@@ -156,11 +156,11 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
 // through the cache (four threads share a row).
 __global__ __launch_bounds__(256) void k_panel(const double* __restrict__ A, int lda, int k0,
                                                int nb, int rows, const double* __restrict__ Linv,
-                                               double* __restrict__ P, const DevScalars* sc,
-                                               int gate) {
+                                               double* __restrict__ P, const int* chol_fail,
+                                               const int* done) {
   __shared__ double sL[NB][NB + 1];  // sL[t][c] = Linv[c][t]
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < NB * NB; e += 256) {
     const int c = e / NB, t = e % NB;
@@ -193,11 +193,11 @@ __global__ __launch_bounds__(256) void k_panel(const double* __restrict__ A, int
 constexpr int ST = 128, SK = 16;
 __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int lda, int k1, int R,
                                               const double* __restrict__ P, int nb,
-                                              const DevScalars* sc, int gate) {
+                                              const int* chol_fail, const int* done) {
   __shared__ double sa[SK][ST + 1];
   __shared__ double sb[SK][ST + 1];
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   // decode the lower-triangular tile index
   const int t = blockIdx.x;
   int bi = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -253,9 +253,9 @@ __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int lda, i
 __global__ __launch_bounds__(256) void k_store_panel(double* __restrict__ A, int lda, int k0,
                                                      int nb, int rows,
                                                      const double* __restrict__ P,
-                                                     const DevScalars* sc, int gate) {
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+                                                     const int* chol_fail, const int* done) {
+  if (done && *done) return;
+  if (*chol_fail) return;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)rows * nb) return;
   const int r = (int)(e / nb), c = (int)(e % nb);
@@ -405,6 +405,28 @@ void orig_prepare(const P4<T>* X, int M, double beta, char* ws, const OrigLayout
                      reinterpret_cast<double*>(ws + L.phi));
 }
 
+void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int* chol_fail,
+                         const int* done, hipStream_t st) {
+  const int nblk = (n + NB - 1) / NB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB;
+    const int nb = std::min(NB, n - k0);
+    double* Li = Linv + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, st, A, lda, k0, nb, Li, chol_fail,
+                       done);
+    const int R = n - k0 - nb;
+    if (R <= 0) continue;
+    hipLaunchKernelGGL(k_panel, dim3((R + 63) / 64), dim3(256), 0, st, A, lda, k0, nb, R, Li, P,
+                       chol_fail, done);
+    const int T_ = (R + ST - 1) / ST;
+    hipLaunchKernelGGL(k_syrk, dim3(T_ * (T_ + 1) / 2), dim3(256), 0, st, A, lda, k0 + nb, R, P,
+                       nb, chol_fail, done);
+    const size_t cnt = (size_t)R * nb;
+    hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, A,
+                       lda, k0, nb, R, P, chol_fail, done);
+  }
+}
+
 template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t st) {
   const OrigLayout& L = *a.L;
   const int M = a.M;
@@ -417,22 +439,7 @@ template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t s
   hipLaunchKernelGGL(k_build_system<T>, dim3(M), dim3(256), 0, st, Phi, A, a.P1, a.Yt, a.X, b, M,
                      a.lmbda, a.sc, g);
   const int nblk = (M + NB - 1) / NB;
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, M - k0);
-    double* Li = Linv + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, st, A, M, k0, nb, Li, a.sc, g);
-    const int R = M - k0 - nb;
-    if (R <= 0) continue;
-    hipLaunchKernelGGL(k_panel, dim3((R + 63) / 64), dim3(256), 0, st, A, M, k0, nb, R, Li, P,
-                       a.sc, g);
-    const int T_ = (R + ST - 1) / ST;
-    hipLaunchKernelGGL(k_syrk, dim3(T_ * (T_ + 1) / 2), dim3(256), 0, st, A, M, k0 + nb, R, P, nb,
-                       a.sc, g);
-    const size_t n = (size_t)R * nb;
-    hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, M,
-                       k0, nb, R, P, a.sc, g);
-  }
+  chol_blocked_launch(A, M, M, Linv, P, &a.sc->chol_fail, g ? &a.sc->done : nullptr, st);
   for (int kb = 0; kb < nblk; ++kb) {
     const int k0 = kb * NB;
     const int nb = std::min(NB, M - k0);

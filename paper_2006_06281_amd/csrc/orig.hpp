@@ -6,6 +6,8 @@
 
 namespace fcpd {
 
+constexpr int kCholBlock = 128;
+
 struct OrigLayout {
   size_t end = 0;
   size_t phi = 0, A = 0, rhs = 0, info = 0, misc = 0;
@@ -26,6 +28,14 @@ template <typename T> struct OrigArgs {
   P4<T>* Xnew;
   P4<T>* W;
 };
+// Blocked right-looking Cholesky (block width kCholBlock) of the lower
+// triangle of the n x n FP64 matrix A (row stride lda), in place.  Linv
+// receives the inverses of the diagonal blocks (ceil(n / NB) blocks of
+// NB x NB, row-major, lower), P is panel scratch of n x NB doubles.  A pivot
+// that is not positive sets *chol_fail and the remaining launches return at
+// once; with done != NULL nothing runs while *done is set.
+void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int* chol_fail,
+                         const int* done, hipStream_t st);
 template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t st);
 template <typename T>
 void orig_prepare(const P4<T>* X, int M, double beta, char* ws, const OrigLayout& L,
