@@ -54,7 +54,11 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # HBM traffic of the dominant kernel per dispatch, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
 # of known size; valid only while the kernel source is unchanged (sha256).
-TRAFFIC = {}
+TRAFFIC = {
+    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "7349c9c3e39526ce1f4bbfb174a817ff1b787e04dc03bd2a468233a671c938da",
+                     "bytes_per_dispatch": 38.47e6 + 21.00e6,
+                     "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
+}
 
 
 def log(*a):
