@@ -70,6 +70,15 @@ typedef enum {
   CPD_EIG_IMPORT = 2       /* caller supplies U (M x K) and Lam (K)            */
 } cpd_eig_mode;
 
+/* Bits of cpd_params.flags (0 = defaults).  By default a single handle sorts
+   its point sets along a Morton curve at init (the caller sees every
+   per-point array in its own order; the permutation is internal) and the
+   E-step skips 64-point tile pairs whose exponentials all underflow to +0,
+   which leaves every result bit-identical to the unskipped computation on
+   the same order.  Batched instances never reorder or skip. */
+#define CPD_FLAG_NO_SORT 1       /* keep the caller's order (implies NO_CULL)   */
+#define CPD_FLAG_NO_CULL 2       /* sort, but evaluate every tile               */
+
 typedef struct {
   int32_t abi_version;     /* must be CPD_ABI_VERSION                          */
   int32_t M, N, D;         /* 1 <= M, N <= 2^26; 1 <= D <= 3                   */
@@ -86,7 +95,7 @@ typedef struct {
   uint64_t seed;           /* TOPK: seed of the Gaussian test matrix           */
   double tol;              /* stop when |sigma2_new - sigma2| < tol            */
   int32_t max_iter;        /* iteration cap of cpd_register (> 0)              */
-  int32_t reserved;        /* must be 0                                        */
+  int32_t flags;           /* CPD_FLAG_* bits, 0 for the defaults              */
 } cpd_params;
 
 typedef struct {

@@ -27,6 +27,7 @@ CPD_E_DEVICE, CPD_E_NUMERIC, CPD_E_UNSUPPORTED = -4, -5, -6
 CPD_METHOD_ORIGINAL, CPD_METHOD_FAST = 0, 1
 CPD_PREC_FP64, CPD_PREC_FP32, CPD_PREC_BF16X = 0, 1, 2
 CPD_EIG_FULL, CPD_EIG_TOPK, CPD_EIG_IMPORT = 0, 1, 2
+CPD_FLAG_NO_SORT, CPD_FLAG_NO_CULL = 1, 2
 
 METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST}
 PRECISIONS = {"fp64": CPD_PREC_FP64, "fp32": CPD_PREC_FP32, "bf16x": CPD_PREC_BF16X}
@@ -53,7 +54,7 @@ class cpd_params(ctypes.Structure):
         ("eig_mode", ctypes.c_int32), ("K", ctypes.c_int32),
         ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
-        ("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32), ("flags", ctypes.c_int32),
     ]
 
 
@@ -163,12 +164,15 @@ def require_device():
 
 def make_params(M, N, D=3, beta=2.0, lam=3.0, w=0.1, sigma2_init=0.0, method="fast",
                 precision="fp32", eig_mode="full", K=0, oversample=20, power_iters=2,
-                seed=0, tol=1e-8, max_iter=1000) -> cpd_params:
+                seed=0, tol=1e-8, max_iter=1000, sort=True, cull=True) -> cpd_params:
+    """cpd_params; sort / cull map to the CPD_FLAG_NO_SORT / CPD_FLAG_NO_CULL
+    bits (spatial order of the points inside the library, far-tile culling)."""
+    flags = (0 if sort else CPD_FLAG_NO_SORT) | (0 if cull else CPD_FLAG_NO_CULL)
     return cpd_params(CPD_ABI_VERSION, int(M), int(N), int(D), float(beta), float(lam),
                       float(w), float(sigma2_init), METHODS.get(method, method),
                       PRECISIONS.get(precision, precision), EIG_MODES.get(eig_mode, eig_mode),
                       int(K), int(oversample), int(power_iters), int(seed), float(tol),
-                      int(max_iter), 0)
+                      int(max_iter), flags)
 
 
 def _ptr(t):

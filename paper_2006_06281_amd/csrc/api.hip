@@ -37,6 +37,8 @@ struct Layout {
   size_t total = 0;
   Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, badcols, badrows, llpart,
       sigpart, initpart, featX, featY;
+  Region permX, permY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
+  bool sorted = false, cull = false;
   Region U, lam, U64, tpart, GT, HT;
   EigLayout eig;
   OrigLayout orig;
@@ -101,6 +103,23 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   add(L, L.llpart, ((N + 255) / 256) * sizeof(double));
   add(L, L.sigpart, 2 * (size_t)sigma2_blocks<T>(p.M) * sizeof(double));
   add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
+  // Single handles keep their points in Morton order (batch members do not).
+  L.sorted = batch_chunk == 0 && !(p.flags & CPD_FLAG_NO_SORT);
+  L.cull = L.sorted && !(p.flags & CPD_FLAG_NO_CULL);
+  if (L.sorted) {
+    size_t n2 = 1;
+    while (n2 < std::max(M, N)) n2 <<= 1;
+    add(L, L.permX, M * sizeof(int));
+    add(L, L.permY, N * sizeof(int));
+    add(L, L.keys, n2 * sizeof(unsigned long long));
+    add(L, L.bbox, (size_t)order_bbox_doubles(p.M + p.N) * sizeof(double));
+    add(L, L.logdtmp, N * sizeof(T));
+    add(L, L.Xraw, M * p4);
+  }
+  if (L.cull) {
+    add(L, L.boxX, 2 * ((M + 63) / 64) * p4);
+    add(L, L.boxY, 2 * ((N + 63) / 64) * p4);
+  }
   L.Kcap = kcap_of(p);
   if (p.method == CPD_METHOD_FAST) {
     const size_t K = (size_t)L.Kcap;
@@ -140,6 +159,13 @@ struct cpd_ctx {
   std::string err;
   template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
   DevScalars* sc() const { return at<DevScalars>(L.sc); }
+  // caller row of internal model / scene row i (NULL: same order)
+  const int* permX() const { return L.sorted ? at<int>(L.permX) : nullptr; }
+  const int* permY() const { return L.sorted ? at<int>(L.permY) : nullptr; }
+  // device address of the iteration frame's origin (NULL: the caller's frame)
+  const double* origin() const { return L.sorted ? sc()->origin : nullptr; }
+  // model points in the caller's frame (internal order), for the Gram matrix
+  template <typename T> const P4<T>* Xgram() const { return at<P4<T>>(L.sorted ? L.Xraw : L.X); }
 };
 
 namespace {
@@ -190,7 +216,8 @@ cpd_status validate(const cpd_params* p) {
   }
   if (!(p->tol >= 0.0)) return fail(nullptr, CPD_E_ARG, "tol must be >= 0");
   if (p->max_iter < 1) return fail(nullptr, CPD_E_ARG, "max_iter must be >= 1");
-  if (p->reserved != 0) return fail(nullptr, CPD_E_ARG, "reserved must be 0");
+  if (p->flags & ~(CPD_FLAG_NO_SORT | CPD_FLAG_NO_CULL))
+    return fail(nullptr, CPD_E_ARG, "unknown bits in flags");
   if (p->precision == CPD_PREC_BF16X && p->method != CPD_METHOD_FAST)
     return fail(nullptr, CPD_E_UNSUPPORTED, "BF16X precision is implemented for the Fast method");
   if (p->precision == CPD_PREC_BF16X && p->D != 3)
@@ -242,6 +269,8 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.ev = ev;
   a.featX = h->at<__bf16>(L.featX);
   a.featY = h->at<__bf16>(L.featY);
+  a.boxX = L.cull ? h->at<P4<T>>(L.boxX) : nullptr;
+  a.boxY = L.cull ? h->at<P4<T>>(L.boxY) : nullptr;
   if (h->p.precision == CPD_PREC_BF16X)
     estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
   else
@@ -365,7 +394,13 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
   const Layout& L = h->L;
   const auto t0 = std::chrono::steady_clock::now();
   if (W0) {
-    phi_apply_launch<T>(h->at<P4<T>>(L.X), static_cast<const T*>(W0), h->at<P4<T>>(L.Xt), h->p.M,
+    const T* w0 = static_cast<const T*>(W0);
+    if (h->permX()) {  // into internal order (Xnew is free before the first step)
+      T* tmp = h->at<T>(L.Xnew);
+      gather_rows_launch<T>(w0, tmp, h->permX(), h->p.M, h->p.D, h->st);
+      w0 = tmp;
+    }
+    phi_apply_launch<T>(h->at<P4<T>>(L.X), w0, h->at<P4<T>>(L.Xt), h->p.M,
                         h->p.D, h->p.beta, h->st);
     if (!(h->p.sigma2_init > 0.0))
       reset_sigma2_launch<T>(h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D,
@@ -407,8 +442,11 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
     for (auto& e : pe.e) (void)hipEventDestroy(e);
   if (s.nonfinite == 2) status = fail(h, CPD_E_NUMERIC, "Cholesky factorisation broke down");
   else if (s.nonfinite) status = fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
-  if (X_out) unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(X_out), h->p.M, h->p.D, h->st);
-  if (W_out) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W_out), h->p.M, h->p.D, h->st);
+  if (X_out)
+    unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(X_out), h->p.M, h->p.D, h->st, h->permX(),
+                     h->origin());
+  if (W_out)
+    unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W_out), h->p.M, h->p.D, h->st, h->permX());
   HIPCHK(h, hipStreamSynchronize(h->st));
   const double total =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -431,6 +469,17 @@ cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
   init_launch<T>(static_cast<const T*>(X), static_cast<const T*>(Y), h->at<P4<T>>(L.X),
                  h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D, h->p.sigma2_init,
                  h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st);
+  if (L.sorted) {
+    // Morton order of X and Y (xs serves as the staging buffer: it holds
+    // max(M, N) rounded up to 256 points and is cleared below); Xt = X.
+    P4<T>* stage = h->at<P4<T>>(L.xs.bytes >= L.ys.bytes ? L.xs : L.ys);
+    spatial_order_launch<T>(h->at<P4<T>>(L.X), h->p.M, h->at<P4<T>>(L.Y), h->p.N,
+                            h->at<int>(L.permX), h->at<int>(L.permY),
+                            h->at<unsigned long long>(L.keys), h->at<double>(L.bbox), stage,
+                            h->at<P4<T>>(L.Xraw), h->sc(), h->st);
+    HIPCHK(h, hipMemcpyAsync(h->ws + L.Xt.off, h->ws + L.X.off, L.X.bytes, hipMemcpyDeviceToDevice,
+                             h->st));
+  }
   // W starts at 0 (so Xt = X); the padding of the prescaled copies stays 0
   HIPCHK(h, hipMemsetAsync(h->ws + L.W.off, 0, L.W.bytes, h->st));
   HIPCHK(h, hipMemsetAsync(h->ws + L.xs.off, 0, L.xs.bytes, h->st));
@@ -448,7 +497,7 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
   if (h->p.method == CPD_METHOD_ORIGINAL) {
     if (U_import || lam_import || omega)
       return fail(h, CPD_E_ARG, "the original method takes no eigen-prep arguments");
-    orig_prepare<T>(h->at<P4<T>>(L.X), h->p.M, h->p.beta, h->ws, L.orig, h->st);
+    orig_prepare<T>(h->Xgram<T>(), h->p.M, h->p.beta, h->ws, L.orig, h->st);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipStreamSynchronize(h->st));
     h->stage = Stage::Prepared;
@@ -459,13 +508,13 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     if (!U_import || !lam_import) return fail(h, CPD_E_ARG, "IMPORT needs U_import and lam_import");
     if (omega) return fail(h, CPD_E_ARG, "omega is only used by TOPK");
     import_eig_launch<T>(U_import, lam_import, h->at<T>(L.U), h->at<double>(L.lam),
-                         h->at<double>(L.U64), h->p.M, h->p.K, h->st);
+                         h->at<double>(L.U64), h->p.M, h->p.K, h->st, h->permX());
     h->K = h->p.K;
   } else {
     if (U_import || lam_import) return fail(h, CPD_E_ARG, "U_import/lam_import are for IMPORT only");
     if (omega && h->p.eig_mode != CPD_EIG_TOPK) return fail(h, CPD_E_ARG, "omega is for TOPK only");
     EigRun r{};
-    r.X = reinterpret_cast<const void*>(h->at<P4<T>>(L.X));
+    r.X = reinterpret_cast<const void*>(h->Xgram<T>());
     r.x_is_double = sizeof(T) == 8;
     r.M = h->p.M;
     r.beta = h->p.beta;
@@ -475,6 +524,11 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     r.power_iters = h->p.power_iters;
     r.seed = h->p.seed;
     r.omega = omega;
+    if (omega && h->permX()) {  // rows into internal order, in the solver's own buffer
+      double* om = reinterpret_cast<double*>(h->ws + L.eig.omega);
+      gather_rows_launch<double>(omega, om, h->permX(), h->p.M, L.eig.n, h->st);
+      r.omega = om;
+    }
     r.ws = h->ws;
     r.L = &L.eig;
     r.U64 = h->at<double>(L.U64);
@@ -499,10 +553,19 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
 template <typename T>
 cpd_status estep_impl(cpd_ctx* h, void* logd, void* P1, void* Yt, void* tbar) {
   const Layout& L = h->L;
-  enqueue_estep<T>(h, 0, static_cast<T*>(logd));
-  if (P1) HIPCHK(h, hipMemcpyAsync(P1, h->ws + L.P1.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
-  if (tbar) HIPCHK(h, hipMemcpyAsync(tbar, h->ws + L.tbar.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
-  if (Yt) unpack_launch<T>(h->at<P4<T>>(L.Yt), static_cast<T*>(Yt), h->p.M, h->p.D, h->st);
+  if (h->permX()) {
+    enqueue_estep<T>(h, 0, logd ? h->at<T>(L.logdtmp) : nullptr);
+    if (logd) scatter_rows_launch<T>(h->at<T>(L.logdtmp), static_cast<T*>(logd), h->permY(), h->p.N, 1, h->st);
+    if (P1) scatter_rows_launch<T>(h->at<T>(L.P1), static_cast<T*>(P1), h->permX(), h->p.M, 1, h->st);
+    if (tbar) scatter_rows_launch<T>(h->at<T>(L.tbar), static_cast<T*>(tbar), h->permX(), h->p.M, 1, h->st);
+  } else {
+    enqueue_estep<T>(h, 0, static_cast<T*>(logd));
+    if (P1) HIPCHK(h, hipMemcpyAsync(P1, h->ws + L.P1.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
+    if (tbar) HIPCHK(h, hipMemcpyAsync(tbar, h->ws + L.tbar.off, sizeof(T) * h->p.M, hipMemcpyDeviceToDevice, h->st));
+  }
+  if (Yt)
+    unpack_launch<T>(h->at<P4<T>>(L.Yt), static_cast<T*>(Yt), h->p.M, h->p.D, h->st, h->permX(),
+                     h->origin());
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->st));
   return CPD_OK;
@@ -519,7 +582,8 @@ __global__ void k_set_sigma2(DevScalars* sc, double s2) {
 template <typename T>
 cpd_status set_state_impl(cpd_ctx* h, const void* Xt, double sigma2) {
   const Layout& L = h->L;
-  pack_launch<T>(static_cast<const T*>(Xt), h->at<P4<T>>(L.Xt), h->p.M, h->p.D, h->st);
+  pack_launch<T>(static_cast<const T*>(Xt), h->at<P4<T>>(L.Xt), h->p.M, h->p.D, h->st, h->permX(),
+                 h->origin());
   hipLaunchKernelGGL(k_set_sigma2, dim3(1), dim3(64), 0, h->st, h->sc(), sigma2);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->st));
@@ -529,8 +593,10 @@ cpd_status set_state_impl(cpd_ctx* h, const void* Xt, double sigma2) {
 template <typename T>
 cpd_status get_state_impl(cpd_ctx* h, void* Xt, void* W, double* sigma2) {
   const Layout& L = h->L;
-  if (Xt) unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(Xt), h->p.M, h->p.D, h->st);
-  if (W) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W), h->p.M, h->p.D, h->st);
+  if (Xt)
+    unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(Xt), h->p.M, h->p.D, h->st, h->permX(),
+                     h->origin());
+  if (W) unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W), h->p.M, h->p.D, h->st, h->permX());
   DevScalars s;
   HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipGetLastError());
@@ -661,7 +727,9 @@ cpd_status cpd_eig_export(cpd_handle h, double* U_out, double* lam_out) {
   if (h->stage != Stage::Prepared || h->p.method != CPD_METHOD_FAST)
     return fail(h, CPD_E_STATE, "no eigenpairs prepared");
   if (!U_out && !lam_out) return fail(h, CPD_E_ARG, "nothing to export");
-  if (U_out)
+  if (U_out && h->permX())
+    scatter_rows_launch<double>(h->at<double>(h->L.U64), U_out, h->permX(), h->p.M, h->K, h->st);
+  else if (U_out)
     HIPCHK(h, hipMemcpyAsync(U_out, h->ws + h->L.U64.off, sizeof(double) * (size_t)h->p.M * h->K,
                              hipMemcpyDeviceToDevice, h->st));
   if (lam_out)

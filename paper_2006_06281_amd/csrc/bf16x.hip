@@ -132,14 +132,21 @@ __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int p
 }
 
 // Pass A partials: part[split][n] = sum over the split's model points of
-// 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.
+// 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
+// wave skips every 64-point model tile whose smallest exponent against its
+// scene tile reaches CullLimit (all its terms are +0).
 __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G, int Mpad, int N,
                                                     int m_chunk, const DevScalars* __restrict__ sc,
-                                                    float* __restrict__ part, int gate) {
+                                                    float* __restrict__ part,
+                                                    const P4<float>* __restrict__ boxX,
+                                                    const P4<float>* __restrict__ boxY, double w,
+                                                    int M, int gate) {
   if (gate && sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 scene columns
+  // the per-column offset the scene features carry (see k_feat_scene)
+  const float ref = (float)fmax(log2_c(sc->sigma2, 3, w, M, N), kRefFloor);
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(G, n0 + 16 * s + (lane & 15), lane);
@@ -147,12 +154,27 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   const int m1 = min(Mpad, m0 + m_chunk);
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  for (int mt = m0; mt < m1; mt += 16) {
-    const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+  const bool cull = boxX != nullptr && n0 < N &&
+                    cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
+  P4<float> blo{}, bhi{};
+  if (cull) {
+    blo = boxY[2 * (n0 >> 6)];
+    bhi = boxY[2 * (n0 >> 6) + 1];
+  }
+  const float lim = CullLimit<float>::value - ref;
+  for (int mt64 = m0; mt64 < m1; mt64 += 64) {
+    if (cull) {
+      const int t = mt64 >> 6;
+      if (box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) >= lim) continue;
+    }
+    const int me = min(m1, mt64 + 64);
+    for (int mt = mt64; mt < me; mt += 16) {
+      const bf16x8 a = load_op(F, mt + (lane & 15), lane);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-      acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+      for (int s = 0; s < 4; ++s) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+        acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+      }
     }
   }
 #pragma unroll
@@ -176,7 +198,9 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
                                                     const P4<float>* __restrict__ ys, int M,
                                                     int Npad, int n_chunk,
                                                     const DevScalars* __restrict__ sc,
-                                                    float* __restrict__ part, int gate) {
+                                                    float* __restrict__ part,
+                                                    const P4<float>* __restrict__ boxX,
+                                                    const P4<float>* __restrict__ boxY, int gate) {
   if (gate && sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 model columns
@@ -190,7 +214,24 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
+  // with boxes: skip 64-point scene tiles whose smallest exponent
+  // |u - v|^2 + min L_n against this wave's model tile reaches CullLimit
+  const bool cull = boxX != nullptr && m0 < M &&
+                    cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
+  P4<float> alo{}, ahi{};
+  if (cull) {
+    alo = boxX[2 * (m0 >> 6)];
+    ahi = boxX[2 * (m0 >> 6) + 1];
+  }
   for (int nt = nb; nt < ne; nt += 16) {
+    if (cull && (nt & 63) == 0) {
+      const int k = nt >> 6;
+      const P4<float> lo = boxY[2 * k];  // lo.w = min L_n of the tile
+      if (box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w >= CullLimit<float>::value) {
+        nt += 48;  // with the loop's 16: the next 64-point tile
+        continue;
+      }
+    }
     const bf16x8 a = load_op(G, nt + (lane & 15), lane);
     P4<float> yv[4];
 #pragma unroll
@@ -246,7 +287,7 @@ void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chun
     const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (lenp + s - 1) / s;
-    c = (c + 15) & ~15;
+    c = (c + 63) & ~63;  // splits start on 64-point tiles (far-tile culling)
     *chunk = c;
     *splits = (lenp + c - 1) / c;
   };
@@ -264,14 +305,14 @@ void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
                      a.w, a.M, a.D, a.featY, a.sc, gate);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
-                     a.featY, Mpad, a.N, a.chunkA, a.sc, a.partA, gate);
+                     a.featY, Mpad, a.N, a.chunkA, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
   colmerge_fix_launch<float>(a, st);
   hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 1,
                      a.w, a.M, a.D, a.featY, a.sc, gate);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
-                     a.featY, a.ys, a.M, Npad, a.chunkB, a.sc, a.partB, gate);
+                     a.featY, a.ys, a.M, Npad, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate);
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
   rowmerge_fix_launch<float>(a, st, /*relative=*/0);
   if (a.ev) (void)hipEventRecord(a.ev[4], st);

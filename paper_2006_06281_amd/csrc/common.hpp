@@ -28,6 +28,10 @@ struct DevScalars {
   int32_t bad_rows;     // rows that need the exact (rescaled) pass B
   int32_t nonfinite;    // 1: sigma^2 became NaN/Inf, 2: Cholesky breakdown
   int32_t chol_fail;    // the original method's factorisation broke down
+  double diam2;         // squared diagonal of the joint bounding box of X and Y
+                        // at init (gates far-tile culling; 0 = never)
+  double origin[3];     // the iteration's frame is the caller's minus origin
+                        // (centre of the scene's bounding box; 0 unless sorted)
 };
 
 __device__ __forceinline__ float fexp2(float v) { return __builtin_amdgcn_exp2f(v); }

@@ -31,25 +31,27 @@ namespace fcpd {
 
 // ---------------------------------------------------------------- prescale
 template <typename T>
+__device__ __forceinline__ P4<T> prescale_point(const P4<T>& p, T s) {
+  return P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
+}
+
+template <typename T>
 __device__ __forceinline__ void prescale_body(const P4<T>* __restrict__ Xt,
                                                   const P4<T>* __restrict__ Y,
                                                   P4<T>* __restrict__ xs,
                                                   P4<T>* __restrict__ ys, int M, int N,
                                                   DevScalars* sc, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const double sk = sqrt(kappa_of(sc->sigma2));
-  const T s = (T)sk;
+  const T s = (T)sqrt(kappa_of(sc->sigma2));
   const int i = bx_ * blockDim.x + threadIdx.x;
   if (i == 0) {
     sc->bad_cols = 0;
     sc->bad_rows = 0;
   }
   if (i < M) {
-    P4<T> p = Xt[i];
-    xs[i] = P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
+    xs[i] = prescale_point<T>(Xt[i], s);
   } else if (i < M + N) {
-    P4<T> p = Y[i - M];
-    ys[i - M] = P4<T>{p.x * s, p.y * s, p.z * s, (T)0};
+    ys[i - M] = prescale_point<T>(Y[i - M], s);
   }
 }
 
@@ -60,6 +62,63 @@ __global__ __launch_bounds__(256) void k_prescale(const P4<T>* __restrict__ Xt,
                                                   P4<T>* __restrict__ ys, int M, int N,
                                                   DevScalars* sc, int gate) {
   prescale_body<T>(Xt, Y, xs, ys, M, N, sc, gate, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Prescale plus the bounding box of every 64-point tile of the prescaled
+// model and scene.  Threads [0, M64) cover the model (M64 = M rounded up to
+// 64), the rest the scene, so every wave sits inside one tile.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prescale_box(const P4<T>* __restrict__ Xt,
+                                                      const P4<T>* __restrict__ Y,
+                                                      P4<T>* __restrict__ xs,
+                                                      P4<T>* __restrict__ ys, int M, int N,
+                                                      DevScalars* sc, int gate,
+                                                      P4<T>* __restrict__ boxX,
+                                                      P4<T>* __restrict__ boxY) {
+  if (gate && sc->done) return;
+  const T s = (T)sqrt(kappa_of(sc->sigma2));
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc->bad_cols = 0;
+    sc->bad_rows = 0;
+  }
+  const int M64 = (M + 63) & ~63;
+  const bool isX = i < M64;
+  const int k = isX ? i : i - M64;
+  const bool valid = k < (isX ? M : N);
+  const T inf = (T)__builtin_inf();
+  T lx = inf, ly = inf, lz = inf, hx = -inf, hy = -inf, hz = -inf, n2 = 0;
+  if (valid) {
+    const P4<T> q = prescale_point<T>(isX ? Xt[k] : Y[k], s);
+    if (isX)
+      xs[k] = q;
+    else
+      ys[k] = q;
+    lx = hx = q.x;
+    ly = hy = q.y;
+    lz = hz = q.z;
+    n2 = q.x * q.x + q.y * q.y + q.z * q.z;
+  }
+  lx = wave_min(lx);
+  ly = wave_min(ly);
+  lz = wave_min(lz);
+  hx = wave_max(hx);
+  hy = wave_max(hy);
+  hz = wave_max(hz);
+  n2 = wave_max(n2);
+  if ((threadIdx.x & 63) == 0 && valid) {
+    P4<T>* box = isX ? boxX : boxY;
+    const int t = k >> 6;
+    box[2 * t] = P4<T>{lx, ly, lz, (T)0};
+    box[2 * t + 1] = P4<T>{hx, hy, hz, n2};
+  }
 }
 
 // ------------------------------------------------------------------ pass A
@@ -79,48 +138,79 @@ __device__ __forceinline__ T sq3(const P4<T>& a, T bx, T by, T bz, T init) {
 }
 
 // part[blockIdx.y * N + n] = sum over this split's model points of
-// 2^(-(|y^_n - x^_m|^2 + ref)).
+// 2^(-(|y^_n - x^_m|^2 + ref)).  A wave owns 64 NB consecutive scene points
+// (lane + 64 j); with boxes it skips every 64-point model tile whose smallest
+// exponent against the wave's tiles reaches CullLimit (all its terms are +0).
 template <typename T, int D, int NB>
 __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int m_chunk, const DevScalars* __restrict__ sc,
-                                                double w, T* __restrict__ part, int gate, int bx_, int by_, int gx_) {
+                                                double w, T* __restrict__ part,
+                                                const P4<T>* __restrict__ boxX,
+                                                const P4<T>* __restrict__ boxY, int gate,
+                                                int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
   const T ref = (T)fmax(l2c, kRefFloor);
-  const int n0 = bx_ * (256 * NB) + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw0 = bx_ * (256 * NB) + wave * (64 * NB);
   const int m0 = by_ * m_chunk;
   const int m1 = min(M, m0 + m_chunk);
   T yx[NB], yy[NB], yz[NB], s[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int n = n0 + j * 256;
+    const int n = nw0 + 64 * j + lane;
     P4<T> p = n < N ? ys[n] : P4<T>{(T)0, (T)0, (T)0, (T)0};
     yx[j] = p.x;
     yy[j] = p.y;
     yz[j] = p.z;
     s[j] = (T)0;
   }
-  int m = m0;
-  for (; m + 4 <= m1; m += 4) {
-    P4<T> a0 = xs[m], a1 = xs[m + 1], a2 = xs[m + 2], a3 = xs[m + 3];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      T e0 = fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
-      T e1 = fexp2(-sq3<T, D>(a1, yx[j], yy[j], yz[j], ref));
-      T e2 = fexp2(-sq3<T, D>(a2, yx[j], yy[j], yz[j], ref));
-      T e3 = fexp2(-sq3<T, D>(a3, yx[j], yy[j], yz[j], ref));
-      s[j] += (e0 + e1) + (e2 + e3);
+  const bool cull = boxX != nullptr && nw0 < N &&
+                    cull_worthwhile(sc, (double)ref, (double)CullLimit<T>::value);
+  P4<T> blo{}, bhi{};
+  if (cull) {
+    const int t0 = nw0 >> 6, t1 = min((N + 63) >> 6, t0 + NB);
+    blo = boxY[2 * t0];
+    bhi = boxY[2 * t0 + 1];
+    for (int t = t0 + 1; t < t1; ++t) {
+      const P4<T> lo = boxY[2 * t], hi = boxY[2 * t + 1];
+      blo = P4<T>{fmin(blo.x, lo.x), fmin(blo.y, lo.y), fmin(blo.z, lo.z), (T)0};
+      bhi = P4<T>{fmax(bhi.x, hi.x), fmax(bhi.y, hi.y), fmax(bhi.z, hi.z), fmax(bhi.w, hi.w)};
     }
   }
-  for (; m < m1; ++m) {
-    P4<T> a0 = xs[m];
+  const T lim = CullLimit<T>::value - ref;
+  for (int mt = m0; mt < m1;) {
+    const int me = min(m1, (mt & ~63) + 64);
+    if (cull) {
+      const int t = mt >> 6;
+      if (box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) >= lim) {
+        mt = me;
+        continue;
+      }
+    }
+    int m = mt;
+    for (; m + 4 <= me; m += 4) {
+      P4<T> a0 = xs[m], a1 = xs[m + 1], a2 = xs[m + 2], a3 = xs[m + 3];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) s[j] += fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+      for (int j = 0; j < NB; ++j) {
+        T e0 = fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+        T e1 = fexp2(-sq3<T, D>(a1, yx[j], yy[j], yz[j], ref));
+        T e2 = fexp2(-sq3<T, D>(a2, yx[j], yy[j], yz[j], ref));
+        T e3 = fexp2(-sq3<T, D>(a3, yx[j], yy[j], yz[j], ref));
+        s[j] += (e0 + e1) + (e2 + e3);
+      }
+    }
+    for (; m < me; ++m) {
+      P4<T> a0 = xs[m];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) s[j] += fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+    }
+    mt = me;
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int n = n0 + j * 256;
+    const int n = nw0 + 64 * j + lane;
     if (n < N) part[(size_t)by_ * N + n] = s[j];
   }
 }
@@ -129,8 +219,11 @@ template <typename T, int D, int NB>
 __global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int m_chunk, const DevScalars* __restrict__ sc,
-                                                double w, T* __restrict__ part, int gate) {
-  colsum_body<T, D, NB>(xs, ys, M, N, m_chunk, sc, w, part, gate, blockIdx.x, blockIdx.y, gridDim.x);
+                                                double w, T* __restrict__ part,
+                                                const P4<T>* __restrict__ boxX,
+                                                const P4<T>* __restrict__ boxY, int gate) {
+  colsum_body<T, D, NB>(xs, ys, M, N, m_chunk, sc, w, part, boxX, boxY, gate, blockIdx.x,
+                        blockIdx.y, gridDim.x);
 }
 
 // L_n = ref + log2(sum_splits part + 2^(log2 c - ref)) into ys[n].w; flags
@@ -140,7 +233,8 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
                                                   P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
-                                                  double* __restrict__ llpart, int gate, int bx_, int by_, int gx_) {
+                                                  double* __restrict__ llpart,
+                                                  P4<T>* __restrict__ boxY, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
@@ -148,6 +242,7 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
   const T ref = (T)refd;
   const int n = bx_ * blockDim.x + threadIdx.x;
   double ln_d = 0.0;
+  T lmin = (T)__builtin_inf();
   if (n < N) {
     T s = (T)0;
     for (int k = 0; k < splits; ++k) s += part[(size_t)k * N + n];
@@ -161,6 +256,13 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
     ys[n].w = L;
     if (logd_out) logd_out[n] = (T)((double)L * kLn2);
     ln_d = (double)L * kLn2;
+    // a column the exact path will redo may only lower the tile minimum:
+    // its L here misses underflowed terms, or is not finite (then -inf)
+    lmin = isfinite(L) ? L : -(T)__builtin_inf();
+  }
+  if (boxY) {
+    lmin = wave_min(lmin);
+    if ((threadIdx.x & 63) == 0 && n < N) boxY[2 * (n >> 6)].w = lmin;
   }
   const double b = block_sum_d(ln_d, sh);
   if (threadIdx.x == 0) llpart[bx_] = b;
@@ -171,8 +273,10 @@ __global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, in
                                                   P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
-                                                  double* __restrict__ llpart, int gate) {
-  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, gate, blockIdx.x, blockIdx.y, gridDim.x);
+                                                  double* __restrict__ llpart,
+                                                  P4<T>* __restrict__ boxY, int gate) {
+  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, boxY, gate,
+                   blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Exact pass A for the flagged columns: two sweeps over all model points,
@@ -217,53 +321,86 @@ __global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
 
 // ------------------------------------------------------------------ pass B
 // part layout: [split][5][M]: r, sum p dx, sum p dy, sum p dz, sum p d2
-// (prescaled differences y^_n - x^_m).
+// (prescaled differences y^_n - x^_m).  A wave owns 64 NB consecutive model
+// points (lane + 64 j); with boxes it skips every 64-point scene tile whose
+// smallest exponent |y^ - x^|^2 + min L_n against the wave's tiles reaches
+// CullLimit (all its terms are +0).
 template <typename T, int D, int NB>
 __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int n_chunk, const DevScalars* __restrict__ sc,
-                                                T* __restrict__ part, int gate, int bx_, int by_, int gx_) {
+                                                T* __restrict__ part,
+                                                const P4<T>* __restrict__ boxX,
+                                                const P4<T>* __restrict__ boxY, int gate,
+                                                int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
-  const int m0 = bx_ * (256 * NB) + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mw0 = bx_ * (256 * NB) + wave * (64 * NB);
   const int nb = by_ * n_chunk;
   const int ne = min(N, nb + n_chunk);
   T ax[NB], ay[NB], az[NB], r[NB], px[NB], py[NB], pz[NB], t[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int m = m0 + j * 256;
+    const int m = mw0 + 64 * j + lane;
     P4<T> p = m < M ? xs[m] : P4<T>{(T)0, (T)0, (T)0, (T)0};
     ax[j] = p.x;
     ay[j] = p.y;
     az[j] = p.z;
     r[j] = px[j] = py[j] = pz[j] = t[j] = (T)0;
   }
-  for (int n = nb; n < ne; ++n) {
-    const P4<T> y = ys[n];  // (x^, y^, z^, L_n)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const T dx = y.x - ax[j];
-      T d2 = dx * dx;
-      T dy = (T)0, dz = (T)0;
-      if (D > 1) {
-        dy = y.y - ay[j];
-        d2 = fma(dy, dy, d2);
-      }
-      if (D > 2) {
-        dz = y.z - az[j];
-        d2 = fma(dz, dz, d2);
-      }
-      const T e = fexp2(-(d2 + y.w));
-      r[j] += e;
-      px[j] = fma(e, dx, px[j]);
-      if (D > 1) py[j] = fma(e, dy, py[j]);
-      if (D > 2) pz[j] = fma(e, dz, pz[j]);
-      t[j] = fma(e, d2, t[j]);
+  // (the gate takes L_n ~ 0: it only decides whether checking can pay)
+  const bool cull = boxX != nullptr && mw0 < M &&
+                    cull_worthwhile(sc, 0.0, (double)CullLimit<T>::value);
+  P4<T> alo{}, ahi{};
+  if (cull) {
+    const int t0 = mw0 >> 6, t1 = min((M + 63) >> 6, t0 + NB);
+    alo = boxX[2 * t0];
+    ahi = boxX[2 * t0 + 1];
+    for (int k = t0 + 1; k < t1; ++k) {
+      const P4<T> lo = boxX[2 * k], hi = boxX[2 * k + 1];
+      alo = P4<T>{fmin(alo.x, lo.x), fmin(alo.y, lo.y), fmin(alo.z, lo.z), (T)0};
+      ahi = P4<T>{fmax(ahi.x, hi.x), fmax(ahi.y, hi.y), fmax(ahi.z, hi.z), fmax(ahi.w, hi.w)};
     }
+  }
+  for (int nt = nb; nt < ne;) {
+    const int nE = min(ne, (nt & ~63) + 64);
+    if (cull) {
+      const int k = nt >> 6;
+      const P4<T> lo = boxY[2 * k];  // lo.w = min L_n of the tile
+      if (box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w >= CullLimit<T>::value) {
+        nt = nE;
+        continue;
+      }
+    }
+    for (int n = nt; n < nE; ++n) {
+      const P4<T> y = ys[n];  // (x^, y^, z^, L_n)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const T dx = y.x - ax[j];
+        T d2 = dx * dx;
+        T dy = (T)0, dz = (T)0;
+        if (D > 1) {
+          dy = y.y - ay[j];
+          d2 = fma(dy, dy, d2);
+        }
+        if (D > 2) {
+          dz = y.z - az[j];
+          d2 = fma(dz, dz, d2);
+        }
+        const T e = fexp2(-(d2 + y.w));
+        r[j] += e;
+        px[j] = fma(e, dx, px[j]);
+        if (D > 1) py[j] = fma(e, dy, py[j]);
+        if (D > 2) pz[j] = fma(e, dz, pz[j]);
+        t[j] = fma(e, d2, t[j]);
+      }
+    }
+    nt = nE;
   }
   T* base = part + (size_t)by_ * 5 * M;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int m = m0 + j * 256;
+    const int m = mw0 + 64 * j + lane;
     if (m < M) {
       base[m] = r[j];
       base[(size_t)M + m] = px[j];
@@ -278,8 +415,11 @@ template <typename T, int D, int NB>
 __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
                                                 int n_chunk, const DevScalars* __restrict__ sc,
-                                                T* __restrict__ part, int gate) {
-  rowsum_body<T, D, NB>(xs, ys, M, N, n_chunk, sc, part, gate, blockIdx.x, blockIdx.y, gridDim.x);
+                                                T* __restrict__ part,
+                                                const P4<T>* __restrict__ boxX,
+                                                const P4<T>* __restrict__ boxY, int gate) {
+  rowsum_body<T, D, NB>(xs, ys, M, N, n_chunk, sc, part, boxX, boxY, gate, blockIdx.x,
+                        blockIdx.y, gridDim.x);
 }
 
 // Row merge: P1_m = r_m, Yt_m = xt_m + (sum p (y - xt)) / r_m, tbar_m.
@@ -398,6 +538,12 @@ __global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
 
 // ------------------------------------------------------------- launchers
 template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st) {
+  if (a.boxX) {
+    const int nthr = ((a.M + 63) & ~63) + a.N;
+    hipLaunchKernelGGL(k_prescale_box<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y,
+                       a.xs, a.ys, a.M, a.N, a.sc, a.gate, a.boxX, a.boxY);
+    return;
+  }
   const int nthr = a.M + a.N;
   hipLaunchKernelGGL(k_prescale<T>, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
                      a.ys, a.M, a.N, a.sc, a.gate);
@@ -406,7 +552,8 @@ template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st
 template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st) {
   const int gate = a.gate;
   hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA, a.splitsA,
-                     a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, gate);
+                     a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, a.boxY,
+                     gate);
   switch (a.D) {
     case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
     case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
@@ -436,9 +583,9 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
     const int tiles = (a.N + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsA);
     switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_colsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
-      case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
-      default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, gate); break;
+      case 1: hipLaunchKernelGGL((k_colsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
+      case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
+      default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
     }
   }
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
@@ -448,9 +595,9 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
     const int tiles = (a.M + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsB);
     switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_rowsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
-      case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
-      default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, gate); break;
+      case 1: hipLaunchKernelGGL((k_rowsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
+      case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
+      default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
     }
   }
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
@@ -468,7 +615,7 @@ void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* ch
     const int smax = (len + 63) / 64;  // at least 64 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (len + s - 1) / s;
-    c = (c + 3) & ~3;
+    c = (c + 63) & ~63;  // splits start on 64-point tiles (far-tile culling)
     *chunk = c;
     *splits = (len + c - 1) / c;
   };
@@ -488,14 +635,15 @@ __global__ __launch_bounds__(256) void kb_colsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkA, D.sc, D.w, D.partA, 1, it.y, it.z, 0);
+  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkA, D.sc, D.w, D.partA,
+                           (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ d,
                                                    const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
-                       D.badcols, D.llpart, 1, it.y, 0, 0);
+                       D.badcols, D.llpart, (P4<float>*)nullptr, 1, it.y, 0, 0);
 }
 __global__ __launch_bounds__(256) void kb_colfix(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
@@ -508,7 +656,8 @@ __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkB, D.sc, D.partB, 1, it.y, it.z, 0);
+  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkB, D.sc, D.partB,
+                           (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ d,
                                                    const int4* __restrict__ items) {

@@ -26,8 +26,41 @@ template <typename T> struct EStepArgs {
   hipEvent_t* ev;    // nullable: 5 events recorded between the stages
   __bf16* featX;     // BF16X: model feature vectors (32 bf16 per point, padded)
   __bf16* featY;     // BF16X: scene feature vectors
+  // Far-tile culling (nullable: no culling).  Per 64-point tile of the
+  // prescaled points, box[2t] = lower corner, box[2t + 1] = upper corner;
+  // boxY[2t].w receives min L_n over the tile after pass A.
+  P4<T>* boxX;       // ceil(M / 64) tiles
+  P4<T>* boxY;       // ceil(N / 64) tiles
 };
 
+// A tile pair whose smallest possible base-2 exponent reaches this value
+// contributes exactly zero: 2^-160 (float) and 2^-1100 (double) are below
+// half the smallest subnormal, so every exp2 of the tile rounds to +0 and
+// skipping the tile leaves every sum bit-identical.
+template <typename T> struct CullLimit;
+template <> struct CullLimit<float> { static constexpr float value = 160.0f; };
+template <> struct CullLimit<double> { static constexpr double value = 1100.0; };
+
+// Lower bound of |u - v|^2 over u in box a, v in box b (corners lo, hi; hi.w
+// holds the largest squared norm of the tile's points).  2^-12 of the larger
+// squared norm is subtracted: it covers the rounding of the squared distances
+// the kernels compute (direct differences, or the split-bf16 dot products of
+// the matrix-core path).
+template <typename T>
+__device__ __forceinline__ T box_gap2(const P4<T>& alo, const P4<T>& ahi, const P4<T>& blo,
+                                      const P4<T>& bhi) {
+  const T gx = fmax(fmax(alo.x - bhi.x, blo.x - ahi.x), (T)0);
+  const T gy = fmax(fmax(alo.y - bhi.y, blo.y - ahi.y), (T)0);
+  const T gz = fmax(fmax(alo.z - bhi.z, blo.z - ahi.z), (T)0);
+  return gx * gx + gy * gy + gz * gz - (T)0x1p-12 * fmax(ahi.w, bhi.w);
+}
+
+// Whether tile checks can pay at this sigma^2: only when pairs half the
+// problem's diameter apart already underflow.  Skipping the checks is always
+// exact (every tile is evaluated), so this is a cost heuristic only.
+__device__ __forceinline__ bool cull_worthwhile(const DevScalars* sc, double ref, double limit) {
+  return 0.25 * sc->diam2 * kappa_of(sc->sigma2) + ref >= limit;
+}
 template <typename T> void estep_launch(const EStepArgs<T>& a, hipStream_t st);
 // pieces shared with the BF16X E-step
 template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st);
@@ -85,9 +118,15 @@ template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
                          double* part, hipStream_t st);
 
-// pack / unpack between row-major M x D arrays and P4 arrays
-template <typename T> void unpack_launch(const P4<T>* src, T* dst, int M, int D, hipStream_t st);
-template <typename T> void pack_launch(const T* src, P4<T>* dst, int M, int D, hipStream_t st);
+// pack / unpack between row-major M x D arrays and P4 arrays; with perm
+// (internal row i <-> caller row perm[i]) pack gathers and unpack scatters;
+// with origin (device, 3 doubles) pack subtracts and unpack adds it.
+template <typename T>
+void unpack_launch(const P4<T>* src, T* dst, int M, int D, hipStream_t st,
+                   const int* perm = nullptr, const double* origin = nullptr);
+template <typename T>
+void pack_launch(const T* src, P4<T>* dst, int M, int D, hipStream_t st,
+                 const int* perm = nullptr, const double* origin = nullptr);
 
 // Xt = X + Phi(X, beta) W (Phi formed on the fly), W row-major M x D
 template <typename T>
@@ -97,7 +136,30 @@ void phi_apply_launch(const P4<T>* X, const T* Wrm, P4<T>* Xt, int M, int D, dou
 // eigen-prep helpers
 template <typename T>
 void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam, double* U64,
-                       int M, int K, hipStream_t st);
+                       int M, int K, hipStream_t st, const int* perm = nullptr);
+
+// ---------------------------------------------------------- spatial order
+// Sorts the model and scene points (P4, in place) along a Morton (Z-order)
+// curve over their joint bounding box, so 64-point tiles are spatially
+// compact for far-tile culling.  permX[i] / permY[i] = the caller's row of
+// internal row i.  Scratch: keys (next power of two >= max(M, N) uint64),
+// bbox (order_bbox_doubles(M + N) doubles), tmp (max(M, N) P4).  Xraw
+// receives the sorted model points in the caller's frame; then both sets
+// are moved (in double) into the iteration's frame, centred on the scene's
+// bounding box: sc->origin.  sc->diam2 = squared diagonal of the joint box.
+int order_bbox_doubles(int n);
+template <typename T>
+void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* permY,
+                          unsigned long long* keys, double* bbox, P4<T>* tmp, P4<T>* Xraw,
+                          DevScalars* sc, hipStream_t st);
+// dst[i, :] = src[perm[i], :] (gather rows) and dst[perm[i], :] = src[i, :]
+// (scatter rows), row-major with `cols` columns.
+template <typename T>
+void gather_rows_launch(const T* src, T* dst, const int* perm, int rows, int cols,
+                        hipStream_t st);
+template <typename T>
+void scatter_rows_launch(const T* src, T* dst, const int* perm, int rows, int cols,
+                         hipStream_t st);
 
 }  // namespace fcpd
 

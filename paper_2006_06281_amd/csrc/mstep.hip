@@ -321,22 +321,36 @@ template <typename T> void sigma2_launch(const Sigma2Args<T>& a, hipStream_t st)
 // -------------------------------------------------------------------- init
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack(const T* __restrict__ src, P4<T>* __restrict__ dst,
-                                              P4<T>* __restrict__ dst2, int M, int D) {
+                                              P4<T>* __restrict__ dst2, int M, int D,
+                                              const int* __restrict__ perm,
+                                              const double* __restrict__ origin) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const T* s = src + (size_t)i * D;
+  const T* s = src + (size_t)(perm ? perm[i] : i) * D;
   P4<T> p{s[0], D > 1 ? s[1] : (T)0, D > 2 ? s[2] : (T)0, (T)0};
+  if (origin) {  // into the iteration's frame (shift in double)
+    p.x = (T)((double)p.x - origin[0]);
+    if (D > 1) p.y = (T)((double)p.y - origin[1]);
+    if (D > 2) p.z = (T)((double)p.z - origin[2]);
+  }
   dst[i] = p;
   if (dst2) dst2[i] = p;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(const P4<T>* __restrict__ src, T* __restrict__ dst,
-                                                int M, int D) {
+                                                int M, int D, const int* __restrict__ perm,
+                                                const double* __restrict__ origin) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
   const P4<T> p = src[i];
-  T* d = dst + (size_t)i * D;
+  T* d = dst + (size_t)(perm ? perm[i] : i) * D;
+  if (origin) {  // back to the caller's frame (shift in double)
+    d[0] = (T)((double)p.x + origin[0]);
+    if (D > 1) d[1] = (T)((double)p.y + origin[1]);
+    if (D > 2) d[2] = (T)((double)p.z + origin[2]);
+    return;
+  }
   d[0] = p.x;
   if (D > 1) d[1] = p.y;
   if (D > 2) d[2] = p.z;
@@ -401,6 +415,8 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
       sc->max_iter = max_iter;
       sc->bad_cols = 0;
       sc->bad_rows = 0;
+      sc->diam2 = 0.0;  // set by the spatial ordering when the handle sorts
+      sc->origin[0] = sc->origin[1] = sc->origin[2] = 0.0;
     }
   }
 }
@@ -411,9 +427,10 @@ template <typename T>
 void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int M, int N, int D,
                  double sigma2_init, double tol, int max_iter, DevScalars* sc, double* part,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, Xin, X, Xt, M, D);
+  hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, Xin, X, Xt, M, D,
+                     (const int*)nullptr, (const double*)nullptr);
   hipLaunchKernelGGL(k_pack<T>, dim3((N + 255) / 256), dim3(256), 0, st, Yin, Y, (P4<T>*)nullptr,
-                     N, D);
+                     N, D, (const int*)nullptr, (const double*)nullptr);
   const int blocks = init_blocks(M, N);
   hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
   hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D,
@@ -429,12 +446,17 @@ void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, D
                      0, 0, sc);
 }
 
-template <typename T> void unpack_launch(const P4<T>* src, T* dst, int M, int D, hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack<T>, dim3((M + 255) / 256), dim3(256), 0, st, src, dst, M, D);
+template <typename T>
+void unpack_launch(const P4<T>* src, T* dst, int M, int D, hipStream_t st, const int* perm,
+                   const double* origin) {
+  hipLaunchKernelGGL(k_unpack<T>, dim3((M + 255) / 256), dim3(256), 0, st, src, dst, M, D, perm,
+                     origin);
 }
-template <typename T> void pack_launch(const T* src, P4<T>* dst, int M, int D, hipStream_t st) {
+template <typename T>
+void pack_launch(const T* src, P4<T>* dst, int M, int D, hipStream_t st, const int* perm,
+                 const double* origin) {
   hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, src, dst,
-                     (P4<T>*)nullptr, M, D);
+                     (P4<T>*)nullptr, M, D, perm, origin);
 }
 
 // --------------------------------------------------------- Xt = X + Phi W
@@ -476,11 +498,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_import_eig(const double* __restrict__ Uin,
                                                     const double* __restrict__ lamin,
                                                     T* __restrict__ U, double* __restrict__ lam,
-                                                    double* __restrict__ U64, int M, int K) {
+                                                    double* __restrict__ U64, int M, int K,
+                                                    const int* __restrict__ perm) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t n = (size_t)M * K;
   if (i < n) {
-    const double v = Uin[i];
+    const size_t r = i / K, k = i % K;
+    const double v = Uin[(perm ? (size_t)perm[r] : r) * K + k];
     U[i] = (T)v;
     if (U64) U64[i] = v;
   }
@@ -489,11 +513,11 @@ __global__ __launch_bounds__(256) void k_import_eig(const double* __restrict__ U
 
 template <typename T>
 void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam, double* U64,
-                       int M, int K, hipStream_t st) {
+                       int M, int K, hipStream_t st, const int* perm) {
   const size_t n = (size_t)M * K;
   const size_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_import_eig<T>, dim3((unsigned)blocks), dim3(256), 0, st, Uin, lamin, U,
-                     lam, U64, M, K);
+                     lam, U64, M, K, perm);
 }
 
 // ------------------------------------------------------------ batched
@@ -572,12 +596,14 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
                                double, double, int, DevScalars*, double*, hipStream_t);      \
   template void reset_sigma2_launch<T>(const P4<T>*, const P4<T>*, int, int, int, DevScalars*, \
                                        double*, hipStream_t);                                 \
-  template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t);                   \
-  template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t);                    \
+  template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t, const int*,       \
+                                 const double*);                                              \
+  template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t, const int*,        \
+                               const double*);                                                \
   template void phi_apply_launch<T>(const P4<T>*, const T*, P4<T>*, int, int, double,         \
                                     hipStream_t);                                             \
   template void import_eig_launch<T>(const double*, const double*, T*, double*, double*, int,  \
-                                     int, hipStream_t);
+                                     int, hipStream_t, const int*);
 FCPD_INST(float)
 FCPD_INST(double)
 

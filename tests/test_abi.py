@@ -73,11 +73,15 @@ def test_bad_params_are_rejected(bad):
     assert e.value.status == fc.CPD_E_ARG
 
 
-def test_reserved_and_version_fields():
+def test_flags_and_version_fields():
     p = fc.make_params(10, 10)
-    p.reserved = 1
+    p.flags = 4  # not a CPD_FLAG_* bit
     with pytest.raises(fc.FastCPDError):
         fc.cpd_workspace_size(p)
+    # the sorted layout carries the permutation, key and tile-box buffers
+    sizes = [fc.cpd_workspace_size(fc.make_params(5000, 3000, sort=s, cull=c))
+             for s, c in ((False, False), (True, False), (True, True))]
+    assert sizes[0] < sizes[1] < sizes[2]
     p = fc.make_params(10, 10)
     p.abi_version = 99
     with pytest.raises(fc.FastCPDError):
