@@ -200,6 +200,26 @@ def cpd_mstep(X, P1, PY, Phi, lmbda, sigma2):
     return W, X + Phi @ W
 
 
+def cpdl_mstep(X, P1, PY, U, lam, lmbda, sigma2):
+    """CPD-L: eq. 21 with Phi replaced by its rank-K approximation
+    Phi~ = U diag(lam) U^T (eq. 19), solved with the matrix inversion lemma.
+
+    With A = lmbda sigma^2 d(P1)^-1 and t = A^-1 (d(P1)^-1 PY - X):
+      (A + U L U^T)^-1 = A^-1 - A^-1 U (L^-1 + U^T A^-1 U)^-1 U^T A^-1,
+    so W = t - A^-1 U z with S z = U^T t, S = L^-1 + U^T A^-1 U (K x K), and
+    Phi~ W = U L (U^T t - (S - L^-1) z) = U z.  Eigenpairs with lam <= 0
+    carry no part of Phi~ and are dropped.  Returns W and Xt = X + U z."""
+    p1 = np.maximum(P1, P1_FLOOR)
+    keep = lam > 0
+    U, lam = U[:, keep], lam[keep]
+    ainv = p1 / (lmbda * sigma2)                  # diagonal of A^-1
+    t = ainv[:, None] * (PY / p1[:, None] - X)
+    S = np.diag(1.0 / lam) + U.T @ (ainv[:, None] * U)
+    z = sla.cho_solve(sla.cho_factor(S, lower=True), U.T @ t)
+    Uz = U @ z
+    return t - ainv[:, None] * Uz, X + Uz
+
+
 def _weighted_sqdist(Xt_old, Y, sigma2, es: EStep, Xt_new, normalised: bool):
     """sum_mn q_mn |y_n - xt_new_m|^2 with q = p' (normalised) or q = p,
     the posterior taken at (Xt_old, sigma2)."""
@@ -273,7 +293,8 @@ def register(X, Y, beta, lmbda, w, method="fast", eig=None, Phi=None,
     """EM loop (order within an iteration: E-step at (Xt_k, sigma2_k), M-step
     with lmbda*sigma2_k, Xt_{k+1}, then sigma2_{k+1} from P'_k and Xt_{k+1}).
 
-    method: "fast" (eq. 5 + eq. 17/20; eig = (U, lam)) or "cpd" (eq. 21).
+    method: "fast" (eq. 5 + eq. 17/20; eig = (U, lam)), "cpd" (eq. 21) or
+    "cpdl" (eq. 21 with the rank-K Phi~ of eq. 19; eig = (U, lam)).
     iters: run exactly this many iterations (no tolerance stop) when given.
     """
     from . import eig64
@@ -282,7 +303,7 @@ def register(X, Y, beta, lmbda, w, method="fast", eig=None, Phi=None,
     M, D = X.shape
     if method == "cpd" or W0 is not None:
         Phi = eig64.gram(X, beta) if Phi is None else Phi
-    if method == "fast" and eig is None:
+    if method in ("fast", "cpdl") and eig is None:
         eig = eig64.eig_full(eig64.gram(X, beta) if Phi is None else Phi)
     Xt = X.copy() if W0 is None else X + Phi @ W0
     s2 = sigma2_init(Xt, Y) if not sigma2_0 else float(sigma2_0)
@@ -297,6 +318,9 @@ def register(X, Y, beta, lmbda, w, method="fast", eig=None, Phi=None,
         if method == "fast":
             W, Xn = fast_mstep(X, es.Yt, eig[0], eig[1], lmbda, s2)
             s2n = sigma2_fast(Xt, Y, s2, es, Xn)
+        elif method == "cpdl":
+            W, Xn = cpdl_mstep(X, es.P1, es.PY, eig[0], eig[1], lmbda, s2)
+            s2n = sigma2_cpd(Xt, Y, s2, es, Xn)
         else:
             W, Xn = cpd_mstep(X, es.P1, es.PY, Phi, lmbda, s2)
             s2n = sigma2_cpd(Xt, Y, s2, es, Xn)

@@ -209,3 +209,60 @@ def test_rmse_definition():
     A = np.array([[0.0, 0, 0], [1.0, 0, 0]])
     B = np.array([[0.0, 0, 3.0], [1.0, 4.0, 0]])
     assert cpd64.rmse(A, B) == pytest.approx(np.sqrt((9 + 16) / 2))
+
+
+def _low_rank(Phi, K):
+    lam, U = np.linalg.eigh(Phi)
+    o = np.argsort(lam)[::-1][:K]
+    return U[:, o], lam[o]
+
+
+def test_cpdl_equals_the_dense_solve_with_the_rank_k_gram():
+    # CPD-L: eq. 21 with Phi~ = U L U^T (eq. 19); the K x K inversion-lemma
+    # form must equal an M x M solve with Phi~ formed explicitly
+    X, Y, es, Phi = _problem(M=50, N=60, beta=1.2)
+    s2, lmbda = 0.25, 2.0
+    for K in (5, 17, 40):
+        U, lam = _low_rank(Phi, K)
+        Pt = (U * lam) @ U.T
+        p1 = es.P1
+        Wd = np.linalg.solve(Pt + lmbda * s2 * np.diag(1.0 / p1), es.PY / p1[:, None] - X)
+        W, Xt = cpd64.cpdl_mstep(X, es.P1, es.PY, U, lam, lmbda, s2)
+        np.testing.assert_allclose(W, Wd, rtol=1e-8, atol=1e-10 * np.abs(Wd).max())
+        np.testing.assert_allclose(Xt, X + Pt @ Wd, rtol=1e-10, atol=1e-12)
+
+
+def test_cpdl_at_full_rank_is_the_original_mstep():
+    X, Y, es, Phi = _problem(M=40, N=45, beta=0.6)   # Phi well conditioned
+    s2, lmbda = 0.3, 1.5
+    U, lam = _low_rank(Phi, 40)
+    assert lam.min() > 1e-8
+    W, Xt = cpd64.cpdl_mstep(X, es.P1, es.PY, U, lam, lmbda, s2)
+    W21, X21 = cpd64.cpd_mstep(X, es.P1, es.PY, Phi, lmbda, s2)
+    np.testing.assert_allclose(Xt, X21, rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(W, W21, rtol=1e-6, atol=1e-8 * np.abs(W21).max())
+
+
+def test_cpdl_w_is_a_stationary_point_of_the_rank_k_objective():
+    # eq. 11's objective with the unnormalised posterior and Phi~ in place of
+    # Phi: its gradient in W vanishes at CPD-L's W (finite differences)
+    X, Y, es, Phi = _problem(M=12, N=15, beta=0.8)
+    s2, lmbda = 0.3, 2.0
+    U, lam = _low_rank(Phi, 6)
+    Pt = (U * lam) @ U.T
+    P = np.exp(-cpd64.sqdist(X, Y) / (2 * s2) - es.logd[None, :])
+    W, _ = cpd64.cpdl_mstep(X, es.P1, es.PY, U, lam, lmbda, s2)
+    h = 1e-5
+    for (i, j) in [(0, 0), (5, 2), (11, 1)]:
+        E = np.zeros_like(W)
+        E[i, j] = h
+        g = (_Qf(W + E, X, Y, P, Pt, s2, lmbda) - _Qf(W - E, X, Y, P, Pt, s2, lmbda)) / (2 * h)
+        assert abs(g) < 1e-6
+
+
+def test_cpdl_registration_runs_and_lowers_sigma2():
+    p = synth.sphere_pair(M=120, N=130, seed=5, coef=0.05)
+    U, lam = _low_rank(eig64.gram(p.X, p.beta), 30)
+    r = cpd64.register(p.X, p.Y, p.beta, p.lam, p.w, "cpdl", eig=(U, lam), iters=30)
+    s = [t[0] for t in r.trace]
+    assert np.all(np.isfinite(r.Xt)) and s[-1] < 0.1 * s[0]
