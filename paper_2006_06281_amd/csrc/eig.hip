@@ -223,6 +223,118 @@ __global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A,
   }
 }
 
+// ------------------------------------------- Phi B on the FP64 matrix cores
+// C = Phi B for the Gram matrix of the points (eq. 11), B and C M x n
+// row-major, with v_mfma_f64_16x16x4f64 (A lane l: row l%16, k = l/16;
+// B lane l: k = l/16, column l%16; D lane l, register r: row 4r + l/16 of
+// column l%16 -- checked on the device).  Block: 128 rows x 128 columns, four waves of 32 rows x 128 columns
+// (2 x 8 accumulator tiles).  Each lane forms its own Phi operand in FP64
+// (one exp per row tile and k-step), so Phi never touches memory; the B
+// chunk (32 x 128) and the chunk's points are staged in LDS.
+constexpr int PR = 128, PC = 128, PK = 32;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// e^x for x <= 0 without branches: Cody-Waite reduction x = k ln2 + r,
+// |r| <= ln2 / 2 (ln2 split into a 32-bit head and its remainder, so k ln2
+// is exact for |k| < 2^21), e^r by its Taylor series to degree 13
+// (truncation below r^14 / 14! < 5e-18), and 2^k applied with v_ldexp_f64,
+// which also produces the subnormal results.  x is clamped at -746, where
+// e^x is below half the smallest subnormal.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  x = fmax(x, -746.0);
+  const double k = rint(x * 1.4426950408889634);
+  const double ln2_hi = 0.693147180369123816490;   // 32 significant bits
+  const double ln2_lo = 1.90821492927058770002e-10;
+  const double r = fma(-k, ln2_lo, fma(-k, ln2_hi, x));
+  double p = 1.0 / 6227020800.0;                     // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_phi_mfma(const P4<PT>* __restrict__ pts, int M,
+                                                  double inv2b2, const double* __restrict__ B,
+                                                  int n, double* __restrict__ C) {
+  __shared__ double sB[PK][PC];
+  __shared__ double sX[PK][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = blockIdx.x * PC, r0 = blockIdx.y * PR + wave * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  double xi[2][3];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int i = r0 + 16 * rt + li;
+    const P4<PT> p = i < M ? pts[i] : P4<PT>{(PT)0, (PT)0, (PT)0, (PT)0};
+    xi[rt][0] = p.x;
+    xi[rt][1] = p.y;
+    xi[rt][2] = p.z;
+  }
+  dbl4 acc[2][8];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) acc[rt][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < M; k0 += PK) {
+#pragma unroll
+    for (int q = 0; q < PK * PC / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int kr = e / PC, cc = e % PC;
+      const int k = k0 + kr, c = c0 + cc;
+      sB[kr][cc] = (k < M && c < n) ? B[(size_t)k * n + c] : 0.0;
+    }
+    if (tid < PK) {
+      const int k = k0 + tid;
+      const P4<PT> p = k < M ? pts[k] : P4<PT>{(PT)0, (PT)0, (PT)0, (PT)0};
+      sX[tid][0] = p.x;
+      sX[tid][1] = p.y;
+      sX[tid][2] = p.z;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ks = 0; ks < PK / 4; ++ks) {
+      const int kr = 4 * ks + lk;
+      const double x0 = sX[kr][0], x1 = sX[kr][1], x2 = sX[kr][2];
+      double a[2];  // (rows of k >= M meet zero rows of the staged B)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        const double dx = xi[rt][0] - x0, dy = xi[rt][1] - x1, dz = xi[rt][2] - x2;
+        a[rt] = exp_nonpos(-(dx * dx + dy * dy + dz * dz) * inv2b2);
+      }
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct) {
+        const double b = sB[kr][16 * ct + li];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      const int c = c0 + 16 * ct + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + 16 * rt + 4 * r + lk;
+        if (i < M && c < n) C[(size_t)i * n + c] = acc[rt][ct][r];
+      }
+    }
+}
+
 // Partial A^T B over a chunk of rows: P[chunk][a][b] = sum_{m in chunk}
 // A[m][a] B[m][b]; A, B are M x n row-major.
 __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
@@ -530,10 +642,10 @@ unsigned blocks_for(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t);
 template <typename PT>
 void phi_times(const Ctx& c, const double* B, double* C, int n) {
   const int M = c.r.M;
-  dim3 grid((n + TC - 1) / TC, (M + TI - 1) / TI);
+  dim3 grid((n + PC - 1) / PC, (M + PR - 1) / PR);
   const double inv2b2 = 1.0 / (2.0 * c.r.beta * c.r.beta);
-  hipLaunchKernelGGL((k_gemm_tile<PT, true>), grid, dim3(256), 0, c.st, (const double*)nullptr, 0,
-                     static_cast<const P4<PT>*>(c.r.X), inv2b2, B, n, C, n, M, M, n);
+  hipLaunchKernelGGL(k_phi_mfma<PT>, grid, dim3(256), 0, c.st, static_cast<const P4<PT>*>(c.r.X),
+                     M, inv2b2, B, n, C);
 }
 
 void gemm_nn(const Ctx& c, const double* A, int lda, const double* B, int ldb, double* C, int ldc,

@@ -92,7 +92,9 @@ __global__ __launch_bounds__(256) void k_build_system(const double* __restrict__
 // ------------------------------------------------------------- diagonal
 // Cholesky of the nb x nb diagonal block at (k0, k0), in LDS; writes L_kk back
 // (lower; the strict upper part is left as is) and Linv = L_kk^-1 (lower,
-// nb x nb, row-major with stride NB).  Breakdown sets *chol_fail.
+// nb x nb, row-major with stride NB).  Breakdown sets *chol_fail.  The
+// inverse is built in the tile's free upper triangle (Linv[r][c] at s[c][r]):
+// thread c runs the forward substitution of column c entirely in LDS.
 __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int lda, int k0,
                                                      int nb, double* __restrict__ Linv,
                                                      int* chol_fail, const int* done) {
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
   if (done && *done) return;
   if (*chol_fail) return;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5;  // 32 x 32 thread grid for updates
   for (int e = tid; e < nb * nb; e += nt) {
     const int r = e / nb, c = e % nb;
     s[r][c] = c <= r ? A[(size_t)(k0 + r) * lda + k0 + c] : 0.0;
@@ -122,10 +125,9 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
     const double piv = s[j][j];
     for (int r = j + 1 + tid; r < nb; r += nt) s[r][j] /= piv;
     __syncthreads();
-    const int len = nb - j - 1;
-    for (int e = tid; e < len * len; e += nt) {
-      const int r = j + 1 + e / len, c = j + 1 + e % len;
-      if (c <= r) s[r][c] -= s[r][j] * s[c][j];
+    for (int r = j + 1 + ty; r < nb; r += 32) {
+      const double lr = s[r][j];
+      for (int c = j + 1 + tx; c <= r; c += 32) s[r][c] -= lr * s[c][j];
     }
     __syncthreads();
   }
@@ -137,17 +139,21 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
     const int r = e / nb, c = e % nb;
     if (c <= r) A[(size_t)(k0 + r) * lda + k0 + c] = s[r][c];
   }
-  // Linv by forward substitution, one column per thread
-  for (int c = tid; c < nb; c += nt) {
-    for (int r = 0; r < nb; ++r) {
-      double v = 0.0;
-      if (r >= c) {
-        v = (r == c) ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) v -= s[r][k] * Linv[(size_t)k * NB + c];
-        v /= s[r][r];
-      }
-      Linv[(size_t)r * NB + c] = v;
+  if (tid < nb) {
+    const int c = tid;
+    const double dcc = 1.0 / s[c][c];
+    for (int r = c + 1; r < nb; ++r) {
+      double v = s[r][c] * dcc;
+      for (int k = c + 1; k < r; ++k) v = fma(s[r][k], s[c][k], v);
+      s[c][r] = -v / s[r][r];
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += nt) {
+    const int r = e / NB, c = e % NB;
+    double v = 0.0;
+    if (r < nb && c < nb) v = r == c ? 1.0 / s[r][r] : (r > c ? s[c][r] : 0.0);
+    Linv[e] = v;
   }
 }
 
