@@ -311,6 +311,52 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
             "run_s_w0": t_run0, "run_s_net": t_runw}
 
 
+def table4_leg(fc, torch, sizes=(4000, 8000, 12000, 16000, 20000, 24000), iters=50):
+    """The paper's scaling protocol (Section IV-B, Table IV) on synthetic
+    stand-ins: scene = a random spherical-harmonic surface of M points, model
+    = the same points under a random affine map; M = N; every method runs
+    exactly `iters` iterations; the low-rank variants keep K = 0.1 M
+    eigenpairs (randomized, p = 20, q = 2); beta = 2, lambda = 3, w = 0.1;
+    FP32 E-step everywhere (the original and CPD-L solves are FP64).
+    Times: t_eig (prepare, host wall), t_c / t_iter / t_o (device events
+    inside cpd_register), t_total = t_eig + the register call's wall time."""
+    import synth
+    methods = (("CPD", dict(method="original")),
+               ("CPD-L", dict(method="cpdl", eig_mode="topk")),
+               ("Fast-CPD", dict(method="fast", eig_mode="full")),
+               ("Fast-CPD-L", dict(method="fast", eig_mode="topk")))
+    rows = []
+    for M in sizes:
+        p = synth.affine_pair(M, seed=M)
+        X = torch.as_tensor(p.X, dtype=torch.float32).cuda().contiguous()
+        Y = torch.as_tensor(p.Y, dtype=torch.float32).cuda().contiguous()
+        for name, kw in methods:
+            k = dict(kw)
+            if k.get("eig_mode") == "topk":
+                k.update(K=M // 10, oversample=20, power_iters=2, seed=0)
+            r = fc.Registration(X, Y, precision="fp32", beta=p.beta, lam=p.lam, w=p.w, tol=0.0,
+                                max_iter=iters, **k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.prepare()
+            torch.cuda.synchronize()
+            t_eig = time.perf_counter() - t0 if name != "CPD" else 0.0
+            t0 = time.perf_counter()
+            out = r.register()
+            torch.cuda.synchronize()
+            run = time.perf_counter() - t0
+            rm = float(np.sqrt(((out.Xt.double().cpu().numpy() - p.Y_hat) ** 2).sum(1).mean()))
+            row = {"M": M, "method": name, "K": r.K if name != "CPD" else M, "iters": out.iters,
+                   "t_c": out.t_c, "t_eig": t_eig, "t_iter": out.t_iter, "t_o": out.t_o,
+                   "t_f": t_eig + out.t_iter, "t_total": t_eig + run, "rmse_eq22": rm}
+            rows.append(row)
+            log(f"table4 {M} {name}: " + ", ".join(f"{a}={b:.4g}" if isinstance(b, float) else
+                                                  f"{a}={b}" for a, b in row.items()))
+            r.close()
+        del X, Y
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,8 +370,9 @@ def main():
                     help="run two 256 MiB device-to-device copies first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--workload", default="surface50k",
-                    choices=["surface50k", "batch256", "warm2000"],
-                    help="batch256 / warm2000: that leg alone, one JSON line of its own")
+                    choices=["surface50k", "batch256", "warm2000", "table4"],
+                    help="batch256 / warm2000 / table4: that leg alone, one JSON line of "
+                         "its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -345,6 +392,20 @@ def main():
                           "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
                           "data": "synthetic", "config": {"workload": b["workload"]},
                           "batch": b}), flush=True)
+        return
+
+    if args.workload == "table4":
+        rows = table4_leg(fc, torch)
+        last = [r for r in rows if r["M"] == max(x["M"] for x in rows)]
+        fl = next(r for r in last if r["method"] == "Fast-CPD-L")
+        print(json.dumps({"metric": "Table IV protocol: total time (s), 50 iterations, per method "
+                                    "and size",
+                          "value": fl["t_total"], "unit": "s (Fast-CPD-L, largest size)",
+                          "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+                          "data": "synthetic",
+                          "config": {"workload": "table4: affine surface pairs M=N in "
+                                                 "{4k..24k}, K=0.1M, 50 iterations"},
+                          "table4": rows}), flush=True)
         return
 
     if args.workload == "warm2000":

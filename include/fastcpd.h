@@ -54,7 +54,10 @@ typedef enum {
 
 typedef enum {
   CPD_METHOD_ORIGINAL = 0, /* eq. 21: M x M SPD solve every iteration          */
-  CPD_METHOD_FAST = 1      /* eq. 5 + eq. 17 (eq. 20 when K < M)               */
+  CPD_METHOD_FAST = 1,     /* eq. 5 + eq. 17 (eq. 20 when K < M)               */
+  CPD_METHOD_ORIGINAL_LOWRANK = 2 /* CPD-L (Section IV-B): eq. 21 with the
+                              rank-K Gram of eq. 19, through a K x K system;
+                              eigen-prep as for FAST; FP32 / FP64            */
 } cpd_method;
 
 typedef enum {

@@ -24,12 +24,13 @@ CPD_OK, CPD_NOT_CONVERGED = 0, 1
 CPD_E_ARG, CPD_E_STATE, CPD_E_WORKSPACE = -1, -2, -3
 CPD_E_DEVICE, CPD_E_NUMERIC, CPD_E_UNSUPPORTED = -4, -5, -6
 
-CPD_METHOD_ORIGINAL, CPD_METHOD_FAST = 0, 1
+CPD_METHOD_ORIGINAL, CPD_METHOD_FAST, CPD_METHOD_ORIGINAL_LOWRANK = 0, 1, 2
 CPD_PREC_FP64, CPD_PREC_FP32, CPD_PREC_BF16X = 0, 1, 2
 CPD_EIG_FULL, CPD_EIG_TOPK, CPD_EIG_IMPORT = 0, 1, 2
 CPD_FLAG_NO_SORT, CPD_FLAG_NO_CULL = 1, 2
 
-METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST}
+METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST,
+           "cpdl": CPD_METHOD_ORIGINAL_LOWRANK}
 PRECISIONS = {"fp64": CPD_PREC_FP64, "fp32": CPD_PREC_FP32, "bf16x": CPD_PREC_BF16X}
 EIG_MODES = {"full": CPD_EIG_FULL, "topk": CPD_EIG_TOPK, "import": CPD_EIG_IMPORT}
 

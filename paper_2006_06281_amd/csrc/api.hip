@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 #include "net.hpp"
 #include "orig.hpp"
+#include "lowrank.hpp"
 
 using namespace fcpd;
 
@@ -42,6 +43,7 @@ struct Layout {
   Region U, lam, U64, tpart, GT, HT;
   EigLayout eig;
   OrigLayout orig;
+  LowRankLayout lr;
   int splitsA = 1, chunkA = 1, splitsB = 1, chunkB = 1;
   int mchunks = 1, mrows = 64;
   int Kcap = 0;
@@ -55,7 +57,7 @@ size_t add(Layout& L, Region& r, size_t bytes) {
 }
 
 int kcap_of(const cpd_params& p) {
-  if (p.method != CPD_METHOD_FAST) return 0;
+  if (p.method == CPD_METHOD_ORIGINAL) return 0;
   if (p.eig_mode == CPD_EIG_FULL) return eig_full_capacity(p.M);
   return p.K;
 }
@@ -121,7 +123,7 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     add(L, L.boxY, 2 * ((N + 63) / 64) * p4);
   }
   L.Kcap = kcap_of(p);
-  if (p.method == CPD_METHOD_FAST) {
+  if (p.method != CPD_METHOD_ORIGINAL) {  // FAST and CPD-L keep eigenpairs
     const size_t K = (size_t)L.Kcap;
     L.mchunks = fast_mstep_chunks<T>(p.M, &L.mrows);
     add(L, L.U, M * K * sizeof(T));
@@ -133,6 +135,10 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     if (p.eig_mode != CPD_EIG_IMPORT) {
       L.eig = eig_layout(p.M, p.eig_mode, p.K, p.oversample, L.total);
       L.total = L.eig.end;
+    }
+    if (p.method == CPD_METHOD_ORIGINAL_LOWRANK) {
+      L.lr = lowrank_layout(p.M, L.Kcap, L.total);
+      L.total = L.lr.end;
     }
   } else {
     L.orig = orig_layout(p.M, (int)sizeof(T), L.total);
@@ -197,11 +203,12 @@ cpd_status validate(const cpd_params* p) {
     return fail(nullptr, CPD_E_ARG, "lambda must be > 0");
   if (!(p->w >= 0.0 && p->w < 1.0)) return fail(nullptr, CPD_E_ARG, "w must satisfy 0 <= w < 1");
   if (!std::isfinite(p->sigma2_init)) return fail(nullptr, CPD_E_ARG, "sigma2_init not finite");
-  if (p->method != CPD_METHOD_ORIGINAL && p->method != CPD_METHOD_FAST)
+  if (p->method != CPD_METHOD_ORIGINAL && p->method != CPD_METHOD_FAST &&
+      p->method != CPD_METHOD_ORIGINAL_LOWRANK)
     return fail(nullptr, CPD_E_ARG, "unknown method");
   if (p->precision < CPD_PREC_FP64 || p->precision > CPD_PREC_BF16X)
     return fail(nullptr, CPD_E_ARG, "unknown precision");
-  if (p->method == CPD_METHOD_FAST) {
+  if (p->method != CPD_METHOD_ORIGINAL) {
     if (p->eig_mode < CPD_EIG_FULL || p->eig_mode > CPD_EIG_IMPORT)
       return fail(nullptr, CPD_E_ARG, "unknown eig_mode");
     if (p->eig_mode != CPD_EIG_FULL && (p->K < 1 || p->K > p->M))
@@ -300,6 +307,23 @@ void enqueue_mstep(cpd_ctx* h, int gate) {
     a.Xnew = h->at<P4<T>>(L.Xnew);
     a.W = h->at<P4<T>>(L.W);
     fast_mstep_launch<T>(a, h->st);
+  } else if (h->p.method == CPD_METHOD_ORIGINAL_LOWRANK) {
+    LowRankArgs<T> a{};
+    a.X = h->at<P4<T>>(L.X);
+    a.Yt = h->at<P4<T>>(L.Yt);
+    a.P1 = h->at<T>(L.P1);
+    a.U64 = h->at<double>(L.U64);
+    a.lam = h->at<double>(L.lam);
+    a.M = h->p.M;
+    a.K = h->K;
+    a.lmbda = h->p.lambda;
+    a.sc = h->sc();
+    a.gate = gate;
+    a.ws = h->ws;
+    a.L = &L.lr;
+    a.Xnew = h->at<P4<T>>(L.Xnew);
+    a.W = h->at<P4<T>>(L.W);
+    lowrank_mstep_launch<T>(a, h->st);
   } else {
     OrigArgs<T> a{};
     a.X = h->at<P4<T>>(L.X);
@@ -326,7 +350,7 @@ void enqueue_sigma2(cpd_ctx* h, int gate) {
   a.Xnew = h->at<P4<T>>(L.Xnew);
   a.Yt = h->at<P4<T>>(L.Yt);
   a.tbar = h->at<T>(L.tbar);
-  a.P1 = h->p.method == CPD_METHOD_ORIGINAL ? h->at<T>(L.P1) : nullptr;
+  a.P1 = h->p.method != CPD_METHOD_FAST ? h->at<T>(L.P1) : nullptr;  // N_P form
   a.M = h->p.M;
   a.N = h->p.N;
   a.D = h->p.D;
@@ -716,7 +740,7 @@ cpd_status cpd_eig_prepare(cpd_handle h, const double* U_import, const double* l
 
 cpd_status cpd_eig_count(cpd_handle h, int32_t* K_out) {
   if (!h || !K_out) return fail(h, CPD_E_ARG, "NULL argument");
-  if (h->stage != Stage::Prepared || h->p.method != CPD_METHOD_FAST)
+  if (h->stage != Stage::Prepared || h->p.method == CPD_METHOD_ORIGINAL)
     return fail(h, CPD_E_STATE, "no eigenpairs prepared");
   *K_out = h->K;
   return CPD_OK;
@@ -724,7 +748,7 @@ cpd_status cpd_eig_count(cpd_handle h, int32_t* K_out) {
 
 cpd_status cpd_eig_export(cpd_handle h, double* U_out, double* lam_out) {
   if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
-  if (h->stage != Stage::Prepared || h->p.method != CPD_METHOD_FAST)
+  if (h->stage != Stage::Prepared || h->p.method == CPD_METHOD_ORIGINAL)
     return fail(h, CPD_E_STATE, "no eigenpairs prepared");
   if (!U_out && !lam_out) return fail(h, CPD_E_ARG, "nothing to export");
   if (U_out && h->permX())

@@ -26,7 +26,8 @@
 namespace fcpd {
 
 namespace {
-constexpr int kTopKMaxCols = 2048;
+constexpr int kTopKMaxCols = 3072;   // K + oversample of the randomized solver
+constexpr int kFullMaxCols = 2048;   // widest basis of the adaptive FULL mode
 constexpr int kCholNB = kCholBlock;  // block width of the blocked Cholesky
 constexpr int kDenseMax = 1024;
 constexpr int kFullOversample = 32;
@@ -36,7 +37,7 @@ constexpr int kJacobiMax = kTopKMaxCols;
 // hundred eigenvalues) need 20-30 sweeps before no rotation is left.
 constexpr int kJacobiSweeps = 100;
 
-int full_widths_max(int M) { return std::min(M, kTopKMaxCols); }
+int full_widths_max(int M) { return std::min(M, kFullMaxCols); }
 
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 }  // namespace
@@ -870,6 +871,19 @@ int run(const EigRun& r, int* K_out, std::string* msg) {
 }
 
 }  // namespace
+
+size_t gram_partial_doubles(int M, int n) { return (size_t)n * n * gram_chunks(M, n); }
+
+void gram_sym_launch(const double* A, const double* B, int M, int n, double* G, double* partials,
+                     hipStream_t st) {
+  const int chunks = gram_chunks(M, n);
+  const int rows = (M + chunks - 1) / chunks;
+  const int nch = (M + rows - 1) / rows;
+  dim3 grid((n + TC - 1) / TC, (n + TI - 1) / TI, nch);
+  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, st, A, B, M, n, rows, partials);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st,
+                     partials, nch, n, G);
+}
 
 int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg) {
   const int rc = r.x_is_double ? run<double>(r, K_out, msg) : run<float>(r, K_out, msg);

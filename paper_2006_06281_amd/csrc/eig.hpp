@@ -42,4 +42,10 @@ int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg);
 
 template <typename T> void convert_u_launch(const double* U64, T* U, size_t n, hipStream_t st);
 
+// G = (A^T B + B^T A) / 2 for M x n row-major FP64 A, B (fixed-order
+// reduction over row chunks; partials: gram_partial_doubles(M, n) doubles).
+size_t gram_partial_doubles(int M, int n);
+void gram_sym_launch(const double* A, const double* B, int M, int n, double* G, double* partials,
+                     hipStream_t st);
+
 }  // namespace fcpd

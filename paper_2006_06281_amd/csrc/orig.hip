@@ -273,10 +273,10 @@ __global__ __launch_bounds__(256) void k_store_panel(double* __restrict__ A, int
 // b_i -= L[i, k-block] z_k for the rows below.
 __global__ __launch_bounds__(256) void k_fwd_diag(double* __restrict__ b, int k0, int nb,
                                                   const double* __restrict__ Linv,
-                                                  const DevScalars* sc, int gate) {
+                                                  const int* chol_fail, const int* done) {
   __shared__ double sb[NB][4];
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < nb * 4; e += 256) sb[e / 4][e % 4] = b[(size_t)(k0 + e / 4) * 4 + e % 4];
   __syncthreads();
@@ -290,11 +290,11 @@ __global__ __launch_bounds__(256) void k_fwd_diag(double* __restrict__ b, int k0
 
 __global__ __launch_bounds__(256) void k_fwd_update(double* __restrict__ b,
                                                     const double* __restrict__ A, int lda, int k0,
-                                                    int nb, int M, const DevScalars* sc,
-                                                    int gate) {
+                                                    int nb, int M, const int* chol_fail,
+                                                    const int* done) {
   __shared__ double sz[NB][4];
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < nb * 4; e += 256) sz[e / 4][e % 4] = b[(size_t)(k0 + e / 4) * 4 + e % 4];
   __syncthreads();
@@ -328,10 +328,10 @@ __global__ __launch_bounds__(256) void k_fwd_update(double* __restrict__ b,
 // Backward: w_k = Linv_k^T z_k, then z_i -= sum_t L[k0+t][i] w_k[t] for i < k0.
 __global__ __launch_bounds__(256) void k_bwd_diag(double* __restrict__ z, int k0, int nb,
                                                   const double* __restrict__ Linv,
-                                                  const DevScalars* sc, int gate) {
+                                                  const int* chol_fail, const int* done) {
   __shared__ double sz[NB][4];
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < nb * 4; e += 256) sz[e / 4][e % 4] = z[(size_t)(k0 + e / 4) * 4 + e % 4];
   __syncthreads();
@@ -345,10 +345,11 @@ __global__ __launch_bounds__(256) void k_bwd_diag(double* __restrict__ z, int k0
 
 __global__ __launch_bounds__(256) void k_bwd_update(double* __restrict__ z,
                                                     const double* __restrict__ A, int lda, int k0,
-                                                    int nb, const DevScalars* sc, int gate) {
+                                                    int nb, const int* chol_fail,
+                                                    const int* done) {
   __shared__ double sw[NB][4];
-  if (gate && sc->done) return;
-  if (sc->chol_fail) return;
+  if (done && *done) return;
+  if (*chol_fail) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < nb * 4; e += 256) sw[e / 4][e % 4] = z[(size_t)(k0 + e / 4) * 4 + e % 4];
   __syncthreads();
@@ -433,6 +434,30 @@ void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int
   }
 }
 
+void chol_solve_launch(const double* A, int lda, int n, const double* Linv, double* b,
+                       const int* chol_fail, const int* done, hipStream_t st) {
+  const int nblk = (n + NB - 1) / NB;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * NB;
+    const int nb = std::min(NB, n - k0);
+    const double* Li = Linv + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(k_fwd_diag, dim3(1), dim3(256), 0, st, b, k0, nb, Li, chol_fail, done);
+    const int R = n - k0 - nb;
+    if (R > 0)
+      hipLaunchKernelGGL(k_fwd_update, dim3((R + 15) / 16), dim3(256), 0, st, b, A, lda, k0, nb, n,
+                         chol_fail, done);
+  }
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    const int k0 = kb * NB;
+    const int nb = std::min(NB, n - k0);
+    const double* Li = Linv + (size_t)kb * NB * NB;
+    hipLaunchKernelGGL(k_bwd_diag, dim3(1), dim3(256), 0, st, b, k0, nb, Li, chol_fail, done);
+    if (k0 > 0)
+      hipLaunchKernelGGL(k_bwd_update, dim3((k0 + 255) / 256), dim3(256), 0, st, b, A, lda, k0, nb,
+                         chol_fail, done);
+  }
+}
+
 template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t st) {
   const OrigLayout& L = *a.L;
   const int M = a.M;
@@ -444,27 +469,9 @@ template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t s
   const int g = a.gate;
   hipLaunchKernelGGL(k_build_system<T>, dim3(M), dim3(256), 0, st, Phi, A, a.P1, a.Yt, a.X, b, M,
                      a.lmbda, a.sc, g);
-  const int nblk = (M + NB - 1) / NB;
-  chol_blocked_launch(A, M, M, Linv, P, &a.sc->chol_fail, g ? &a.sc->done : nullptr, st);
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, M - k0);
-    const double* Li = Linv + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(k_fwd_diag, dim3(1), dim3(256), 0, st, b, k0, nb, Li, a.sc, g);
-    const int R = M - k0 - nb;
-    if (R > 0)
-      hipLaunchKernelGGL(k_fwd_update, dim3((R + 15) / 16), dim3(256), 0, st, b, A, M, k0, nb, M,
-                         a.sc, g);
-  }
-  for (int kb = nblk - 1; kb >= 0; --kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, M - k0);
-    const double* Li = Linv + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(k_bwd_diag, dim3(1), dim3(256), 0, st, b, k0, nb, Li, a.sc, g);
-    if (k0 > 0)
-      hipLaunchKernelGGL(k_bwd_update, dim3((k0 + 255) / 256), dim3(256), 0, st, b, A, M, k0, nb,
-                         a.sc, g);
-  }
+  const int* done = g ? &a.sc->done : nullptr;
+  chol_blocked_launch(A, M, M, Linv, P, &a.sc->chol_fail, done, st);
+  chol_solve_launch(A, M, M, Linv, b, &a.sc->chol_fail, done, st);
   hipLaunchKernelGGL(k_phi_apply_stored<T>, dim3((M + 3) / 4), dim3(256), 0, st, Phi, b, a.X, M,
                      a.Xnew, a.W, a.sc, g);
 }

@@ -36,6 +36,10 @@ template <typename T> struct OrigArgs {
 // once; with done != NULL nothing runs while *done is set.
 void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int* chol_fail,
                          const int* done, hipStream_t st);
+// Solves L L^T x = b in place with the factor and block inverses left by
+// chol_blocked_launch; b holds n rows of 4 doubles (columns 0..2 used).
+void chol_solve_launch(const double* A, int lda, int n, const double* Linv, double* b,
+                       const int* chol_fail, const int* done, hipStream_t st);
 template <typename T> void orig_mstep_launch(const OrigArgs<T>& a, hipStream_t st);
 template <typename T>
 void orig_prepare(const P4<T>* X, int M, double beta, char* ws, const OrigLayout& L,

@@ -32,7 +32,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["PointPair", "sphere_pair", "surface_pair", "batch_pairs",
+__all__ = ["PointPair", "sphere_pair", "surface_pair", "batch_pairs", "affine_pair",
            "coef_std", "workload"]
 
 
@@ -190,6 +190,24 @@ def surface_pair(M=10000, N=None, seed=1, beta=2.0, lam=3.0, w=0.1,
     return PointPair(np.ascontiguousarray(X), Y, Y_hat, beta, lam, w, seed,
                      {"kind": "surface", "field_rms": field_rms, "outliers": outlier_frac,
                       "noise": noise, "outlier_box": outlier_box, "harmonics": surf.terms})
+
+
+def affine_pair(M=4000, seed=0, beta=2.0, lam=3.0, w=0.1, a_std=0.1, t_std=0.1):
+    """The scaling experiment's kind of input (Section IV-B): the scene is a
+    surface point set (a random spherical-harmonic surface stands in for the
+    scanned bunny), the model the same points under a random affine map
+    x = A y + t, A = I + N(0, a_std^2) entries, t ~ N(0, t_std^2).  No noise
+    or outliers.  Y_hat (the true position of each model point) is the scene
+    point it came from; the scene rows are shuffled."""
+    rng = np.random.default_rng(seed)
+    surf = _Surface(rng)
+    Y = surf.sample(rng, M, 0.02)
+    A = np.eye(3) + rng.normal(0.0, a_std, (3, 3))
+    t = rng.normal(0.0, t_std, 3)
+    X = Y @ A.T + t
+    perm = rng.permutation(M)
+    return PointPair(np.ascontiguousarray(X), np.ascontiguousarray(Y[perm]), Y.copy(), beta, lam,
+                     w, seed, {"kind": "affine", "A": A, "t": t})
 
 
 def batch_pairs(B=256, m_range=(500, 8000), seed0=1000, w=0.1,
