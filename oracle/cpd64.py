@@ -220,6 +220,54 @@ def cpdl_mstep(X, P1, PY, U, lam, lmbda, sigma2):
     return t - ainv[:, None] * Uz, X + Uz
 
 
+def nearest(A, B):
+    """For every row of A the index of its nearest row of B (squared
+    Euclidean distance, lowest index on ties)."""
+    out = np.empty(A.shape[0], dtype=np.int64)
+    for s, e in _chunks(A.shape[0], 2048):
+        out[s:e] = np.argmin(sqdist(A[s:e], B), axis=1)
+    return out
+
+
+def mutual_matches(Fixed, Moved):
+    """One-to-one correspondences after a registration of `Moved` onto
+    `Fixed`: for every fixed point f the nearest moved point m(f), kept only
+    when f is also m(f)'s nearest fixed point (mutual nearest neighbours);
+    -1 otherwise."""
+    fm = nearest(Fixed, Moved)
+    mf = nearest(Moved, Fixed)
+    return np.where(mf[fm] == np.arange(Fixed.shape[0]), fm, -1)
+
+
+def matched_mstep(X, Y, match, Phi, lmbda, sigma2):
+    """The transformation from given one-to-one correspondences (the second
+    half of the two-way scheme for one-sided occlusion, Section IV-A): eq. 21
+    with P1_m = 1 and PY_m = y_match(m) for matched model points and P1_m = 0
+    (an infinite penalty, so w_m = 0) for the rest.  On the matched set S:
+    (Phi_SS + lmbda sigma^2 I) W_S = Y_match(S) - X_S; then Xt = X + Phi_{:,S} W_S
+    moves every model point."""
+    S = np.flatnonzero(match >= 0)
+    W = np.zeros_like(X)
+    if S.size:
+        A = Phi[np.ix_(S, S)] + lmbda * sigma2 * np.eye(S.size)
+        W[S] = sla.cho_solve(sla.cho_factor(A, lower=True), Y[match[S]] - X[S])
+    return W, X + Phi @ W
+
+
+def register_two_way(X, Y, beta, lmbda, w, **kw):
+    """Two-way registration for a scene with missing points (Section IV-A):
+    register the scene onto the model first, take the mutual-nearest
+    one-to-one correspondences, then solve the model's transformation from
+    them (matched_mstep, with sigma^2 from the first registration).
+    Returns (Xt, W, match, first-stage result)."""
+    from . import eig64
+    rev = register(Y, X, beta, lmbda, w, "fast", **kw)
+    match = mutual_matches(X, rev.Xt)
+    Phi = eig64.gram(X, beta)
+    W, Xt = matched_mstep(X, Y, match, Phi, lmbda, rev.sigma2)
+    return Xt, W, match, rev
+
+
 def _weighted_sqdist(Xt_old, Y, sigma2, es: EStep, Xt_new, normalised: bool):
     """sum_mn q_mn |y_n - xt_new_m|^2 with q = p' (normalised) or q = p,
     the posterior taken at (Xt_old, sigma2)."""

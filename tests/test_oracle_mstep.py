@@ -266,3 +266,59 @@ def test_cpdl_registration_runs_and_lowers_sigma2():
     r = cpd64.register(p.X, p.Y, p.beta, p.lam, p.w, "cpdl", eig=(U, lam), iters=30)
     s = [t[0] for t in r.trace]
     assert np.all(np.isfinite(r.Xt)) and s[-1] < 0.1 * s[0]
+
+
+def test_nearest_and_mutual_matches_by_loops():
+    rng = np.random.default_rng(9)
+    F = rng.normal(size=(9, 3))
+    Mv = rng.normal(size=(7, 3))
+    Mv[3] = Mv[1]                     # a tie: the lower index wins
+    nn = cpd64.nearest(F, Mv)
+    for i in range(9):
+        d = [((F[i] - Mv[j]) ** 2).sum() for j in range(7)]
+        assert nn[i] == int(np.argmin(d))
+    mt = cpd64.mutual_matches(F, Mv)
+    for i in range(9):
+        j = nn[i]
+        back = int(np.argmin([((Mv[j] - F[k]) ** 2).sum() for k in range(9)]))
+        assert mt[i] == (j if back == i else -1)
+    assert 3 not in set(mt)
+
+
+def test_matched_mstep_with_identity_matches_is_eq15():
+    # every model point matched one-to-one: eq. 21 with P1 = 1 and PY = the
+    # matched scene points, i.e. eq. 15 with Yt = Y[match]
+    X, Y, es, Phi = _problem(M=30, N=30)
+    s2, lmbda = 0.2, 3.0
+    match = np.random.default_rng(2).permutation(30)
+    W, Xt = cpd64.matched_mstep(X, Y, match, Phi, lmbda, s2)
+    W15, X15 = cpd64.inverse_mstep(X, Y[match], Phi, lmbda, s2)
+    np.testing.assert_allclose(Xt, X15, rtol=1e-10, atol=1e-12)
+
+
+def test_matched_mstep_is_the_limit_of_eq21_with_vanishing_weights():
+    # unmatched rows: P1 -> 0 in eq. 21 drives their W to 0; the matched-set
+    # solve is that limit (P1 = 1e-12 on unmatched rows, PY = P1 Y[match])
+    X, Y, es, Phi = _problem(M=40, N=35, beta=0.9)
+    s2, lmbda = 0.3, 2.0
+    rng = np.random.default_rng(3)
+    match = np.where(rng.random(40) < 0.6, rng.integers(0, 35, 40), -1)
+    W, Xt = cpd64.matched_mstep(X, Y, match, Phi, lmbda, s2)
+    P1 = np.where(match >= 0, 1.0, 1e-12)
+    PY = P1[:, None] * np.where(match[:, None] >= 0, Y[np.maximum(match, 0)], 0.0)
+    W21, X21 = cpd64.cpd_mstep(X, P1, PY, Phi, lmbda, s2)
+    np.testing.assert_allclose(Xt, X21, rtol=1e-7, atol=1e-9)
+
+
+def test_two_way_recovers_a_deformation_with_missing_scene_points():
+    # the scene lacks a third of the model's points (one-sided occlusion):
+    # the two-way result is closer to the truth than the direct registration
+    p = synth.sphere_pair(M=300, N=300, seed=4, coef=0.03, outlier_frac=0.0)
+    keep = p.Y[:, 2] < 0.35                      # cut the scene's top cap
+    Y = p.Y[keep]
+    direct = cpd64.register(p.X, Y, p.beta, p.lam, 0.1, "fast", iters=60)
+    Xt, W, match, rev = cpd64.register_two_way(p.X, Y, p.beta, p.lam, 0.1, iters=60)
+    e_direct = cpd64.rmse(direct.Xt, p.Y_hat)
+    e_two = cpd64.rmse(Xt, p.Y_hat)
+    assert (match >= 0).sum() > 0.3 * Y.shape[0]
+    assert e_two < e_direct
