@@ -200,6 +200,31 @@ cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar);
 cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
+/* Two-way registration for a scene with missing points (Section IV-A): the
+   scene is first registered onto the model, one-to-one correspondences are
+   taken from that result, and the model's transformation is solved from
+   them.  These two calls provide the steps on top of cpd_register.
+
+   cpd_matches: for every scene point n of h (caller's row order) the
+   caller's row of the nearest transformed model point, -1 when mutual_only
+   and n is not also that point's nearest scene point (squared Euclidean
+   distance in the working precision, lowest index on ties).  match_out:
+   device, N int32.  Synchronises h's stream.
+
+   cpd_solve_matches: the transformation from given one-to-one
+   correspondences, eq. 21 with P1_m = 1 and PY_m = y_match[m] for matched
+   model points and P1_m = 0 (an infinite penalty: w_m = 0) for the rest,
+   evaluated with h's eigenpairs through the K x K system of CPD-L; every
+   model point moves (Xt = X + U z).  match: device, M int32, caller's scene
+   row or -1 (out-of-range entries count as unmatched).  sigma2 > 0 sets the
+   handle's sigma^2 (typically the first registration's final value).
+   X_out, W_out: device M x D or NULL; the handle's state becomes the result.
+   h: a prepared FAST or CPD-L handle (CPD_E_STATE otherwise); a system that
+   is not positive definite returns CPD_E_NUMERIC. */
+cpd_status cpd_matches(cpd_handle h, int32_t mutual_only, int32_t* match_out);
+cpd_status cpd_solve_matches(cpd_handle h, const int32_t* match, double sigma2, void* X_out,
+                             void* W_out);
+
 cpd_status cpd_destroy(cpd_handle h);
 
 /* ------------------------------------------------------------------ batch

@@ -39,6 +39,7 @@ EXPORTED = [
     "cpd_eig_export", "cpd_step", "cpd_register", "cpd_set_state",
     "cpd_get_state", "cpd_estep", "cpd_destroy", "cpd_status_str",
     "cpd_last_error", "cpd_abi_version", "cpd_build_info", "cpd_time_kernels",
+    "cpd_matches", "cpd_solve_matches",
     "cpd_batch_workspace_size", "cpd_batch_init", "cpd_batch_prepare", "cpd_batch_register",
     "cpd_batch_info", "cpd_batch_destroy",
     "cpdnet_param_count", "cpdnet_init", "cpdnet_workspace_size", "cpdnet_forward",
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "cpd_estep": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "cpd_destroy": ([vp], ctypes.c_int),
         "cpd_time_kernels": ([vp, ctypes.c_int32, P(ctypes.c_double)], ctypes.c_int),
+        "cpd_matches": ([vp, ctypes.c_int32, vp], ctypes.c_int),
+        "cpd_solve_matches": ([vp, vp, ctypes.c_double, vp, vp], ctypes.c_int),
         "cpd_batch_workspace_size": ([ctypes.c_int32, P(cpd_params), P(sz)], ctypes.c_int),
         "cpd_batch_init": ([P(vp), ctypes.c_int32, P(cpd_params), vp, vp, P(ctypes.c_int64),
                             P(ctypes.c_int64), vp, sz, vp], ctypes.c_int),
@@ -481,6 +484,24 @@ class Registration:
         s2 = cpd_get_state(self.h, Xt, W)
         return Xt, W, s2
 
+    def matches(self, mutual_only=True):
+        """For every scene point the nearest transformed model point (caller's
+        rows), -1 for pairs that are not mutual nearest neighbours."""
+        import torch
+        out = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        _check(load_library().cpd_matches(self.h, int(bool(mutual_only)), _ptr(out)), self.h)
+        return out
+
+    def solve_matches(self, match, sigma2):
+        """The model's transformation from one-to-one correspondences (match:
+        M int32 CUDA tensor, scene row or -1): (Xt, W)."""
+        import torch
+        Xt = torch.empty(self.M, self.D, dtype=self.dtype, device=self.device)
+        W = torch.empty_like(Xt)
+        _check(load_library().cpd_solve_matches(self.h, _ptr(match), float(sigma2), _ptr(Xt),
+                                                _ptr(W)), self.h)
+        return Xt, W
+
     def register(self, W0=None) -> RegistrationResult:
         import torch
         Xt = torch.empty(self.M, self.D, dtype=self.dtype, device=self.device)
@@ -499,3 +520,25 @@ class Registration:
             self.close()
         except Exception:
             pass
+
+
+def register_two_way(X, Y, stream=None, **kw):
+    """Two-way registration for a scene with missing points (Section IV-A):
+    register Y onto X, take the mutual-nearest one-to-one correspondences,
+    then solve X's transformation from them with sigma^2 from the first
+    stage.  kw: Registration parameters (method FAST or CPD-L).  Returns
+    (Xt, W, match, first-stage RegistrationResult)."""
+    rev = Registration(Y, X, stream=stream, **kw)
+    try:
+        rev.prepare()
+        first = rev.register()
+        match = rev.matches(mutual_only=True)
+    finally:
+        rev.close()
+    fwd = Registration(X, Y, stream=stream, **kw)
+    try:
+        fwd.prepare()
+        Xt, W = fwd.solve_matches(match, first.sigma2)
+    finally:
+        fwd.close()
+    return Xt, W, match, first

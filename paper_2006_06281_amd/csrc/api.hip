@@ -38,7 +38,7 @@ struct Layout {
   size_t total = 0;
   Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, badcols, badrows, llpart,
       sigpart, initpart, featX, featY;
-  Region permX, permY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
+  Region permX, permY, invY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
   bool sorted = false, cull = false;
   Region U, lam, U64, tpart, GT, HT;
   EigLayout eig;
@@ -113,6 +113,7 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     while (n2 < std::max(M, N)) n2 <<= 1;
     add(L, L.permX, M * sizeof(int));
     add(L, L.permY, N * sizeof(int));
+    add(L, L.invY, N * sizeof(int));
     add(L, L.keys, n2 * sizeof(unsigned long long));
     add(L, L.bbox, (size_t)order_bbox_doubles(p.M + p.N) * sizeof(double));
     add(L, L.logdtmp, N * sizeof(T));
@@ -136,7 +137,9 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
       L.eig = eig_layout(p.M, p.eig_mode, p.K, p.oversample, L.total);
       L.total = L.eig.end;
     }
-    if (p.method == CPD_METHOD_ORIGINAL_LOWRANK) {
+    // the K x K system: CPD-L's M-step, and the matched solve of two-way
+    // registration on a single Fast handle
+    if (p.method == CPD_METHOD_ORIGINAL_LOWRANK || batch_chunk == 0) {
       L.lr = lowrank_layout(p.M, L.Kcap, L.total);
       L.total = L.lr.end;
     }
@@ -168,6 +171,7 @@ struct cpd_ctx {
   // caller row of internal model / scene row i (NULL: same order)
   const int* permX() const { return L.sorted ? at<int>(L.permX) : nullptr; }
   const int* permY() const { return L.sorted ? at<int>(L.permY) : nullptr; }
+  const int* invY() const { return L.sorted ? at<int>(L.invY) : nullptr; }
   // device address of the iteration frame's origin (NULL: the caller's frame)
   const double* origin() const { return L.sorted ? sc()->origin : nullptr; }
   // model points in the caller's frame (internal order), for the Gram matrix
@@ -498,7 +502,7 @@ cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
     // max(M, N) rounded up to 256 points and is cleared below); Xt = X.
     P4<T>* stage = h->at<P4<T>>(L.xs.bytes >= L.ys.bytes ? L.xs : L.ys);
     spatial_order_launch<T>(h->at<P4<T>>(L.X), h->p.M, h->at<P4<T>>(L.Y), h->p.N,
-                            h->at<int>(L.permX), h->at<int>(L.permY),
+                            h->at<int>(L.permX), h->at<int>(L.permY), h->at<int>(L.invY),
                             h->at<unsigned long long>(L.keys), h->at<double>(L.bbox), stage,
                             h->at<P4<T>>(L.Xraw), h->sc(), h->st);
     HIPCHK(h, hipMemcpyAsync(h->ws + L.Xt.off, h->ws + L.X.off, L.X.bytes, hipMemcpyDeviceToDevice,
@@ -600,7 +604,60 @@ __global__ void k_set_sigma2(DevScalars* sc, double s2) {
     sc->sigma2 = s2;
     sc->done = 0;
     sc->converged = 0;
+    sc->nonfinite = 0;
+    sc->chol_fail = 0;
   }
+}
+
+template <typename T>
+cpd_status matches_impl(cpd_ctx* h, int mutual_only, int32_t* out) {
+  const Layout& L = h->L;
+  matches_launch<T>(h->at<P4<T>>(L.Xt), h->p.M, h->at<P4<T>>(L.Y), h->p.N, mutual_only,
+                    h->permX(), h->permY(), h->at<int>(L.badrows), h->at<int>(L.badcols), out,
+                    h->st);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
+}
+
+template <typename T>
+cpd_status solve_matches_impl(cpd_ctx* h, const int32_t* match, double sigma2, void* X_out,
+                              void* W_out) {
+  const Layout& L = h->L;
+  hipLaunchKernelGGL(k_set_sigma2, dim3(1), dim3(64), 0, h->st, h->sc(), sigma2);
+  match_in_launch<T>(match, h->p.M, h->p.N, h->permX(), h->invY(), h->at<P4<T>>(L.X),
+                     h->at<P4<T>>(L.Y), h->at<T>(L.P1), h->at<P4<T>>(L.Yt), h->st);
+  LowRankArgs<T> a{};
+  a.X = h->at<P4<T>>(L.X);
+  a.Yt = h->at<P4<T>>(L.Yt);
+  a.P1 = h->at<T>(L.P1);
+  a.U64 = h->at<double>(L.U64);
+  a.lam = h->at<double>(L.lam);
+  a.M = h->p.M;
+  a.K = h->K;
+  a.lmbda = h->p.lambda;
+  a.sc = h->sc();
+  a.gate = 0;
+  a.ws = h->ws;
+  a.L = &L.lr;
+  a.Xnew = h->at<P4<T>>(L.Xnew);
+  a.W = h->at<P4<T>>(L.W);
+  lowrank_mstep_launch<T>(a, h->st);
+  HIPCHK(h, hipMemcpyAsync(h->ws + L.Xt.off, h->ws + L.Xnew.off, L.Xt.bytes, hipMemcpyDeviceToDevice,
+                           h->st));
+  DevScalars s{};
+  HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  if (s.nonfinite) return fail(h, CPD_E_NUMERIC, "the matched system is not positive definite");
+  if (X_out)
+    unpack_launch<T>(h->at<P4<T>>(L.Xt), static_cast<T*>(X_out), h->p.M, h->p.D, h->st, h->permX(),
+                     h->origin());
+  if (W_out)
+    unpack_launch<T>(h->at<P4<T>>(L.W), static_cast<T*>(W_out), h->p.M, h->p.D, h->st, h->permX());
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return CPD_OK;
 }
 
 template <typename T>
@@ -793,6 +850,24 @@ cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar) {
   if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
   return is_f64(h) ? estep_impl<double>(h, logd, P1, Yt, tbar)
                    : estep_impl<float>(h, logd, P1, Yt, tbar);
+}
+
+cpd_status cpd_matches(cpd_handle h, int32_t mutual_only, int32_t* match_out) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  if (!match_out) return fail(h, CPD_E_ARG, "match_out is NULL");
+  return is_f64(h) ? matches_impl<double>(h, mutual_only != 0, match_out)
+                   : matches_impl<float>(h, mutual_only != 0, match_out);
+}
+
+cpd_status cpd_solve_matches(cpd_handle h, const int32_t* match, double sigma2, void* X_out,
+                             void* W_out) {
+  if (!h) return fail(nullptr, CPD_E_ARG, "handle is NULL");
+  if (!match) return fail(h, CPD_E_ARG, "match is NULL");
+  if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(h, CPD_E_ARG, "sigma2 must be > 0");
+  if (h->stage != Stage::Prepared || h->p.method == CPD_METHOD_ORIGINAL)
+    return fail(h, CPD_E_STATE, "cpd_solve_matches needs a prepared FAST or CPD-L handle");
+  return is_f64(h) ? solve_matches_impl<double>(h, match, sigma2, X_out, W_out)
+                   : solve_matches_impl<float>(h, match, sigma2, X_out, W_out);
 }
 
 cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms) {

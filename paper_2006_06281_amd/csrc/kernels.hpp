@@ -143,15 +143,28 @@ void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam
 // curve over their joint bounding box, so 64-point tiles are spatially
 // compact for far-tile culling.  permX[i] / permY[i] = the caller's row of
 // internal row i.  Scratch: keys (next power of two >= max(M, N) uint64),
-// bbox (order_bbox_doubles(M + N) doubles), tmp (max(M, N) P4).  Xraw
+// bbox (order_bbox_doubles(M + N) doubles), tmp (max(M, N) P4).  invY is
+// the inverse of permY (internal row of a caller's scene row).  Xraw
 // receives the sorted model points in the caller's frame; then both sets
 // are moved (in double) into the iteration's frame, centred on the scene's
 // bounding box: sc->origin.  sc->diam2 = squared diagonal of the joint box.
 int order_bbox_doubles(int n);
 template <typename T>
 void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* permY,
-                          unsigned long long* keys, double* bbox, P4<T>* tmp, P4<T>* Xraw,
-                          DevScalars* sc, hipStream_t st);
+                          int* invY, unsigned long long* keys, double* bbox, P4<T>* tmp,
+                          P4<T>* Xraw, DevScalars* sc, hipStream_t st);
+// ------------------------------------------------------- two-way matching
+// out (N, caller order): for every scene point its nearest transformed model
+// point (caller's row), -1 when mutual_only and the pair is not mutual.
+template <typename T>
+void matches_launch(const P4<T>* Xt, int M, const P4<T>* Y, int N, int mutual_only,
+                    const int* permX, const int* permY, int* nnXY, int* nnYX, int32_t* out,
+                    hipStream_t st);
+// P1 (indicator) and Yt (matched scene point) from a caller-order match list.
+template <typename T>
+void match_in_launch(const int32_t* match, int M, int N, const int* permX, const int* invY,
+                     const P4<T>* X, const P4<T>* Y, T* P1, P4<T>* Yt, hipStream_t st);
+
 // dst[i, :] = src[perm[i], :] (gather rows) and dst[perm[i], :] = src[i, :]
 // (scatter rows), row-major with `cols` columns.
 template <typename T>

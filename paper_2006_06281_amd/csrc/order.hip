@@ -132,18 +132,21 @@ __global__ __launch_bounds__(256) void k_bitonic(u64* __restrict__ a, int j, int
 template <typename T>
 __global__ __launch_bounds__(256) void k_perm_gather(const u64* __restrict__ keys, int n,
                                                      int* __restrict__ perm,
+                                                     int* __restrict__ inv,
                                                      const P4<T>* __restrict__ src,
                                                      P4<T>* __restrict__ dst) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int idx = (int)(uint32_t)(keys[i] & 0xFFFFFFFFull);
   perm[i] = idx;
+  if (inv) inv[idx] = i;
   dst[i] = src[idx];
 }
 
 template <typename T>
-void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* permY, u64* keys,
-                          double* bbox, P4<T>* tmp, P4<T>* Xraw, DevScalars* sc, hipStream_t st) {
+void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* permY, int* invY,
+                          u64* keys, double* bbox, P4<T>* tmp, P4<T>* Xraw, DevScalars* sc,
+                          hipStream_t st) {
   // the origin of the iteration's frame: centre of the scene's bounding box;
   // then the joint box for the Morton grid
   hipLaunchKernelGGL(k_bbox_part<T>, dim3(kBBoxBlocks), dim3(256), 0, st, Y, N, Y, 0, bbox);
@@ -151,7 +154,7 @@ void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* per
   hipLaunchKernelGGL(k_bbox_part<T>, dim3(kBBoxBlocks), dim3(256), 0, st, X, M, Y, N, bbox);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, bbox, kBBoxBlocks, sc, 1);
   const double* box = bbox + 6 * kBBoxBlocks;
-  auto one = [&](P4<T>* P, int n, int* perm) {
+  auto one = [&](P4<T>* P, int n, int* perm, int* inv) {
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
     const unsigned g = (unsigned)((n2 + 255) / 256);
@@ -160,11 +163,11 @@ void spatial_order_launch(P4<T>* X, int M, P4<T>* Y, int N, int* permX, int* per
       for (int j = k >> 1; j > 0; j >>= 1)
         hipLaunchKernelGGL(k_bitonic, dim3(g), dim3(256), 0, st, keys, j, k, n2);
     hipLaunchKernelGGL(k_perm_gather<T>, dim3((n + 255) / 256), dim3(256), 0, st, keys, n, perm,
-                       P, tmp);
+                       inv, P, tmp);
     (void)hipMemcpyAsync(P, tmp, sizeof(P4<T>) * (size_t)n, hipMemcpyDeviceToDevice, st);
   };
-  one(X, M, permX);
-  one(Y, N, permY);
+  one(X, M, permX, nullptr);
+  one(Y, N, permY, invY);
   // the caller's frame is kept for the Gram matrix; the iteration runs in
   // the centred frame (unused coordinates are 0 and stay 0)
   (void)hipMemcpyAsync(Xraw, X, sizeof(P4<T>) * (size_t)M, hipMemcpyDeviceToDevice, st);
@@ -209,11 +212,11 @@ void scatter_rows_launch(const T* src, T* dst, const int* perm, int rows, int co
                      dst, perm, rows, cols);
 }
 
-template void spatial_order_launch<float>(P4<float>*, int, P4<float>*, int, int*, int*, u64*,
-                                          double*, P4<float>*, P4<float>*, DevScalars*,
+template void spatial_order_launch<float>(P4<float>*, int, P4<float>*, int, int*, int*, int*,
+                                          u64*, double*, P4<float>*, P4<float>*, DevScalars*,
                                           hipStream_t);
-template void spatial_order_launch<double>(P4<double>*, int, P4<double>*, int, int*, int*, u64*,
-                                           double*, P4<double>*, P4<double>*, DevScalars*,
+template void spatial_order_launch<double>(P4<double>*, int, P4<double>*, int, int*, int*, int*,
+                                           u64*, double*, P4<double>*, P4<double>*, DevScalars*,
                                            hipStream_t);
 template void gather_rows_launch<float>(const float*, float*, const int*, int, int, hipStream_t);
 template void gather_rows_launch<double>(const double*, double*, const int*, int, int,
