@@ -228,11 +228,20 @@ __global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A,
 // C = Phi B for the Gram matrix of the points (eq. 11), B and C M x n
 // row-major, with v_mfma_f64_16x16x4f64 (A lane l: row l%16, k = l/16;
 // B lane l: k = l/16, column l%16; D lane l, register r: row 4r + l/16 of
-// column l%16 -- checked on the device).  Block: 128 rows x 128 columns, four waves of 32 rows x 128 columns
-// (2 x 8 accumulator tiles).  Each lane forms its own Phi operand in FP64
-// (one exp per row tile and k-step), so Phi never touches memory; the B
-// chunk (32 x 128) and the chunk's points are staged in LDS.
-constexpr int PR = 128, PC = 128, PK = 32;
+// column l%16 -- checked on the device).  An output tile is 128 rows x 16 CT
+// columns: four waves of 32 rows (2 x CT accumulator tiles).  Each lane forms
+// its own Phi operand in FP64 (one exp per row tile and k-step), so Phi never
+// touches memory.
+//
+// Work split (stream-K): the units (tile, chunk of 16 k-rows) are numbered
+// tile-major and a persistent grid of G blocks takes G equal contiguous
+// ranges, so every block does the same number of matrix-core steps whatever
+// the tile count.  A block writes a tile it finishes from chunk 0 straight to
+// C; the one tile it enters mid-way (its first) goes to its own slot of a
+// scratch buffer, and a fix-up kernel adds those slots to C in block order,
+// so the result does not depend on timing.  The B chunk of the next unit is
+// loaded into registers while the current one is multiplied from LDS.
+constexpr int PR = 128, PK = 16;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // e^x for x <= 0 without branches: Cody-Waite reduction x = k ln2 + r,
@@ -264,76 +273,191 @@ __device__ __forceinline__ double exp_nonpos(double x) {
   return __builtin_amdgcn_ldexp(p, (int)k);
 }
 
-template <typename PT>
-__global__ __launch_bounds__(256) void k_phi_mfma(const P4<PT>* __restrict__ pts, int M,
-                                                  double inv2b2, const double* __restrict__ B,
-                                                  int n, double* __restrict__ C) {
-  __shared__ double sB[PK][PC];
-  __shared__ double sX[PK][4];
+struct PhiSplit {
+  int tiles_c;    // column tiles (16 CT columns each)
+  int KC;         // chunks of PK k-rows
+  long long U;    // units = tiles * KC
+  int G;          // blocks
+};
+
+__device__ __forceinline__ long long unit_begin(const PhiSplit& s, int g) {
+  return s.U * g / s.G;
+}
+
+// the block whose range holds unit u
+__device__ __forceinline__ int block_of_unit(const PhiSplit& s, long long u) {
+  int g = (int)(u * s.G / s.U);
+  while (g + 1 < s.G && unit_begin(s, g + 1) <= u) ++g;
+  while (g > 0 && unit_begin(s, g) > u) --g;
+  return g;
+}
+
+template <typename PT, int CT>
+__global__ __launch_bounds__(256, 2) void k_phi_mfma(const P4<PT>* __restrict__ pts, int M,
+                                                     double inv2b2, const double* __restrict__ B,
+                                                     int n, double* __restrict__ C,
+                                                     double* __restrict__ slot, PhiSplit sp) {
+  constexpr int NC = 16 * CT;
+  __shared__ double sB[2][PK][NC];
+  __shared__ double sX[2][PK][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = blockIdx.x * PC, r0 = blockIdx.y * PR + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  double xi[2][3];
+  const int g = blockIdx.x;
+  const long long ub = unit_begin(sp, g), ue = unit_begin(sp, g + 1);
+  if (ub >= ue) return;
+
+  // B chunk of unit (tile ft, chunk fj) into registers: PK x NC = 256 CT
+  // elements as CT slabs of 8 rows x 32 columns, one element per thread and
+  // slab (row tid/32, column tid%32 of the slab), so a thread's addresses
+  // differ by constants.  Out-of-range elements read the chunk's first
+  // element; they are zeroed when stored to LDS, so no instruction between
+  // the loads and the end of the chunk's products waits for them.
+  static_assert(PK == 16 && CT % 2 == 0, "two slabs of 8 rows, CT/2 of 32 columns");
+  double pre[CT];
+  P4<PT> pp{};
+  int fkmax = 0, fcmax = 0;  // in-range rows and columns of the fetched chunk
+  const int sr = tid >> 5, sc = tid & 31;
+  auto fetch = [&](int ft, int fj) {
+    const int k0 = fj * PK, c0 = (ft % sp.tiles_c) * NC;
+    const double* Bk = B + (size_t)k0 * n + c0;
+    fkmax = M - k0;
+    fcmax = n - c0;
+    // the thread's offset, recomputed per fetch (an empty asm hides that it
+    // is loop invariant: keeping CT offsets live across the loop spills)
+    int base = sr * n + sc;
+    asm volatile("" : "+v"(base));
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const int i = r0 + 16 * rt + li;
-    const P4<PT> p = i < M ? pts[i] : P4<PT>{(PT)0, (PT)0, (PT)0, (PT)0};
-    xi[rt][0] = p.x;
-    xi[rt][1] = p.y;
-    xi[rt][2] = p.z;
-  }
-  dbl4 acc[2][8];
+    for (int q = 0; q < CT; ++q) {
+      const int rs = 8 * (q / (CT / 2)), cs = 32 * (q % (CT / 2));
+      const bool ok = sr + rs < fkmax && sc + cs < fcmax;
+      pre[q] = Bk[ok ? (uint32_t)(base + rs * n + cs) : 0u];
+    }
+    if (tid < PK) pp = pts[min(k0 + tid, M - 1)];
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < CT; ++q) {
+      const int rs = 8 * (q / (CT / 2)), cs = 32 * (q % (CT / 2));
+      const bool ok = sr + rs < fkmax && sc + cs < fcmax;
+      sB[buf][sr + rs][sc + cs] = ok ? pre[q] : 0.0;
+    }
+    if (tid < PK) {
+      const bool ok = tid < fkmax;
+      sX[buf][tid][0] = ok ? (double)pp.x : 0.0;
+      sX[buf][tid][1] = ok ? (double)pp.y : 0.0;
+      sX[buf][tid][2] = ok ? (double)pp.z : 0.0;
+    }
+  };
+
+  int t = (int)(ub / sp.KC), j = (int)(ub - (long long)t * sp.KC);
+  int j_first = j;  // chunk the current segment started at
+  PT xi[2][3];  // this lane's row points, widened to FP64 at use
+  auto rows_of = [&](int tile) {
+    const int r0 = (tile / sp.tiles_c) * PR + wave * 32;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int i = r0 + 16 * rt + li;
+      const P4<PT> p = i < M ? pts[i] : P4<PT>{(PT)0, (PT)0, (PT)0, (PT)0};
+      xi[rt][0] = p.x;
+      xi[rt][1] = p.y;
+      xi[rt][2] = p.z;
+    }
+    // complete these loads here: otherwise the products' loop waits at its
+    // head for every load in flight, the B prefetch included
+    asm volatile("" ::"v"(xi[0][0]), "v"(xi[0][1]), "v"(xi[0][2]), "v"(xi[1][0]),
+                 "v"(xi[1][1]), "v"(xi[1][2]));
+  };
+  rows_of(t);
+  dbl4 acc[2][CT];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct) acc[rt][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < M; k0 += PK) {
-#pragma unroll
-    for (int q = 0; q < PK * PC / 256; ++q) {
-      const int e = tid + 256 * q;
-      const int kr = e / PC, cc = e % PC;
-      const int k = k0 + kr, c = c0 + cc;
-      sB[kr][cc] = (k < M && c < n) ? B[(size_t)k * n + c] : 0.0;
-    }
-    if (tid < PK) {
-      const int k = k0 + tid;
-      const P4<PT> p = k < M ? pts[k] : P4<PT>{(PT)0, (PT)0, (PT)0, (PT)0};
-      sX[tid][0] = p.x;
-      sX[tid][1] = p.y;
-      sX[tid][2] = p.z;
-    }
-    __syncthreads();
-#pragma unroll 2
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  fetch(t, j);
+  stash(0);
+  __syncthreads();
+  for (long long u = ub; u < ue; ++u) {
+    const int buf = (int)((u - ub) & 1);
+    const bool more = u + 1 < ue;
+    const bool last_chunk = j == sp.KC - 1;
+    if (more) fetch(last_chunk ? t + 1 : t, last_chunk ? 0 : j + 1);
+#pragma unroll 1
     for (int ks = 0; ks < PK / 4; ++ks) {
       const int kr = 4 * ks + lk;
-      const double x0 = sX[kr][0], x1 = sX[kr][1], x2 = sX[kr][2];
+      const double x0 = sX[buf][kr][0], x1 = sX[buf][kr][1], x2 = sX[buf][kr][2];
       double a[2];  // (rows of k >= M meet zero rows of the staged B)
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
-        const double dx = xi[rt][0] - x0, dy = xi[rt][1] - x1, dz = xi[rt][2] - x2;
+        const double dx = (double)xi[rt][0] - x0, dy = (double)xi[rt][1] - x1,
+                     dz = (double)xi[rt][2] - x2;
         a[rt] = exp_nonpos(-(dx * dx + dy * dy + dz * dz) * inv2b2);
       }
 #pragma unroll
-      for (int ct = 0; ct < 8; ++ct) {
-        const double b = sB[kr][16 * ct + li];
+      for (int ct = 0; ct < CT; ++ct) {
+        const double b = sB[buf][kr][16 * ct + li];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
           acc[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][ct], 0, 0, 0);
       }
     }
+    if (more) stash(buf ^ 1);
+    if (last_chunk || !more) {
+      // end of a segment: chunk 0 was ours -> C, else this block's slot
+      // (one store pattern for both: uniform base, row stride, bounds)
+      const int r0 = (t / sp.tiles_c) * PR, c0 = (t % sp.tiles_c) * NC;
+      const bool own = j_first == 0;
+      char* base = own ? reinterpret_cast<char*>(C + (size_t)r0 * n + c0)
+                       : reinterpret_cast<char*>(slot + (size_t)g * PR * NC);
+      const int stride = own ? n : NC, rmax = own ? M - r0 : PR, cmax = own ? n - c0 : NC;
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ri = wave * 32 + 16 * rt + 4 * r + lk;
+          if (ri < rmax) {
+            char* row = base + 8u * (uint32_t)(ri * stride);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              const int cc = 16 * ct + li;
+              if (cc < cmax) *reinterpret_cast<double*>(row + 8u * (uint32_t)cc) = acc[rt][ct][r];
+            }
+          }
+        }
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+      if (more) {
+        ++t;
+        j = j_first = 0;
+        rows_of(t);
+      }
+    } else {
+      ++j;
+    }
     __syncthreads();
   }
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      const int c = c0 + 16 * ct + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = r0 + 16 * rt + 4 * r + lk;
-        if (i < M && c < n) C[(size_t)i * n + c] = acc[rt][ct][r];
-      }
-    }
+}
+
+// Tiles shared by several blocks: C (the part from chunk 0) += the slots of
+// the later blocks, in block order.  One block per tile.
+template <int CT>
+__global__ __launch_bounds__(256) void k_phi_fix(double* __restrict__ C, int M, int n,
+                                                 const double* __restrict__ slot, PhiSplit sp) {
+  constexpr int NC = 16 * CT;
+  const int t = blockIdx.x;
+  const long long u0 = (long long)t * sp.KC;
+  const int ga = block_of_unit(sp, u0), gb = block_of_unit(sp, u0 + sp.KC - 1);
+  if (ga == gb) return;
+  const int r0 = (t / sp.tiles_c) * PR, c0 = (t % sp.tiles_c) * NC;
+  for (int e = threadIdx.x; e < PR * NC; e += 256) {
+    const int i = r0 + e / NC, c = c0 + e % NC;
+    if (i >= M || c >= n) continue;
+    double v = C[(size_t)i * n + c];
+    for (int g = ga + 1; g <= gb; ++g) v += slot[(size_t)g * PR * NC + e];
+    C[(size_t)i * n + c] = v;
+  }
 }
 
 // Partial A^T B over a chunk of rows: P[chunk][a][b] = sum_{m in chunk}
@@ -640,13 +764,41 @@ struct Ctx {
 
 unsigned blocks_for(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename PT>
-void phi_times(const Ctx& c, const double* B, double* C, int n) {
+template <typename PT, int CT>
+void phi_launch(const Ctx& c, const double* B, double* C, int n, double* scratch) {
   const int M = c.r.M;
-  dim3 grid((n + PC - 1) / PC, (M + PR - 1) / PR);
+  constexpr int NC = 16 * CT;
+  PhiSplit sp;
+  sp.tiles_c = (n + NC - 1) / NC;
+  sp.KC = (M + PK - 1) / PK;
+  const int tiles = ((M + PR - 1) / PR) * sp.tiles_c;
+  sp.U = (long long)tiles * sp.KC;
+  // one block per resident slot, at most one scratch slot per block
+  int dev = 0, cus = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_phi_mfma<PT, CT>, 256, 0);
+  long long G = (long long)std::max(cus, 1) * std::max(per, 1);
+  G = std::min<long long>(G, sp.U);
+  G = std::min<long long>(G, (long long)((size_t)M * c.L.n / ((size_t)PR * NC)));
+  sp.G = (int)std::max<long long>(G, 1);
   const double inv2b2 = 1.0 / (2.0 * c.r.beta * c.r.beta);
-  hipLaunchKernelGGL(k_phi_mfma<PT>, grid, dim3(256), 0, c.st, static_cast<const P4<PT>*>(c.r.X),
-                     M, inv2b2, B, n, C);
+  hipLaunchKernelGGL((k_phi_mfma<PT, CT>), dim3(sp.G), dim3(256), 0, c.st,
+                     static_cast<const P4<PT>*>(c.r.X), M, inv2b2, B, n, C, scratch, sp);
+  if (sp.G > 1)
+    hipLaunchKernelGGL(k_phi_fix<CT>, dim3(tiles), dim3(256), 0, c.st, C, M, n,
+                       (const double*)scratch, sp);
+}
+
+// C = Phi B (M x n); scratch: an M x L.n buffer that is free meanwhile.
+// Output tiles of 160 columns when that pads n less than 128 would.
+template <typename PT>
+void phi_times(const Ctx& c, const double* B, double* C, int n, double* scratch) {
+  const int w8 = (n + 127) / 128 * 8, w10 = (n + 159) / 160 * 10;
+  if (w10 < w8)
+    phi_launch<PT, 10>(c, B, C, n, scratch);
+  else
+    phi_launch<PT, 8>(c, B, C, n, scratch);
 }
 
 void gemm_nn(const Ctx& c, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
@@ -790,13 +942,15 @@ int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64
     hipLaunchKernelGGL(k_gauss, dim3(blocks_for((cnt + 3) / 4)), dim3(256), 0, c.st, Om, cnt, seed);
     O = Om;
   }
-  phi_times<PT>(c, O, Z, n);
+  // scratch of the products: Q before the first orthonormalisation, then
+  // Omega's buffer (Omega is read only by the first product)
+  phi_times<PT>(c, O, Z, n, Q);
   if (orth(c, Z, Q, n, msg)) return 1;
   for (int it = 0; it < q; ++it) {
-    phi_times<PT>(c, Q, Z, n);
+    phi_times<PT>(c, Q, Z, n, Om);
     if (orth(c, Z, Q, n, msg)) return 1;
   }
-  phi_times<PT>(c, Q, Z, n);  // Z = Phi Q
+  phi_times<PT>(c, Q, Z, n, Om);  // Z = Phi Q
   gram(c, Q, Z, n, B);        // B = Q^T Phi Q (symmetrised)
   if (jacobi_sorted(c, B, V, n, vals, msg)) return 1;
   hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)n * K)), dim3(256), 0, c.st, V, n,

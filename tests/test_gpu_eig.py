@@ -83,6 +83,35 @@ def test_randomized_topk(lib, given_omega):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("M,K,over,precision", [(2503, 130, 20, "fp32"), (1507, 290, 30, "fp64")])
+def test_randomized_topk_wide_tiles(lib, M, K, over, precision):
+    """Widths served by 160-column output tiles (n = 150: ten padded columns;
+    n = 320: two full tiles), ragged M, FP32 and FP64 point storage: every
+    product with Phi splits its tiles over several blocks."""
+    import torch
+    say("randomized topk wide tiles", M, K + over, precision)
+    p = synth.surface_pair(M=M, N=M, seed=8, beta=1.5, lam=2.0, w=0.2)
+    X = _f32(p.X)
+    q = 2
+    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=12)
+    Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    r = lib.Registration(dev(X, dt), dev(_f32(p.Y), dt), precision=precision, beta=p.beta,
+                         lam=p.lam, w=p.w, eig_mode="topk", K=K, oversample=over,
+                         power_iters=q, seed=5, tol=0.0, max_iter=5)
+    r.prepare(omega=dev(Om, torch.float64))
+    U, lam = (host(t) for t in r.export_eig())
+    err = np.abs(lam - lo).max() / lo[0]
+    say("max |lam - lam_oracle| / lam_1", err)
+    np.testing.assert_allclose(lam, lo, rtol=0, atol=1e-11 * lo[0])
+    np.testing.assert_allclose(U.T @ U, np.eye(K), atol=1e-10)
+    rows = np.random.default_rng(1).choice(p.M, 40, replace=False)
+    Phr = np.exp(-cpd64.sqdist(X[rows], X) / (2 * p.beta ** 2))
+    big = lam > 1e-8 * lam[0]
+    res = Phr @ U[:, big] - U[rows][:, big] * lam[big]
+    assert np.abs(res).max() < 1e-9 * lam[0]
+
+
 def test_full_mode_above_dense_limit(lib):
     """FULL mode at 3000 points (randomized, width grown to round-off) gives
     the registration of the dense eigendecomposition."""
