@@ -70,7 +70,7 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.phi = take((size_t)M * M * sizeof(double));
     L.V = take((size_t)M * M * sizeof(double));
     L.ritz = take((size_t)M * sizeof(double));
-    L.misc = take(((size_t)M * sizeof(int) + 64) + (64 + 4 * (size_t)(M / 2 + 1)) * sizeof(double));
+    L.misc = take(((size_t)M * sizeof(int) + 64) + (65 + 8 * (size_t)(M / 2 + 1)) * sizeof(double));
   } else {
     int n;
     if (mode == 0)
@@ -90,7 +90,7 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.phi = take(nn);  // the n x n Rayleigh-Ritz / Gram matrix
     L.chol = take((size_t)n * kCholNB * sizeof(double));
     L.ritz = take((size_t)n * sizeof(double));
-    L.misc = take(((size_t)n * sizeof(int) + 64) + (64 + 4 * (size_t)(n / 2 + 1)) * sizeof(double));
+    L.misc = take(((size_t)n * sizeof(int) + 64) + (65 + 8 * (size_t)(n / 2 + 1)) * sizeof(double));
   }
   L.end = off;
   return L;
@@ -595,14 +595,18 @@ __global__ __launch_bounds__(256) void k_tri_inv_t(const double* __restrict__ G,
 // ------------------------------------------------------------ Jacobi
 // Cyclic two-sided Jacobi on a symmetric n x n matrix A (row-major, global).
 // Round-robin ordering: in each of the n-1 steps of a sweep the n/2 pairs are
-// disjoint, so their rotations commute.  A step is two launches over the
-// whole GPU: k_jac_rows (one block per pair: rotation from the pair's 2 x 2
-// block, then rows p, q of J^T A) and k_jac_cols (columns p, q of A J and of
-// V J, the 2 x 2 block set to its exact rotated values so round-off cannot
-// keep re-opening it).  A pair is rotated while |a_pq| exceeds both
-// eps sqrt(|a_pp a_qq|) (relative accuracy) and 1e-16 |A|_F (entries below
-// are round-off of the largest eigenvalues).  V accumulates the rotations;
-// on exit diag(A) holds the eigenvalues.
+// disjoint, so their rotations commute.  A step is A <- J^T A J; the column
+// half of step s is deferred to step s+1, whose pairs also cover every row
+// once, so one launch per step suffices: the block of pair (p, q) loads rows
+// p and q, applies step s's column rotations to them (the rotated 2 x 2
+// blocks set to their exact values so round-off cannot keep re-opening
+// them), takes its own rotation from the now current 2 x 2 block, applies it
+// to the two rows and writes them back; V's rows p and q get step s's column
+// rotations alongside.  A final launch applies the last step's columns.  A
+// pair is rotated while |a_pq| exceeds both eps sqrt(|a_pp a_qq|) (relative
+// accuracy) and 1e-16 |A|_F (entries below are round-off of the largest
+// eigenvalues).  V accumulates the rotations; on exit diag(A) holds the
+// eigenvalues.
 __device__ __forceinline__ void rr_pair(int k, int step, int n, int* p, int* q) {
   const int np = (n + 1) & ~1;
   auto pos = [&](int t) { return t == 0 ? 0 : ((t - 1 + step) % (np - 1)) + 1; };
@@ -630,24 +634,78 @@ __global__ __launch_bounds__(256) void k_jac_init(const double* __restrict__ A,
   if (threadIdx.x == 0) normsq[blockIdx.x] = part;
 }
 
-__global__ __launch_bounds__(256) void k_jac_rows(double* __restrict__ A, int n, int step,
-                                                  const double* __restrict__ normsq, int nparts,
-                                                  double* __restrict__ prm,
-                                                  int* __restrict__ rotated) {
-  __shared__ double sc_[4];
-  const int k = blockIdx.x;
-  int p, q;
-  rr_pair(k, step, n, &p, &q);
+// Sum of the k_jac_init partials (the squared Frobenius norm).
+__global__ void k_jac_norm(double* __restrict__ normsq, int nparts) {
   if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < nparts; ++i) t += normsq[i];
+    normsq[nparts] = t;
+  }
+}
+
+// One step (step < 0: only the deferred columns of step `prev`).  prm holds
+// (c, s, a_pp', a_qq') per pair; prm_prev is NULL before the first step.
+// Dynamic LDS: rows p and q of A and of V (4 n doubles).
+__global__ __launch_bounds__(256) void k_jac_step(double* __restrict__ A, double* __restrict__ V,
+                                                  int n, int step, int prev,
+                                                  const double* __restrict__ prm_prev,
+                                                  double* __restrict__ prm,
+                                                  const double* __restrict__ normtot,
+                                                  int* __restrict__ rotated) {
+  extern __shared__ double rows_lds[];
+  double* ra[2] = {rows_lds, rows_lds + n};
+  double* rv[2] = {rows_lds + 2 * n, rows_lds + 3 * n};
+  __shared__ double cs_[2];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  int p, q;
+  rr_pair(k, step >= 0 ? step : 0, n, &p, &q);
+  const bool two = q < n;
+  for (int j = tid; j < n; j += 256) {
+    ra[0][j] = A[(size_t)p * n + j];
+    ra[1][j] = two ? A[(size_t)q * n + j] : 0.0;
+    rv[0][j] = V[(size_t)p * n + j];
+    rv[1][j] = two ? V[(size_t)q * n + j] : 0.0;
+  }
+  __syncthreads();
+  if (prm_prev) {
+    const int half = ((n + 1) & ~1) / 2;
+    for (int kk = tid; kk < half; kk += 256) {
+      int pp, qq;
+      rr_pair(kk, prev, n, &pp, &qq);
+      if (qq >= n) continue;
+      const double c = prm_prev[4 * kk + 0], s = prm_prev[4 * kk + 1];
+      if (s == 0.0) continue;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int ri = r == 0 ? p : q;
+        if (r == 1 && !two) break;
+        double* a = ra[r];
+        if (ri == pp) {
+          a[pp] = prm_prev[4 * kk + 2];
+          a[qq] = 0.0;
+        } else if (ri == qq) {
+          a[pp] = 0.0;
+          a[qq] = prm_prev[4 * kk + 3];
+        } else {
+          const double x = a[pp], y = a[qq];
+          a[pp] = c * x - s * y;
+          a[qq] = s * x + c * y;
+        }
+        double* v = rv[r];
+        const double x = v[pp], y = v[qq];
+        v[pp] = c * x - s * y;
+        v[qq] = s * x + c * y;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
     double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
-    if (q < n) {
-      double nsq = 0.0;
-      for (int i = 0; i < nparts; ++i) nsq += normsq[i];
-      const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-      const double apq = A[(size_t)p * n + q];
+    if (step >= 0 && two) {
+      const double app = ra[0][p], aqq = ra[1][q], apq = ra[0][q];
       const double aa = fabs(apq);
       const double eps = 1.1102230246251565e-16;
-      if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-16 * sqrt(nsq)) {
+      if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-16 * sqrt(normtot[0])) {
         const double tau = (aqq - app) / (2.0 * apq);
         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
         c = 1.0 / sqrt(1.0 + t * t);
@@ -657,48 +715,28 @@ __global__ __launch_bounds__(256) void k_jac_rows(double* __restrict__ A, int n,
         rotated[0] = 1;
       }
     }
-    sc_[0] = c;
-    sc_[1] = s;
-    prm[4 * k + 0] = c;
-    prm[4 * k + 1] = s;
-    prm[4 * k + 2] = dp;
-    prm[4 * k + 3] = dq;
+    cs_[0] = c;
+    cs_[1] = s;
+    if (step >= 0) {
+      prm[4 * k + 0] = c;
+      prm[4 * k + 1] = s;
+      prm[4 * k + 2] = dp;
+      prm[4 * k + 3] = dq;
+    }
   }
   __syncthreads();
-  const double c = sc_[0], s = sc_[1];
-  if (q >= n || s == 0.0) return;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
-    A[(size_t)p * n + j] = c * ap - s * aq;
-    A[(size_t)q * n + j] = s * ap + c * aq;
+  const double c = cs_[0], s = cs_[1];
+  for (int j = tid; j < n; j += 256) {
+    const double x = ra[0][j], y = ra[1][j];
+    V[(size_t)p * n + j] = rv[0][j];
+    if (two) {
+      A[(size_t)p * n + j] = c * x - s * y;
+      A[(size_t)q * n + j] = s * x + c * y;
+      V[(size_t)q * n + j] = rv[1][j];
+    } else {
+      A[(size_t)p * n + j] = x;
+    }
   }
-}
-
-__global__ __launch_bounds__(256) void k_jac_cols(double* __restrict__ A, double* __restrict__ V,
-                                                  int n, int step,
-                                                  const double* __restrict__ prm) {
-  const int k = blockIdx.x;
-  int p, q;
-  rr_pair(k, step, n, &p, &q);
-  if (q >= n) return;
-  const double c = prm[4 * k + 0], s = prm[4 * k + 1];
-  if (s == 0.0) return;
-  const int i = blockIdx.y * 256 + threadIdx.x;
-  if (i >= n) return;
-  const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
-  if (i == p) {
-    A[(size_t)p * n + p] = prm[4 * k + 2];
-    A[(size_t)p * n + q] = 0.0;
-  } else if (i == q) {
-    A[(size_t)q * n + p] = 0.0;
-    A[(size_t)q * n + q] = prm[4 * k + 3];
-  } else {
-    A[(size_t)i * n + p] = c * ap - s * aq;
-    A[(size_t)i * n + q] = s * ap + c * aq;
-  }
-  const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
-  V[(size_t)i * n + p] = c * vp - s * vq;
-  V[(size_t)i * n + q] = s * vp + c * vq;
 }
 
 __global__ void k_flag_clear(int* f) {
@@ -898,25 +936,39 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
   }
   int* perm = misc_int(c);
   int* flag = misc_int(c) + n + 1;
-  double* scratch = misc_dbl(c, n);  // [0..64): norm partials, then 4 per pair
+  double* scratch = misc_dbl(c, n);  // [0..64): norm partials, [64] their sum, 2 x 4 per pair
   double* normsq = scratch;
-  double* prm = scratch + 64;
   const int half = ((n + 1) & ~1) / 2;
+  double* prm_buf[2] = {scratch + 65, scratch + 65 + 4 * (size_t)half};
   hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
-  int sweep = 0;
+  hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, c.st, normsq, 64);
+  const double* normtot = normsq + 64;
+  const size_t lds = 4 * (size_t)n * sizeof(double);
+  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_jac_step),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds) != hipSuccess) {
+    *msg = "Jacobi: LDS request refused";
+    return 2;
+  }
+  int sweep = 0, prev = 0, launched = 0;
+  const double* prm_prev = nullptr;
   for (; sweep < kJacobiSweeps; ++sweep) {
     hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c.st, flag);
     for (int step = 0; step < 2 * half - 1; ++step) {
-      hipLaunchKernelGGL(k_jac_rows, dim3(half), dim3(256), 0, c.st, A, n, step, normsq, 64, prm,
-                         flag);
-      hipLaunchKernelGGL(k_jac_cols, dim3(half, (n + 255) / 256), dim3(256), 0, c.st, A, V, n,
-                         step, prm);
+      double* prm = prm_buf[launched++ & 1];
+      hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, step, prev,
+                         prm_prev, prm, normtot, flag);
+      prev = step;
+      prm_prev = prm;
     }
     int h = 0;
     (void)hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c.st);
     (void)hipStreamSynchronize(c.st);
     if (!h) break;
   }
+  if (prm_prev)  // the last step's column rotations
+    hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, -1, prev, prm_prev,
+                       (double*)nullptr, normtot, flag);
   hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);
   if (sweep >= kJacobiSweeps) {
     *msg = "Jacobi did not converge";
@@ -952,7 +1004,7 @@ int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64
   }
   phi_times<PT>(c, Q, Z, n, Om);  // Z = Phi Q
   gram(c, Q, Z, n, B);        // B = Q^T Phi Q (symmetrised)
-  if (jacobi_sorted(c, B, V, n, vals, msg)) return 1;
+  if (const int rc = jacobi_sorted(c, B, V, n, vals, msg)) return rc;
   hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)n * K)), dim3(256), 0, c.st, V, n,
                      misc_int(c), K, S);
   gemm_nn(c, Q, n, S, K, c.r.U64, K, M, n, K);
@@ -979,7 +1031,7 @@ int dense_full(const Ctx& c, int* K_out, std::string* msg) {
   double* vals = c.at(c.L.ritz);
   hipLaunchKernelGGL(k_phi_dense<PT>, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st,
                      static_cast<const P4<PT>*>(c.r.X), M, 1.0 / (2.0 * c.r.beta * c.r.beta), Phi);
-  if (jacobi_sorted(c, Phi, V, M, vals, msg)) return 1;
+  if (const int rc = jacobi_sorted(c, Phi, V, M, vals, msg)) return rc;
   hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st, V, M,
                      misc_int(c), M, c.r.U64);
   hipLaunchKernelGGL(k_copy_lam, dim3(blocks_for(M)), dim3(256), 0, c.st, vals, M, c.r.lam);
