@@ -93,8 +93,8 @@ __global__ __launch_bounds__(256) void k_build_system(const double* __restrict__
 // Cholesky of the nb x nb diagonal block at (k0, k0), in LDS; writes L_kk back
 // (lower; the strict upper part is left as is) and Linv = L_kk^-1 (lower,
 // nb x nb, row-major with stride NB).  Breakdown sets *chol_fail.  The
-// inverse is built in the tile's free upper triangle (Linv[r][c] at s[c][r]):
-// thread c runs the forward substitution of column c entirely in LDS.
+// inverse is built in the tile's free upper triangle (Linv[r][c] at s[c][r]),
+// one row per step, all columns of the row in parallel.
 __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int lda, int k0,
                                                      int nb, double* __restrict__ Linv,
                                                      int* chol_fail, const int* done) {
@@ -110,45 +110,60 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
   }
   if (tid == 0) fail = 0;
   __syncthreads();
+  // one barrier per column: step j updates the trailing triangle with the
+  // unscaled column j (s[r][c] -= s[r][j] s[c][j] / d_j) and scales column
+  // j - 1, which no thread reads any more
+  double dprev = 1.0;
   for (int j = 0; j < nb; ++j) {
-    if (tid == 0) {
-      const double d = s[j][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        fail = 1;
-        s[j][j] = 1.0;
-      } else {
-        s[j][j] = sqrt(d);
-      }
+    const double d = s[j][j];  // every thread reads the same pivot
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) fail = 1;
+      break;
     }
-    __syncthreads();
-    if (fail) break;
-    const double piv = s[j][j];
-    for (int r = j + 1 + tid; r < nb; r += nt) s[r][j] /= piv;
-    __syncthreads();
+    const double inv = 1.0 / d;
     for (int r = j + 1 + ty; r < nb; r += 32) {
-      const double lr = s[r][j];
+      const double lr = s[r][j] * inv;
       for (int c = j + 1 + tx; c <= r; c += 32) s[r][c] -= lr * s[c][j];
     }
+    if (j > 0) {
+      const double piv = sqrt(dprev);
+      for (int r = j - 1 + tid; r < nb; r += nt) s[r][j - 1] = r == j - 1 ? piv : s[r][j - 1] / piv;
+    }
+    dprev = d;
     __syncthreads();
   }
+  __syncthreads();
   if (fail) {
     if (tid == 0) *chol_fail = 1;
     return;
   }
+  {
+    const double piv = sqrt(dprev);
+    for (int r = nb - 1 + tid; r < nb; r += nt) s[r][nb - 1] = piv;
+  }
+  __syncthreads();
   for (int e = tid; e < nb * nb; e += nt) {
     const int r = e / nb, c = e % nb;
     if (c <= r) A[(size_t)(k0 + r) * lda + k0 + c] = s[r][c];
   }
-  if (tid < nb) {
-    const int c = tid;
-    const double dcc = 1.0 / s[c][c];
-    for (int r = c + 1; r < nb; ++r) {
-      double v = s[r][c] * dcc;
-      for (int k = c + 1; k < r; ++k) v = fma(s[r][k], s[c][k], v);
-      s[c][r] = -v / s[r][r];
+  // X = L^-1 row by row: X[r][c] = -(sum_{c<=k<r} L[r][k] X[k][c]) / L[r][r]
+  // for c < r, all columns at once, eight threads per column splitting the
+  // sum (X[k][c] for k > c lives at s[c][k]; X[c][c] = 1 / L[c][c])
+  {
+    const int c = tid >> 3, g = tid & 7;
+    for (int r = 1; r < nb; ++r) {
+      double v = 0.0;
+      if (c < r) {
+        if (g == 0) v = s[r][c] / s[c][c];
+        for (int k = c + 1 + g; k < r; k += 8) v = fma(s[r][k], s[c][k], v);
+      }
+      v += __shfl_xor(v, 1, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 4, 8);
+      if (c < r && g == 0) s[c][r] = -v / s[r][r];
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int e = tid; e < NB * NB; e += nt) {
     const int r = e / NB, c = e % NB;
     double v = 0.0;
