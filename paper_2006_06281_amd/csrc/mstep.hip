@@ -178,7 +178,161 @@ __global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
   apply_body<T, LDS>(X, U, GTg, HTg, M, K, sc, Xnew, W, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
-constexpr int kTRows = 128;
+// The same two products with 16-byte loads of U, for FP32 with K a multiple
+// of 4 (rows of U then start 16-byte aligned) and K <= 1024.
+//
+// T: the block's threads split into RP = 256 / (K/4) row lanes of K/4
+// threads; thread (r, q) accumulates k = 4q..4q+3 over rows m = m0 + r,
+// m0 + r + RP, ...; the row lanes are summed in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_tpart4(const P4<float>* __restrict__ X,
+                                                const P4<float>* __restrict__ Yt,
+                                                const float* __restrict__ U, int M, int K,
+                                                int rows, const DevScalars* __restrict__ sc,
+                                                float* __restrict__ tpart, int gate) {
+  __shared__ float red[256 * 12];
+  if (gate && sc->done) return;
+  const int KQ = K >> 2, RP = 256 / KQ;
+  const int r = threadIdx.x / KQ, q = threadIdx.x - r * KQ;
+  const float4* U4 = reinterpret_cast<const float4*>(U);
+  float a[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) a[i] = 0.f;
+  const int m0 = blockIdx.x * rows, m1 = min(M, m0 + rows);
+  if (r < RP) {
+#pragma unroll 4
+    for (int m = m0 + r; m < m1; m += RP) {
+      const P4<float> y = Yt[m], x = X[m];
+      const float rx = y.x - x.x, ry = y.y - x.y, rz = y.z - x.z;
+      const float4 u = U4[(size_t)m * KQ + q];
+      const float uk[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        a[3 * j + 0] = fmaf(uk[j], rx, a[3 * j + 0]);
+        a[3 * j + 1] = fmaf(uk[j], ry, a[3 * j + 1]);
+        a[3 * j + 2] = fmaf(uk[j], rz, a[3 * j + 2]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) red[threadIdx.x * 12 + i] = a[i];
+  __syncthreads();
+  if (threadIdx.x < KQ) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      float t = 0.f;
+      for (int rr = 0; rr < RP; ++rr) t += red[(rr * KQ + q) * 12 + i];
+      a[i] = t;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float* o = tpart + ((size_t)blockIdx.x * K + 4 * q + j) * 4;
+      *reinterpret_cast<float4*>(o) = make_float4(a[3 * j], a[3 * j + 1], a[3 * j + 2], 0.f);
+    }
+  }
+}
+
+// Xnew_m = X_m + U_m . HT, W_m = U_m . GT: sixteen lanes per row, four rows
+// per wave in flight together, 64 rows per block.  GT and HT sit in LDS as
+// six float arrays, so the four factors of a lane's float4 of U are 16-byte
+// reads that fall on distinct banks across the sixteen lanes.
+__global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
+                                                const float* __restrict__ U,
+                                                const P4<float>* __restrict__ GTg,
+                                                const P4<float>* __restrict__ HTg, int M, int K,
+                                                const DevScalars* __restrict__ sc,
+                                                P4<float>* __restrict__ Xnew,
+                                                P4<float>* __restrict__ W, int gate) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (gate && sc->done) return;
+  float* f = reinterpret_cast<float*>(smem);  // gx gy gz hx hy hz, K each
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const P4<float> g = GTg[k], h = HTg[k];
+    f[k] = g.x;
+    f[K + k] = g.y;
+    f[2 * K + k] = g.z;
+    f[3 * K + k] = h.x;
+    f[4 * K + k] = h.y;
+    f[5 * K + k] = h.z;
+  }
+  __syncthreads();
+  const float4* F4 = reinterpret_cast<const float4*>(f);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane >> 4, l16 = lane & 15;
+  const int KQ = K >> 2;
+  const float4* U4 = reinterpret_cast<const float4*>(U);
+  float acc[4][6];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[it][c] = 0.f;
+    if (m < M) {
+      const float4* u = U4 + (size_t)m * KQ;
+      for (int qq = l16; qq < KQ; qq += 16) {
+        const float4 v = u[qq];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const float4 w = F4[c * KQ + qq];
+          acc[it][c] = fmaf(v.x, w.x, fmaf(v.y, w.y, fmaf(v.z, w.z, fmaf(v.w, w.w, acc[it][c]))));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) acc[it][c] += __shfl_xor(acc[it][c], o, 16);
+    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+    if (l16 == 0 && m < M) {
+      const P4<float> x = X[m];
+      Xnew[m] = P4<float>{x.x + acc[it][3], x.y + acc[it][4], x.z + acc[it][5], 0.f};
+      W[m] = P4<float>{acc[it][0], acc[it][1], acc[it][2], 0.f};
+    }
+  }
+}
+
+// T_k over the row chunks with 16-byte loads: one block of 256 threads per
+// k (lane-strided chunk sums, then waves, in a fixed order), then GT_k, HT_k
+// as in tmerge_body.
+__global__ __launch_bounds__(256) void k_tmerge4(const float* __restrict__ tpart, int chunks,
+                                                 const double* __restrict__ lam, int K,
+                                                 double lmbda, const DevScalars* __restrict__ sc,
+                                                 P4<float>* __restrict__ GT,
+                                                 P4<float>* __restrict__ HT, int gate) {
+  __shared__ float sh[4][3];
+  if (gate && sc->done) return;
+  const int k = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  float tx = 0.f, ty = 0.f, tz = 0.f;
+  for (int c = threadIdx.x; c < chunks; c += 256) {
+    const float4 v = *reinterpret_cast<const float4*>(tpart + ((size_t)c * K + k) * 4);
+    tx += v.x;
+    ty += v.y;
+    tz += v.z;
+  }
+  tx = wave_sum(tx);
+  ty = wave_sum(ty);
+  tz = wave_sum(tz);
+  if (lane == 0) {
+    sh[wid][0] = tx;
+    sh[wid][1] = ty;
+    sh[wid][2] = tz;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tx = (sh[0][0] + sh[1][0]) + (sh[2][0] + sh[3][0]);
+    ty = (sh[0][1] + sh[1][1]) + (sh[2][1] + sh[3][1]);
+    tz = (sh[0][2] + sh[1][2]) + (sh[2][2] + sh[3][2]);
+    const double lp = fmax(lam[k], 0.0);
+    const double g = 1.0 / (lp + lmbda * sc->sigma2);
+    const double h = lp * g;
+    GT[k] = P4<float>{(float)(g * tx), (float)(g * ty), (float)(g * tz), 0.f};
+    HT[k] = P4<float>{(float)(h * tx), (float)(h * ty), (float)(h * tz), 0.f};
+  }
+}
+
+constexpr int kTRows = 64;
 constexpr size_t kApplyLdsBytes = 65536;
 
 template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk) {
@@ -187,6 +341,23 @@ template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk) {
 }
 
 template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st) {
+  if (sizeof(T) == 4 && a.K % 4 == 0 && a.K <= 1024) {
+    const float* U = reinterpret_cast<const float*>(a.U);
+    const P4<float>* X = reinterpret_cast<const P4<float>*>(a.X);
+    hipLaunchKernelGGL(k_tpart4, dim3(a.chunks), dim3(256), 0, st, X,
+                       reinterpret_cast<const P4<float>*>(a.Yt), U, a.M, a.K, a.rows_per_chunk,
+                       a.sc, reinterpret_cast<float*>(a.tpart), a.gate);
+    hipLaunchKernelGGL(k_tmerge4, dim3(a.K), dim3(256), 0, st,
+                       reinterpret_cast<const float*>(a.tpart), a.chunks, a.lam, a.K, a.lmbda, a.sc,
+                       reinterpret_cast<P4<float>*>(a.GT), reinterpret_cast<P4<float>*>(a.HT),
+                       a.gate);
+    hipLaunchKernelGGL(k_apply4, dim3((a.M + 63) / 64), dim3(256), 6 * a.K * sizeof(float), st,
+                       X, U, reinterpret_cast<const P4<float>*>(a.GT),
+                       reinterpret_cast<const P4<float>*>(a.HT), a.M, a.K, a.sc,
+                       reinterpret_cast<P4<float>*>(a.Xnew), reinterpret_cast<P4<float>*>(a.W),
+                       a.gate);
+    return;
+  }
   const int kt = a.K <= 256 ? 1 : (a.K <= 512 ? 2 : 4);
   dim3 g1(a.chunks, (a.K + 256 * kt - 1) / (256 * kt));
   if (kt == 1)
