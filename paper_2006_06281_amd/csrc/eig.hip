@@ -141,53 +141,54 @@ __global__ __launch_bounds__(256) void k_gauss(double* __restrict__ out, size_t 
 }
 
 // ---------------------------------------------------- 64 x 64 FP64 tiles
-// C[i][c] = sum_j A[i][j] B[j][c] for a 64 x 64 output tile per block, 4 x 4
-// per thread, contraction in steps of 32 staged through LDS.  A is either a
-// row-major matrix (lda) or the Gram matrix of the points, formed on the fly:
-// A[i][j] = exp(-|x_i - x_j|^2 / (2 beta^2)) (eq. 11).
+// Dense FP64 products in 64 x 64 output tiles per block, contraction in
+// steps of 32 staged through LDS, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; A lane l: row l%16, k = l/16; B lane l: k = l/16,
+// column l%16; D lane l, register r: row 4r + l/16 of column l%16).  Each of
+// the four waves owns a 32 x 32 quadrant (2 x 2 accumulator tiles).
 constexpr int TI = 64, TC = 64, TJ = 32;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-template <typename PT, bool PHI>
+// acc += X^T Y over the 32 staged rows, X = sX[k][row], Y = sY[k][col], for
+// the quadrant at (wr, wc).
+__device__ __forceinline__ void mfma_quadrant(const double (*sX)[TI + 2],
+                                              const double (*sY)[TC + 2], int wr, int wc,
+                                              int lane, dbl4 acc[2][2]) {
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < TJ / 4; ++ks) {
+    const int k = 4 * ks + lk;
+    const double x0 = sX[k][wr + li], x1 = sX[k][wr + 16 + li];
+    const double y0 = sY[k][wc + li], y1 = sY[k][wc + 16 + li];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// C[i][c] = sum_j A[i][j] B[j][c], A rows x inner (lda), B inner x cols (ldb).
 __global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A, int lda,
-                                                   const P4<PT>* __restrict__ pts, double inv2b2,
                                                    const double* __restrict__ B, int ldb,
                                                    double* __restrict__ C, int ldc, int rows,
                                                    int inner, int cols) {
-  __shared__ double sA[TJ][TI + 2];
-  __shared__ double sB[TJ][TC + 2];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  __shared__ double sA[TJ][TI + 2];  // sA[j][i]
+  __shared__ double sB[TJ][TC + 2];  // sB[j][c]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int i0 = blockIdx.y * TI, c0 = blockIdx.x * TC;
-  double acc[4][4];
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  // the 8 (i, jj) elements of A this thread fills: i = tid & 63, jj = (tid >> 6) + 4 k
-  const int fi = tid & 63;
-  double xi0 = 0, xi1 = 0, xi2 = 0;
-  if (PHI && i0 + fi < rows) {
-    const P4<PT> p = pts[i0 + fi];
-    xi0 = p.x;
-    xi1 = p.y;
-    xi2 = p.z;
-  }
+    for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int fi = tid & 63;  // A: row i0 + fi, columns j0 + (tid >> 6) + 4 k
   for (int j0 = 0; j0 < inner; j0 += TJ) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int jj = (tid >> 6) + 4 * k;
       const int i = i0 + fi, j = j0 + jj;
-      double v = 0.0;
-      if (i < rows && j < inner) {
-        if (PHI) {
-          const P4<PT> q = pts[j];
-          const double dx = xi0 - (double)q.x, dy = xi1 - (double)q.y, dz = xi2 - (double)q.z;
-          v = exp(-(dx * dx + dy * dy + dz * dz) * inv2b2);
-        } else {
-          v = A[(size_t)i * lda + j];
-        }
-      }
-      sA[jj][fi] = v;
+      sA[jj][fi] = (i < rows && j < inner) ? A[(size_t)i * lda + j] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -197,31 +198,19 @@ __global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A,
       sB[jj][c] = (j < inner && cc < cols) ? B[(size_t)j * ldb + cc] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int jj = 0; jj < TJ; ++jj) {
-      double a[4], b[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a[t] = sA[jj][ty * 4 + t];
-        b[t] = sB[jj][tx * 4 + t];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
-    }
+    mfma_quadrant(sA, sB, wr, wc, lane, acc);
     __syncthreads();
   }
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int i = i0 + ty * 4 + x;
-    if (i >= rows) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int c = c0 + tx * 4 + y;
-      if (c < cols) C[(size_t)i * ldc + c] = acc[x][y];
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wr + 16 * x + 4 * r + lk, c = c0 + wc + 16 * y + li;
+        if (i < rows && c < cols) C[(size_t)i * ldc + c] = acc[x][y][r];
+      }
 }
 
 // ------------------------------------------- Phi B on the FP64 matrix cores
@@ -242,7 +231,6 @@ __global__ __launch_bounds__(256) void k_gemm_tile(const double* __restrict__ A,
 // so the result does not depend on timing.  The B chunk of the next unit is
 // loaded into registers while the current one is multiplied from LDS.
 constexpr int PR = 128, PK = 16;
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // e^x for x <= 0 without branches: Cody-Waite reduction x = k ln2 + r,
 // |r| <= ln2 / 2 (ln2 split into a 32-bit head and its remainder, so k ln2
@@ -465,18 +453,18 @@ __global__ __launch_bounds__(256) void k_phi_fix(double* __restrict__ C, int M, 
 __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
                                                    const double* __restrict__ B, int M, int n,
                                                    int rows_per_chunk, double* __restrict__ P) {
-  __shared__ double sA[TJ][TI + 2];
-  __shared__ double sB[TJ][TC + 2];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  __shared__ double sA[TJ][TI + 2];  // sA[m][a]
+  __shared__ double sB[TJ][TC + 2];  // sB[m][b]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int a0 = blockIdx.y * TI, b0 = blockIdx.x * TC;
   const int m0 = blockIdx.z * rows_per_chunk;
   const int m1 = min(M, m0 + rows_per_chunk);
-  double acc[4][4];
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int mb = m0; mb < m1; mb += TJ) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -487,32 +475,20 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
       sB[r][c] = (m < m1 && b0 + c < n) ? B[(size_t)m * n + b0 + c] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int r = 0; r < TJ; ++r) {
-      double a[4], b[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a[t] = sA[r][ty * 4 + t];
-        b[t] = sB[r][tx * 4 + t];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
-    }
+    mfma_quadrant(sA, sB, wr, wc, lane, acc);
     __syncthreads();
   }
   double* out = P + (size_t)blockIdx.z * n * n;
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int a = a0 + ty * 4 + x;
-    if (a >= n) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int b = b0 + tx * 4 + y;
-      if (b < n) out[(size_t)a * n + b] = acc[x][y];
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + wr + 16 * x + 4 * r + lk, b = b0 + wc + 16 * y + li;
+        if (a < n && b < n) out[(size_t)a * n + b] = acc[x][y][r];
+      }
 }
 
 // G = sum of chunk partials, symmetrised: G = (S + S^T)/2.
@@ -842,8 +818,8 @@ void phi_times(const Ctx& c, const double* B, double* C, int n, double* scratch)
 void gemm_nn(const Ctx& c, const double* A, int lda, const double* B, int ldb, double* C, int ldc,
              int rows, int inner, int cols) {
   dim3 grid((cols + TC - 1) / TC, (rows + TI - 1) / TI);
-  hipLaunchKernelGGL((k_gemm_tile<double, false>), grid, dim3(256), 0, c.st, A, lda,
-                     (const P4<double>*)nullptr, 0.0, B, ldb, C, ldc, rows, inner, cols);
+  hipLaunchKernelGGL(k_gemm_tile, grid, dim3(256), 0, c.st, A, lda, B, ldb, C, ldc, rows, inner,
+                     cols);
 }
 
 void gram(const Ctx& c, const double* A, const double* B, int n, double* G) {
