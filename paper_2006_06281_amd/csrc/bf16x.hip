@@ -131,13 +131,13 @@ __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int p
   return *reinterpret_cast<const bf16x8*>(feat + (size_t)point * 32 + 8 * (lane >> 4));
 }
 
-// Pass A partials: part[split][n] = sum over the split's model points of
-// 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
+// Pass A partials: part[split][n] = sum over the split's model points (every
+// S-th 64-point tile) of 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
 // wave skips every 64-point model tile whose smallest exponent against its
 // scene tile reaches CullLimit (all its terms are +0).
 __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G, int Mpad, int N,
-                                                    int m_chunk, const DevScalars* __restrict__ sc,
+                                                    const DevScalars* __restrict__ sc,
                                                     float* __restrict__ part,
                                                     const P4<float>* __restrict__ boxX,
                                                     const P4<float>* __restrict__ boxY, double w,
@@ -145,16 +145,19 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   if (gate && sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 scene columns
+  if (n0 >= N) return;  // padding only: nothing of it is stored
   // the per-column offset the scene features carry (see k_feat_scene)
   const float ref = (float)fmax(log2_c(sc->sigma2, 3, w, M, N), kRefFloor);
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(G, n0 + 16 * s + (lane & 15), lane);
-  const int m0 = blockIdx.y * m_chunk;
-  const int m1 = min(Mpad, m0 + m_chunk);
+  // this split's model tiles: every S-th 64-row tile from tile blockIdx.y
+  // (S = gridDim.y splits), so the tiles near any scene column, which are
+  // consecutive in the spatial order, spread evenly over the splits
+  const int S = gridDim.y, tiles = (Mpad + 63) >> 6;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  const bool cull = boxX != nullptr && n0 < N &&
+  const bool cull = boxX != nullptr &&
                     cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
   P4<float> blo{}, bhi{};
   if (cull) {
@@ -162,18 +165,31 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
     bhi = boxY[2 * (n0 >> 6) + 1];
   }
   const float lim = CullLimit<float>::value - ref;
-  for (int mt64 = m0; mt64 < m1; mt64 += 64) {
+  // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
+  // tiles to evaluate
+  for (int i0 = 0; (int)blockIdx.y + S * i0 < tiles; i0 += 64) {
+    const int t0 = blockIdx.y + S * i0;
+    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
     if (cull) {
-      const int t = mt64 >> 6;
-      if (box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) >= lim) continue;
+      bool kp = false;
+      if (lane < ntiles) {
+        const int t = t0 + S * lane;
+        kp = box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) < lim;
+      }
+      keep = __ballot(kp);
     }
-    const int me = min(m1, mt64 + 64);
-    for (int mt = mt64; mt < me; mt += 16) {
-      const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+    while (keep) {
+      const int mt64 = 64 * (t0 + S * __builtin_ctzll(keep));
+      keep &= keep - 1;
+      const int me = min(Mpad, mt64 + 64);
+      for (int mt = mt64; mt < me; mt += 16) {
+        const bf16x8 a = load_op(F, mt + (lane & 15), lane);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-        acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+        for (int s = 0; s < 4; ++s) {
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+          acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+        }
       }
     }
   }
@@ -191,24 +207,27 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   }
 }
 
-// Pass B partials: part[split][5][M] = sum over the split's scene points of
-// p, p*v (prescaled, absolute), p*|u - v|^2 with p = 2^-(|u - v|^2 + L_n).
+// Pass B partials: part[split][5][M] = sum over the split's scene points
+// (every S-th 64-point tile) of p, p*v (prescaled, absolute), p*|u - v|^2
+// with p = 2^-(|u - v|^2 + L_n).
 __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G,
                                                     const P4<float>* __restrict__ ys, int M,
-                                                    int Npad, int n_chunk,
-                                                    const DevScalars* __restrict__ sc,
+                                                    int Npad, const DevScalars* __restrict__ sc,
                                                     float* __restrict__ part,
                                                     const P4<float>* __restrict__ boxX,
                                                     const P4<float>* __restrict__ boxY, int gate) {
   if (gate && sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 model columns
+  if (m0 >= M) return;  // padding only: nothing of it is stored
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
-  const int nb = blockIdx.y * n_chunk;
-  const int ne = min(Npad, nb + n_chunk);
+  // this split's scene tiles: every S-th 64-row tile from tile blockIdx.y
+  // (S = gridDim.y splits), so the tiles near any model point, which are
+  // consecutive in the spatial order, spread evenly over the splits
+  const int S = gridDim.y, tiles = (Npad + 63) >> 6;
   float r[4], px[4], py[4], pz[4], t[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
@@ -216,38 +235,50 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
   // with boxes: skip 64-point scene tiles whose smallest exponent
   // |u - v|^2 + min L_n against this wave's model tile reaches CullLimit
-  const bool cull = boxX != nullptr && m0 < M &&
-                    cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
+  const bool cull = boxX != nullptr && cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
   P4<float> alo{}, ahi{};
   if (cull) {
     alo = boxX[2 * (m0 >> 6)];
     ahi = boxX[2 * (m0 >> 6) + 1];
   }
-  for (int nt = nb; nt < ne; nt += 16) {
-    if (cull && (nt & 63) == 0) {
-      const int k = nt >> 6;
-      const P4<float> lo = boxY[2 * k];  // lo.w = min L_n of the tile
-      if (box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w >= CullLimit<float>::value) {
-        nt += 48;  // with the loop's 16: the next 64-point tile
-        continue;
+  // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
+  // tiles to evaluate
+  for (int i0 = 0; (int)blockIdx.y + S * i0 < tiles; i0 += 64) {
+    const int t0 = blockIdx.y + S * i0;
+    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
+    if (cull) {
+      bool kp = false;
+      if (lane < ntiles) {
+        const int k = t0 + S * lane;
+        const P4<float> lo = boxY[2 * k];  // lo.w = min L_n of the tile
+        kp = box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w < CullLimit<float>::value;
       }
+      keep = __ballot(kp);
     }
-    const bf16x8 a = load_op(G, nt + (lane & 15), lane);
-    P4<float> yv[4];
+    while (keep) {
+      const int n64 = 64 * (t0 + S * __builtin_ctzll(keep));
+      keep &= keep - 1;
+      const int te = min(Npad, n64 + 64);
+      for (int nt = n64; nt < te; nt += 16) {
+        const bf16x8 a = load_op(G, nt + (lane & 15), lane);
+        P4<float> yv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
+        for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+        for (int s = 0; s < 4; ++s) {
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float p = fexp2(-d[q]);
-        const float d2 = d[q] - yv[q].w;
-        r[s] += p;
-        px[s] = fmaf(p, yv[q].x, px[s]);
-        py[s] = fmaf(p, yv[q].y, py[s]);
-        pz[s] = fmaf(p, yv[q].z, pz[s]);
-        t[s] = fmaf(p, d2, t[s]);
+          for (int q = 0; q < 4; ++q) {
+            const float p = fexp2(-d[q]);
+            const float d2 = d[q] - yv[q].w;
+            r[s] += p;
+            px[s] = fmaf(p, yv[q].x, px[s]);
+            py[s] = fmaf(p, yv[q].y, py[s]);
+            pz[s] = fmaf(p, yv[q].z, pz[s]);
+            t[s] = fmaf(p, d2, t[s]);
+          }
+        }
       }
     }
   }
@@ -287,7 +318,7 @@ void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chun
     const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (lenp + s - 1) / s;
-    c = (c + 63) & ~63;  // splits start on 64-point tiles (far-tile culling)
+    c = (c + 63) & ~63;  // whole 64-point tiles per split (a split takes every S-th tile)
     *chunk = c;
     *splits = (lenp + c - 1) / c;
   };
@@ -305,14 +336,14 @@ void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
                      a.w, a.M, a.D, a.featY, a.sc, gate);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
-                     a.featY, Mpad, a.N, a.chunkA, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
+                     a.featY, Mpad, a.N, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
   colmerge_fix_launch<float>(a, st);
   hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 1,
                      a.w, a.M, a.D, a.featY, a.sc, gate);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
-                     a.featY, a.ys, a.M, Npad, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate);
+                     a.featY, a.ys, a.M, Npad, a.sc, a.partB, a.boxX, a.boxY, gate);
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
   rowmerge_fix_launch<float>(a, st, /*relative=*/0);
   if (a.ev) (void)hipEventRecord(a.ev[4], st);

@@ -154,6 +154,7 @@ __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
   const T ref = (T)fmax(l2c, kRefFloor);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw0 = bx_ * (256 * NB) + wave * (64 * NB);
+  if (nw0 >= N) return;  // padding only: nothing of it is stored
   const int m0 = by_ * m_chunk;
   const int m1 = min(M, m0 + m_chunk);
   T yx[NB], yy[NB], yz[NB], s[NB];
@@ -336,6 +337,7 @@ __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
   if (gate && sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mw0 = bx_ * (256 * NB) + wave * (64 * NB);
+  if (mw0 >= M) return;  // padding only: nothing of it is stored
   const int nb = by_ * n_chunk;
   const int ne = min(N, nb + n_chunk);
   T ax[NB], ay[NB], az[NB], r[NB], px[NB], py[NB], pz[NB], t[NB];

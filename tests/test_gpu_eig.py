@@ -112,6 +112,24 @@ def test_randomized_topk_wide_tiles(lib, M, K, over, precision):
     assert np.abs(res).max() < 1e-9 * lam[0]
 
 
+def test_randomized_topk_tiny(lib):
+    """40 points, K + p = 12: a single output tile and a single block."""
+    import torch
+    say("randomized topk tiny")
+    p = synth.sphere_pair(M=40, N=45, seed=21)
+    X = _f32(p.X)
+    K, over, q = 8, 4, 2
+    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=3)
+    Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
+    r = lib.Registration(dev(X, torch.float32), dev(_f32(p.Y), torch.float32), precision="fp32",
+                         beta=p.beta, lam=p.lam, w=p.w, eig_mode="topk", K=K, oversample=over,
+                         power_iters=q, seed=5, tol=0.0, max_iter=5)
+    r.prepare(omega=dev(Om, torch.float64))
+    U, lam = (host(t) for t in r.export_eig())
+    np.testing.assert_allclose(lam, lo, rtol=0, atol=1e-11 * lo[0])
+    np.testing.assert_allclose(U.T @ U, np.eye(K), atol=1e-10)
+
+
 def test_full_mode_above_dense_limit(lib):
     """FULL mode at 3000 points (randomized, width grown to round-off) gives
     the registration of the dense eigendecomposition."""

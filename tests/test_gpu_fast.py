@@ -128,6 +128,24 @@ def test_topk_import_matches_low_rank_oracle(lib):
     assert cpd64.rel_rms(host(out.Xt), ref.Xt) < 1e-5
 
 
+@pytest.mark.parametrize("K", [1024, 1028, 302])
+def test_topk_import_vector_and_scalar_mstep(lib, K):
+    """K = 1024: the widest K the 16-byte M-step path takes (one row lane of
+    256 threads); 1028 and 302 (not a multiple of 4) take the scalar path."""
+    import torch
+    say("topk import K", K)
+    p = synth.sphere_pair(M=1100, N=1000, seed=13)
+    U, lam = _oracle_eig(p.X, p.beta)
+    ref = cpd64.register(p.X, p.Y, p.beta, p.lam, p.w, "fast", eig=(U[:, :K], lam[:K]), iters=10)
+    r = _reg(lib, p.X, p.Y, "fp32", beta=p.beta, lam=p.lam, w=p.w, eig_mode="import", K=K,
+             tol=0.0, max_iter=10)
+    r.prepare(dev(U[:, :K], torch.float64), dev(lam[:K], torch.float64))
+    out = r.register()
+    err = cpd64.rel_rms(host(out.Xt), ref.Xt)
+    say("rel_rms", err)
+    assert err < 1e-5
+
+
 def test_warm_start_sets_xt_from_w0(lib):
     import torch
     say("warm start")
