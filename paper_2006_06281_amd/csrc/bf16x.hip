@@ -131,8 +131,9 @@ __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int p
   return *reinterpret_cast<const bf16x8*>(feat + (size_t)point * 32 + 8 * (lane >> 4));
 }
 
-// Pass A partials: part[split][n] = sum over the split's model points (every
-// S-th 64-point tile) of 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
+// Pass A partials: part[split][n] = sum over the split's model points (with
+// culling every S-th 64-point tile, else a contiguous range) of
+// 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
 // wave skips every 64-point model tile whose smallest exponent against its
 // scene tile reaches CullLimit (all its terms are +0).
 __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
@@ -151,14 +152,16 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(G, n0 + 16 * s + (lane & 15), lane);
-  // this split's model tiles: every S-th 64-row tile from tile blockIdx.y
-  // (S = gridDim.y splits), so the tiles near any scene column, which are
-  // consecutive in the spatial order, spread evenly over the splits
+  // with culling, this split's model tiles are every S-th 64-row tile from
+  // tile blockIdx.y (S = gridDim.y splits): the tiles near any scene column,
+  // consecutive in the spatial order, then spread evenly over the splits
   const int S = gridDim.y, tiles = (Mpad + 63) >> 6;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  const bool cull = boxX != nullptr &&
-                    cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
+  // the split layout follows the sigma^2 gate alone, so a handle without
+  // boxes adds the same terms in the same order (culling stays bit-exact)
+  const bool spread = cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
+  const bool cull = boxX != nullptr && spread;
   P4<float> blo{}, bhi{};
   if (cull) {
     blo = boxY[2 * (n0 >> 6)];
@@ -167,20 +170,25 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   const float lim = CullLimit<float>::value - ref;
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
-  for (int i0 = 0; (int)blockIdx.y + S * i0 < tiles; i0 += 64) {
-    const int t0 = blockIdx.y + S * i0;
-    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+  // (while culling cannot pay every tile is evaluated and consecutive tiles
+  // per split read better, so the split then takes a contiguous range)
+  const int per = (tiles + S - 1) / S;
+  const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
+  const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
+  for (int i0 = 0; i0 < tn; i0 += 64) {
+    const int t0 = tb + ts * i0;
+    const int ntiles = min(64, tn - i0);
     uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
     if (cull) {
       bool kp = false;
       if (lane < ntiles) {
-        const int t = t0 + S * lane;
+        const int t = t0 + ts * lane;
         kp = box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) < lim;
       }
       keep = __ballot(kp);
     }
     while (keep) {
-      const int mt64 = 64 * (t0 + S * __builtin_ctzll(keep));
+      const int mt64 = 64 * (t0 + ts * __builtin_ctzll(keep));
       keep &= keep - 1;
       const int me = min(Mpad, mt64 + 64);
       for (int mt = mt64; mt < me; mt += 16) {
@@ -208,8 +216,8 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
 }
 
 // Pass B partials: part[split][5][M] = sum over the split's scene points
-// (every S-th 64-point tile) of p, p*v (prescaled, absolute), p*|u - v|^2
-// with p = 2^-(|u - v|^2 + L_n).
+// (with culling every S-th 64-point tile, else a contiguous range) of p, p*v
+// (prescaled, absolute), p*|u - v|^2 with p = 2^-(|u - v|^2 + L_n).
 __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G,
                                                     const P4<float>* __restrict__ ys, int M,
@@ -224,9 +232,9 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
-  // this split's scene tiles: every S-th 64-row tile from tile blockIdx.y
-  // (S = gridDim.y splits), so the tiles near any model point, which are
-  // consecutive in the spatial order, spread evenly over the splits
+  // with culling, this split's scene tiles are every S-th 64-row tile from
+  // tile blockIdx.y (S = gridDim.y splits): the tiles near any model point,
+  // consecutive in the spatial order, then spread evenly over the splits
   const int S = gridDim.y, tiles = (Npad + 63) >> 6;
   float r[4], px[4], py[4], pz[4], t[4];
 #pragma unroll
@@ -235,7 +243,9 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
   // with boxes: skip 64-point scene tiles whose smallest exponent
   // |u - v|^2 + min L_n against this wave's model tile reaches CullLimit
-  const bool cull = boxX != nullptr && cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
+  // (the split layout follows the sigma^2 gate alone: see pass A)
+  const bool spread = cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
+  const bool cull = boxX != nullptr && spread;
   P4<float> alo{}, ahi{};
   if (cull) {
     alo = boxX[2 * (m0 >> 6)];
@@ -243,21 +253,26 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   }
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
-  for (int i0 = 0; (int)blockIdx.y + S * i0 < tiles; i0 += 64) {
-    const int t0 = blockIdx.y + S * i0;
-    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+  // (while culling cannot pay every tile is evaluated and consecutive tiles
+  // per split read better, so the split then takes a contiguous range)
+  const int per = (tiles + S - 1) / S;
+  const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
+  const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
+  for (int i0 = 0; i0 < tn; i0 += 64) {
+    const int t0 = tb + ts * i0;
+    const int ntiles = min(64, tn - i0);
     uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
     if (cull) {
       bool kp = false;
       if (lane < ntiles) {
-        const int k = t0 + S * lane;
+        const int k = t0 + ts * lane;
         const P4<float> lo = boxY[2 * k];  // lo.w = min L_n of the tile
         kp = box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w < CullLimit<float>::value;
       }
       keep = __ballot(kp);
     }
     while (keep) {
-      const int n64 = 64 * (t0 + S * __builtin_ctzll(keep));
+      const int n64 = 64 * (t0 + ts * __builtin_ctzll(keep));
       keep &= keep - 1;
       const int te = min(Npad, n64 + 64);
       for (int nt = n64; nt < te; nt += 16) {
@@ -318,7 +333,7 @@ void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chun
     const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (lenp + s - 1) / s;
-    c = (c + 63) & ~63;  // whole 64-point tiles per split (a split takes every S-th tile)
+    c = (c + 63) & ~63;  // whole 64-point tiles per split
     *chunk = c;
     *splits = (lenp + c - 1) / c;
   };

@@ -137,14 +137,15 @@ __device__ __forceinline__ T sq3(const P4<T>& a, T bx, T by, T bz, T init) {
   return q;
 }
 
-// part[blockIdx.y * N + n] = sum over this split's model points of
-// 2^(-(|y^_n - x^_m|^2 + ref)).  A wave owns 64 NB consecutive scene points
-// (lane + 64 j); with boxes it skips every 64-point model tile whose smallest
-// exponent against the wave's tiles reaches CullLimit (all its terms are +0).
+// part[split * N + n] = sum over this split's model points (every S-th
+// 64-point tile from tile `split`) of 2^(-(|y^_n - x^_m|^2 + ref)).  A wave
+// owns 64 NB consecutive scene points (lane + 64 j); with boxes it skips
+// every model tile whose smallest exponent against the wave's tiles reaches
+// CullLimit (all its terms are +0).
 template <typename T, int D, int NB>
 __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
-                                                int m_chunk, const DevScalars* __restrict__ sc,
+                                                int S, const DevScalars* __restrict__ sc,
                                                 double w, T* __restrict__ part,
                                                 const P4<T>* __restrict__ boxX,
                                                 const P4<T>* __restrict__ boxY, int gate,
@@ -155,8 +156,7 @@ __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw0 = bx_ * (256 * NB) + wave * (64 * NB);
   if (nw0 >= N) return;  // padding only: nothing of it is stored
-  const int m0 = by_ * m_chunk;
-  const int m1 = min(M, m0 + m_chunk);
+  const int tiles = (M + 63) >> 6;
   T yx[NB], yy[NB], yz[NB], s[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -181,33 +181,42 @@ __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
     }
   }
   const T lim = CullLimit<T>::value - ref;
-  for (int mt = m0; mt < m1;) {
-    const int me = min(m1, (mt & ~63) + 64);
+  // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
+  // tiles to evaluate
+  for (int i0 = 0; by_ + S * i0 < tiles; i0 += 64) {
+    const int t0 = by_ + S * i0;
+    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
     if (cull) {
-      const int t = mt >> 6;
-      if (box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) >= lim) {
-        mt = me;
-        continue;
+      bool kp = false;
+      if (lane < ntiles) {
+        const int t = t0 + S * lane;
+        kp = box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) < lim;
+      }
+      keep = __ballot(kp);
+    }
+    while (keep) {
+      const int mt = 64 * (t0 + S * __builtin_ctzll(keep));
+      keep &= keep - 1;
+      const int me = min(M, mt + 64);
+      int m = mt;
+      for (; m + 4 <= me; m += 4) {
+        P4<T> a0 = xs[m], a1 = xs[m + 1], a2 = xs[m + 2], a3 = xs[m + 3];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          T e0 = fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
+          T e1 = fexp2(-sq3<T, D>(a1, yx[j], yy[j], yz[j], ref));
+          T e2 = fexp2(-sq3<T, D>(a2, yx[j], yy[j], yz[j], ref));
+          T e3 = fexp2(-sq3<T, D>(a3, yx[j], yy[j], yz[j], ref));
+          s[j] += (e0 + e1) + (e2 + e3);
+        }
+      }
+      for (; m < me; ++m) {
+        P4<T> a0 = xs[m];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) s[j] += fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
       }
     }
-    int m = mt;
-    for (; m + 4 <= me; m += 4) {
-      P4<T> a0 = xs[m], a1 = xs[m + 1], a2 = xs[m + 2], a3 = xs[m + 3];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        T e0 = fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
-        T e1 = fexp2(-sq3<T, D>(a1, yx[j], yy[j], yz[j], ref));
-        T e2 = fexp2(-sq3<T, D>(a2, yx[j], yy[j], yz[j], ref));
-        T e3 = fexp2(-sq3<T, D>(a3, yx[j], yy[j], yz[j], ref));
-        s[j] += (e0 + e1) + (e2 + e3);
-      }
-    }
-    for (; m < me; ++m) {
-      P4<T> a0 = xs[m];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) s[j] += fexp2(-sq3<T, D>(a0, yx[j], yy[j], yz[j], ref));
-    }
-    mt = me;
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -219,11 +228,11 @@ __device__ __forceinline__ void colsum_body(const P4<T>* __restrict__ xs,
 template <typename T, int D, int NB>
 __global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
-                                                int m_chunk, const DevScalars* __restrict__ sc,
+                                                const DevScalars* __restrict__ sc,
                                                 double w, T* __restrict__ part,
                                                 const P4<T>* __restrict__ boxX,
                                                 const P4<T>* __restrict__ boxY, int gate) {
-  colsum_body<T, D, NB>(xs, ys, M, N, m_chunk, sc, w, part, boxX, boxY, gate, blockIdx.x,
+  colsum_body<T, D, NB>(xs, ys, M, N, gridDim.y, sc, w, part, boxX, boxY, gate, blockIdx.x,
                         blockIdx.y, gridDim.x);
 }
 
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
 template <typename T, int D, int NB>
 __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
-                                                int n_chunk, const DevScalars* __restrict__ sc,
+                                                int S, const DevScalars* __restrict__ sc,
                                                 T* __restrict__ part,
                                                 const P4<T>* __restrict__ boxX,
                                                 const P4<T>* __restrict__ boxY, int gate,
@@ -338,8 +347,7 @@ __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mw0 = bx_ * (256 * NB) + wave * (64 * NB);
   if (mw0 >= M) return;  // padding only: nothing of it is stored
-  const int nb = by_ * n_chunk;
-  const int ne = min(N, nb + n_chunk);
+  const int tiles = (N + 63) >> 6;
   T ax[NB], ay[NB], az[NB], r[NB], px[NB], py[NB], pz[NB], t[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -364,40 +372,49 @@ __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
       ahi = P4<T>{fmax(ahi.x, hi.x), fmax(ahi.y, hi.y), fmax(ahi.z, hi.z), fmax(ahi.w, hi.w)};
     }
   }
-  for (int nt = nb; nt < ne;) {
-    const int nE = min(ne, (nt & ~63) + 64);
+  // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
+  // tiles to evaluate
+  for (int i0 = 0; by_ + S * i0 < tiles; i0 += 64) {
+    const int t0 = by_ + S * i0;
+    const int ntiles = min(64, (tiles - t0 + S - 1) / S);
+    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
     if (cull) {
-      const int k = nt >> 6;
-      const P4<T> lo = boxY[2 * k];  // lo.w = min L_n of the tile
-      if (box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w >= CullLimit<T>::value) {
-        nt = nE;
-        continue;
+      bool kp = false;
+      if (lane < ntiles) {
+        const int k = t0 + S * lane;
+        const P4<T> lo = boxY[2 * k];  // lo.w = min L_n of the tile
+        kp = box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w < CullLimit<T>::value;
       }
+      keep = __ballot(kp);
     }
-    for (int n = nt; n < nE; ++n) {
-      const P4<T> y = ys[n];  // (x^, y^, z^, L_n)
+    while (keep) {
+      const int nt = 64 * (t0 + S * __builtin_ctzll(keep));
+      keep &= keep - 1;
+      const int nE = min(N, nt + 64);
+      for (int n = nt; n < nE; ++n) {
+        const P4<T> y = ys[n];  // (x^, y^, z^, L_n)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const T dx = y.x - ax[j];
-        T d2 = dx * dx;
-        T dy = (T)0, dz = (T)0;
-        if (D > 1) {
-          dy = y.y - ay[j];
-          d2 = fma(dy, dy, d2);
+        for (int j = 0; j < NB; ++j) {
+          const T dx = y.x - ax[j];
+          T d2 = dx * dx;
+          T dy = (T)0, dz = (T)0;
+          if (D > 1) {
+            dy = y.y - ay[j];
+            d2 = fma(dy, dy, d2);
+          }
+          if (D > 2) {
+            dz = y.z - az[j];
+            d2 = fma(dz, dz, d2);
+          }
+          const T e = fexp2(-(d2 + y.w));
+          r[j] += e;
+          px[j] = fma(e, dx, px[j]);
+          if (D > 1) py[j] = fma(e, dy, py[j]);
+          if (D > 2) pz[j] = fma(e, dz, pz[j]);
+          t[j] = fma(e, d2, t[j]);
         }
-        if (D > 2) {
-          dz = y.z - az[j];
-          d2 = fma(dz, dz, d2);
-        }
-        const T e = fexp2(-(d2 + y.w));
-        r[j] += e;
-        px[j] = fma(e, dx, px[j]);
-        if (D > 1) py[j] = fma(e, dy, py[j]);
-        if (D > 2) pz[j] = fma(e, dz, pz[j]);
-        t[j] = fma(e, d2, t[j]);
       }
     }
-    nt = nE;
   }
   T* base = part + (size_t)by_ * 5 * M;
 #pragma unroll
@@ -416,11 +433,11 @@ __device__ __forceinline__ void rowsum_body(const P4<T>* __restrict__ xs,
 template <typename T, int D, int NB>
 __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
                                                 const P4<T>* __restrict__ ys, int M, int N,
-                                                int n_chunk, const DevScalars* __restrict__ sc,
+                                                const DevScalars* __restrict__ sc,
                                                 T* __restrict__ part,
                                                 const P4<T>* __restrict__ boxX,
                                                 const P4<T>* __restrict__ boxY, int gate) {
-  rowsum_body<T, D, NB>(xs, ys, M, N, n_chunk, sc, part, boxX, boxY, gate, blockIdx.x,
+  rowsum_body<T, D, NB>(xs, ys, M, N, gridDim.y, sc, part, boxX, boxY, gate, blockIdx.x,
                         blockIdx.y, gridDim.x);
 }
 
@@ -585,9 +602,9 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
     const int tiles = (a.N + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsA);
     switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_colsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
-      case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
-      default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkA, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
+      case 1: hipLaunchKernelGGL((k_colsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
+      case 2: hipLaunchKernelGGL((k_colsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
+      default: hipLaunchKernelGGL((k_colsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.w, a.partA, a.boxX, a.boxY, gate); break;
     }
   }
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
@@ -597,9 +614,9 @@ void estep_launch(const EStepArgs<T>& a, hipStream_t st) {
     const int tiles = (a.M + 256 * NB - 1) / (256 * NB);
     dim3 grid(tiles, a.splitsB);
     switch (a.D) {
-      case 1: hipLaunchKernelGGL((k_rowsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
-      case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
-      default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.chunkB, a.sc, a.partB, a.boxX, a.boxY, gate); break;
+      case 1: hipLaunchKernelGGL((k_rowsum<T, 1, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.partB, a.boxX, a.boxY, gate); break;
+      case 2: hipLaunchKernelGGL((k_rowsum<T, 2, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.partB, a.boxX, a.boxY, gate); break;
+      default: hipLaunchKernelGGL((k_rowsum<T, 3, NB>), grid, dim3(256), 0, st, a.xs, a.ys, a.M, a.N, a.sc, a.partB, a.boxX, a.boxY, gate); break;
     }
   }
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
@@ -617,7 +634,7 @@ void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* ch
     const int smax = (len + 63) / 64;  // at least 64 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (len + s - 1) / s;
-    c = (c + 63) & ~63;  // splits start on 64-point tiles (far-tile culling)
+    c = (c + 63) & ~63;  // whole 64-point tiles per split (a split takes every S-th tile)
     *chunk = c;
     *splits = (len + c - 1) / c;
   };
@@ -637,7 +654,7 @@ __global__ __launch_bounds__(256) void kb_colsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkA, D.sc, D.w, D.partA,
+  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsA, D.sc, D.w, D.partA,
                            (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ d,
@@ -658,7 +675,7 @@ __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.chunkB, D.sc, D.partB,
+  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsB, D.sc, D.partB,
                            (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ d,
