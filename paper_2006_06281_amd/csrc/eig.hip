@@ -33,6 +33,7 @@ constexpr int kDenseMax = 1024;
 constexpr int kFullOversample = 32;
 constexpr int kGramMaxChunks = 64;
 constexpr int kJacobiMax = kTopKMaxCols;
+constexpr int kJacobiStagedMax = 1024;  // one launch per step up to this size
 // Graded spectra (Gaussian Gram matrices reach round-off within a few
 // hundred eigenvalues) need 20-30 sweeps before no rotation is left.
 constexpr int kJacobiSweeps = 100;
@@ -573,13 +574,15 @@ __global__ __launch_bounds__(256) void k_tri_inv_t(const double* __restrict__ G,
 // Round-robin ordering: in each of the n-1 steps of a sweep the n/2 pairs are
 // disjoint, so their rotations commute.  A step is A <- J^T A J; the column
 // half of step s is deferred to step s+1, whose pairs also cover every row
-// once, so one launch per step suffices: the block of pair (p, q) loads rows
+// once, so up to n = 1024 one launch per step suffices: the block of pair
+// (p, q) loads rows
 // p and q, applies step s's column rotations to them (the rotated 2 x 2
 // blocks set to their exact values so round-off cannot keep re-opening
 // them), takes its own rotation from the now current 2 x 2 block, applies it
 // to the two rows and writes them back; V's rows p and q get step s's column
-// rotations alongside.  A final launch applies the last step's columns.  A
-// pair is rotated while |a_pq| exceeds both eps sqrt(|a_pp a_qq|) (relative
+// rotations alongside.  A final launch applies the last step's columns.
+// (Wider matrices use two launches per step; see k_jac_rows.)  A pair is
+// rotated while |a_pq| exceeds both eps sqrt(|a_pp a_qq|) (relative
 // accuracy) and 1e-16 |A|_F (entries below are round-off of the largest
 // eigenvalues).  V accumulates the rotations; on exit diag(A) holds the
 // eigenvalues.
@@ -713,6 +716,80 @@ __global__ __launch_bounds__(256) void k_jac_step(double* __restrict__ A, double
       A[(size_t)p * n + j] = x;
     }
   }
+}
+
+// Wide matrices (n > 1024, where four staged rows per pair would leave two
+// blocks per CU): a step is two launches, k_jac_rows (one block per pair:
+// rotation from the pair's current 2 x 2 block, then rows p, q of J^T A)
+// and k_jac_cols (columns p, q of A J, the 2 x 2 block set exactly, and of
+// V J), which keeps every CU busy with short independent accesses.
+__global__ __launch_bounds__(256) void k_jac_rows(double* __restrict__ A, int n, int step,
+                                                  const double* __restrict__ normtot,
+                                                  double* __restrict__ prm,
+                                                  int* __restrict__ rotated) {
+  __shared__ double cs_[2];
+  const int k = blockIdx.x;
+  int p, q;
+  rr_pair(k, step, n, &p, &q);
+  if (threadIdx.x == 0) {
+    double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
+    if (q < n) {
+      const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+      const double apq = A[(size_t)p * n + q];
+      const double aa = fabs(apq);
+      const double eps = 1.1102230246251565e-16;
+      if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-16 * sqrt(normtot[0])) {
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + t * t);
+        s = t * c;
+        dp = app - t * apq;
+        dq = aqq + t * apq;
+        rotated[0] = 1;
+      }
+    }
+    cs_[0] = c;
+    cs_[1] = s;
+    prm[4 * k + 0] = c;
+    prm[4 * k + 1] = s;
+    prm[4 * k + 2] = dp;
+    prm[4 * k + 3] = dq;
+  }
+  __syncthreads();
+  const double c = cs_[0], s = cs_[1];
+  if (q >= n || s == 0.0) return;
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
+    A[(size_t)p * n + j] = c * ap - s * aq;
+    A[(size_t)q * n + j] = s * ap + c * aq;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_jac_cols(double* __restrict__ A, double* __restrict__ V,
+                                                  int n, int step,
+                                                  const double* __restrict__ prm) {
+  const int k = blockIdx.x;
+  int p, q;
+  rr_pair(k, step, n, &p, &q);
+  if (q >= n) return;
+  const double c = prm[4 * k + 0], s = prm[4 * k + 1];
+  if (s == 0.0) return;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
+  if (i == p) {
+    A[(size_t)p * n + p] = prm[4 * k + 2];
+    A[(size_t)p * n + q] = 0.0;
+  } else if (i == q) {
+    A[(size_t)q * n + p] = 0.0;
+    A[(size_t)q * n + q] = prm[4 * k + 3];
+  } else {
+    A[(size_t)i * n + p] = c * ap - s * aq;
+    A[(size_t)i * n + q] = s * ap + c * aq;
+  }
+  const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
+  V[(size_t)i * n + p] = c * vp - s * vq;
+  V[(size_t)i * n + q] = s * vp + c * vq;
 }
 
 __global__ void k_flag_clear(int* f) {
@@ -919,21 +996,23 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
   hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
   hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, c.st, normsq, 64);
   const double* normtot = normsq + 64;
+  const bool staged = n <= kJacobiStagedMax;
   const size_t lds = 4 * (size_t)n * sizeof(double);
-  if (lds > 65536 && hipFuncSetAttribute(reinterpret_cast<const void*>(k_jac_step),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)lds) != hipSuccess) {
-    *msg = "Jacobi: LDS request refused";
-    return 2;
-  }
   int sweep = 0, prev = 0, launched = 0;
   const double* prm_prev = nullptr;
   for (; sweep < kJacobiSweeps; ++sweep) {
     hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c.st, flag);
     for (int step = 0; step < 2 * half - 1; ++step) {
       double* prm = prm_buf[launched++ & 1];
-      hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, step, prev,
-                         prm_prev, prm, normtot, flag);
+      if (staged) {
+        hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, step, prev,
+                           prm_prev, prm, normtot, flag);
+      } else {
+        hipLaunchKernelGGL(k_jac_rows, dim3(half), dim3(256), 0, c.st, A, n, step, normtot, prm,
+                           flag);
+        hipLaunchKernelGGL(k_jac_cols, dim3(half, (n + 255) / 256), dim3(256), 0, c.st, A, V, n,
+                           step, prm);
+      }
       prev = step;
       prm_prev = prm;
     }
@@ -942,7 +1021,7 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
     (void)hipStreamSynchronize(c.st);
     if (!h) break;
   }
-  if (prm_prev)  // the last step's column rotations
+  if (staged && prm_prev)  // the last step's column rotations
     hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, -1, prev, prm_prev,
                        (double*)nullptr, normtot, flag);
   hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);
