@@ -54,8 +54,8 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
 # of known size; valid only while the kernel source is unchanged (sha256).
 TRAFFIC = {
-    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "1cfaeb6f4b01d6372d0e537bad1a345ce01c940a7986e8016d5827eba28bdfac",
-                     "bytes_per_dispatch": 38.49e6 + 21.00e6,
+    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "78be112d052361ce7aa55782ba5db0cf803258bd8bb2aea001f3e2484557c288",
+                     "bytes_per_dispatch": 38.48e6 + 21.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
 }
 
@@ -416,9 +416,10 @@ def main():
                     help="run two 256 MiB device-to-device copies first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--workload", default="surface50k",
-                    choices=["surface50k", "batch256", "warm2000", "table4"],
-                    help="batch256 / warm2000 / table4: that leg alone, one JSON line of "
-                         "its own")
+                    choices=["surface50k", "batch256", "warm2000", "table4", "converge07"],
+                    help="batch256 / warm2000 / table4 / converge07 (surface50k at the "
+                         "paper's w = 0.7, eigen-prep and one run to tolerance): that leg "
+                         "alone, one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -463,6 +464,30 @@ def main():
                           "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 net, f32 EM",
                           "data": "synthetic", "config": {"workload": b["workload"]},
                           "warm_start": b}), flush=True)
+        return
+
+    if args.workload == "converge07":
+        pair = synth.workload("surface50k")
+        X = torch.as_tensor(pair.X, dtype=torch.float32).cuda().contiguous()
+        Y = torch.as_tensor(pair.Y, dtype=torch.float32).cuda().contiguous()
+        reg = fc.Registration(X, Y, precision=args.precision, beta=pair.beta, lam=pair.lam,
+                              w=0.7, eig_mode="topk", K=300, oversample=20, power_iters=2,
+                              seed=0, tol=1e-8, max_iter=1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reg.prepare()
+        torch.cuda.synchronize()
+        t_eig = time.perf_counter() - t0
+        c = converge_run(reg, pair, t_eig)
+        log(f"converge07: {c}")
+        print(json.dumps({"metric": "time-to-converge (s), surface50k at w = 0.7",
+                          "value": c["time_to_converge_s"], "unit": "s",
+                          "n_gpus": 1, "higher_is_better": False,
+                          "dtype": "bf16x-f32" if args.precision == "bf16x" else "f32",
+                          "data": "synthetic",
+                          "config": {"workload": "surface50k, w=0.7, Fast CPD top-K=300 "
+                                                 "(p=20, q=2), tol 1e-8"},
+                          "converge": c}), flush=True)
         return
 
     if args.copy_calibration:
