@@ -105,7 +105,7 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   add(L, L.llpart, ((N + 255) / 256) * sizeof(double));
   add(L, L.sigpart, 2 * (size_t)sigma2_blocks<T>(p.M) * sizeof(double));
   add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
-  // Single handles keep their points in Morton order (batch members do not).
+  // Single handles keep their points in Hilbert order (batch members do not).
   L.sorted = batch_chunk == 0 && !(p.flags & CPD_FLAG_NO_SORT);
   L.cull = L.sorted && !(p.flags & CPD_FLAG_NO_CULL);
   if (L.sorted) {
@@ -498,7 +498,7 @@ cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
                  h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D, h->p.sigma2_init,
                  h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st);
   if (L.sorted) {
-    // Morton order of X and Y (xs serves as the staging buffer: it holds
+    // Hilbert order of X and Y (xs serves as the staging buffer: it holds
     // max(M, N) rounded up to 256 points and is cleared below); Xt = X.
     P4<T>* stage = h->at<P4<T>>(L.xs.bytes >= L.ys.bytes ? L.xs : L.ys);
     spatial_order_launch<T>(h->at<P4<T>>(L.X), h->p.M, h->at<P4<T>>(L.Y), h->p.N,

@@ -139,8 +139,8 @@ void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam
                        int M, int K, hipStream_t st, const int* perm = nullptr);
 
 // ---------------------------------------------------------- spatial order
-// Sorts the model and scene points (P4, in place) along a Morton (Z-order)
-// curve over their joint bounding box, so 64-point tiles are spatially
+// Sorts the model and scene points (P4, in place) along a Hilbert curve over
+// their joint bounding box, so 64-point tiles are spatially
 // compact for far-tile culling.  permX[i] / permY[i] = the caller's row of
 // internal row i.  Scratch: keys (next power of two >= max(M, N) uint64),
 // bbox (order_bbox_doubles(M + N) doubles), tmp (max(M, N) P4).  invY is
