@@ -45,17 +45,13 @@ __device__ __forceinline__ void split3(float u, __bf16& a, __bf16& b, __bf16& c)
   c = (__bf16)r2;
 }
 
-// Model features from the prescaled model xs (P4, M valid of Mpad).
-__global__ __launch_bounds__(256) void k_feat_model(const P4<float>* __restrict__ xs, int M,
-                                                    int Mpad, __bf16* __restrict__ F,
-                                                    const DevScalars* __restrict__ sc, int gate) {
-  if (gate && sc->done) return;
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= Mpad) return;
+// Feature vector of one prescaled model point (valid = false: a padding row,
+// whose norm slot carries kPadOffset).
+__device__ __forceinline__ void model_feat(const P4<float>& p, bool valid,
+                                           __bf16* __restrict__ dst) {
   __bf16 f[32];
   for (int k = 0; k < 32; ++k) f[k] = (__bf16)0.0f;
-  if (m < M) {
-    const P4<float> p = xs[m];
+  if (valid) {
     const float c[3] = {p.x, p.y, p.z};
     for (int d = 0; d < 3; ++d) {
       __bf16 a, b, e;
@@ -73,7 +69,7 @@ __global__ __launch_bounds__(256) void k_feat_model(const P4<float>* __restrict_
     f[18] = (__bf16)kPadOffset;
   }
   f[21] = f[22] = f[23] = (__bf16)1.0f;
-  bf16x8* out = reinterpret_cast<bf16x8*>(F + (size_t)m * 32);
+  bf16x8* out = reinterpret_cast<bf16x8*>(dst);
   for (int q = 0; q < 4; ++q) {
     bf16x8 v;
     for (int t = 0; t < 8; ++t) v[t] = f[8 * q + t];
@@ -81,19 +77,13 @@ __global__ __launch_bounds__(256) void k_feat_model(const P4<float>* __restrict_
   }
 }
 
-// Scene features; extra = the pass-A reference (use_L = 0) or L_n = ys[n].w.
-__global__ __launch_bounds__(256) void k_feat_scene(const P4<float>* __restrict__ ys, int N,
-                                                    int Npad, int use_L, double w, int M, int D,
-                                                    __bf16* __restrict__ G,
-                                                    const DevScalars* __restrict__ sc, int gate) {
-  if (gate && sc->done) return;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= Npad) return;
+// Feature vector of one prescaled scene point with its offset `extra`.
+__device__ __forceinline__ void scene_feat(const P4<float>& p, bool valid, float extra,
+                                           __bf16* __restrict__ dst) {
   __bf16 g[32];
   for (int k = 0; k < 32; ++k) g[k] = (__bf16)0.0f;
   g[18] = g[19] = g[20] = (__bf16)1.0f;
-  if (n < N) {
-    const P4<float> p = ys[n];
+  if (valid) {
     const float c[3] = {p.x, p.y, p.z};
     for (int d = 0; d < 3; ++d) {
       __bf16 a, b, e;
@@ -107,24 +97,96 @@ __global__ __launch_bounds__(256) void k_feat_scene(const P4<float>* __restrict_
       g[6 * d + 4] = b2;
       g[6 * d + 5] = a2;
     }
-    float extra;
-    if (use_L) {
-      extra = p.w;
-    } else {
-      const double l2c = log2_c(sc->sigma2, D, w, M, N);
-      extra = (float)fmax(l2c, kRefFloor);
-    }
     const float m = p.x * p.x + p.y * p.y + p.z * p.z + extra;
     split3(m, g[21], g[22], g[23]);
   } else {
     g[21] = (__bf16)kPadOffset;
   }
-  bf16x8* out = reinterpret_cast<bf16x8*>(G + (size_t)n * 32);
+  bf16x8* out = reinterpret_cast<bf16x8*>(dst);
   for (int q = 0; q < 4; ++q) {
     bf16x8 v;
     for (int t = 0; t < 8; ++t) v[t] = g[8 * q + t];
     out[q] = v;
   }
+}
+
+// The iteration's first kernel in this mode: prescale (xs, ys), the 64-point
+// tile boxes when culling is on (as k_prescale_box), the model features and
+// the scene features with the pass-A reference.  Threads [0, M64) cover the
+// model rows (M64 = M rounded up to 64), the rest the scene rows up to Npad,
+// so every wave sits inside one tile.
+__global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restrict__ Xt,
+                                                      const P4<float>* __restrict__ Y,
+                                                      P4<float>* __restrict__ xs,
+                                                      P4<float>* __restrict__ ys, int M, int N,
+                                                      int Mpad, int Npad, DevScalars* sc,
+                                                      int gate, P4<float>* __restrict__ boxX,
+                                                      P4<float>* __restrict__ boxY,
+                                                      __bf16* __restrict__ F,
+                                                      __bf16* __restrict__ G, double w, int D) {
+  if (gate && sc->done) return;
+  const float s = (float)sqrt(kappa_of(sc->sigma2));
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    sc->bad_cols = 0;
+    sc->bad_rows = 0;
+  }
+  const int M64 = (M + 63) & ~63;
+  const bool isX = i < M64;
+  const int k = isX ? i : i - M64;
+  const bool valid = k < (isX ? M : N);
+  P4<float> q{0.f, 0.f, 0.f, 0.f};
+  if (valid) {
+    const P4<float> p = isX ? Xt[k] : Y[k];
+    q = P4<float>{p.x * s, p.y * s, p.z * s, 0.f};
+    if (isX)
+      xs[k] = q;
+    else
+      ys[k] = q;
+  }
+  if (isX && k < Mpad) model_feat(q, valid, F + (size_t)k * 32);
+  if (!isX && k < Npad) {
+    const float ref = (float)fmax(log2_c(sc->sigma2, D, w, M, N), kRefFloor);
+    scene_feat(q, valid, ref, G + (size_t)k * 32);
+  }
+  if (boxX) {
+    const float inf = __builtin_inff();
+    float lx = inf, ly = inf, lz = inf, hx = -inf, hy = -inf, hz = -inf, n2 = 0.f;
+    if (valid) {
+      lx = hx = q.x;
+      ly = hy = q.y;
+      lz = hz = q.z;
+      n2 = q.x * q.x + q.y * q.y + q.z * q.z;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lx = fminf(lx, __shfl_xor(lx, o, 64));
+      ly = fminf(ly, __shfl_xor(ly, o, 64));
+      lz = fminf(lz, __shfl_xor(lz, o, 64));
+      hx = fmaxf(hx, __shfl_xor(hx, o, 64));
+      hy = fmaxf(hy, __shfl_xor(hy, o, 64));
+      hz = fmaxf(hz, __shfl_xor(hz, o, 64));
+      n2 = fmaxf(n2, __shfl_xor(n2, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && valid) {
+      P4<float>* box = isX ? boxX : boxY;
+      const int t = k >> 6;
+      box[2 * t] = P4<float>{lx, ly, lz, 0.f};
+      box[2 * t + 1] = P4<float>{hx, hy, hz, n2};
+    }
+  }
+}
+
+// Scene features with L_n = ys[n].w (pass B).
+__global__ __launch_bounds__(256) void k_feat_scene_L(const P4<float>* __restrict__ ys, int N,
+                                                      int Npad, __bf16* __restrict__ G,
+                                                      const DevScalars* __restrict__ sc,
+                                                      int gate) {
+  if (gate && sc->done) return;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= Npad) return;
+  const P4<float> p = n < N ? ys[n] : P4<float>{0.f, 0.f, 0.f, 0.f};
+  scene_feat(p, n < N, p.w, G + (size_t)n * 32);
 }
 
 __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int point, int lane) {
@@ -147,7 +209,7 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 scene columns
   if (n0 >= N) return;  // padding only: nothing of it is stored
-  // the per-column offset the scene features carry (see k_feat_scene)
+  // the per-column offset the scene features carry (see k_bfx_prescale)
   const float ref = (float)fmax(log2_c(sc->sigma2, 3, w, M, N), kRefFloor);
   bf16x8 b[4];
 #pragma unroll
@@ -344,18 +406,17 @@ void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chun
 void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
   const int Mpad = (a.M + 15) & ~15, Npad = (a.N + 15) & ~15;
   const int gate = a.gate;
-  prescale_launch<float>(a, st);
-  hipLaunchKernelGGL(k_feat_model, dim3((Mpad + 255) / 256), dim3(256), 0, st, a.xs, a.M, Mpad,
-                     a.featX, a.sc, gate);
-  hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 0,
-                     a.w, a.M, a.D, a.featY, a.sc, gate);
+  const int nthr = ((a.M + 63) & ~63) + Npad;
+  hipLaunchKernelGGL(k_bfx_prescale, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
+                     a.ys, a.M, a.N, Mpad, Npad, a.sc, gate, a.boxX, a.boxY, a.featX, a.featY,
+                     a.w, a.D);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
                      a.featY, Mpad, a.N, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
   colmerge_fix_launch<float>(a, st);
-  hipLaunchKernelGGL(k_feat_scene, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad, 1,
-                     a.w, a.M, a.D, a.featY, a.sc, gate);
+  hipLaunchKernelGGL(k_feat_scene_L, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad,
+                     a.featY, a.sc, gate);
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
                      a.featY, a.ys, a.M, Npad, a.sc, a.partB, a.boxX, a.boxY, gate);

@@ -705,7 +705,6 @@ void batch_estep_launch(const InstDesc* d, const BatchItems& it, hipStream_t st)
 
 template void estep_launch<float>(const EStepArgs<float>&, hipStream_t);
 template void estep_launch<double>(const EStepArgs<double>&, hipStream_t);
-template void prescale_launch<float>(const EStepArgs<float>&, hipStream_t);
 template void colmerge_fix_launch<float>(const EStepArgs<float>&, hipStream_t);
 template void rowmerge_fix_launch<float>(const EStepArgs<float>&, hipStream_t, int);
 template void estep_splits<float>(int, int, int*, int*, int*, int*);

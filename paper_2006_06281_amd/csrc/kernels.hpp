@@ -63,7 +63,6 @@ __device__ __forceinline__ bool cull_worthwhile(const DevScalars* sc, double ref
 }
 template <typename T> void estep_launch(const EStepArgs<T>& a, hipStream_t st);
 // pieces shared with the BF16X E-step
-template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st);
 template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st);
 template <typename T> void rowmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st, int relative);
 void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
