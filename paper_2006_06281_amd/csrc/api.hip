@@ -120,8 +120,9 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     add(L, L.Xraw, M * p4);
   }
   if (L.cull) {
-    add(L, L.boxX, 2 * ((M + 63) / 64) * p4);
-    add(L, L.boxY, 2 * ((N + 63) / 64) * p4);
+    // boxes of 64-point tiles (FP32 / FP64 E-step) or 16-point tiles (BF16X)
+    add(L, L.boxX, 2 * ((M + 15) / 16) * p4);
+    add(L, L.boxY, 2 * ((N + 15) / 16) * p4);
   }
   L.Kcap = kcap_of(p);
   if (p.method != CPD_METHOD_ORIGINAL) {  // FAST and CPD-L keep eigenpairs
@@ -282,6 +283,7 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.featY = h->at<__bf16>(L.featY);
   a.boxX = L.cull ? h->at<P4<T>>(L.boxX) : nullptr;
   a.boxY = L.cull ? h->at<P4<T>>(L.boxY) : nullptr;
+  a.box_shift = h->p.precision == CPD_PREC_BF16X ? 4 : 6;
   if (h->p.precision == CPD_PREC_BF16X)
     estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
   else

@@ -110,8 +110,8 @@ __device__ __forceinline__ void scene_feat(const P4<float>& p, bool valid, float
   }
 }
 
-// The iteration's first kernel in this mode: prescale (xs, ys), the 64-point
-// tile boxes when culling is on (as k_prescale_box), the model features and
+// The iteration's first kernel in this mode: prescale (xs, ys), the boxes of
+// 16-point tiles when culling is on, the model features and
 // the scene features with the pass-A reference.  Threads [0, M64) cover the
 // model rows (M64 = M rounded up to 64), the rest the scene rows up to Npad,
 // so every wave sits inside one tile.
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
     const float ref = (float)fmax(log2_c(sc->sigma2, D, w, M, N), kRefFloor);
     scene_feat(q, valid, ref, G + (size_t)k * 32);
   }
-  if (boxX) {
+  if (boxX) {  // boxes of 16-point tiles
     const float inf = __builtin_inff();
     float lx = inf, ly = inf, lz = inf, hx = -inf, hy = -inf, hz = -inf, n2 = 0.f;
     if (valid) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
       n2 = q.x * q.x + q.y * q.y + q.z * q.z;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = 8; o > 0; o >>= 1) {
       lx = fminf(lx, __shfl_xor(lx, o, 64));
       ly = fminf(ly, __shfl_xor(ly, o, 64));
       lz = fminf(lz, __shfl_xor(lz, o, 64));
@@ -168,9 +168,9 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
       hz = fmaxf(hz, __shfl_xor(hz, o, 64));
       n2 = fmaxf(n2, __shfl_xor(n2, o, 64));
     }
-    if ((threadIdx.x & 63) == 0 && valid) {
+    if ((threadIdx.x & 15) == 0 && valid) {
       P4<float>* box = isX ? boxX : boxY;
-      const int t = k >> 6;
+      const int t = k >> 4;
       box[2 * t] = P4<float>{lx, ly, lz, 0.f};
       box[2 * t + 1] = P4<float>{hx, hy, hz, n2};
     }
@@ -193,11 +193,24 @@ __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int p
   return *reinterpret_cast<const bf16x8*>(feat + (size_t)point * 32 + 8 * (lane >> 4));
 }
 
+// Box of a wave's 64 points: the union of its valid 16-point tile boxes
+// (first tile t0, `valid` of them), hi.w the largest squared norm.
+__device__ __forceinline__ void wave_box(const P4<float>* __restrict__ box, int t0, int valid,
+                                         P4<float>& lo, P4<float>& hi) {
+  lo = box[2 * t0];
+  hi = box[2 * t0 + 1];
+  for (int j = 1; j < valid; ++j) {
+    const P4<float> l = box[2 * (t0 + j)], h = box[2 * (t0 + j) + 1];
+    lo = P4<float>{fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.f};
+    hi = P4<float>{fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), fmaxf(hi.w, h.w)};
+  }
+}
+
 // Pass A partials: part[split][n] = sum over the split's model points (with
-// culling every S-th 64-point tile, else a contiguous range) of
+// culling every S-th 16-point tile, else a contiguous range) of
 // 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
-// wave skips every 64-point model tile whose smallest exponent against its
-// scene tile reaches CullLimit (all its terms are +0).
+// wave skips every 16-point model tile whose smallest exponent against its
+// 64 scene points reaches CullLimit (all its terms are +0).
 __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G, int Mpad, int N,
                                                     const DevScalars* __restrict__ sc,
@@ -214,10 +227,10 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(G, n0 + 16 * s + (lane & 15), lane);
-  // with culling, this split's model tiles are every S-th 64-row tile from
+  // with culling, this split's model tiles are every S-th 16-row tile from
   // tile blockIdx.y (S = gridDim.y splits): the tiles near any scene column,
   // consecutive in the spatial order, then spread evenly over the splits
-  const int S = gridDim.y, tiles = (Mpad + 63) >> 6;
+  const int S = gridDim.y, tiles = Mpad >> 4;
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   // the split layout follows the sigma^2 gate alone, so a handle without
@@ -225,10 +238,7 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   const bool spread = cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
   const bool cull = boxX != nullptr && spread;
   P4<float> blo{}, bhi{};
-  if (cull) {
-    blo = boxY[2 * (n0 >> 6)];
-    bhi = boxY[2 * (n0 >> 6) + 1];
-  }
+  if (cull) wave_box(boxY, n0 >> 4, min(4, (N - n0 + 15) >> 4), blo, bhi);
   const float lim = CullLimit<float>::value - ref;
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
@@ -250,16 +260,13 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
       keep = __ballot(kp);
     }
     while (keep) {
-      const int mt64 = 64 * (t0 + ts * __builtin_ctzll(keep));
+      const int mt = 16 * (t0 + ts * __builtin_ctzll(keep));
       keep &= keep - 1;
-      const int me = min(Mpad, mt64 + 64);
-      for (int mt = mt64; mt < me; mt += 16) {
-        const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+      const bf16x8 a = load_op(F, mt + (lane & 15), lane);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-          acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
-        }
+      for (int s = 0; s < 4; ++s) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+        acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
       }
     }
   }
@@ -278,7 +285,7 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
 }
 
 // Pass B partials: part[split][5][M] = sum over the split's scene points
-// (with culling every S-th 64-point tile, else a contiguous range) of p, p*v
+// (with culling every S-th 16-point tile, else a contiguous range) of p, p*v
 // (prescaled, absolute), p*|u - v|^2 with p = 2^-(|u - v|^2 + L_n).
 __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G,
@@ -294,25 +301,22 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
-  // with culling, this split's scene tiles are every S-th 64-row tile from
+  // with culling, this split's scene tiles are every S-th 16-row tile from
   // tile blockIdx.y (S = gridDim.y splits): the tiles near any model point,
   // consecutive in the spatial order, then spread evenly over the splits
-  const int S = gridDim.y, tiles = (Npad + 63) >> 6;
+  const int S = gridDim.y, tiles = Npad >> 4;
   float r[4], px[4], py[4], pz[4], t[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
-  // with boxes: skip 64-point scene tiles whose smallest exponent
-  // |u - v|^2 + min L_n against this wave's model tile reaches CullLimit
+  // with boxes: skip 16-point scene tiles whose smallest exponent
+  // |u - v|^2 + min L_n against this wave's model points reaches CullLimit
   // (the split layout follows the sigma^2 gate alone: see pass A)
   const bool spread = cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
   const bool cull = boxX != nullptr && spread;
   P4<float> alo{}, ahi{};
-  if (cull) {
-    alo = boxX[2 * (m0 >> 6)];
-    ahi = boxX[2 * (m0 >> 6) + 1];
-  }
+  if (cull) wave_box(boxX, m0 >> 4, min(4, (M - m0 + 15) >> 4), alo, ahi);
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
   // (while culling cannot pay every tile is evaluated and consecutive tiles
@@ -334,27 +338,24 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
       keep = __ballot(kp);
     }
     while (keep) {
-      const int n64 = 64 * (t0 + ts * __builtin_ctzll(keep));
+      const int nt = 16 * (t0 + ts * __builtin_ctzll(keep));
       keep &= keep - 1;
-      const int te = min(Npad, n64 + 64);
-      for (int nt = n64; nt < te; nt += 16) {
-        const bf16x8 a = load_op(G, nt + (lane & 15), lane);
-        P4<float> yv[4];
+      const bf16x8 a = load_op(G, nt + (lane & 15), lane);
+      P4<float> yv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
+      for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float p = fexp2(-d[q]);
-            const float d2 = d[q] - yv[q].w;
-            r[s] += p;
-            px[s] = fmaf(p, yv[q].x, px[s]);
-            py[s] = fmaf(p, yv[q].y, py[s]);
-            pz[s] = fmaf(p, yv[q].z, pz[s]);
-            t[s] = fmaf(p, d2, t[s]);
-          }
+        for (int q = 0; q < 4; ++q) {
+          const float p = fexp2(-d[q]);
+          const float d2 = d[q] - yv[q].w;
+          r[s] += p;
+          px[s] = fmaf(p, yv[q].x, px[s]);
+          py[s] = fmaf(p, yv[q].y, py[s]);
+          pz[s] = fmaf(p, yv[q].z, pz[s]);
+          t[s] = fmaf(p, d2, t[s]);
         }
       }
     }
@@ -395,7 +396,7 @@ void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chun
     const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
     int c = (lenp + s - 1) / s;
-    c = (c + 63) & ~63;  // whole 64-point tiles per split
+    c = (c + 63) & ~63;
     *chunk = c;
     *splits = (lenp + c - 1) / c;
   };

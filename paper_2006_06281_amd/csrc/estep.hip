@@ -244,7 +244,7 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
-                                                  P4<T>* __restrict__ boxY, int gate, int bx_, int by_, int gx_) {
+                                                  P4<T>* __restrict__ boxY, int box_shift, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
@@ -270,9 +270,9 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
     // its L here misses underflowed terms, or is not finite (then -inf)
     lmin = isfinite(L) ? L : -(T)__builtin_inf();
   }
-  if (boxY) {
-    lmin = wave_min(lmin);
-    if ((threadIdx.x & 63) == 0 && n < N) boxY[2 * (n >> 6)].w = lmin;
+  if (boxY) {  // min over the 2^box_shift columns of the tile (4 or 6)
+    for (int o = 1 << (box_shift - 1); o > 0; o >>= 1) lmin = fmin(lmin, __shfl_xor(lmin, o, kWave));
+    if ((threadIdx.x & ((1 << box_shift) - 1)) == 0 && n < N) boxY[2 * (n >> box_shift)].w = lmin;
   }
   const double b = block_sum_d(ln_d, sh);
   if (threadIdx.x == 0) llpart[bx_] = b;
@@ -284,9 +284,10 @@ __global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, in
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
-                                                  P4<T>* __restrict__ boxY, int gate) {
-  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, boxY, gate,
-                   blockIdx.x, blockIdx.y, gridDim.x);
+                                                  P4<T>* __restrict__ boxY, int box_shift,
+                                                  int gate) {
+  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, boxY, box_shift,
+                   gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Exact pass A for the flagged columns: two sweeps over all model points,
@@ -572,7 +573,7 @@ template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_
   const int gate = a.gate;
   hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA, a.splitsA,
                      a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, a.boxY,
-                     gate);
+                     a.box_shift, gate);
   switch (a.D) {
     case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
     case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ 
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
-                       D.badcols, D.llpart, (P4<float>*)nullptr, 1, it.y, 0, 0);
+                       D.badcols, D.llpart, (P4<float>*)nullptr, 6, 1, it.y, 0, 0);
 }
 __global__ __launch_bounds__(256) void kb_colfix(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {

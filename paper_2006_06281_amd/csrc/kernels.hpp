@@ -26,11 +26,13 @@ template <typename T> struct EStepArgs {
   hipEvent_t* ev;    // nullable: 5 events recorded between the stages
   __bf16* featX;     // BF16X: model feature vectors (32 bf16 per point, padded)
   __bf16* featY;     // BF16X: scene feature vectors
-  // Far-tile culling (nullable: no culling).  Per 64-point tile of the
-  // prescaled points, box[2t] = lower corner, box[2t + 1] = upper corner;
-  // boxY[2t].w receives min L_n over the tile after pass A.
-  P4<T>* boxX;       // ceil(M / 64) tiles
-  P4<T>* boxY;       // ceil(N / 64) tiles
+  // Far-tile culling (nullable: no culling).  Per tile of 2^box_shift
+  // prescaled points (64 in the FP32 / FP64 passes, 16 in BF16X), box[2t] =
+  // lower corner, box[2t + 1] = upper corner; boxY[2t].w receives min L_n
+  // over the tile after pass A.
+  P4<T>* boxX;       // ceil(M / 2^box_shift) tiles
+  P4<T>* boxY;       // ceil(N / 2^box_shift) tiles
+  int box_shift = 6;
 };
 
 // A tile pair whose smallest possible base-2 exponent reaches this value
