@@ -284,6 +284,7 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.boxX = L.cull ? h->at<P4<T>>(L.boxX) : nullptr;
   a.boxY = L.cull ? h->at<P4<T>>(L.boxY) : nullptr;
   a.box_shift = h->p.precision == CPD_PREC_BF16X ? 4 : 6;
+  a.featY_L = h->p.precision == CPD_PREC_BF16X ? a.featY : nullptr;
   if (h->p.precision == CPD_PREC_BF16X)
     estep_bf16x_launch(reinterpret_cast<const EStepArgs<float>&>(a), h->st);
   else

@@ -27,88 +27,13 @@
 // Pass B: a wave keeps four 16-point model tiles (B) and streams scene tiles
 // (A, extra = L_n); per pair: exp, and the sums of p, p*v, p*|u - v|^2.
 // Padded points carry a 3e30 offset so their exponentials are exactly 0.
+#include "bf16x_feat.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace fcpd {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr float kPadOffset = 3.0e30f;
-
-__device__ __forceinline__ void split3(float u, __bf16& a, __bf16& b, __bf16& c) {
-  a = (__bf16)u;
-  const float r1 = u - (float)a;
-  b = (__bf16)r1;
-  const float r2 = r1 - (float)b;
-  c = (__bf16)r2;
-}
-
-// Feature vector of one prescaled model point (valid = false: a padding row,
-// whose norm slot carries kPadOffset).
-__device__ __forceinline__ void model_feat(const P4<float>& p, bool valid,
-                                           __bf16* __restrict__ dst) {
-  __bf16 f[32];
-  for (int k = 0; k < 32; ++k) f[k] = (__bf16)0.0f;
-  if (valid) {
-    const float c[3] = {p.x, p.y, p.z};
-    for (int d = 0; d < 3; ++d) {
-      __bf16 a, b, e;
-      split3(c[d], a, b, e);
-      f[6 * d + 0] = a;
-      f[6 * d + 1] = a;
-      f[6 * d + 2] = b;
-      f[6 * d + 3] = a;
-      f[6 * d + 4] = b;
-      f[6 * d + 5] = e;
-    }
-    const float n = p.x * p.x + p.y * p.y + p.z * p.z;
-    split3(n, f[18], f[19], f[20]);
-  } else {
-    f[18] = (__bf16)kPadOffset;
-  }
-  f[21] = f[22] = f[23] = (__bf16)1.0f;
-  bf16x8* out = reinterpret_cast<bf16x8*>(dst);
-  for (int q = 0; q < 4; ++q) {
-    bf16x8 v;
-    for (int t = 0; t < 8; ++t) v[t] = f[8 * q + t];
-    out[q] = v;
-  }
-}
-
-// Feature vector of one prescaled scene point with its offset `extra`.
-__device__ __forceinline__ void scene_feat(const P4<float>& p, bool valid, float extra,
-                                           __bf16* __restrict__ dst) {
-  __bf16 g[32];
-  for (int k = 0; k < 32; ++k) g[k] = (__bf16)0.0f;
-  g[18] = g[19] = g[20] = (__bf16)1.0f;
-  if (valid) {
-    const float c[3] = {p.x, p.y, p.z};
-    for (int d = 0; d < 3; ++d) {
-      __bf16 a, b, e;
-      split3(c[d], a, b, e);
-      const __bf16 a2 = (__bf16)(-2.0f * (float)a), b2 = (__bf16)(-2.0f * (float)b),
-                   e2 = (__bf16)(-2.0f * (float)e);
-      g[6 * d + 0] = a2;
-      g[6 * d + 1] = b2;
-      g[6 * d + 2] = a2;
-      g[6 * d + 3] = e2;
-      g[6 * d + 4] = b2;
-      g[6 * d + 5] = a2;
-    }
-    const float m = p.x * p.x + p.y * p.y + p.z * p.z + extra;
-    split3(m, g[21], g[22], g[23]);
-  } else {
-    g[21] = (__bf16)kPadOffset;
-  }
-  bf16x8* out = reinterpret_cast<bf16x8*>(dst);
-  for (int q = 0; q < 4; ++q) {
-    bf16x8 v;
-    for (int t = 0; t < 8; ++t) v[t] = g[8 * q + t];
-    out[q] = v;
-  }
-}
 
 // The iteration's first kernel in this mode: prescale (xs, ys), the boxes of
 // 16-point tiles when culling is on, the model features and
@@ -175,18 +100,6 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
       box[2 * t + 1] = P4<float>{hx, hy, hz, n2};
     }
   }
-}
-
-// Scene features with L_n = ys[n].w (pass B).
-__global__ __launch_bounds__(256) void k_feat_scene_L(const P4<float>* __restrict__ ys, int N,
-                                                      int Npad, __bf16* __restrict__ G,
-                                                      const DevScalars* __restrict__ sc,
-                                                      int gate) {
-  if (gate && sc->done) return;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= Npad) return;
-  const P4<float> p = n < N ? ys[n] : P4<float>{0.f, 0.f, 0.f, 0.f};
-  scene_feat(p, n < N, p.w, G + (size_t)n * 32);
 }
 
 __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int point, int lane) {
@@ -415,9 +328,7 @@ void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
   hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
                      a.featY, Mpad, a.N, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
   if (a.ev) (void)hipEventRecord(a.ev[1], st);
-  colmerge_fix_launch<float>(a, st);
-  hipLaunchKernelGGL(k_feat_scene_L, dim3((Npad + 255) / 256), dim3(256), 0, st, a.ys, a.N, Npad,
-                     a.featY, a.sc, gate);
+  colmerge_fix_launch<float>(a, st);  // also refreshes the scene features with L_n
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
                      a.featY, a.ys, a.M, Npad, a.sc, a.partB, a.boxX, a.boxY, gate);

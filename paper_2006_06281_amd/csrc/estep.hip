@@ -24,6 +24,7 @@
 // Both passes split the long reduction axis over blockIdx.y so a launch has
 // thousands of workgroups; partial sums go to a [split][...] buffer and are
 // merged in a fixed order (deterministic, no float atomics).
+#include "bf16x_feat.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -244,7 +245,8 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
                                                   int M, int N, int D, DevScalars* sc, double w,
                                                   int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
-                                                  P4<T>* __restrict__ boxY, int box_shift, int gate, int bx_, int by_, int gx_) {
+                                                  P4<T>* __restrict__ boxY, int box_shift,
+                                                  __bf16* __restrict__ featL, int gate, int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
@@ -265,6 +267,12 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
     }
     ys[n].w = L;
     if (logd_out) logd_out[n] = (T)((double)L * kLn2);
+    if constexpr (sizeof(T) == 4) {  // BF16X: the scene features of pass B
+      if (featL) {
+        const P4<T> y = ys[n];
+        scene_feat(P4<float>{y.x, y.y, y.z, L}, true, L, featL + (size_t)n * 32);
+      }
+    }
     ln_d = (double)L * kLn2;
     // a column the exact path will redo may only lower the tile minimum:
     // its L here misses underflowed terms, or is not finite (then -inf)
@@ -285,9 +293,9 @@ __global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, in
                                                   int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
                                                   P4<T>* __restrict__ boxY, int box_shift,
-                                                  int gate) {
+                                                  __bf16* __restrict__ featL, int gate) {
   colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, boxY, box_shift,
-                   gate, blockIdx.x, blockIdx.y, gridDim.x);
+                   featL, gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Exact pass A for the flagged columns: two sweeps over all model points,
@@ -296,7 +304,8 @@ template <typename T, int D>
 __device__ __forceinline__ void colfix_body(const P4<T>* __restrict__ xs,
                                                 P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                 int M, int N, DevScalars* sc, double w,
-                                                const int* __restrict__ badlist, int gate, int bx_, int by_, int gx_) {
+                                                const int* __restrict__ badlist,
+                                                __bf16* __restrict__ featL, int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const int nbad = sc->bad_cols;
   const int lane = threadIdx.x & 63;
@@ -318,6 +327,10 @@ __device__ __forceinline__ void colfix_body(const P4<T>* __restrict__ xs,
       const double L = mx + log2(s);
       ys[n].w = (T)L;
       if (logd_out) logd_out[n] = (T)(L * kLn2);
+      if constexpr (sizeof(T) == 4) {
+        if (featL) scene_feat(P4<float>{y.x, y.y, y.z, (float)L}, true, (float)L,
+                              featL + (size_t)n * 32);
+      }
     }
   }
 }
@@ -326,8 +339,10 @@ template <typename T, int D>
 __global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
                                                 P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                 int M, int N, DevScalars* sc, double w,
-                                                const int* __restrict__ badlist, int gate) {
-  colfix_body<T, D>(xs, ys, logd_out, M, N, sc, w, badlist, gate, blockIdx.x, blockIdx.y, gridDim.x);
+                                                const int* __restrict__ badlist,
+                                                __bf16* __restrict__ featL, int gate) {
+  colfix_body<T, D>(xs, ys, logd_out, M, N, sc, w, badlist, featL, gate, blockIdx.x, blockIdx.y,
+                    gridDim.x);
 }
 
 // ------------------------------------------------------------------ pass B
@@ -573,11 +588,11 @@ template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_
   const int gate = a.gate;
   hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA, a.splitsA,
                      a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, a.boxY,
-                     a.box_shift, gate);
+                     a.box_shift, a.featY_L, gate);
   switch (a.D) {
-    case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
-    case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
-    default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, gate); break;
+    case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
+    case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
+    default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
   }
 }
 
@@ -663,14 +678,15 @@ __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ 
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
-                       D.badcols, D.llpart, (P4<float>*)nullptr, 6, 1, it.y, 0, 0);
+                       D.badcols, D.llpart, (P4<float>*)nullptr, 6, (__bf16*)nullptr, 1, it.y,
+                       0, 0);
 }
 __global__ __launch_bounds__(256) void kb_colfix(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  colfix_body<float, 3>(D.xs, D.ys, (float*)nullptr, D.M, D.N, D.sc, D.w, D.badcols, 1, it.y, 0,
-                        it.z);
+  colfix_body<float, 3>(D.xs, D.ys, (float*)nullptr, D.M, D.N, D.sc, D.w, D.badcols,
+                        (__bf16*)nullptr, 1, it.y, 0, it.z);
 }
 __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
