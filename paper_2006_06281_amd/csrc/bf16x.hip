@@ -106,16 +106,28 @@ __device__ __forceinline__ bf16x8 load_op(const __bf16* __restrict__ feat, int p
   return *reinterpret_cast<const bf16x8*>(feat + (size_t)point * 32 + 8 * (lane >> 4));
 }
 
-// Box of a wave's 64 points: the union of its valid 16-point tile boxes
-// (first tile t0, `valid` of them), hi.w the largest squared norm.
-__device__ __forceinline__ void wave_box(const P4<float>* __restrict__ box, int t0, int valid,
-                                         P4<float>& lo, P4<float>& hi) {
-  lo = box[2 * t0];
-  hi = box[2 * t0 + 1];
-  for (int j = 1; j < valid; ++j) {
-    const P4<float> l = box[2 * (t0 + j)], h = box[2 * (t0 + j) + 1];
-    lo = P4<float>{fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.f};
-    hi = P4<float>{fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), fmaxf(hi.w, h.w)};
+// A compile-time flag passed to a generic lambda: the culled and the plain
+// tile loops are compiled separately, so the plain one keeps its straight-line
+// schedule.
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
+
+// Boxes of a wave's four 16-point tiles (first tile t0, `valid` of them);
+// the missing ones are empty (every gap to them is infinite).
+__device__ __forceinline__ void wave_boxes(const P4<float>* __restrict__ box, int t0, int valid,
+                                           P4<float> lo[4], P4<float> hi[4]) {
+  const float inf = __builtin_inff();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < valid) {
+      lo[j] = box[2 * (t0 + j)];
+      hi[j] = box[2 * (t0 + j) + 1];
+    } else {
+      lo[j] = P4<float>{inf, inf, inf, 0.f};
+      hi[j] = P4<float>{-inf, -inf, -inf, 0.f};
+    }
   }
 }
 
@@ -124,7 +136,7 @@ __device__ __forceinline__ void wave_box(const P4<float>* __restrict__ box, int 
 // 2^-(|u - v|^2 + ref).  Block: 4 waves x 64 scene points.  With boxes a
 // wave skips every 16-point model tile whose smallest exponent against its
 // 64 scene points reaches CullLimit (all its terms are +0).
-__global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_bfx_colsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G, int Mpad, int N,
                                                     const DevScalars* __restrict__ sc,
                                                     float* __restrict__ part,
@@ -150,8 +162,6 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   // boxes adds the same terms in the same order (culling stays bit-exact)
   const bool spread = cull_worthwhile(sc, (double)ref, (double)CullLimit<float>::value);
   const bool cull = boxX != nullptr && spread;
-  P4<float> blo{}, bhi{};
-  if (cull) wave_box(boxY, n0 >> 4, min(4, (N - n0 + 15) >> 4), blo, bhi);
   const float lim = CullLimit<float>::value - ref;
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
@@ -160,29 +170,47 @@ __global__ __launch_bounds__(256) void k_bfx_colsum(const __bf16* __restrict__ F
   const int per = (tiles + S - 1) / S;
   const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
   const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
-  for (int i0 = 0; i0 < tn; i0 += 64) {
-    const int t0 = tb + ts * i0;
-    const int ntiles = min(64, tn - i0);
-    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
-    if (cull) {
-      bool kp = false;
-      if (lane < ntiles) {
-        const int t = t0 + ts * lane;
-        kp = box_gap2(boxX[2 * t], boxX[2 * t + 1], blo, bhi) < lim;
-      }
-      keep = __ballot(kp);
-    }
-    while (keep) {
-      const int mt = 16 * (t0 + ts * __builtin_ctzll(keep));
-      keep &= keep - 1;
-      const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+  auto tiles_loop = [&](auto masked) {
+    constexpr bool MASK = decltype(masked)::value;
+    for (int i0 = 0; i0 < tn; i0 += 64) {
+      const int t0 = tb + ts * i0;
+      const int ntiles = min(64, tn - i0);
+      uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
+      int cols = 15;  // per tile (lane): the column tiles it is evaluated against
+      if (MASK) {
+        // the wave's four 16-column tiles (reloaded per group, not held in
+        // registers): a model tile is evaluated against each of them only
+        // where it can contribute
+        P4<float> blo[4], bhi[4];
+        wave_boxes(boxY, n0 >> 4, min(4, (N - n0 + 15) >> 4), blo, bhi);
+        cols = 0;
+        if (lane < ntiles) {
+          const int t = t0 + ts * lane;
+          const P4<float> lo = boxX[2 * t], hi = boxX[2 * t + 1];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-        acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+          for (int j = 0; j < 4; ++j) cols |= (box_gap2(lo, hi, blo[j], bhi[j]) < lim) << j;
+        }
+        keep = __ballot(cols != 0);
+      }
+      while (keep) {
+        const int i = __builtin_ctzll(keep);
+        keep &= keep - 1;
+        const int mt = 16 * (t0 + ts * i);
+        const int cm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(cols, i, 64)) : 15;
+        const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if (MASK && !(cm & (1 << s))) continue;  // all its terms are +0
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+          acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+        }
       }
     }
-  }
+  };
+  if (cull)
+    tiles_loop(Flag<true>{});
+  else
+    tiles_loop(Flag<false>{});
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     acc[s] += __shfl_xor(acc[s], 16, 64);
@@ -228,8 +256,6 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   // (the split layout follows the sigma^2 gate alone: see pass A)
   const bool spread = cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
   const bool cull = boxX != nullptr && spread;
-  P4<float> alo{}, ahi{};
-  if (cull) wave_box(boxX, m0 >> 4, min(4, (M - m0 + 15) >> 4), alo, ahi);
   // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
   // tiles to evaluate
   // (while culling cannot pay every tile is evaluated and consecutive tiles
@@ -237,42 +263,59 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   const int per = (tiles + S - 1) / S;
   const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
   const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
-  for (int i0 = 0; i0 < tn; i0 += 64) {
-    const int t0 = tb + ts * i0;
-    const int ntiles = min(64, tn - i0);
-    uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
-    if (cull) {
-      bool kp = false;
-      if (lane < ntiles) {
-        const int k = t0 + ts * lane;
-        const P4<float> lo = boxY[2 * k];  // lo.w = min L_n of the tile
-        kp = box_gap2(alo, ahi, lo, boxY[2 * k + 1]) + lo.w < CullLimit<float>::value;
+  auto tiles_loop = [&](auto masked) {
+    constexpr bool MASK = decltype(masked)::value;
+    for (int i0 = 0; i0 < tn; i0 += 64) {
+      const int t0 = tb + ts * i0;
+      const int ntiles = min(64, tn - i0);
+      uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
+      int rows = 15;  // per tile (lane): the model row tiles it is evaluated against
+      if (MASK) {
+        // the wave's four 16-row model tiles (reloaded per group): a scene
+        // tile is evaluated against each of them only where it can contribute
+        P4<float> alo[4], ahi[4];
+        wave_boxes(boxX, m0 >> 4, min(4, (M - m0 + 15) >> 4), alo, ahi);
+        rows = 0;
+        if (lane < ntiles) {
+          const int k = t0 + ts * lane;
+          const P4<float> lo = boxY[2 * k], hi = boxY[2 * k + 1];  // lo.w = min L_n
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            rows |= (box_gap2(alo[j], ahi[j], lo, hi) + lo.w < CullLimit<float>::value) << j;
+        }
+        keep = __ballot(rows != 0);
       }
-      keep = __ballot(kp);
-    }
-    while (keep) {
-      const int nt = 16 * (t0 + ts * __builtin_ctzll(keep));
-      keep &= keep - 1;
-      const bf16x8 a = load_op(G, nt + (lane & 15), lane);
-      P4<float> yv[4];
+      while (keep) {
+        const int i = __builtin_ctzll(keep);
+        keep &= keep - 1;
+        const int nt = 16 * (t0 + ts * i);
+        const int rm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(rows, i, 64)) : 15;
+        const bf16x8 a = load_op(G, nt + (lane & 15), lane);
+        P4<float> yv[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
+        for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+        for (int s = 0; s < 4; ++s) {
+          if (MASK && !(rm & (1 << s))) continue;  // all its terms are +0
+          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float p = fexp2(-d[q]);
-          const float d2 = d[q] - yv[q].w;
-          r[s] += p;
-          px[s] = fmaf(p, yv[q].x, px[s]);
-          py[s] = fmaf(p, yv[q].y, py[s]);
-          pz[s] = fmaf(p, yv[q].z, pz[s]);
-          t[s] = fmaf(p, d2, t[s]);
+          for (int q = 0; q < 4; ++q) {
+            const float p = fexp2(-d[q]);
+            const float d2 = d[q] - yv[q].w;
+            r[s] += p;
+            px[s] = fmaf(p, yv[q].x, px[s]);
+            py[s] = fmaf(p, yv[q].y, py[s]);
+            pz[s] = fmaf(p, yv[q].z, pz[s]);
+            t[s] = fmaf(p, d2, t[s]);
+          }
         }
       }
     }
-  }
+  };
+  if (cull)
+    tiles_loop(Flag<true>{});
+  else
+    tiles_loop(Flag<false>{});
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
 #pragma unroll
