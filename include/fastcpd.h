@@ -74,11 +74,12 @@ typedef enum {
 } cpd_eig_mode;
 
 /* Bits of cpd_params.flags (0 = defaults).  By default a single handle sorts
-   its point sets along a Morton curve at init (the caller sees every
+   its point sets along a Hilbert curve at init (the caller sees every
    per-point array in its own order; the permutation is internal) and the
-   E-step skips 64-point tile pairs whose exponentials all underflow to +0,
-   which leaves every result bit-identical to the unskipped computation on
-   the same order.  Batched instances never reorder or skip. */
+   E-step skips tile pairs (64-point tiles in FP32 / FP64, 16-point tiles in
+   BF16X) whose exponentials all underflow to +0, which leaves every result
+   bit-identical to the unskipped computation on the same order.  Batched
+   instances never reorder or skip. */
 #define CPD_FLAG_NO_SORT 1       /* keep the caller's order (implies NO_CULL)   */
 #define CPD_FLAG_NO_CULL 2       /* sort, but evaluate every tile               */
 

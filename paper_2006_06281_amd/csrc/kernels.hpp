@@ -142,8 +142,8 @@ void import_eig_launch(const double* Uin, const double* lamin, T* U, double* lam
 
 // ---------------------------------------------------------- spatial order
 // Sorts the model and scene points (P4, in place) along a Hilbert curve over
-// their joint bounding box, so 64-point tiles are spatially
-// compact for far-tile culling.  permX[i] / permY[i] = the caller's row of
+// their joint bounding box, so runs of consecutive points (the culling
+// tiles) are spatially compact.  permX[i] / permY[i] = the caller's row of
 // internal row i.  Scratch: keys (next power of two >= max(M, N) uint64),
 // bbox (order_bbox_doubles(M + N) doubles), tmp (max(M, N) P4).  invY is
 // the inverse of permY (internal row of a caller's scene row).  Xraw

@@ -1,5 +1,6 @@
 // Spatial ordering of the point sets.  The E-step's far-tile culling skips
-// 64-point tiles whose exponentials all underflow; that only pays when the
+// tiles of consecutive points (64 in FP32 / FP64, 16 in BF16X) whose
+// exponentials all underflow; that only pays when the
 // points of a tile are close together, so at init the model and scene points
 // are sorted along a Hilbert curve over their joint bounding box (unlike a
 // Morton curve it has no long jumps between consecutive cells, so a run of
