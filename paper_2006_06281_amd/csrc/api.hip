@@ -36,7 +36,7 @@ struct Region {
 // Byte offsets of every buffer inside the caller's workspace.
 struct Layout {
   size_t total = 0;
-  Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, badcols, badrows, llpart,
+  Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, nnY, nnX, llpart,
       sigpart, initpart, featX, featY;
   Region permX, permY, invY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
   bool sorted = false, cull = false;
@@ -100,8 +100,9 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   add(L, L.tbar, M * sizeof(T));
   add(L, L.partA, (size_t)L.splitsA * N * sizeof(T));
   add(L, L.partB, (size_t)L.splitsB * 5 * M * sizeof(T));
-  add(L, L.badcols, N * sizeof(int));
-  add(L, L.badrows, M * sizeof(int));
+  // nearest-neighbour indices of the two-way matching (per scene / model point)
+  add(L, L.nnY, N * sizeof(int));
+  add(L, L.nnX, M * sizeof(int));
   add(L, L.llpart, ((N + 255) / 256) * sizeof(double));
   add(L, L.sigpart, 2 * (size_t)sigma2_blocks<T>(p.M) * sizeof(double));
   add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
@@ -271,8 +272,6 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.chunkB = L.chunkB;
   a.partA = h->at<T>(L.partA);
   a.partB = h->at<T>(L.partB);
-  a.badcols = h->at<int>(L.badcols);
-  a.badrows = h->at<int>(L.badrows);
   a.llpart = h->at<double>(L.llpart);
   a.logd_out = logd_out;
   a.Yt = h->at<P4<T>>(L.Yt);
@@ -616,7 +615,7 @@ template <typename T>
 cpd_status matches_impl(cpd_ctx* h, int mutual_only, int32_t* out) {
   const Layout& L = h->L;
   matches_launch<T>(h->at<P4<T>>(L.Xt), h->p.M, h->at<P4<T>>(L.Y), h->p.N, mutual_only,
-                    h->permX(), h->permY(), h->at<int>(L.badrows), h->at<int>(L.badcols), out,
+                    h->permX(), h->permY(), h->at<int>(L.nnX), h->at<int>(L.nnY), out,
                     h->st);
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->st));
@@ -903,7 +902,6 @@ size_t batch_item_capacity(int B, const cpd_params* p) {
     n += (M + N + 255) / 256;                        // prescale
     n += tA * sA + tB * sB;                          // colsum, rowsum
     n += (N + 255) / 256 + (M + 255) / 256;          // merges
-    n += 4;                                          // fix-up
     n += (size_t)((M + 127) / 128) * 8;              // tpart (chunks x k groups)
     n += (size_t)eig_topk_max_cols();                // tmerge
     n += (M + 63) / 64 + (M + 255) / 256 + 1;        // apply, sigpart, final
@@ -977,7 +975,7 @@ cpd_status bfail(cpd_batch_ctx* b, cpd_status s, const std::string& m) {
 // Descriptors and work lists for split length `chunk`; uploads both.
 cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
   std::vector<InstDesc> d(b->B);
-  std::vector<int4> pre, cs, cm, fx, rs, rm, tp, tm, ap, sp, in;
+  std::vector<int4> pre, cs, cm, rs, rm, tp, tm, ap, sp, in;
   int maxK = 1;
   for (int i = 0; i < b->B; ++i) maxK = std::max(maxK, b->inst[i]->K);
   const int kt = maxK <= 256 ? 1 : (maxK <= 512 ? 2 : 4);
@@ -997,8 +995,6 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
     D.tbar = h->at<float>(L.tbar);
     D.partA = h->at<float>(L.partA);
     D.partB = h->at<float>(L.partB);
-    D.badcols = h->at<int>(L.badcols);
-    D.badrows = h->at<int>(L.badrows);
     D.llpart = h->at<double>(L.llpart);
     D.sigpart = h->at<double>(L.sigpart);
     D.U = h->at<float>(L.U);
@@ -1023,7 +1019,6 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
     for (int t = 0; t < (D.N + 1023) / 1024; ++t)
       for (int s = 0; s < D.splitsA; ++s) cs.push_back(make_int4(i, t, s, 0));
     for (int x = 0; x < (D.N + 255) / 256; ++x) cm.push_back(make_int4(i, x, 0, 0));
-    for (int x = 0; x < 4; ++x) fx.push_back(make_int4(i, x, 4, 0));
     for (int t = 0; t < (D.M + 1023) / 1024; ++t)
       for (int s = 0; s < D.splitsB; ++s) rs.push_back(make_int4(i, t, s, 0));
     for (int x = 0; x < (D.M + 255) / 256; ++x) rm.push_back(make_int4(i, x, 0, 0));
@@ -1035,15 +1030,15 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
     in.push_back(make_int4(i, 0, 0, 0));
   }
   std::vector<int4> all;
-  std::vector<const std::vector<int4>*> lists = {&pre, &cs, &cm, &fx, &rs, &rm, &tp, &tm, &ap, &sp, &in};
+  std::vector<const std::vector<int4>*> lists = {&pre, &cs, &cm, &rs, &rm, &tp, &tm, &ap, &sp, &in};
   for (auto* l : lists) all.insert(all.end(), l->begin(), l->end());
   if (all.size() > b->hd.item_cap) return bfail(b, CPD_E_WORKSPACE, "batch work list too large");
   int4* dev = reinterpret_cast<int4*>(b->ws + b->hd.items);
   size_t o = 0;
-  const int4** ptrs[] = {&b->items.prescale, &b->items.colsum, &b->items.colmerge, &b->items.fix,
+  const int4** ptrs[] = {&b->items.prescale, &b->items.colsum, &b->items.colmerge,
                          &b->items.rowsum, &b->items.rowmerge, &b->items.tpart, &b->items.tmerge,
                          &b->items.apply, &b->items.sigpart, &b->items.inst};
-  int* counts[] = {&b->items.n_prescale, &b->items.n_colsum, &b->items.n_colmerge, &b->items.n_fix,
+  int* counts[] = {&b->items.n_prescale, &b->items.n_colsum, &b->items.n_colmerge,
                    &b->items.n_rowsum, &b->items.n_rowmerge, &b->items.n_tpart, &b->items.n_tmerge,
                    &b->items.n_apply, &b->items.n_sigpart, &b->items.n_inst};
   for (size_t q = 0; q < lists.size(); ++q) {

@@ -52,10 +52,6 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
   if (gate && sc->done) return;
   const float s = (float)sqrt(kappa_of(sc->sigma2));
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    sc->bad_cols = 0;
-    sc->bad_rows = 0;
-  }
   const int M64 = (M + 63) & ~63;
   const bool isX = i < M64;
   const int k = isX ? i : i - M64;

@@ -24,8 +24,6 @@ struct DevScalars {
   int32_t max_iter;
   int32_t done;         // converged or capped: later steps are no-ops
   int32_t converged;
-  int32_t bad_cols;     // columns that need the exact (rescaled) pass A
-  int32_t bad_rows;     // rows that need the exact (rescaled) pass B
   int32_t nonfinite;    // 1: sigma^2 became NaN/Inf, 2: Cholesky breakdown
   int32_t chol_fail;    // the original method's factorisation broke down
   double diam2;         // squared diagonal of the joint bounding box of X and Y

@@ -13,13 +13,15 @@
 //   sink makes the fixed reference exact: every term is <= 2^(-ref) and a
 //   term that underflows is < 2^-126 * c <= 2^-126 * d_n.  Columns whose sum
 //   still falls below 2^-60 of the reference (only possible with w = 0 or an
-//   extreme c) are recomputed exactly by colfix with their own maximum.
+//   extreme c) are recomputed exactly, with their own maximum, by their
+//   wave inside the column merge.
 // Pass B (rows): p_mn = 2^(-|y^_n - x^_m|^2 - L_n) <= 1; per row m it sums
 //   r_m = sum_n p_mn (P1, eq. 21), sum_n p_mn (y^_n - x^_m) (gives P'Y of
 //   eq. 5 relative to the point itself) and sum_n p_mn |y^_n - x^_m|^2.
 //   Rows whose r_m underflows (a model point far from every scene point) are
-//   recomputed exactly by rowfix, which shifts by the row's own maximum --
-//   the constrained posterior p'_mn = p_mn / r_m is then still defined.
+//   recomputed exactly inside the row merge, shifted by the row's own
+//   maximum -- the constrained posterior p'_mn = p_mn / r_m is then still
+//   defined.
 //
 // Both passes split the long reduction axis over blockIdx.y so a launch has
 // thousands of workgroups; partial sums go to a [split][...] buffer and are
@@ -45,10 +47,6 @@ __device__ __forceinline__ void prescale_body(const P4<T>* __restrict__ Xt,
   if (gate && sc->done) return;
   const T s = (T)sqrt(kappa_of(sc->sigma2));
   const int i = bx_ * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    sc->bad_cols = 0;
-    sc->bad_rows = 0;
-  }
   if (i < M) {
     xs[i] = prescale_point<T>(Xt[i], s);
   } else if (i < M + N) {
@@ -86,10 +84,6 @@ __global__ __launch_bounds__(256) void k_prescale_box(const P4<T>* __restrict__ 
   if (gate && sc->done) return;
   const T s = (T)sqrt(kappa_of(sc->sigma2));
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    sc->bad_cols = 0;
-    sc->bad_rows = 0;
-  }
   const int M64 = (M + 63) & ~63;
   const bool isX = i < M64;
   const int k = isX ? i : i - M64;
@@ -237,16 +231,45 @@ __global__ __launch_bounds__(256) void k_colsum(const P4<T>* __restrict__ xs,
                         blockIdx.y, gridDim.x);
 }
 
-// L_n = ref + log2(sum_splits part + 2^(log2 c - ref)) into ys[n].w; flags
-// columns that need the exact path; per-block partial of sum_n ln d_n.
+// Exact L_n of one scene point y by the whole wave: two sweeps over all
+// model points, the first for the column maximum, the second for the
+// shifted sum.  Every lane returns the same value.
+template <typename T, int D>
+__device__ double exact_col_L(const P4<T>* __restrict__ xs, const P4<T> y, int M, double l2c) {
+  const int lane = threadIdx.x & 63;
+  double mx = l2c;
+  for (int m = lane; m < M; m += 64) mx = fmax(mx, -(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0));
+  mx = wave_max(mx);
+  double s = 0.0;
+  for (int m = lane; m < M; m += 64) s += exp2(-(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0) - mx);
+  s = wave_sum(s) + exp2(l2c - mx);
+  return mx + log2(s);
+}
+
+template <typename T>
+__device__ double exact_col_L(const P4<T>* __restrict__ xs, const P4<T> y, int M, double l2c,
+                              int D) {
+  switch (D) {
+    case 1: return exact_col_L<T, 1>(xs, y, M, l2c);
+    case 2: return exact_col_L<T, 2>(xs, y, M, l2c);
+    default: return exact_col_L<T, 3>(xs, y, M, l2c);
+  }
+}
+
+// L_n = ref + log2(sum_splits part + 2^(log2 c - ref)) into ys[n].w, and a
+// per-block partial of sum_n ln d_n.  A column whose sum falls below 2^-60
+// of the reference takes the exact path: its wave computes it here, all
+// lanes together, one such column after another (rare: w = 0 or an
+// extreme c; it costs nothing when no column needs it).
 template <typename T>
 __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int splits,
                                                   P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                   int M, int N, int D, DevScalars* sc, double w,
-                                                  int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
                                                   P4<T>* __restrict__ boxY, int box_shift,
-                                                  __bf16* __restrict__ featL, int gate, int bx_, int by_, int gx_) {
+                                                  __bf16* __restrict__ featL,
+                                                  const P4<T>* __restrict__ xs, int gate,
+                                                  int bx_, int by_, int gx_) {
   __shared__ double sh[16];
   if (gate && sc->done) return;
   const double l2c = log2_c(sc->sigma2, D, w, M, N);
@@ -255,16 +278,24 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
   const int n = bx_ * blockDim.x + threadIdx.x;
   double ln_d = 0.0;
   T lmin = (T)__builtin_inf();
+  T L = (T)0;
+  bool bad = false;
   if (n < N) {
     T s = (T)0;
     for (int k = 0; k < splits; ++k) s += part[(size_t)k * N + n];
     s += (T)exp2(l2c - refd);  // the outlier sink c, relative to ref (0 if w = 0)
-    const T L = ref + flog2(s);
-    const bool bad = !(s >= (T)0x1p-60) || !isfinite(L);
-    if (bad) {
-      const int k = atomicAdd(&sc->bad_cols, 1);
-      badlist[k] = n;
+    L = ref + flog2(s);
+    bad = !(s >= (T)0x1p-60) || !isfinite(L);
+  }
+  {
+    const int lane = threadIdx.x & 63;
+    for (uint64_t bm = __ballot(bad); bm; bm &= bm - 1) {
+      const int j = __builtin_ctzll(bm);
+      const double Lx = exact_col_L<T>(xs, ys[n - lane + j], M, l2c, D);
+      if (lane == j) L = (T)Lx;
     }
+  }
+  if (n < N) {
     ys[n].w = L;
     if (logd_out) logd_out[n] = (T)((double)L * kLn2);
     if constexpr (sizeof(T) == 4) {  // BF16X: the scene features of pass B
@@ -274,8 +305,6 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
       }
     }
     ln_d = (double)L * kLn2;
-    // a column the exact path will redo may only lower the tile minimum:
-    // its L here misses underflowed terms, or is not finite (then -inf)
     lmin = isfinite(L) ? L : -(T)__builtin_inf();
   }
   if (boxY) {  // min over the 2^box_shift columns of the tile (4 or 6)
@@ -290,59 +319,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_colmerge(const T* __restrict__ part, int splits,
                                                   P4<T>* __restrict__ ys, T* __restrict__ logd_out,
                                                   int M, int N, int D, DevScalars* sc, double w,
-                                                  int* __restrict__ badlist,
                                                   double* __restrict__ llpart,
                                                   P4<T>* __restrict__ boxY, int box_shift,
-                                                  __bf16* __restrict__ featL, int gate) {
-  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, badlist, llpart, boxY, box_shift,
-                   featL, gate, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-// Exact pass A for the flagged columns: two sweeps over all model points,
-// the first for the column maximum, the second for the shifted sum.
-template <typename T, int D>
-__device__ __forceinline__ void colfix_body(const P4<T>* __restrict__ xs,
-                                                P4<T>* __restrict__ ys, T* __restrict__ logd_out,
-                                                int M, int N, DevScalars* sc, double w,
-                                                const int* __restrict__ badlist,
-                                                __bf16* __restrict__ featL, int gate, int bx_, int by_, int gx_) {
-  if (gate && sc->done) return;
-  const int nbad = sc->bad_cols;
-  const int lane = threadIdx.x & 63;
-  const int wglobal = (bx_ * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gx_ * blockDim.x) >> 6;
-  const double l2c = log2_c(sc->sigma2, D, w, M, N);
-  for (int b = wglobal; b < nbad; b += nwaves) {
-    const int n = badlist[b];
-    const P4<T> y = ys[n];
-    double mx = l2c;
-    for (int m = lane; m < M; m += 64)
-      mx = fmax(mx, -(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0));
-    mx = wave_max(mx);
-    double s = 0.0;
-    for (int m = lane; m < M; m += 64)
-      s += exp2(-(double)sq3<T, D>(xs[m], y.x, y.y, y.z, (T)0) - mx);
-    s = wave_sum(s) + exp2(l2c - mx);
-    if (lane == 0) {
-      const double L = mx + log2(s);
-      ys[n].w = (T)L;
-      if (logd_out) logd_out[n] = (T)(L * kLn2);
-      if constexpr (sizeof(T) == 4) {
-        if (featL) scene_feat(P4<float>{y.x, y.y, y.z, (float)L}, true, (float)L,
-                              featL + (size_t)n * 32);
-      }
-    }
-  }
-}
-
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_colfix(const P4<T>* __restrict__ xs,
-                                                P4<T>* __restrict__ ys, T* __restrict__ logd_out,
-                                                int M, int N, DevScalars* sc, double w,
-                                                const int* __restrict__ badlist,
-                                                __bf16* __restrict__ featL, int gate) {
-  colfix_body<T, D>(xs, ys, logd_out, M, N, sc, w, badlist, featL, gate, blockIdx.x, blockIdx.y,
-                    gridDim.x);
+                                                  __bf16* __restrict__ featL,
+                                                  const P4<T>* __restrict__ xs, int gate) {
+  colmerge_body<T>(part, splits, ys, logd_out, M, N, D, sc, w, llpart, boxY, box_shift, featL, xs,
+                   gate, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // ------------------------------------------------------------------ pass B
@@ -457,33 +439,99 @@ __global__ __launch_bounds__(256) void k_rowsum(const P4<T>* __restrict__ xs,
                         blockIdx.y, gridDim.x);
 }
 
+// Exact pass B of one model row m by the whole wave: shift by the row
+// maximum of -(|y^_n - x^_m|^2 + L_n), then the sums r, p (y^ - x^), p d2.
+// Every lane returns the same values; P1_m = r 2^mx.
+template <typename T, int D>
+__device__ void exact_row(const P4<T>* __restrict__ xs, const P4<T>* __restrict__ ys, int m,
+                          int N, double& r, double& px, double& py, double& pz, double& t,
+                          double& mx) {
+  const int lane = threadIdx.x & 63;
+  const P4<T> a = xs[m];
+  mx = -__builtin_inf();
+  for (int n = lane; n < N; n += 64) {
+    const P4<T> y = ys[n];
+    mx = fmax(mx, -((double)sq3<T, D>(a, y.x, y.y, y.z, (T)0) + (double)y.w));
+  }
+  mx = wave_max(mx);
+  r = px = py = pz = t = 0.0;
+  for (int n = lane; n < N; n += 64) {
+    const P4<T> y = ys[n];
+    const double dx = (double)y.x - a.x;
+    const double dy = D > 1 ? (double)y.y - a.y : 0.0;
+    const double dz = D > 2 ? (double)y.z - a.z : 0.0;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    const double e = exp2(-(d2 + (double)y.w) - mx);
+    r += e;
+    px += e * dx;
+    py += e * dy;
+    pz += e * dz;
+    t += e * d2;
+  }
+  r = wave_sum(r);
+  px = wave_sum(px);
+  py = wave_sum(py);
+  pz = wave_sum(pz);
+  t = wave_sum(t);
+}
+
+// Row m's outputs from the exact (shifted, well-scaled) sums: P1 keeps its
+// true (tiny or zero) value, Yt and tbar come from the shifted sums.
+template <typename T>
+__device__ __forceinline__ void store_exact_row(const P4<T>* __restrict__ Xt,
+                                                P4<T>* __restrict__ Yt, T* __restrict__ P1,
+                                                T* __restrict__ tbar, int m, double kap,
+                                                double r, double px, double py, double pz,
+                                                double t, double mx) {
+  const double isk = 1.0 / sqrt(kap);
+  const P4<T> x = Xt[m];
+  Yt[m] = P4<T>{(T)(x.x + px / r * isk), (T)(x.y + py / r * isk), (T)(x.z + pz / r * isk), (T)0};
+  P1[m] = (T)(r * exp2(mx));
+  tbar[m] = (T)(t / r / kap);
+}
+
 // Row merge: P1_m = r_m, Yt_m = xt_m + (sum p (y - xt)) / r_m, tbar_m.
 // relative = 1: the sums hold p (y^ - x^) (direct-difference pass B);
 // relative = 0: they hold p y^ (absolute, the matrix-core pass B).
+// A row whose r_m underflows takes the exact path: its wave computes it
+// here, one such row after another.
 template <typename T>
 __device__ __forceinline__ void rowmerge_body(const T* __restrict__ part, int splits,
                                                   const P4<T>* __restrict__ Xt,
                                                   P4<T>* __restrict__ Yt, T* __restrict__ P1,
-                                                  T* __restrict__ tbar, int M,
-                                                  DevScalars* sc, int* __restrict__ badlist,
-                                                  int relative, int gate, int bx_, int by_, int gx_) {
+                                                  T* __restrict__ tbar, int M, DevScalars* sc,
+                                                  int relative, const P4<T>* __restrict__ xs,
+                                                  const P4<T>* __restrict__ ys, int N, int D,
+                                                  int gate, int bx_, int by_, int gx_) {
   if (gate && sc->done) return;
   const int m = bx_ * blockDim.x + threadIdx.x;
-  if (m >= M) return;
   const double kap = kappa_of(sc->sigma2);
   T r = 0, px = 0, py = 0, pz = 0, t = 0;
-  for (int k = 0; k < splits; ++k) {
-    const T* b = part + (size_t)k * 5 * M;
-    r += b[m];
-    px += b[(size_t)M + m];
-    py += b[(size_t)2 * M + m];
-    pz += b[(size_t)3 * M + m];
-    t += b[(size_t)4 * M + m];
+  if (m < M) {
+    for (int k = 0; k < splits; ++k) {
+      const T* b = part + (size_t)k * 5 * M;
+      r += b[m];
+      px += b[(size_t)M + m];
+      py += b[(size_t)2 * M + m];
+      pz += b[(size_t)3 * M + m];
+      t += b[(size_t)4 * M + m];
+    }
   }
-  const bool tiny = !(r >= (T)(sizeof(T) == 4 ? 0x1p-60 : 0x1p-900));
-  if (tiny) {
-    const int k = atomicAdd(&sc->bad_rows, 1);
-    badlist[k] = m;
+  const bool tiny = m < M && !(r >= (T)(sizeof(T) == 4 ? 0x1p-60 : 0x1p-900));
+  {
+    const int lane = threadIdx.x & 63;
+    for (uint64_t bm = __ballot(tiny); bm; bm &= bm - 1) {
+      const int j = __builtin_ctzll(bm);
+      const int mj = m - lane + j;
+      double er, ex, ey, ez, et, mx;
+      switch (D) {
+        case 1: exact_row<T, 1>(xs, ys, mj, N, er, ex, ey, ez, et, mx); break;
+        case 2: exact_row<T, 2>(xs, ys, mj, N, er, ex, ey, ez, et, mx); break;
+        default: exact_row<T, 3>(xs, ys, mj, N, er, ex, ey, ez, et, mx); break;
+      }
+      if (lane == j) store_exact_row<T>(Xt, Yt, P1, tbar, mj, kap, er, ex, ey, ez, et, mx);
+    }
+    if (tiny || m >= M) return;
   }
   const T inv = (T)1 / r;
   const T isk = (T)(1.0 / sqrt(kap));
@@ -498,77 +546,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_rowmerge(const T* __restrict__ part, int splits,
                                                   const P4<T>* __restrict__ Xt,
                                                   P4<T>* __restrict__ Yt, T* __restrict__ P1,
-                                                  T* __restrict__ tbar, int M,
-                                                  DevScalars* sc, int* __restrict__ badlist,
-                                                  int relative, int gate) {
-  rowmerge_body<T>(part, splits, Xt, Yt, P1, tbar, M, sc, badlist, relative, gate, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-// Exact pass B for flagged rows: shift by the row maximum of
-// -(|y^_n - x^_m|^2 + L_n), then the same sums.  P1 keeps its true (tiny or
-// zero) value; Yt and tbar come from the shifted, well-scaled sums.
-template <typename T, int D>
-__device__ __forceinline__ void rowfix_body(const P4<T>* __restrict__ xs,
-                                                const P4<T>* __restrict__ ys,
-                                                const P4<T>* __restrict__ Xt,
-                                                P4<T>* __restrict__ Yt, T* __restrict__ P1,
-                                                T* __restrict__ tbar, int M, int N,
-                                                DevScalars* sc, const int* __restrict__ badlist,
-                                                int gate, int bx_, int by_, int gx_) {
-  if (gate && sc->done) return;
-  const int nbad = sc->bad_rows;
-  const int lane = threadIdx.x & 63;
-  const int wglobal = (bx_ * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gx_ * blockDim.x) >> 6;
-  const double kap = kappa_of(sc->sigma2);
-  for (int b = wglobal; b < nbad; b += nwaves) {
-    const int m = badlist[b];
-    const P4<T> a = xs[m];
-    double mx = -__builtin_inf();
-    for (int n = lane; n < N; n += 64) {
-      const P4<T> y = ys[n];
-      mx = fmax(mx, -((double)sq3<T, D>(a, y.x, y.y, y.z, (T)0) + (double)y.w));
-    }
-    mx = wave_max(mx);
-    double r = 0, px = 0, py = 0, pz = 0, t = 0;
-    for (int n = lane; n < N; n += 64) {
-      const P4<T> y = ys[n];
-      const double dx = (double)y.x - a.x;
-      const double dy = D > 1 ? (double)y.y - a.y : 0.0;
-      const double dz = D > 2 ? (double)y.z - a.z : 0.0;
-      const double d2 = dx * dx + dy * dy + dz * dz;
-      const double e = exp2(-(d2 + (double)y.w) - mx);
-      r += e;
-      px += e * dx;
-      py += e * dy;
-      pz += e * dz;
-      t += e * d2;
-    }
-    r = wave_sum(r);
-    px = wave_sum(px);
-    py = wave_sum(py);
-    pz = wave_sum(pz);
-    t = wave_sum(t);
-    if (lane == 0) {
-      const double isk = 1.0 / sqrt(kap);
-      const P4<T> x = Xt[m];
-      Yt[m] = P4<T>{(T)(x.x + px / r * isk), (T)(x.y + py / r * isk),
-                    (T)(x.z + pz / r * isk), (T)0};
-      P1[m] = (T)(r * exp2(mx));
-      tbar[m] = (T)(t / r / kap);
-    }
-  }
-}
-
-template <typename T, int D>
-__global__ __launch_bounds__(256) void k_rowfix(const P4<T>* __restrict__ xs,
-                                                const P4<T>* __restrict__ ys,
-                                                const P4<T>* __restrict__ Xt,
-                                                P4<T>* __restrict__ Yt, T* __restrict__ P1,
-                                                T* __restrict__ tbar, int M, int N,
-                                                DevScalars* sc, const int* __restrict__ badlist,
-                                                int gate) {
-  rowfix_body<T, D>(xs, ys, Xt, Yt, P1, tbar, M, N, sc, badlist, gate, blockIdx.x, blockIdx.y, gridDim.x);
+                                                  T* __restrict__ tbar, int M, DevScalars* sc,
+                                                  int relative, const P4<T>* __restrict__ xs,
+                                                  const P4<T>* __restrict__ ys, int N, int D,
+                                                  int gate) {
+  rowmerge_body<T>(part, splits, Xt, Yt, P1, tbar, M, sc, relative, xs, ys, N, D, gate, blockIdx.x,
+                   blockIdx.y, gridDim.x);
 }
 
 // ------------------------------------------------------------- launchers
@@ -586,26 +569,19 @@ template <typename T> void prescale_launch(const EStepArgs<T>& a, hipStream_t st
 
 template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st) {
   const int gate = a.gate;
+  // the exact path for underflowed columns runs inside the merge
   hipLaunchKernelGGL(k_colmerge<T>, dim3((a.N + 255) / 256), dim3(256), 0, st, a.partA, a.splitsA,
-                     a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.badcols, a.llpart, a.boxY,
-                     a.box_shift, a.featY_L, gate);
-  switch (a.D) {
-    case 1: hipLaunchKernelGGL((k_colfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
-    case 2: hipLaunchKernelGGL((k_colfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
-    default: hipLaunchKernelGGL((k_colfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.logd_out, a.M, a.N, a.sc, a.w, a.badcols, a.featY_L, gate); break;
-  }
+                     a.ys, a.logd_out, a.M, a.N, a.D, a.sc, a.w, a.llpart, a.boxY, a.box_shift,
+                     a.featY_L, (const P4<T>*)a.xs, gate);
 }
 
 template <typename T>
 void rowmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st, int relative) {
   const int gate = a.gate;
+  // the exact path for underflowed rows runs inside the merge
   hipLaunchKernelGGL(k_rowmerge<T>, dim3((a.M + 255) / 256), dim3(256), 0, st, a.partB, a.splitsB,
-                     a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, a.badrows, relative, gate);
-  switch (a.D) {
-    case 1: hipLaunchKernelGGL((k_rowfix<T, 1>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-    case 2: hipLaunchKernelGGL((k_rowfix<T, 2>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-    default: hipLaunchKernelGGL((k_rowfix<T, 3>), dim3(32), dim3(256), 0, st, a.xs, a.ys, a.Xt, a.Yt, a.P1, a.tbar, a.M, a.N, a.sc, a.badrows, gate); break;
-  }
+                     a.Xt, a.Yt, a.P1, a.tbar, a.M, a.sc, relative, (const P4<T>*)a.xs,
+                     (const P4<T>*)a.ys, a.N, a.D, gate);
 }
 
 template <typename T>
@@ -678,15 +654,7 @@ __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ 
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
-                       D.badcols, D.llpart, (P4<float>*)nullptr, 6, (__bf16*)nullptr, 1, it.y,
-                       0, 0);
-}
-__global__ __launch_bounds__(256) void kb_colfix(const InstDesc* __restrict__ d,
-                                                 const int4* __restrict__ items) {
-  const int4 it = items[blockIdx.x];
-  const InstDesc& D = d[it.x];
-  colfix_body<float, 3>(D.xs, D.ys, (float*)nullptr, D.M, D.N, D.sc, D.w, D.badcols,
-                        (__bf16*)nullptr, 1, it.y, 0, it.z);
+                       D.llpart, (P4<float>*)nullptr, 6, (__bf16*)nullptr, D.xs, 1, it.y, 0, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
@@ -699,25 +667,15 @@ __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ 
                                                    const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  rowmerge_body<float>(D.partB, D.splitsB, D.Xt, D.Yt, D.P1, D.tbar, D.M, D.sc, D.badrows, 1, 1,
-                       it.y, 0, 0);
+  rowmerge_body<float>(D.partB, D.splitsB, D.Xt, D.Yt, D.P1, D.tbar, D.M, D.sc, 1, D.xs, D.ys,
+                       D.N, 3, 1, it.y, 0, 0);
 }
-__global__ __launch_bounds__(256) void kb_rowfix(const InstDesc* __restrict__ d,
-                                                 const int4* __restrict__ items) {
-  const int4 it = items[blockIdx.x];
-  const InstDesc& D = d[it.x];
-  rowfix_body<float, 3>(D.xs, D.ys, D.Xt, D.Yt, D.P1, D.tbar, D.M, D.N, D.sc, D.badrows, 1, it.y,
-                        0, it.z);
-}
-
 void batch_estep_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
   hipLaunchKernelGGL(kb_prescale, dim3(it.n_prescale), dim3(256), 0, st, d, it.prescale);
   hipLaunchKernelGGL(kb_colsum, dim3(it.n_colsum), dim3(256), 0, st, d, it.colsum);
   hipLaunchKernelGGL(kb_colmerge, dim3(it.n_colmerge), dim3(256), 0, st, d, it.colmerge);
-  hipLaunchKernelGGL(kb_colfix, dim3(it.n_fix), dim3(256), 0, st, d, it.fix);
   hipLaunchKernelGGL(kb_rowsum, dim3(it.n_rowsum), dim3(256), 0, st, d, it.rowsum);
   hipLaunchKernelGGL(kb_rowmerge, dim3(it.n_rowmerge), dim3(256), 0, st, d, it.rowmerge);
-  hipLaunchKernelGGL(kb_rowfix, dim3(it.n_fix), dim3(256), 0, st, d, it.fix);
 }
 
 template void estep_launch<float>(const EStepArgs<float>&, hipStream_t);

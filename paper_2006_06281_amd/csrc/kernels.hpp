@@ -16,8 +16,6 @@ template <typename T> struct EStepArgs {
   int splitsA, chunkA, splitsB, chunkB;
   T* partA;          // splitsA * N
   T* partB;          // splitsB * 5 * M
-  int* badcols;      // N
-  int* badrows;      // M
   double* llpart;    // ceil(N / 256)
   T* logd_out;       // nullable (N)
   P4<T>* Yt;         // out (M)
@@ -199,8 +197,6 @@ struct InstDesc {
   float* tbar;
   float* partA;
   float* partB;
-  int* badcols;
-  int* badrows;
   double* llpart;
   double* sigpart;
   const float* U;
@@ -218,9 +214,9 @@ struct InstDesc {
 // Work items: (instance, block index x, block index y, unused), one per
 // workgroup of the corresponding stage.
 struct BatchItems {
-  const int4 *prescale, *colsum, *colmerge, *fix, *rowsum, *rowmerge, *tpart, *tmerge, *apply,
+  const int4 *prescale, *colsum, *colmerge, *rowsum, *rowmerge, *tpart, *tmerge, *apply,
       *sigpart, *inst;
-  int n_prescale, n_colsum, n_colmerge, n_fix, n_rowsum, n_rowmerge, n_tpart, n_tmerge, n_apply,
+  int n_prescale, n_colsum, n_colmerge, n_rowsum, n_rowmerge, n_tpart, n_tmerge, n_apply,
       n_sigpart, n_inst;
   int kt;             // eigenpairs per thread in k_tpart (from the largest K)
   int maxK;

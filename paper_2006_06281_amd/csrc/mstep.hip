@@ -584,8 +584,6 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
       sc->tol = tol;
       sc->iter = 0;
       sc->max_iter = max_iter;
-      sc->bad_cols = 0;
-      sc->bad_rows = 0;
       sc->diam2 = 0.0;  // set by the spatial ordering when the handle sorts
       sc->origin[0] = sc->origin[1] = sc->origin[2] = 0.0;
     }

@@ -38,6 +38,32 @@ def test_bf16x_estep(lib, M, N, w, s2):
     np.testing.assert_allclose(host(g["P1"]), es.P1, rtol=1e-2, atol=1e-30)
 
 
+def test_bf16x_far_rows_and_empty_columns_take_the_exact_path(lib):
+    """A model point 300 units from the scene (its row underflows) and, with
+    w = 0, a scene point at 160 sigma from every model point (its column
+    underflows): both take the exact path inside the merges, and the column's
+    refreshed L_n must reach pass B's scene features."""
+    import torch
+    X = np.array([[0.0, 0, 0], [0.05, 0, 0], [300.0, 0, 0], [0, 0.02, 0]])
+    Y = np.array([[0.01, 0, 0], [-0.02, 0, 0], [0, 0.03, 0], [0, -5.0, 0], [2.0, 0, 0]])
+    for w in (0.0, 0.1):
+        say("bf16x far rows", w)
+        r = lib.Registration(dev(X, torch.float32), dev(Y, torch.float32), precision="bf16x",
+                             beta=1.0, lam=2.0, w=w, eig_mode="import", K=1)
+        r.set_state(dev(X, torch.float32), 1e-3)
+        g = r.estep()
+        es = cpd64.estep(X, Y, 1e-3, w)
+        Yt = host(g["Yt"])
+        assert np.all(np.isfinite(Yt))
+        err = cpd64.rel_rms(Yt, es.Yt)
+        say("Yt rel_rms", err)
+        # as in FP32: without the sink the lone column's exponents are ~1.8e4
+        assert err < (TOL if w > 0 else 2e-3)
+        np.testing.assert_allclose(host(g["logd"]), es.logd, rtol=0,
+                                   atol=1e-2 * max(1, np.abs(es.logd).max()))
+        np.testing.assert_allclose(host(g["P1"]), es.P1, rtol=1e-2, atol=1e-30)
+
+
 def test_bf16x_matches_fp32_closely(lib):
     """The split-bf16 cross term carries 24 significant bits: at moderate
     sigma^2 the BF16X E-step agrees with the fp32 direct-difference one far
