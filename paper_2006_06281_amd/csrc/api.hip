@@ -104,7 +104,8 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   add(L, L.nnY, N * sizeof(int));
   add(L, L.nnX, M * sizeof(int));
   add(L, L.llpart, ((N + 255) / 256) * sizeof(double));
-  add(L, L.sigpart, 2 * (size_t)sigma2_blocks<T>(p.M) * sizeof(double));
+  // sigma^2 partials: per 256 rows (k_sig_part) or per 64 (fused into the M-step)
+  add(L, L.sigpart, 2 * (size_t)std::max(sigma2_blocks<T>(p.M), (p.M + 63) / 64) * sizeof(double));
   add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
   // Single handles keep their points in Hilbert order (batch members do not).
   L.sorted = batch_chunk == 0 && !(p.flags & CPD_FLAG_NO_SORT);
@@ -166,6 +167,7 @@ struct cpd_ctx {
   hipStream_t st = nullptr;
   Stage stage = Stage::Init;
   int K = 0;  // eigenpairs held
+  int sig_fused = 0;  // sigma^2 partials the last enqueued M-step wrote (0: none)
   double t_eig = 0.0;
   std::string err;
   template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
@@ -312,7 +314,10 @@ void enqueue_mstep(cpd_ctx* h, int gate) {
     a.HT = h->at<P4<T>>(L.HT);
     a.Xnew = h->at<P4<T>>(L.Xnew);
     a.W = h->at<P4<T>>(L.W);
-    fast_mstep_launch<T>(a, h->st);
+    a.Xt = h->at<P4<T>>(L.Xt);
+    a.tbar = h->at<T>(L.tbar);
+    a.sigpart = h->at<double>(L.sigpart);
+    h->sig_fused = fast_mstep_launch<T>(a, h->st);
   } else if (h->p.method == CPD_METHOD_ORIGINAL_LOWRANK) {
     LowRankArgs<T> a{};
     a.X = h->at<P4<T>>(L.X);
@@ -329,6 +334,7 @@ void enqueue_mstep(cpd_ctx* h, int gate) {
     a.L = &L.lr;
     a.Xnew = h->at<P4<T>>(L.Xnew);
     a.W = h->at<P4<T>>(L.W);
+    h->sig_fused = 0;
     lowrank_mstep_launch<T>(a, h->st);
   } else {
     OrigArgs<T> a{};
@@ -344,6 +350,7 @@ void enqueue_mstep(cpd_ctx* h, int gate) {
     a.L = &L.orig;
     a.Xnew = h->at<P4<T>>(L.Xnew);
     a.W = h->at<P4<T>>(L.W);
+    h->sig_fused = 0;
     orig_mstep_launch<T>(a, h->st);
   }
 }
@@ -365,6 +372,10 @@ void enqueue_sigma2(cpd_ctx* h, int gate) {
   a.gate = gate;
   a.part = h->at<double>(L.sigpart);
   a.blocks = sigma2_blocks<T>(h->p.M);
+  if (h->sig_fused > 0) {  // the M-step already wrote the partials
+    a.fused = 1;
+    a.blocks = h->sig_fused;
+  }
   a.llpart = h->at<double>(L.llpart);
   a.llblocks = (h->p.N + 255) / 256;
   sigma2_launch<T>(a, h->st);

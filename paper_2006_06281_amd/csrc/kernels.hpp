@@ -86,8 +86,15 @@ template <typename T> struct FastMArgs {
   P4<T>* HT;         // K: h_k T_k
   P4<T>* Xnew;       // out (M)
   P4<T>* W;          // out (M)
+  // Optional (sigpart non-null): where the vectorised apply kernel runs
+  // (FP32, K % 4 == 0, K <= 1024) it also writes the per-block partials of
+  // the sigma^2 update and retires the iterate into Xt (the sig_part work);
+  // fast_mstep_launch then returns the number of partials, else 0.
+  P4<T>* Xt = nullptr;
+  const T* tbar = nullptr;
+  double* sigpart = nullptr;  // 2 per block of 64 rows
 };
-template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st);
+template <typename T> int fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st);
 template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk);
 
 template <typename T> struct Sigma2Args {
@@ -104,6 +111,7 @@ template <typename T> struct Sigma2Args {
   int blocks;
   const double* llpart;
   int llblocks;
+  int fused = 0;      // 1: the M-step wrote the partials and retired the iterate
 };
 template <typename T> void sigma2_launch(const Sigma2Args<T>& a, hipStream_t st);
 template <typename T> int sigma2_blocks(int M);

@@ -241,8 +241,13 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
                                                 const P4<float>* __restrict__ HTg, int M, int K,
                                                 const DevScalars* __restrict__ sc,
                                                 P4<float>* __restrict__ Xnew,
-                                                P4<float>* __restrict__ W, int gate) {
+                                                P4<float>* __restrict__ W, int gate,
+                                                P4<float>* __restrict__ Xt,
+                                                const P4<float>* __restrict__ Yt,
+                                                const float* __restrict__ tbar,
+                                                double* __restrict__ sigpart) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sh[16];
   if (gate && sc->done) return;
   float* f = reinterpret_cast<float*>(smem);  // gx gy gz hx hy hz, K each
   for (int k = threadIdx.x; k < K; k += 256) {
@@ -278,6 +283,8 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
       }
     }
   }
+  const bool retire = sigpart && !sc->nonfinite;  // a failed M-step keeps the iterate
+  double v = 0.0;
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
 #pragma unroll
@@ -287,8 +294,25 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
     const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
     if (l16 == 0 && m < M) {
       const P4<float> x = X[m];
-      Xnew[m] = P4<float>{x.x + acc[it][3], x.y + acc[it][4], x.z + acc[it][5], 0.f};
+      const P4<float> a{x.x + acc[it][3], x.y + acc[it][4], x.z + acc[it][5], 0.f};
+      Xnew[m] = a;
       W[m] = P4<float>{acc[it][0], acc[it][1], acc[it][2], 0.f};
+      if (sigpart) {  // the row's sigma^2 term (sig_part_body) and the retirement
+        const P4<float> b = Xt[m], y = Yt[m];
+        const double bx = b.x, by = b.y, bz = b.z;
+        const double ex = bx - a.x, ey = by - a.y, ez = bz - a.z;
+        const double cross = ((double)y.x - bx) * ex + ((double)y.y - by) * ey +
+                             ((double)y.z - bz) * ez;
+        v += (double)tbar[m] + 2.0 * cross + ex * ex + ey * ey + ez * ez;
+        if (retire) Xt[m] = a;
+      }
+    }
+  }
+  if (sigpart) {
+    const double s1 = block_sum_d(v, sh);
+    if (threadIdx.x == 0) {
+      sigpart[2 * blockIdx.x] = s1;
+      sigpart[2 * blockIdx.x + 1] = 0.0;
     }
   }
 }
@@ -340,8 +364,12 @@ template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk) {
   return (M + kTRows - 1) / kTRows;
 }
 
-template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st) {
-  if (sizeof(T) == 4 && a.K % 4 == 0 && a.K <= 1024) {
+template <typename T> bool fast_mstep_vec4(int K) {
+  return sizeof(T) == 4 && K % 4 == 0 && K <= 1024;
+}
+
+template <typename T> int fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st) {
+  if (fast_mstep_vec4<T>(a.K)) {
     const float* U = reinterpret_cast<const float*>(a.U);
     const P4<float>* X = reinterpret_cast<const P4<float>*>(a.X);
     hipLaunchKernelGGL(k_tpart4, dim3(a.chunks), dim3(256), 0, st, X,
@@ -355,8 +383,10 @@ template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t 
                        X, U, reinterpret_cast<const P4<float>*>(a.GT),
                        reinterpret_cast<const P4<float>*>(a.HT), a.M, a.K, a.sc,
                        reinterpret_cast<P4<float>*>(a.Xnew), reinterpret_cast<P4<float>*>(a.W),
-                       a.gate);
-    return;
+                       a.gate, reinterpret_cast<P4<float>*>(a.Xt),
+                       reinterpret_cast<const P4<float>*>(a.Yt),
+                       reinterpret_cast<const float*>(a.tbar), a.sigpart);
+    return a.sigpart ? (a.M + 63) / 64 : 0;
   }
   const int kt = a.K <= 256 ? 1 : (a.K <= 512 ? 2 : 4);
   dim3 g1(a.chunks, (a.K + 256 * kt - 1) / (256 * kt));
@@ -375,6 +405,7 @@ template <typename T> void fast_mstep_launch(const FastMArgs<T>& a, hipStream_t 
   else
     hipLaunchKernelGGL((k_apply<T, false>), g3, dim3(256), 0, st, a.X, a.U, a.GT, a.HT, a.M,
                        a.K, a.sc, a.Xnew, a.W, a.gate);
+  return 0;
 }
 
 // ------------------------------------------------------------------ sigma^2
@@ -483,8 +514,9 @@ __global__ __launch_bounds__(256) void k_sig_final(const double* __restrict__ pa
 template <typename T> int sigma2_blocks(int M) { return (M + 255) / 256; }
 
 template <typename T> void sigma2_launch(const Sigma2Args<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_sig_part<T>, dim3(a.blocks), dim3(256), 0, st, a.Xt, a.Xnew, a.Yt, a.tbar,
-                     a.P1, a.M, a.sc, a.part, a.gate);
+  if (!a.fused)
+    hipLaunchKernelGGL(k_sig_part<T>, dim3(a.blocks), dim3(256), 0, st, a.Xt, a.Xnew, a.Yt,
+                       a.tbar, a.P1, a.M, a.sc, a.part, a.gate);
   hipLaunchKernelGGL(k_sig_final<T>, dim3(1), dim3(256), 0, st, a.part, a.blocks, a.llpart,
                      a.llblocks, a.M, a.N, a.D, a.w, a.P1 != nullptr ? 1 : 0, a.sc, a.gate);
 }
@@ -757,7 +789,7 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
 }
 
 #define FCPD_INST(T)                                                                          \
-  template void fast_mstep_launch<T>(const FastMArgs<T>&, hipStream_t);                      \
+  template int fast_mstep_launch<T>(const FastMArgs<T>&, hipStream_t);                       \
   template int fast_mstep_chunks<T>(int, int*);                                              \
   template void sigma2_launch<T>(const Sigma2Args<T>&, hipStream_t);                         \
   template int sigma2_blocks<T>(int);                                                        \
