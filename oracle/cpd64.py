@@ -106,7 +106,7 @@ class EStep:
 
 
 def estep(Xt: np.ndarray, Y: np.ndarray, sigma2: float, w: float,
-          chunk: int | None = None) -> EStep:
+          chunk: int | None = None, rows: np.ndarray | None = None) -> EStep:
     """Eq. 4 posterior with the eq. 5 row constraint, evaluated in log space.
 
     a_mn   = -|y_n - xt_m|^2 / (2 sigma^2)
@@ -114,6 +114,9 @@ def estep(Xt: np.ndarray, Y: np.ndarray, sigma2: float, w: float,
     log p_mn = a_mn - log d_n                                  (eq. 4)
     log r_m  = logsumexp_n log p_mn,  p'_mn = p_mn / r_m       (eq. 5)
     Yt_m = sum_n p'_mn y_n ;  tbar_m = sum_n p'_mn |y_n - xt_m|^2
+
+    rows: evaluate the row quantities (logr, Yt, tbar) for these model rows
+    only; log d_n still sums over every model point.
     """
     M, D = Xt.shape
     N = Y.shape[0]
@@ -130,6 +133,8 @@ def estep(Xt: np.ndarray, Y: np.ndarray, sigma2: float, w: float,
             ext = np.vstack([A, np.full((1, e - s), lc)])
         return logsumexp(ext, axis=0)
     logd = np.concatenate(_pmap(col, cks))
+    if rows is not None:
+        Xt = Xt[rows]
 
     # row pass 1: row maxima of log p_mn
     def rowmax(se):

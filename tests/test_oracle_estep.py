@@ -139,3 +139,18 @@ def test_sigma2_init_is_the_mean_square_distance():
     X, Y = _rand(13, 17, seed=10)
     brute = sum(((Y[n] - X[m]) ** 2).sum() for m in range(13) for n in range(17))
     assert cpd64.sigma2_init(X, Y) == pytest.approx(brute / (3 * 13 * 17), rel=1e-13)
+
+
+def test_row_subset_matches_full_evaluation():
+    """estep(rows=...) gives the sampled rows of the full evaluation (log d_n
+    still over every model point)."""
+    rng = np.random.default_rng(21)
+    Y = rng.normal(size=(90, 3))
+    Xt = Y[rng.choice(90, 70)] + 0.1 * rng.normal(size=(70, 3))
+    full = cpd64.estep(Xt, Y, 0.05, 0.2)
+    rows = np.array([3, 17, 40, 69])
+    sub = cpd64.estep(Xt, Y, 0.05, 0.2, rows=rows)
+    np.testing.assert_allclose(sub.logd, full.logd, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(sub.logr, full.logr[rows], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(sub.Yt, full.Yt[rows], rtol=1e-13)
+    np.testing.assert_allclose(sub.tbar, full.tbar[rows], rtol=1e-12)
