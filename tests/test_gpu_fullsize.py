@@ -79,3 +79,34 @@ def test_fullsize_bf16x_estep_matches_oracle(lib, pair, state):
     assert rel_P1.max() < bar_P1
     assert err_Yt < 1e-3
     assert np.all(err_t < bar_t)
+
+
+def test_fullsize_bf16x_iteration_matches_oracle(lib, pair):
+    """One whole iteration at 50k from the late state with K = 300 imported
+    eigenpairs (a seeded orthonormal basis and a decaying spectrum, so the
+    oracle needs no 50k eigensolve): E-step, Fast M-step (eq. 20), sigma^2
+    (eq. 18 with P').  Transformed points to 1e-3 relative RMS, sigma^2 to
+    1e-3 relative."""
+    import torch
+    X, Y = _f32(pair.X), _f32(pair.Y)
+    M = X.shape[0]
+    K = 300
+    rng = np.random.default_rng(11)
+    U, _ = np.linalg.qr(rng.normal(size=(M, K)))
+    lam = np.sort(M * 0.5 ** (np.arange(K) / 12.0))[::-1].copy()
+    Xt, s2 = _f32(pair.Y_hat), 7.1e-4
+    say("fullsize iteration K", K, "sigma2", s2)
+    r = lib.Registration(dev(X, torch.float32), dev(Y, torch.float32), precision="bf16x",
+                         beta=pair.beta, lam=pair.lam, w=pair.w, eig_mode="import", K=K,
+                         tol=0.0, max_iter=10)
+    r.prepare(U=dev(U, torch.float64), lam=dev(lam, torch.float64))
+    r.set_state(dev(Xt, torch.float32), s2)
+    r.step()
+    Xg, _, s2g = r.state()
+    es = cpd64.estep(Xt, Y, s2, pair.w)
+    _, Xo = cpd64.fast_mstep(X, es.Yt, U, lam, pair.lam, s2)
+    s2o = cpd64.sigma2_fast(Xt, Y, s2, es, Xo)
+    err = cpd64.rel_rms(host(Xg), Xo)
+    say("Xt rel_rms", err, "sigma2", s2g, s2o, "rel", abs(s2g - s2o) / s2o)
+    assert err < 1e-3
+    assert abs(s2g - s2o) < 1e-3 * s2o
