@@ -341,19 +341,48 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
 
 void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
   const int target = 4096;
-  auto plan = [&](int cols, int len, int* splits, int* chunk) {
+  // cap > 0: resident blocks of the pass on the device.  The split count is
+  // then raised (by at most half) until the launch is just under a whole
+  // number of rounds of resident blocks, so the last round is not a thin
+  // tail that leaves most SIMDs short of the waves that hide the latency.
+  auto plan = [&](int cols, int len, int cap, int* splits, int* chunk) {
     const int lenp = (len + 15) & ~15;
     const int tiles = (cols + 255) / 256;
     int s = (target + tiles - 1) / tiles;
     const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
     s = s < 1 ? 1 : (s > smax ? smax : s);
-    int c = (lenp + s - 1) / s;
-    c = (c + 63) & ~63;
+    auto layout = [&](int q, int* c_out) {
+      int c = (lenp + q - 1) / q;
+      c = (c + 63) & ~63;
+      *c_out = c;
+      return (lenp + c - 1) / c;
+    };
+    int c = 0, S = layout(s, &c);
+    if (cap > 0) {
+      for (int q = s; q <= s + s / 2 && q <= smax; ++q) {
+        int cq = 0;
+        const int Sq = layout(q, &cq);
+        const double r = (double)tiles * Sq / cap;
+        if (std::ceil(r) - r < 0.1) {
+          S = Sq;
+          c = cq;
+          break;
+        }
+      }
+    }
     *chunk = c;
-    *splits = (lenp + c - 1) / c;
+    *splits = S;
   };
-  plan(N, M, splitsA, chunkA);
-  plan(M, N, splitsB, chunkB);
+  // pass B, the dominant kernel, runs few waves per SIMD (its register
+  // budget), so it is the one whose tail costs: size its splits to the device
+  int capB = 0, dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bfx_rowsum, 256, 0) == hipSuccess)
+    capB = cus * per;
+  (void)hipGetLastError();  // no device (a CPU-only query): the plain plan
+  plan(N, M, 0, splitsA, chunkA);
+  plan(M, N, capB, splitsB, chunkB);
 }
 
 void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
