@@ -282,6 +282,9 @@ __device__ __forceinline__ void colmerge_body(const T* __restrict__ part, int sp
   bool bad = false;
   if (n < N) {
     T s = (T)0;
+    // unrolled so that several splits' loads are in flight (the sum keeps
+    // its order)
+#pragma unroll 8
     for (int k = 0; k < splits; ++k) s += part[(size_t)k * N + n];
     s += (T)exp2(l2c - refd);  // the outlier sink c, relative to ref (0 if w = 0)
     L = ref + flog2(s);
@@ -508,6 +511,7 @@ __device__ __forceinline__ void rowmerge_body(const T* __restrict__ part, int sp
   const double kap = kappa_of(sc->sigma2);
   T r = 0, px = 0, py = 0, pz = 0, t = 0;
   if (m < M) {
+#pragma unroll 4
     for (int k = 0; k < splits; ++k) {
       const T* b = part + (size_t)k * 5 * M;
       r += b[m];
