@@ -54,8 +54,8 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
 # of known size; valid only while the kernel source is unchanged (sha256).
 TRAFFIC = {
-    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "7913d3db6cbb68a6eb120abf7994766c317b131283712406e7943a02f263a970",
-                     "bytes_per_dispatch": 38.49e6 + 21.00e6,
+    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "094e5ee6ddba5d9e2bd3aa864e530959e5e7959075235c17380825a06b47c1f9",
+                     "bytes_per_dispatch": 38.49e6 + 26.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
 }
 
