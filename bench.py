@@ -30,24 +30,25 @@ sys.path.insert(0, ROOT)
 METRIC = "time-to-converge (s) & EM iters/s at M=N=50k, 3D; vs plain CPD same GPU"
 
 # Roofline of the E-step passes (ALU bound: O(M + N) bytes against O(M N)
-# arithmetic).  The algorithmic work per model-scene pair is counted in VALU
-# issue slots of the formulation each kernel implements (one slot = one
-# 64-lane instruction on a 16-lane SIMD = 4 cycles; v_exp_f32 takes two slots,
-# measured: 1.79e13 exp/s against 3.57e13 FMA/s on the chip), and expressed as
-# FP32 FMA-equivalent FLOP (2 per slot) so it compares with the non-packed
-# FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz = 78.6
-# TFLOP/s (this build disables packed FP32, so 157.3 is not reachable).
-#   FP32  pass A: 3 sub + 3 (mul, 2 fma) for |y - x|^2, exp, add        = 9
-#         pass B: the same 6, add L_n, exp, add (P1), 3 fma (PY), fma (t) = 14
-#   BF16X pass A: |y - x|^2 from the matrix cores; exp, add            = 3
-#         pass B: exp, sub L_n, add (P1), 3 fma (PY), fma (t)          = 8
-# BF16X also spends one v_mfma_f32_16x16x32_bf16 per 256 pairs; it runs in
-# the matrix pipe, beside the VALU work of the other waves on the SIMD, and is
-# not counted.
-SLOTS = {("fp32", "passA"): 9, ("fp32", "passB"): 14,
-         ("bf16x", "passA"): 3, ("bf16x", "passB"): 8}
-PEAK_VALU_FP32_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
-PEAK_EXP_PER_S = 19.66e12      # v_exp_f32 at half the FMA issue rate
+# arithmetic).  The algorithmic work per model-scene pair is counted in FP32
+# vector slots of the formulation each kernel implements, one slot being one
+# lane-operation at the chip's FP32 vector rate (256 CU x 4 SIMD x 32 lanes x
+# 2.4 GHz; x 2 FLOP per FMA = the published 157.3 TFLOP/s).  Non-packed FP32
+# FMAs reach 23.4 lanes/cycle/SIMD on the chip (73% of that rate, a
+# 32-chain microbenchmark), so the full vector rate, not half of it, is the
+# ceiling even with packed FP32 disabled.  v_exp_f32 runs at a quarter of
+# the rate (measured 6.8 lanes/cycle/SIMD) and does not overlap the FMAs of
+# other waves, so an exponential counts 4 slots.
+#   FP32  pass A: 3 sub + 3 (mul, 2 fma) for |y - x|^2, exp, add        = 11
+#         pass B: the same 6, add L_n, exp, add (P1), 3 fma (PY), fma (t) = 16
+#   BF16X pass A: |y - x|^2 from the matrix cores; exp, add            = 5
+#         pass B: exp, sub L_n, add (P1), 3 fma (PY), fma (t)          = 10
+# BF16X also spends one v_mfma_f32_16x16x32_bf16 per 256 pairs in the matrix
+# pipe; it is not counted.
+SLOTS = {("fp32", "passA"): 11, ("fp32", "passB"): 16,
+         ("bf16x", "passA"): 5, ("bf16x", "passB"): 10}
+PEAK_VALU_FP32_TFLOPS = 157.3  # 256 CU x 4 SIMD x 32 lanes x 2 (FMA) x 2.4 GHz
+PEAK_EXP_PER_S = 19.66e12      # v_exp_f32 at a quarter of the vector rate
 KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
                ("bf16x", "passA"): "k_bfx_colsum", ("bf16x", "passB"): "k_bfx_rowsum"}
 # HBM traffic of the dominant kernel per dispatch, from two rocprofv3 --pmc
@@ -91,7 +92,7 @@ def roofline_of(kern, pairs, precision):
     return {"bound": "alu", "kernel": b["kernel"] + " (E-step pass B)",
             "achieved": b["achieved"], "peak": PEAK_VALU_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": b["frac"], "traffic": traffic,
-            "flop_model": "FMA-equivalent VALU issue slots per pair x pairs per launch",
+            "flop_model": "FMA-equivalent FP32 vector slots per pair (exp = 4) x pairs per launch",
             "stages": out}
 
 
