@@ -79,7 +79,7 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   if (batch_chunk > 0)
     chunk_plan(p.M, p.N, batch_chunk, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
   else if (p.precision == CPD_PREC_BF16X)
-    bfx_splits(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
+    bfx_splits(p.M, p.N, 0, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
   else
     estep_splits<T>(p.M, p.N, &L.splitsA, &L.chunkA, &L.splitsB, &L.chunkB);
   const size_t M256 = (size_t)pad256(p.M), N256 = (size_t)pad256(p.N);
@@ -99,7 +99,11 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   add(L, L.P1, M * sizeof(T));
   add(L, L.tbar, M * sizeof(T));
   add(L, L.partA, (size_t)L.splitsA * N * sizeof(T));
-  add(L, L.partB, (size_t)L.splitsB * 5 * M * sizeof(T));
+  // (BF16X: room for the most splits cpd_init may fit to the device)
+  const int splitsB_cap = (batch_chunk == 0 && p.precision == CPD_PREC_BF16X)
+                              ? std::max(L.splitsB, bfx_splitsB_max(p.M, p.N))
+                              : L.splitsB;
+  add(L, L.partB, (size_t)splitsB_cap * 5 * M * sizeof(T));
   // nearest-neighbour indices of the two-way matching (per scene / model point)
   add(L, L.nnY, N * sizeof(int));
   add(L, L.nnX, M * sizeof(int));
@@ -789,6 +793,9 @@ cpd_status cpd_init(cpd_handle* out, const cpd_params* p, const void* X, const v
   if (!h) return fail(nullptr, CPD_E_DEVICE, "out of host memory");
   h->p = *p;
   h->L = L;
+  if (p->precision == CPD_PREC_BF16X)  // fit pass B's splits to this device
+    bfx_splits(p->M, p->N, bfx_resident_blocksB(), &h->L.splitsA, &h->L.chunkA, &h->L.splitsB,
+               &h->L.chunkB);
   h->ws = static_cast<char*>(workspace);
   h->st = static_cast<hipStream_t>(hip_stream);
   const cpd_status s = is_f64(h) ? init_impl<double>(h, X, Y) : init_impl<float>(h, X, Y);

@@ -339,50 +339,66 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   }
 }
 
-void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
-  const int target = 4096;
-  // cap > 0: resident blocks of the pass on the device.  The split count is
-  // then raised (by at most half) until the launch is just under a whole
-  // number of rounds of resident blocks, so the last round is not a thin
-  // tail that leaves most SIMDs short of the waves that hide the latency.
-  auto plan = [&](int cols, int len, int cap, int* splits, int* chunk) {
-    const int lenp = (len + 15) & ~15;
-    const int tiles = (cols + 255) / 256;
-    int s = (target + tiles - 1) / tiles;
-    const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
-    s = s < 1 ? 1 : (s > smax ? smax : s);
-    auto layout = [&](int q, int* c_out) {
-      int c = (lenp + q - 1) / q;
-      c = (c + 63) & ~63;
-      *c_out = c;
-      return (lenp + c - 1) / c;
-    };
-    int c = 0, S = layout(s, &c);
-    if (cap > 0) {
-      for (int q = s; q <= s + s / 2 && q <= smax; ++q) {
-        int cq = 0;
-        const int Sq = layout(q, &cq);
-        const double r = (double)tiles * Sq / cap;
-        if (std::ceil(r) - r < 0.1) {
-          S = Sq;
-          c = cq;
-          break;
-        }
-      }
+namespace {
+constexpr int kBfxTarget = 4096;  // blocks per pass before any device fitting
+
+// Split count s for `len` reduction points over `cols` output points, and
+// its chunk; the plain plan, or (q > 0) the layout for q splits.
+int bfx_plan(int cols, int len, int q, int* chunk) {
+  const int lenp = (len + 15) & ~15;
+  const int tiles = (cols + 255) / 256;
+  int s = q > 0 ? q : (kBfxTarget + tiles - 1) / tiles;
+  const int smax = (lenp + 127) / 128;  // at least 128 reduction steps per split
+  s = s < 1 ? 1 : (s > smax ? smax : s);
+  int c = (lenp + s - 1) / s;
+  c = (c + 63) & ~63;
+  *chunk = c;
+  return (lenp + c - 1) / c;
+}
+}  // namespace
+
+// capB > 0: resident k_bfx_rowsum blocks on the device.  Pass B's split
+// count is then raised (by at most half) until the launch is just under a
+// whole number of rounds of resident blocks, so the last round is not a thin
+// tail that leaves most SIMDs short of the waves that hide the latency (pass
+// B runs few waves per SIMD, its register budget; pass A is left as
+// planned).  Every choice fits the buffer bfx_splitsB_max sizes.
+void bfx_splits(int M, int N, int capB, int* splitsA, int* chunkA, int* splitsB, int* chunkB) {
+  *splitsA = bfx_plan(N, M, 0, chunkA);
+  int c = 0;
+  const int s0 = bfx_plan(M, N, 0, &c);
+  *splitsB = s0;
+  *chunkB = c;
+  if (capB <= 0) return;
+  const int tiles = (M + 255) / 256;
+  for (int q = s0; q <= s0 + s0 / 2; ++q) {
+    int cq = 0;
+    const int Sq = bfx_plan(M, N, q, &cq);
+    const double r = (double)tiles * Sq / capB;
+    if (std::ceil(r) - r < 0.1) {
+      *splitsB = Sq;
+      *chunkB = cq;
+      return;
     }
-    *chunk = c;
-    *splits = S;
-  };
-  // pass B, the dominant kernel, runs few waves per SIMD (its register
-  // budget), so it is the one whose tail costs: size its splits to the device
-  int capB = 0, dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bfx_rowsum, 256, 0) == hipSuccess)
-    capB = cus * per;
-  (void)hipGetLastError();  // no device (a CPU-only query): the plain plan
-  plan(N, M, 0, splitsA, chunkA);
-  plan(M, N, capB, splitsB, chunkB);
+  }
+}
+
+int bfx_splitsB_max(int M, int N) {
+  int c = 0, best = 0;
+  const int s0 = bfx_plan(M, N, 0, &c);
+  for (int q = s0; q <= s0 + s0 / 2; ++q) best = std::max(best, bfx_plan(M, N, q, &c));
+  return best;
+}
+
+int bfx_resident_blocksB() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bfx_rowsum, 256, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return cus * per;
 }
 
 void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {

@@ -66,7 +66,10 @@ template <typename T> void estep_launch(const EStepArgs<T>& a, hipStream_t st);
 // pieces shared with the BF16X E-step
 template <typename T> void colmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st);
 template <typename T> void rowmerge_fix_launch(const EStepArgs<T>& a, hipStream_t st, int relative);
-void bfx_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
+// BF16X split plan; capB: resident pass-B blocks on the device (0: unknown).
+void bfx_splits(int M, int N, int capB, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
+int bfx_splitsB_max(int M, int N);  // the most pass-B splits any capB can give
+int bfx_resident_blocksB();         // on the current device; 0 if it cannot say
 inline int pad256(int n) { return (n + 255) & ~255; }
 template <typename T>
 void estep_splits(int M, int N, int* splitsA, int* chunkA, int* splitsB, int* chunkB);
