@@ -208,15 +208,19 @@ __global__ __launch_bounds__(256) void k_panel(const double* __restrict__ A, int
   }
 }
 
-// Trailing update A[k1+i][k1+j] -= sum_t P[i][t] P[j][t] for i >= j (tiles of
-// 128 x 128 on or below the diagonal; 8 x 8 per thread, strided so LDS reads
-// are broadcast or conflict-free).
+// Trailing update A[k1+i][k1+j] -= sum_t P[i][t] P[j][t] for i >= j, on the
+// FP64 matrix cores: tiles of 128 x 128 on or below the diagonal, four waves
+// of 64 x 64 (4 x 4 v_mfma_f64_16x16x4f64 accumulators each), the panel rows
+// staged in LDS 16 k at a time.  MFMA operands: A lane l = row l%16, k l/16;
+// B lane l = column l%16, k l/16; D lane l, register r = row 4r + l/16,
+// column l%16.
 constexpr int ST = 128, SK = 16;
-__global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int lda, int k1, int R,
-                                              const double* __restrict__ P, int nb,
-                                              const int* chol_fail, const int* done) {
-  __shared__ double sa[SK][ST + 1];
-  __shared__ double sb[SK][ST + 1];
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256, 2) void k_syrk(double* __restrict__ A, int lda, int k1, int R,
+                                                 const double* __restrict__ P, int nb,
+                                                 const int* chol_fail, const int* done) {
+  __shared__ double sa[SK][ST + 2];
+  __shared__ double sb[SK][ST + 2];
   if (done && *done) return;
   if (*chol_fail) return;
   // decode the lower-triangular tile index
@@ -226,12 +230,14 @@ __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int lda, i
   while (bi * (bi + 1) / 2 > t) --bi;
   const int bj = t - bi * (bi + 1) / 2;
   const int i0 = bi * ST, j0 = bj * ST;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[8][8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  dbl4_t acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = dbl4_t{0.0, 0.0, 0.0, 0.0};
   for (int kk = 0; kk < nb; kk += SK) {
     // 128 rows x 16 k of each operand: 2048 values, 8 per thread
 #pragma unroll
@@ -244,31 +250,35 @@ __global__ __launch_bounds__(256) void k_syrk(double* __restrict__ A, int lda, i
       sb[k][r] = (rj < R && gk < nb) ? P[(size_t)rj * NB + gk] : 0.0;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < SK; ++k) {
-      double a[8], b[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = sa[k][ty + 16 * q];
-        b[q] = sb[k][tx + 16 * q];
+    for (int ks = 0; ks < SK / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      double x[4], y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[q] = sa[k][wr + 16 * q + li];
+        y[q] = sb[k][wc + 16 * q + li];
       }
 #pragma unroll
-      for (int x = 0; x < 8; ++x)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int y = 0; y < 8; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 8; ++x) {
-    const int i = i0 + ty + 16 * x;
-    if (i >= R) continue;
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int y = 0; y < 8; ++y) {
-      const int j = j0 + tx + 16 * y;
-      if (j <= i) A[(size_t)(k1 + i) * lda + k1 + j] -= acc[x][y];
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + wr + 16 * a + 4 * r + lk;
+      if (i >= R) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int j = j0 + wc + 16 * b + li;
+        if (j <= i) A[(size_t)(k1 + i) * lda + k1 + j] -= acc[a][b][r];
+      }
     }
-  }
 }
 
 __global__ __launch_bounds__(256) void k_store_panel(double* __restrict__ A, int lda, int k0,
