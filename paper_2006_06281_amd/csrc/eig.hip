@@ -921,8 +921,11 @@ double* misc_dbl(const Ctx& c, int n) {
 // is numerically rank deficient (the Gram spectrum reaches round-off within a
 // few hundred eigenvalues), so three shifted passes bring it to a condition
 // number that plain passes handle, and two clean plain passes finish.  A plain
-// pass that breaks down is redone with the shift.  Returns 0 or 1.
-int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg) {
+// pass that breaks down is redone with the shift.  full = false (a basis the
+// range finder only multiplies by Phi again) stops after the shifted passes:
+// what the next product needs is the span, which a basis orthonormal to the
+// shift's level (~1e-8) spans as well as an exact one.  Returns 0 or 1.
+int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg, bool full = true) {
   const int M = c.r.M;
   double* G = c.at(c.L.phi);
   double* Tt = c.at(c.L.V);
@@ -950,7 +953,7 @@ int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg) {
   const double* src = Z;
   int plain_ok = 0, pass = 0;
   const int max_passes = 10;
-  for (; pass < max_passes && plain_ok < 2; ++pass) {
+  for (; pass < max_passes && (full ? plain_ok < 2 : pass < 3); ++pass) {
     const bool shifted = pass < 3;
     if (factor(src, shifted)) {
       if (shifted) {
@@ -971,7 +974,7 @@ int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg) {
     gemm_nn(c, src, n, Tt, n, dst, n, M, n, n);
     src = dst;
   }
-  if (plain_ok < 2) {
+  if (full && plain_ok < 2) {
     *msg = "CholeskyQR did not reach orthonormality";
     return 1;
   }
@@ -1052,10 +1055,10 @@ int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64
   // scratch of the products: Q before the first orthonormalisation, then
   // Omega's buffer (Omega is read only by the first product)
   phi_times<PT>(c, O, Z, n, Q);
-  if (orth(c, Z, Q, n, msg)) return 1;
+  if (orth(c, Z, Q, n, msg, q == 0)) return 1;
   for (int it = 0; it < q; ++it) {
     phi_times<PT>(c, Q, Z, n, Om);
-    if (orth(c, Z, Q, n, msg)) return 1;
+    if (orth(c, Z, Q, n, msg, it == q - 1)) return 1;  // the last basis is the one kept
   }
   phi_times<PT>(c, Q, Z, n, Om);  // Z = Phi Q
   gram(c, Q, Z, n, B);        // B = Q^T Phi Q (symmetrised)
