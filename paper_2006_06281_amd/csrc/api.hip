@@ -449,7 +449,8 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
                         h->p.D, h->p.beta, h->st);
     if (!(h->p.sigma2_init > 0.0))
       reset_sigma2_launch<T>(h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D,
-                             h->sc(), h->at<double>(L.initpart), h->st);
+                             h->sc(), h->at<double>(L.initpart), h->st,
+                             h->p.precision == CPD_PREC_BF16X ? kBfxSigma2FloorRel : 0.0);
   }
   hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 1);
   HIPCHK(h, hipGetLastError());
@@ -513,7 +514,8 @@ cpd_status init_impl(cpd_ctx* h, const void* X, const void* Y) {
   const Layout& L = h->L;
   init_launch<T>(static_cast<const T*>(X), static_cast<const T*>(Y), h->at<P4<T>>(L.X),
                  h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D, h->p.sigma2_init,
-                 h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st);
+                 h->p.tol, h->p.max_iter, h->sc(), h->at<double>(L.initpart), h->st,
+                 h->p.precision == CPD_PREC_BF16X ? kBfxSigma2FloorRel : 0.0);
   if (L.sorted) {
     // Hilbert order of X and Y (xs serves as the staging buffer: it holds
     // max(M, N) rounded up to 256 points and is cleared below); Xt = X.

@@ -123,11 +123,15 @@ template <typename T> int sigma2_blocks(int M);
 template <typename T>
 void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int M, int N, int D,
                  double sigma2_init, double tol, int max_iter, DevScalars* sc, double* part,
-                 hipStream_t st);
+                 hipStream_t st, double floor_rel = 0.0);
 int init_blocks(int M, int N);
 template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
-                         double* part, hipStream_t st);
+                         double* part, hipStream_t st, double floor_rel = 0.0);
+// sigma^2 floor of the BF16X mode, relative to D times the data's closed-form
+// sigma^2_0: keeps its exponent error (2^-21 3 kappa R^2 base-2 units, R the
+// extent of the points) well below one unit, so no exponential overflows.
+constexpr double kBfxSigma2FloorRel = 1e-5;
 
 // pack / unpack between row-major M x D arrays and P4 arrays; with perm
 // (internal row i <-> caller row perm[i]) pack gathers and unpack scatters;

@@ -589,10 +589,13 @@ __global__ __launch_bounds__(256) void k_s2init_part(const P4<T>* __restrict__ X
 
 // sigma^2_0 = sum_mn |y_n - x_m|^2 / (D M N)
 //          = (N sum|u|^2 + M sum|v|^2 - 2 (sum u).(sum v)) / (D M N)
+// The floor below which sigma^2 is not lowered is 1e-10 sigma^2_0, and at
+// least floor_rel D times that closed-form value of the data (floor_rel > 0
+// for the BF16X mode, whose exponent error grows as 1 / sigma^2).
 __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__ part, int blocks,
                                                       int M, int N, int D, double given,
                                                       double tol, int max_iter, int set_all,
-                                                      DevScalars* sc) {
+                                                      DevScalars* sc, double floor_rel) {
   __shared__ double sh[16];
   double v[8];
   for (int j = 0; j < 8; ++j) {
@@ -601,14 +604,12 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
     v[j] = block_sum_d(a, sh);
   }
   if (threadIdx.x == 0) {
-    double s2 = given;
-    if (!(given > 0.0)) {
-      const double cross = v[0] * v[4] + v[1] * v[5] + v[2] * v[6];
-      s2 = ((double)N * v[3] + (double)M * v[7] - 2.0 * cross) / ((double)D * M * N);
-    }
+    const double cross = v[0] * v[4] + v[1] * v[5] + v[2] * v[6];
+    const double s2data = ((double)N * v[3] + (double)M * v[7] - 2.0 * cross) / ((double)D * M * N);
+    const double s2 = given > 0.0 ? given : s2data;
     sc->sigma2 = s2;
     sc->sigma2_start = s2;
-    sc->sigma2_floor = 1e-10 * s2;
+    sc->sigma2_floor = fmax(1e-10 * s2, floor_rel * D * s2data);
     sc->dsigma2 = 0.0;
     sc->done = 0;
     sc->converged = 0;
@@ -630,7 +631,7 @@ int init_blocks(int M, int N) { return (M + N + 255) / 256; }
 template <typename T>
 void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int M, int N, int D,
                  double sigma2_init, double tol, int max_iter, DevScalars* sc, double* part,
-                 hipStream_t st) {
+                 hipStream_t st, double floor_rel) {
   hipLaunchKernelGGL(k_pack<T>, dim3((M + 255) / 256), dim3(256), 0, st, Xin, X, Xt, M, D,
                      (const int*)nullptr, (const double*)nullptr);
   hipLaunchKernelGGL(k_pack<T>, dim3((N + 255) / 256), dim3(256), 0, st, Yin, Y, (P4<T>*)nullptr,
@@ -638,16 +639,16 @@ void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int 
   const int blocks = init_blocks(M, N);
   hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
   hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D,
-                     sigma2_init, tol, max_iter, 1, sc);
+                     sigma2_init, tol, max_iter, 1, sc, floor_rel);
 }
 
 template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
-                         double* part, hipStream_t st) {
+                         double* part, hipStream_t st, double floor_rel) {
   const int blocks = init_blocks(M, N);
   hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
   hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D, -1.0, 0.0,
-                     0, 0, sc);
+                     0, 0, sc, floor_rel);
 }
 
 template <typename T>
@@ -797,9 +798,10 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
   template void sigma2_launch<T>(const Sigma2Args<T>&, hipStream_t);                         \
   template int sigma2_blocks<T>(int);                                                        \
   template void init_launch<T>(const T*, const T*, P4<T>*, P4<T>*, P4<T>*, int, int, int,     \
-                               double, double, int, DevScalars*, double*, hipStream_t);      \
+                               double, double, int, DevScalars*, double*, hipStream_t,       \
+                               double);                                                       \
   template void reset_sigma2_launch<T>(const P4<T>*, const P4<T>*, int, int, int, DevScalars*, \
-                                       double*, hipStream_t);                                 \
+                                       double*, hipStream_t, double);                         \
   template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t, const int*,       \
                                  const double*);                                              \
   template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t, const int*,        \

@@ -168,3 +168,38 @@ def test_state_machine(lib):
     with pytest.raises(lib.FastCPDError) as e:
         r.step()
     assert e.value.status == lib.CPD_E_STATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x"])
+def test_identical_sets_are_a_fixed_point(lib, precision):
+    """Y = X through the ABI, as the oracle's pin: from sigma^2 far below the
+    closest pair's squared distance every point's posterior is itself, so one
+    step leaves Xt at X (W = 0); from the standard sigma^2_0 the registration
+    ends at X."""
+    import torch
+    X = synth.workload("small500").X[:200]
+    if precision != "fp64":
+        X = X.astype(np.float32).astype(np.float64)
+    U, lam = _oracle_eig(X, 2.0)
+    h2 = cpd64.sqdist(X, X)[~np.eye(len(X), dtype=bool)].min()
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    scale = np.abs(X).max()
+    atol = (1e-12 if precision == "fp64" else 1e-6) * scale
+    say("fixed point", precision, "h^2", h2)
+    r = lib.Registration(dev(X, dt), dev(X, dt), precision=precision, beta=2.0, lam=3.0, w=0.1,
+                         eig_mode="import", K=len(X), sigma2_init=1e-4 * h2, tol=0.0, max_iter=1)
+    r.prepare(dev(U, torch.float64), dev(lam, torch.float64))
+    out = r.register()
+    np.testing.assert_allclose(host(out.Xt), X, rtol=0, atol=atol)
+    if precision != "bf16x":
+        # direct differences make the self term's y - x exactly 0, so W = 0
+        # (BF16X sums p y absolutely: its rounding noise reaches W through
+        # 1 / (lam_i + lambda sigma^2), but not Xt)
+        assert np.abs(host(out.W)).max() < atol
+    r = lib.Registration(dev(X, dt), dev(X, dt), precision=precision, beta=2.0, lam=3.0, w=0.1,
+                         eig_mode="import", K=len(X), tol=1e-10, max_iter=1000)
+    r.prepare(dev(U, torch.float64), dev(lam, torch.float64))
+    out = r.register()
+    err = cpd64.rel_rms(host(out.Xt), X)
+    say("converged", out.converged, "iters", out.iters, "rel_rms", err)
+    assert err < (1e-6 if precision == "fp64" else 1e-4)
