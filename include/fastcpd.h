@@ -66,7 +66,7 @@ typedef enum {
   CPD_PREC_BF16X = 2       /* E-step squared distances from bf16 products on
                               the matrix cores, fp32 accumulate and exp; its
                               exponent error grows as 1/sigma^2, so sigma^2 is
-                              not lowered below 1e-5 D times the data's
+                              not lowered below 1e-7 D times the data's
                               closed-form sigma^2_0 in this mode              */
 } cpd_precision;
 
