@@ -203,3 +203,25 @@ def test_identical_sets_are_a_fixed_point(lib, precision):
     err = cpd64.rel_rms(host(out.Xt), X)
     say("converged", out.converged, "iters", out.iters, "rel_rms", err)
     assert err < (1e-6 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x"])
+def test_translation_is_recovered(lib, precision):
+    """Y = X + t through the ABI: a rigid shift lies in the span the Gaussian
+    field can represent smoothly, and the registration ends on Y (as the
+    oracle's pin does)."""
+    import torch
+    X = synth.workload("small500").X[:300]
+    Y = X + np.array([0.3, -0.2, 0.1])
+    if precision != "fp64":
+        X = X.astype(np.float32).astype(np.float64)
+        Y = Y.astype(np.float32).astype(np.float64)
+    U, lam = _oracle_eig(X, 2.0)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    r = lib.Registration(dev(X, dt), dev(Y, dt), precision=precision, beta=2.0, lam=3.0, w=0.1,
+                         eig_mode="import", K=len(X), tol=1e-10, max_iter=1000)
+    r.prepare(dev(U, torch.float64), dev(lam, torch.float64))
+    out = r.register()
+    err = cpd64.rmse(host(out.Xt), Y)
+    say("translation", precision, "iters", out.iters, "rmse", err)
+    assert out.converged and err < 1e-3
