@@ -167,8 +167,10 @@ cpd_status cpd_eig_export(cpd_handle h, double* U_out, double* lam_out);
 cpd_status cpd_step(cpd_handle h, cpd_step_info* info);
 
 /* Iterate from the current state until |dsigma^2| < tol or max_iter steps.
- * W0 (device, M x D, nullable) sets Xt = X + Phi W0 and resets sigma^2 to its
- * start value first (warm start).  X_out (device, M x D) receives Xt; W_out
+ * W0 (device, M x D, nullable) first starts a new run from Xt = X + Phi W0
+ * (warm start) with sigma^2 = sigma2_init when that is > 0, else the standard
+ * start sum_mn |y_n - xt_m|^2 / (D M N) at that Xt; the previous run's
+ * sigma^2 is never reused.  X_out (device, M x D) receives Xt; W_out
  * (nullable) receives W.  res (host, nullable) gets counts and the timing
  * split of the paper's runtime protocol (Section IV).  Returns
  * CPD_NOT_CONVERGED when the cap was hit. */
@@ -203,7 +205,6 @@ cpd_status cpd_estep(cpd_handle h, void* logd, void* P1, void* Yt, void* tbar);
  * Synchronises the stream. */
 cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms);
 
-/* Release the handle (host memory only; the workspace stays the caller's). */
 /* Two-way registration for a scene with missing points (Section IV-A): the
    scene is first registered onto the model, one-to-one correspondences are
    taken from that result, and the model's transformation is solved from
@@ -229,6 +230,7 @@ cpd_status cpd_matches(cpd_handle h, int32_t mutual_only, int32_t* match_out);
 cpd_status cpd_solve_matches(cpd_handle h, const int32_t* match, double sigma2, void* X_out,
                              void* W_out);
 
+/* Release the handle (host memory only; the workspace stays the caller's). */
 cpd_status cpd_destroy(cpd_handle h);
 
 /* ------------------------------------------------------------------ batch

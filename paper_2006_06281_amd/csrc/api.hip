@@ -188,6 +188,14 @@ struct cpd_ctx {
 
 namespace {
 
+// A HIP event released when the guard leaves scope.
+struct EventGuard {
+  hipEvent_t e = nullptr;
+  ~EventGuard() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 cpd_status fail(cpd_ctx* h, cpd_status s, const std::string& msg) {
   g_last_error = msg;
   if (h) h->err = msg;
@@ -447,21 +455,22 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
     }
     phi_apply_launch<T>(h->at<P4<T>>(L.X), w0, h->at<P4<T>>(L.Xt), h->p.M,
                         h->p.D, h->p.beta, h->st);
-    if (!(h->p.sigma2_init > 0.0))
-      reset_sigma2_launch<T>(h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D,
-                             h->sc(), h->at<double>(L.initpart), h->st,
-                             h->p.precision == CPD_PREC_BF16X ? kBfxSigma2FloorRel : 0.0);
+    // sigma^2 of the warm start: the closed form at X + Phi W0, or the
+    // caller's sigma2_init (never the previous run's value)
+    reset_sigma2_launch<T>(h->at<P4<T>>(L.Xt), h->at<P4<T>>(L.Y), h->p.M, h->p.N, h->p.D,
+                           h->sc(), h->at<double>(L.initpart), h->st,
+                           h->p.sigma2_init > 0.0 ? kS2Start : kS2Warm);
   }
   hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 1);
   HIPCHK(h, hipGetLastError());
   // Iterations are enqueued in batches; after convergence the remaining
   // launches of a batch see sc->done and return at once.
   const int batch = 8;
-  std::vector<PhaseEvents> evs;
-  if (res) {
-    evs.resize(batch);
-    for (auto& pe : evs)
-      for (auto& e : pe.e) HIPCHK(h, hipEventCreate(&e));
+  std::vector<EventGuard> guards(res ? 4 * batch : 0);
+  std::vector<PhaseEvents> evs(res ? batch : 0);
+  for (int i = 0; i < (int)guards.size(); ++i) {
+    HIPCHK(h, hipEventCreate(&guards[i].e));
+    evs[i / 4].e[i % 4] = guards[i].e;
   }
   double t_c = 0, t_it = 0;
   DevScalars s{};
@@ -484,8 +493,6 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
     done_iters += nb;
     if (s.done) break;
   }
-  for (auto& pe : evs)
-    for (auto& e : pe.e) (void)hipEventDestroy(e);
   if (s.nonfinite == 2) status = fail(h, CPD_E_NUMERIC, "Cholesky factorisation broke down");
   else if (s.nonfinite) status = fail(h, CPD_E_NUMERIC, "sigma^2 became non-finite");
   if (X_out)
@@ -707,8 +714,12 @@ cpd_status get_state_impl(cpd_ctx* h, void* Xt, void* W, double* sigma2) {
 
 template <typename T>
 cpd_status time_impl(cpd_ctx* h, int reps, double* out) {
+  EventGuard g[8];
   hipEvent_t e[8];
-  for (auto& x : e) HIPCHK(h, hipEventCreate(&x));
+  for (int i = 0; i < 8; ++i) {
+    HIPCHK(h, hipEventCreate(&g[i].e));
+    e[i] = g[i].e;
+  }
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 0);
   cpd_status s = CPD_OK;
@@ -737,7 +748,6 @@ cpd_status time_impl(cpd_ctx* h, int reps, double* out) {
     acc[5] += ms[6];                // sigma^2
     acc[7] += tot;
   }
-  for (auto& x : e) (void)hipEventDestroy(x);
   if (s != CPD_OK) return s;
   for (int i = 0; i < 8; ++i) out[i] = acc[i] / reps;
   return CPD_OK;
@@ -1087,6 +1097,8 @@ __global__ void kb_reset(const InstDesc* __restrict__ d, int B, int restart) {
   DevScalars* sc = d[i].sc;
   if (restart) {
     sc->sigma2 = sc->sigma2_start;
+    sc->sigma2_floor = fmax(1e-10 * sc->sigma2_start, sc->floor_data);
+    sc->dsigma2 = 0.0;
     sc->nonfinite = 0;
   }
   sc->iter = 0;
@@ -1207,9 +1219,10 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   int best = kBatchChunks[0];
   if (tune) {
     float best_ms = 1e30f;
-    hipEvent_t e0, e1;
-    HIPCHK(nullptr, hipEventCreate(&e0));
-    HIPCHK(nullptr, hipEventCreate(&e1));
+    EventGuard g0, g1;
+    HIPCHK(nullptr, hipEventCreate(&g0.e));
+    HIPCHK(nullptr, hipEventCreate(&g1.e));
+    hipEvent_t e0 = g0.e, e1 = g1.e;
     for (int c = 0; c < 4; ++c) {
       const cpd_status s = batch_build(b, kBatchChunks[c]);
       if (s != CPD_OK) return s;
@@ -1227,8 +1240,6 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
         best = kBatchChunks[c];
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
   }
   cpd_status s = batch_build(b, best);
   if (s != CPD_OK) return s;
@@ -1252,10 +1263,13 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
                               cpd_result* res) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
   if (!b->prepared) return bfail(b, CPD_E_STATE, "cpd_batch_prepare must run first");
-  // order after the caller's stream
-  hipEvent_t ev0, ev1;
-  HIPCHK(nullptr, hipEventCreate(&ev0));
-  HIPCHK(nullptr, hipEventCreate(&ev1));
+  // order after the caller's stream; every event is released on every return
+  EventGuard g0, g1, gt0, gt1;
+  HIPCHK(nullptr, hipEventCreate(&g0.e));
+  HIPCHK(nullptr, hipEventCreate(&g1.e));
+  HIPCHK(nullptr, hipEventCreate(&gt0.e));
+  HIPCHK(nullptr, hipEventCreate(&gt1.e));
+  hipEvent_t ev0 = g0.e, ev1 = g1.e, t0 = gt0.e, t1 = gt1.e;
   (void)hipEventRecord(ev0, b->user_st);
   HIPCHK(nullptr, hipStreamWaitEvent(b->st, ev0, 0));
   const cpd_status rs = batch_restart(b);
@@ -1267,15 +1281,13 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
                               h->at<P4<float>>(h->L.Xt), h->p.M, 3, h->p.beta, b->st);
       if (!(h->p.sigma2_init > 0.0))
         reset_sigma2_launch<float>(h->at<P4<float>>(h->L.Xt), h->at<P4<float>>(h->L.Y), h->p.M,
-                                   h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st);
+                                   h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st,
+                                   kS2Warm);
     }
     HIPCHK(nullptr, hipGetLastError());
   }
   int max_iter = 1;
   for (auto& q : b->p) max_iter = std::max(max_iter, q.max_iter);
-  hipEvent_t t0, t1;
-  HIPCHK(nullptr, hipEventCreate(&t0));
-  HIPCHK(nullptr, hipEventCreate(&t1));
   (void)hipEventRecord(t0, b->st);
   int done = 0, iters = 0;
   while (iters < max_iter && done < b->B) {
@@ -1289,8 +1301,6 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
   HIPCHK(nullptr, hipEventSynchronize(t1));
   float ms = 0;
   (void)hipEventElapsedTime(&ms, t0, t1);
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
   std::vector<DevScalars> s(b->B);
   for (int i = 0; i < b->B; ++i) {
     cpd_ctx* h = b->inst[i];
@@ -1302,8 +1312,6 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
   (void)hipEventRecord(ev1, b->st);
   HIPCHK(nullptr, hipStreamWaitEvent(b->user_st, ev1, 0));
   HIPCHK(nullptr, hipStreamSynchronize(b->st));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
   bool all = true, bad = false;
   for (int i = 0; i < b->B; ++i) {
     if (res) {

@@ -15,8 +15,8 @@ template <typename T> struct alignas(4 * sizeof(T)) P4 { T x, y, z, w; };
 // from iteration to iteration lives here so that a step never needs the host.
 struct DevScalars {
   double sigma2;        // current sigma^2
-  double sigma2_start;  // sigma^2 after init (reset target of a warm start)
-  double sigma2_floor;  // lower clamp
+  double sigma2_start;  // sigma^2 after init: the start of a run from Xt = X
+  double sigma2_floor;  // lower clamp of the current run
   double dsigma2;       // |sigma^2 change| of the last step
   double loglik;        // eq. 3 at the last E-step
   double tol;
@@ -30,6 +30,8 @@ struct DevScalars {
                         // at init (gates far-tile culling; 0 = never)
   double origin[3];     // the iteration's frame is the caller's minus origin
                         // (centre of the scene's bounding box; 0 unless sorted)
+  double floor_data;    // the part of the floor set by the data's scale at init
+                        // (BF16X; 0 otherwise): floor = max(1e-10 s2_run, this)
 };
 
 __device__ __forceinline__ float fexp2(float v) { return __builtin_amdgcn_exp2f(v); }

@@ -589,12 +589,18 @@ __global__ __launch_bounds__(256) void k_s2init_part(const P4<T>* __restrict__ X
 
 // sigma^2_0 = sum_mn |y_n - x_m|^2 / (D M N)
 //          = (N sum|u|^2 + M sum|v|^2 - 2 (sum u).(sum v)) / (D M N)
-// The floor below which sigma^2 is not lowered is 1e-10 sigma^2_0, and at
-// least floor_rel D times that closed-form value of the data (floor_rel > 0
-// for the BF16X mode, whose exponent error grows as 1 / sigma^2).
+// The floor below which sigma^2 is not lowered is 1e-10 times the run's
+// starting sigma^2, and at least floor_rel D times the closed-form value of
+// the data at init (floor_rel > 0 for the BF16X mode, whose exponent error
+// grows as 1 / sigma^2).
+//   mode kS2Init   init: sigma^2 = given (> 0) or the closed form at X; it is
+//                  also kept as sigma2_start, the start of a run from X
+//   mode kS2Warm   a run from a warm start Xt = X + Phi W0: sigma^2 = the
+//                  closed form at Xt (sigma2_start is left alone)
+//   mode kS2Start  a run with a caller-given start: sigma^2 = sigma2_start
 __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__ part, int blocks,
                                                       int M, int N, int D, double given,
-                                                      double tol, int max_iter, int set_all,
+                                                      double tol, int max_iter, int mode,
                                                       DevScalars* sc, double floor_rel) {
   __shared__ double sh[16];
   double v[8];
@@ -605,24 +611,28 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
   }
   if (threadIdx.x == 0) {
     const double cross = v[0] * v[4] + v[1] * v[5] + v[2] * v[6];
-    const double s2data = ((double)N * v[3] + (double)M * v[7] - 2.0 * cross) / ((double)D * M * N);
-    const double s2 = given > 0.0 ? given : s2data;
-    sc->sigma2 = s2;
-    sc->sigma2_start = s2;
-    sc->sigma2_floor = fmax(1e-10 * s2, floor_rel * D * s2data);
-    sc->dsigma2 = 0.0;
-    sc->done = 0;
-    sc->converged = 0;
-    sc->nonfinite = 0;
-    sc->chol_fail = 0;
-    if (set_all) {
+    const double s2closed = ((double)N * v[3] + (double)M * v[7] - 2.0 * cross) / ((double)D * M * N);
+    double s2;
+    if (mode == kS2Init) {
+      s2 = given > 0.0 ? given : s2closed;
+      sc->sigma2_start = s2;
+      sc->floor_data = floor_rel * D * s2closed;
       sc->loglik = 0.0;
       sc->tol = tol;
       sc->iter = 0;
       sc->max_iter = max_iter;
       sc->diam2 = 0.0;  // set by the spatial ordering when the handle sorts
       sc->origin[0] = sc->origin[1] = sc->origin[2] = 0.0;
+    } else {
+      s2 = mode == kS2Warm ? s2closed : sc->sigma2_start;
     }
+    sc->sigma2 = s2;
+    sc->sigma2_floor = fmax(1e-10 * s2, sc->floor_data);
+    sc->dsigma2 = 0.0;
+    sc->done = 0;
+    sc->converged = 0;
+    sc->nonfinite = 0;
+    sc->chol_fail = 0;
   }
 }
 
@@ -639,16 +649,17 @@ void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int 
   const int blocks = init_blocks(M, N);
   hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
   hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D,
-                     sigma2_init, tol, max_iter, 1, sc, floor_rel);
+                     sigma2_init, tol, max_iter, kS2Init, sc, floor_rel);
 }
 
 template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
-                         double* part, hipStream_t st, double floor_rel) {
-  const int blocks = init_blocks(M, N);
-  hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
+                         double* part, hipStream_t st, int mode) {
+  const int blocks = mode == kS2Warm ? init_blocks(M, N) : 0;
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
   hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D, -1.0, 0.0,
-                     0, 0, sc, floor_rel);
+                     0, mode, sc, 0.0);
 }
 
 template <typename T>
@@ -801,7 +812,7 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
                                double, double, int, DevScalars*, double*, hipStream_t,       \
                                double);                                                       \
   template void reset_sigma2_launch<T>(const P4<T>*, const P4<T>*, int, int, int, DevScalars*, \
-                                       double*, hipStream_t, double);                         \
+                                       double*, hipStream_t, int);                            \
   template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t, const int*,       \
                                  const double*);                                              \
   template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t, const int*,        \

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x"])
-def test_culling_is_bit_exact_and_active(lib, precision):
+def test_culling_is_bit_exact(lib, precision):
     import torch
     p = synth.surface_pair(M=6000, N=5000, seed=11, beta=2.0, lam=3.0, w=0.7, outlier_frac=0.05)
     X, Y = dev(p.X, torch.float32), dev(p.Y, torch.float32)
@@ -31,10 +31,9 @@ def test_culling_is_bit_exact_and_active(lib, precision):
                              eig_mode="topk", K=100, seed=3, tol=1e-8, max_iter=400, cull=cull)
         r.prepare()
         res = r.register()
-        kern = r.time_kernels(reps=5)  # at the converged state
-        out[cull] = (res, kern)
+        out[cull] = res
         r.close()
-    (a, ka), (b, kb) = out[False], out[True]
+    a, b = out[False], out[True]
     say("iters", a.iters, b.iters, "sigma2", a.sigma2)
     assert a.iters == b.iters and a.sigma2 == b.sigma2
     assert torch.equal(a.Xt, b.Xt) and torch.equal(a.W, b.W)
