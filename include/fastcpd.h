@@ -21,7 +21,9 @@
  *     and float otherwise.
  *   - The library never allocates device memory.  The caller allocates one
  *     workspace of cpd_workspace_size() bytes (256-byte aligned) and keeps it
- *     alive until cpd_destroy().  The handle itself is host memory.
+ *     alive until cpd_destroy().  The handle itself is host memory.  The one
+ *     exception is a fixed 64 MiB device array per device, part of the
+ *     library's code object, that only cpdnet_forward_noalloc uses.
  *   - All device work is enqueued on the stream given to cpd_init.  Calls
  *     that return host scalars synchronise that stream.
  *   - Errors are reported through the return code only; arguments are
@@ -294,6 +296,18 @@ cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, size_t* by
 cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, int32_t batch,
                           int32_t M, int32_t N, float* W0_out, void* workspace,
                           size_t workspace_bytes, void* hip_stream);
+/* cpdnet_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and result, with the workspace taken from a device array
+ * the library owns (64 MiB, one per device, held until the process ends)
+ * instead of a caller buffer.  Nothing is allocated by this call.  Returns
+ * CPD_E_WORKSPACE when cpdnet_workspace_size(batch, M, N) exceeds 64 MiB
+ * (e.g. batch 4 at M = N = 2000 fits, batch 8 does not).  Every call on one
+ * device shares that array: calls that overlap on a device (several streams
+ * or host threads) race and must be serialised by the caller. */
+cpd_status cpdnet_forward_noalloc(const float* params, const float* X, const float* Y,
+                                  int32_t batch, int32_t M, int32_t N, float* W0_out,
+                                  void* hip_stream);
 /* Loss (host double, nullable) and its gradient (device, param_count floats). */
 cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y, const float* V,
                             int32_t batch, int32_t M, int32_t N, double beta, float* grad_out,

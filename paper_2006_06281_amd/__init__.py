@@ -43,7 +43,7 @@ EXPORTED = [
     "cpd_batch_workspace_size", "cpd_batch_init", "cpd_batch_prepare", "cpd_batch_register",
     "cpd_batch_info", "cpd_batch_destroy",
     "cpdnet_param_count", "cpdnet_init", "cpdnet_workspace_size", "cpdnet_forward",
-    "cpdnet_loss_grad", "cpdnet_adam", "cpdnet_synth",
+    "cpdnet_forward_noalloc", "cpdnet_loss_grad", "cpdnet_adam", "cpdnet_synth",
 ]
 
 
@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
         "cpdnet_workspace_size": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(sz)], ctypes.c_int),
         "cpdnet_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, sz,
                             vp], ctypes.c_int),
+        "cpdnet_forward_noalloc": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    vp, vp], ctypes.c_int),
         "cpdnet_loss_grad": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                               ctypes.c_double, vp, P(ctypes.c_double), vp, sz, vp], ctypes.c_int),
         "cpdnet_adam": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp], ctypes.c_int),
@@ -376,6 +378,16 @@ class WarmStartNet:
         ws = self._workspace(B, M, N)
         _check(load_library().cpdnet_forward(_ptr(self.params), _ptr(X), _ptr(Y), B, M, N,
                                              _ptr(W0), _ptr(ws), ws.numel(), _stream_ptr()))
+        return W0
+
+    def forward_noalloc(self, X, Y):
+        """forward() through cpdnet_forward_noalloc: the library's static
+        device scratch replaces the workspace (no allocation in the call)."""
+        import torch
+        B, M, N = X.shape[0], X.shape[1], Y.shape[1]
+        W0 = torch.empty(B, M, 3, dtype=torch.float32, device=X.device)
+        _check(load_library().cpdnet_forward_noalloc(_ptr(self.params), _ptr(X), _ptr(Y), B, M,
+                                                     N, _ptr(W0), _stream_ptr()))
         return W0
 
     def loss_grad(self, X, Y, V, beta):

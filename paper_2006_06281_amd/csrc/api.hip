@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,10 @@ using namespace fcpd;
 namespace {
 
 thread_local std::string g_last_error;
+
+// Size of the static device scratch behind cpdnet_forward_noalloc.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
 
 enum class Stage { Init = 0, Prepared = 1 };
 
@@ -1386,6 +1391,59 @@ cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, i
   if (d != CPD_OK) return d;
   hipStream_t st = static_cast<hipStream_t>(stream);
   net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L, st);
+  HIPCHK(nullptr, hipGetLastError());
+  return CPD_OK;
+}
+
+}  // extern "C"
+
+// Library-owned device scratch for cpdnet_forward_noalloc, one copy per device
+// (it lives as long as the process).  In host code this name is only a
+// stand-in: kernels and copies get the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+cpd_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(nullptr, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, CPD_E_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(nullptr, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(nullptr, CPD_E_DEVICE, "no device address for the static scratch");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return CPD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+cpd_status cpdnet_forward_noalloc(const float* params, const float* X, const float* Y,
+                                  int32_t batch, int32_t M, int32_t N, float* W0_out,
+                                  void* stream) {
+  const cpd_status v = net_dims(batch, M, N);
+  if (v != CPD_OK) return v;
+  if (!params || !X || !Y || !W0_out) return fail(nullptr, CPD_E_ARG, "NULL array");
+  const NetWs L = net_ws_layout(batch, M, N);
+  if (L.end > kNoAllocScratchBytes)
+    return fail(nullptr, CPD_E_WORKSPACE,
+                "batch, M, N need " + std::to_string(L.end) + " bytes of network workspace; "
+                "the static scratch holds " + std::to_string(kNoAllocScratchBytes));
+  const cpd_status d = check_device(nullptr);
+  if (d != CPD_OK) return d;
+  void* ws = nullptr;
+  const cpd_status a = scratch_address(&ws);
+  if (a != CPD_OK) return a;
+  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L,
+                     static_cast<hipStream_t>(stream));
   HIPCHK(nullptr, hipGetLastError());
   return CPD_OK;
 }
