@@ -207,22 +207,16 @@ def cpd_mstep(X, P1, PY, Phi, lmbda, sigma2):
 
 def cpdl_mstep(X, P1, PY, U, lam, lmbda, sigma2):
     """CPD-L: eq. 21 with Phi replaced by its rank-K approximation
-    Phi~ = U diag(lam) U^T (eq. 19), solved with the matrix inversion lemma.
-
-    With A = lmbda sigma^2 d(P1)^-1 and t = A^-1 (d(P1)^-1 PY - X):
-      (A + U L U^T)^-1 = A^-1 - A^-1 U (L^-1 + U^T A^-1 U)^-1 U^T A^-1,
-    so W = t - A^-1 U z with S z = U^T t, S = L^-1 + U^T A^-1 U (K x K), and
-    Phi~ W = U L (U^T t - (S - L^-1) z) = U z.  Eigenpairs with lam <= 0
-    carry no part of Phi~ and are dropped.  Returns W and Xt = X + U z."""
+    Phi~ = U diag(lam) U^T (eq. 19, lam clamped at 0), solved as written:
+    W = (Phi~ + lmbda sigma^2 d(P1)^-1)^-1 (d(P1)^-1 PY - X) by Cholesky,
+    Xt = X + Phi~ W.  Phi~ is formed as an M x M matrix, so this is for the
+    sizes a dense factorisation allows."""
     p1 = np.maximum(P1, P1_FLOOR)
-    keep = lam > 0
-    U, lam = U[:, keep], lam[keep]
-    ainv = p1 / (lmbda * sigma2)                  # diagonal of A^-1
-    t = ainv[:, None] * (PY / p1[:, None] - X)
-    S = np.diag(1.0 / lam) + U.T @ (ainv[:, None] * U)
-    z = sla.cho_solve(sla.cho_factor(S, lower=True), U.T @ t)
-    Uz = U @ z
-    return t - ainv[:, None] * Uz, X + Uz
+    Phit = (U * np.maximum(lam, 0.0)) @ U.T
+    A = Phit + lmbda * sigma2 * np.diag(1.0 / p1)
+    rhs = PY / p1[:, None] - X
+    W = sla.cho_solve(sla.cho_factor(A, lower=True), rhs)
+    return W, X + Phit @ W
 
 
 def nearest(A, B):

@@ -9,7 +9,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
                            range finder with subspace iteration and a
                            Rayleigh-Ritz step (Halko, Martinsson & Tropp,
                            SIAM Review 53(2), 2011).  The Gaussian test matrix
-                           Omega is an input, so the caller controls the draw.
+                           Omega is an input (synth.gaussian_matrix draws it),
+                           so the same draw can feed the GPU solver.
 """
 from __future__ import annotations
 
@@ -68,7 +69,3 @@ def eig_topk(X: np.ndarray, beta: float, K: int, Omega: np.ndarray,
     order = np.argsort(theta)[::-1][:K]
     return np.ascontiguousarray(Q @ S[:, order]), theta[order]
 
-
-def gaussian_test_matrix(M: int, cols: int, seed: int) -> np.ndarray:
-    """A seeded N(0,1) M x cols matrix (numpy PCG64) for eig_topk."""
-    return np.random.default_rng(seed).standard_normal((M, cols))

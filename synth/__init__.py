@@ -33,7 +33,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["PointPair", "sphere_pair", "surface_pair", "batch_pairs", "affine_pair",
-           "coef_std", "workload"]
+           "coef_std", "workload", "gaussian_matrix"]
 
 
 @dataclass
@@ -225,6 +225,12 @@ def batch_pairs(B=256, m_range=(500, 8000), seed0=1000, w=0.1,
         out.append(surface_pair(M, N, seed=seed0 + i, beta=beta, lam=lam, w=w,
                                 outlier_frac=outlier_frac))
     return out
+
+
+def gaussian_matrix(rows: int, cols: int, seed: int) -> np.ndarray:
+    """A seeded N(0, 1) rows x cols float64 matrix (numpy PCG64): the test
+    matrix of a randomized eigensolver, or random probe vectors."""
+    return np.random.default_rng(seed).standard_normal((rows, cols))
 
 
 def workload(name: str, **kw) -> PointPair:

@@ -92,7 +92,7 @@ def test_bf16x_registration(lib):
                            outlier_frac=0.2, noise=0.02)
     X, Y = _f32(p.X), _f32(p.Y)
     K, over = 200, 20
-    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=4)
+    Om = synth.gaussian_matrix(p.M, K + over, seed=4)
     Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=2)
     ref = cpd64.register(X, Y, p.beta, p.lam, p.w, "fast", eig=(Uo, lo), iters=20)
     r = lib.Registration(dev(X, torch.float32), dev(Y, torch.float32), precision="bf16x",

@@ -60,7 +60,7 @@ def test_randomized_topk(lib, given_omega):
     p = synth.surface_pair(M=3000, N=3000, seed=3, beta=1.5, lam=2.0, w=0.2)
     X = _f32(p.X)
     K, over, q = 100, 20, 2
-    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=11)
+    Om = synth.gaussian_matrix(p.M, K + over, seed=11)
     Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
     r = lib.Registration(dev(X, torch.float32), dev(_f32(p.Y), torch.float32), precision="fp32",
                          beta=p.beta, lam=p.lam, w=p.w, eig_mode="topk", K=K, oversample=over,
@@ -93,7 +93,7 @@ def test_randomized_topk_wide_tiles(lib, M, K, over, precision):
     p = synth.surface_pair(M=M, N=M, seed=8, beta=1.5, lam=2.0, w=0.2)
     X = _f32(p.X)
     q = 2
-    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=12)
+    Om = synth.gaussian_matrix(p.M, K + over, seed=12)
     Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
     dt = torch.float64 if precision == "fp64" else torch.float32
     r = lib.Registration(dev(X, dt), dev(_f32(p.Y), dt), precision=precision, beta=p.beta,
@@ -119,7 +119,7 @@ def test_randomized_topk_tiny(lib):
     p = synth.sphere_pair(M=40, N=45, seed=21)
     X = _f32(p.X)
     K, over, q = 8, 4, 2
-    Om = eig64.gaussian_test_matrix(p.M, K + over, seed=3)
+    Om = synth.gaussian_matrix(p.M, K + over, seed=3)
     Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
     r = lib.Registration(dev(X, torch.float32), dev(_f32(p.Y), torch.float32), precision="fp32",
                          beta=p.beta, lam=p.lam, w=p.w, eig_mode="topk", K=K, oversample=over,

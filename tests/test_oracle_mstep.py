@@ -118,7 +118,7 @@ def test_topk_matches_eigh_and_eckart_young():
     Phi = eig64.gram(X, 2.0)
     U, lam = eig64.eig_full(Phi)
     K = 40
-    Om = eig64.gaussian_test_matrix(len(X), K + 10, seed=3)
+    Om = synth.gaussian_matrix(len(X), K + 10, seed=3)
     Uk, lk = eig64.eig_topk(X, 2.0, K, Om, power_iters=2)
     np.testing.assert_allclose(lk, lam[:K], rtol=1e-10, atol=1e-12 * lam[0])
     err = np.linalg.eigvalsh(Phi - Uk @ np.diag(lk) @ Uk.T)
@@ -211,25 +211,64 @@ def test_rmse_definition():
     assert cpd64.rmse(A, B) == pytest.approx(np.sqrt((9 + 16) / 2))
 
 
+def test_rel_rms_by_hand():
+    # B's rows have mean (1, 0, 0); centred, |B - mean|_F^2 = 1 + 1 = 2.
+    # A differs from B by 1 in one entry: rel_rms = 1 / sqrt(2)
+    B = np.array([[0.0, 0, 0], [2.0, 0, 0]])
+    A = np.array([[0.0, 1, 0], [2.0, 0, 0]])
+    assert cpd64.rel_rms(A, B) == pytest.approx(1.0 / np.sqrt(2.0), rel=1e-15)
+    # a common translation of both sets changes nothing (centred denominator)
+    t = np.array([100.0, -50.0, 7.0])
+    assert cpd64.rel_rms(A + t, B + t) == pytest.approx(1.0 / np.sqrt(2.0), rel=1e-12)
+    # errors of 3 and 4 over a set with centred norm 10 (rows -5, +5, 0 in x)
+    B = np.array([[-5.0, 0, 0], [5.0, 0, 0], [0.0, 0, 0]])
+    A = B + np.array([[0.0, 3, 0], [0.0, 0, 4], [0.0, 0, 0]])
+    assert cpd64.rel_rms(A, B) == pytest.approx(5.0 / np.sqrt(50.0), rel=1e-15)
+    # it is not symmetric: the denominator is the second argument's spread
+    assert cpd64.rel_rms(B, A) != pytest.approx(cpd64.rel_rms(A, B))
+    # one point: the uncentred norm
+    assert cpd64.rel_rms(np.array([[3.0, 4, 0]]), np.array([[0.0, 0, 5.0]])) == \
+        pytest.approx(np.sqrt(9 + 16 + 25) / 5.0)
+    assert cpd64.rel_rms(B, B) == 0.0
+
+
 def _low_rank(Phi, K):
     lam, U = np.linalg.eigh(Phi)
     o = np.argsort(lam)[::-1][:K]
     return U[:, o], lam[o]
 
 
-def test_cpdl_equals_the_dense_solve_with_the_rank_k_gram():
-    # CPD-L: eq. 21 with Phi~ = U L U^T (eq. 19); the K x K inversion-lemma
-    # form must equal an M x M solve with Phi~ formed explicitly
+def test_cpdl_equals_the_matrix_inversion_lemma_form():
+    # CPD-L: eq. 21 with Phi~ = U L U^T (eq. 19).  The oracle factorises the
+    # M x M matrix; the same W follows from the Sherman-Morrison-Woodbury
+    # identity through a K x K system, an independent route:
+    #   A = lmbda s2 d(P1)^-1,  t = A^-1 (d(P1)^-1 PY - X),
+    #   (A + U L U^T)^-1 = A^-1 - A^-1 U (L^-1 + U^T A^-1 U)^-1 U^T A^-1
     X, Y, es, Phi = _problem(M=50, N=60, beta=1.2)
     s2, lmbda = 0.25, 2.0
     for K in (5, 17, 40):
         U, lam = _low_rank(Phi, K)
-        Pt = (U * lam) @ U.T
-        p1 = es.P1
-        Wd = np.linalg.solve(Pt + lmbda * s2 * np.diag(1.0 / p1), es.PY / p1[:, None] - X)
+        ainv = es.P1 / (lmbda * s2)
+        t = ainv[:, None] * (es.PY / es.P1[:, None] - X)
+        S = np.diag(1.0 / lam) + U.T @ (ainv[:, None] * U)
+        z = np.linalg.solve(S, U.T @ t)
+        Ww = t - ainv[:, None] * (U @ z)
         W, Xt = cpd64.cpdl_mstep(X, es.P1, es.PY, U, lam, lmbda, s2)
-        np.testing.assert_allclose(W, Wd, rtol=1e-8, atol=1e-10 * np.abs(Wd).max())
-        np.testing.assert_allclose(Xt, X + Pt @ Wd, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(W, Ww, rtol=1e-8, atol=1e-10 * np.abs(Ww).max())
+        # and Phi~ W collapses to U z (L (U^T t - (S - L^-1) z) = z)
+        np.testing.assert_allclose(Xt, X + U @ z, rtol=1e-10, atol=1e-12)
+
+
+def test_cpdl_drops_pairs_with_negative_eigenvalues():
+    # lam <= 0 carries no part of Phi~ (clamped at 0): adding such a pair
+    # leaves the result unchanged
+    X, Y, es, Phi = _problem(M=30, N=35, beta=1.0)
+    U, lam = _low_rank(Phi, 8)
+    W, Xt = cpd64.cpdl_mstep(X, es.P1, es.PY, U[:, :7], lam[:7], 2.0, 0.3)
+    lam2 = lam.copy()
+    lam2[7] = -0.5
+    W2, Xt2 = cpd64.cpdl_mstep(X, es.P1, es.PY, U, lam2, 2.0, 0.3)
+    np.testing.assert_allclose(Xt2, Xt, rtol=1e-12, atol=1e-13)
 
 
 def test_cpdl_at_full_rank_is_the_original_mstep():
