@@ -358,6 +358,52 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
             "run_s_w0": t_run0, "run_s_net": t_runw}
 
 
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense bf16 matrix rate of the MI355X
+
+
+def net_gemm_flop(M, N, H=256):
+    """Algorithmic matrix-core work of one warm-start training pair: every
+    256 x 256 layer (three encoder layers on M + N points, the head's f Wa on
+    M points) runs once forward and twice backward (input gradient and
+    weight gradient), 2 FLOP per multiply-add."""
+    rows = 3 * (M + N) + M
+    return 3 * rows * 2 * H * H
+
+
+def warm_train_leg(fc, torch, steps, warmup, M=2000, batch=32, beta=2.0):
+    """Training throughput of the warm-start network alone: `warmup` then
+    `steps` Adam steps of `batch` device-drawn pairs at M = N = 2000 (pair
+    generation, forward, loss, backward, Adam), timed with HIP events on the
+    current stream; the GEMM roofline is the algorithmic matrix-core FLOP of
+    a step over the step time."""
+    coef = 0.3 * np.sqrt(500.0 / M)
+    net = fc.WarmStartNet(seed=1)
+    st = torch.cuda.current_stream()
+
+    def step(k):
+        X, Y, V = fc.synth_pairs(batch, M, beta=beta, coef=coef, seed0=10_000_000 + batch * k)
+        net.train_step(X, Y, V, beta=beta, lr=1e-3, want_loss=False)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(steps):
+        step(warmup + k)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flop = net_gemm_flop(M, M) * batch
+    ach = flop / (ms * 1e-3) / 1e12
+    return {"ms_per_step": ms, "pairs_per_s": batch / (ms * 1e-3), "batch": batch, "M": M,
+            "N": M, "gemm_flop_per_step": flop,
+            "roofline": {"bound": "mfma", "kernel": "whole training step (all kernels)",
+                         "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / PEAK_BF16_MFMA_TFLOPS, "traffic": None,
+                         "flop_model": "3 x (3 (M + N) + M) x 2 x 256^2 per pair"}}
+
+
 def table4_leg(fc, torch, sizes=(4000, 8000, 12000, 16000, 20000, 24000), iters=50):
     """The paper's scaling protocol (Section IV-B, Table IV) on synthetic
     stand-ins: scene = a random spherical-harmonic surface of M points, model
@@ -417,7 +463,8 @@ def main():
                     help="run two 256 MiB device-to-device copies first (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--workload", default="surface50k",
-                    choices=["surface50k", "batch256", "warm2000", "table4", "converge07"],
+                    choices=["surface50k", "batch256", "warm2000", "warmtrain", "table4",
+                             "converge07"],
                     help="batch256 / warm2000 / table4 / converge07 (surface50k at the "
                          "paper's w = 0.7, eigen-prep and one run to tolerance): that leg "
                          "alone, one JSON line of its own")
@@ -465,6 +512,19 @@ def main():
                           "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 net, f32 EM",
                           "data": "synthetic", "config": {"workload": b["workload"]},
                           "warm_start": b}), flush=True)
+        return
+
+    if args.workload == "warmtrain":
+        b = warm_train_leg(fc, torch, args.steps, args.warmup)
+        log(f"warmtrain: {b}")
+        print(json.dumps({"metric": "warm-start network training pairs/s",
+                          "value": b["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+                          "dtype": "bf16", "data": "synthetic",
+                          "config": {"workload": "warm2000 training: batch 32 pairs, M=N=2000, "
+                                                 "sphere recipe drawn on the device"},
+                          "roofline": b["roofline"], "train": b}), flush=True)
         return
 
     if args.workload == "converge07":

@@ -284,35 +284,46 @@ cpd_status cpd_batch_destroy(cpd_batch hb);
  * a shared per-point MLP on [p, flag] (4 -> 256 -> 256 -> 256 -> 256, ReLU),
  * max-pooled per set into g_X and g_Y, and a head per model point
  * z = relu(f(x_m) Wa + g_X Wb + g_Y Wc + bh), W0_m = z Wo + bo.  The 256 x 256
- * products run on the matrix cores in bf16 with fp32 accumulation; the
- * parameters are one fp32 array (order W1 b1 W2 b2 W3 b3 W4 b4 Wa Wb Wc bh Wo
- * bo, every W as [fan_in][fan_out]).  Training minimises the displacement
- * error |Phi W0 - V*|^2 / M averaged over a batch (Phi formed on the fly).
- * All arrays are device float arrays; a batch packs `batch` instances of M
- * model and N scene points each, row-major x 3. */
+ * products run on the matrix cores with fp32 accumulation; `precision`
+ * selects how activations, inter-layer gradients and the 256 x 256 weight
+ * copies are stored: CPDNET_BF16 (the training and inference mode) or
+ * CPDNET_FP32 (the same kernels in fp32, a reference for the bf16 mode).  The
+ * parameters are one fp32 array (order W1 b1 W2 b2 W3 b3 W4 b4 Wa Wb Wc bh
+ * Wo bo, every W as [fan_in][fan_out]).  Training minimises the displacement
+ * error |Phi W0 - V*|^2 / M averaged over a batch (Phi formed on the fly in
+ * fp32).  All arrays are device float arrays; a batch packs `batch`
+ * instances of M model and N scene points each, row-major x 3.  The
+ * workspace (256-byte aligned) is sized by cpdnet_workspace_size for the
+ * same (batch, M, N, precision). */
+#define CPDNET_BF16 0
+#define CPDNET_FP32 1
+
 cpd_status cpdnet_param_count(size_t* count);
 cpd_status cpdnet_init(float* params, uint64_t seed, float out_scale, void* hip_stream);
-cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, size_t* bytes);
+cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, int32_t precision,
+                                 size_t* bytes);
 cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, int32_t batch,
-                          int32_t M, int32_t N, float* W0_out, void* workspace,
-                          size_t workspace_bytes, void* hip_stream);
+                          int32_t M, int32_t N, int32_t precision, float* W0_out,
+                          void* workspace, size_t workspace_bytes, void* hip_stream);
 /* cpdnet_forward for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same kernels and result, with the workspace taken from a device array
  * the library owns (64 MiB, one per device, held until the process ends)
  * instead of a caller buffer.  Nothing is allocated by this call.  Returns
- * CPD_E_WORKSPACE when cpdnet_workspace_size(batch, M, N) exceeds 64 MiB
- * (e.g. batch 4 at M = N = 2000 fits, batch 8 does not).  Every call on one
- * device shares that array: calls that overlap on a device (several streams
- * or host threads) race and must be serialised by the caller. */
+ * CPD_E_WORKSPACE when cpdnet_workspace_size(batch, M, N, precision) exceeds
+ * 64 MiB (e.g. bf16 with batch 4 at M = N = 2000 fits, batch 8 does not).
+ * Every call on one device shares that array: calls that overlap on a device
+ * (several streams or host threads) race and must be serialised by the
+ * caller. */
 cpd_status cpdnet_forward_noalloc(const float* params, const float* X, const float* Y,
-                                  int32_t batch, int32_t M, int32_t N, float* W0_out,
-                                  void* hip_stream);
-/* Loss (host double, nullable) and its gradient (device, param_count floats). */
+                                  int32_t batch, int32_t M, int32_t N, int32_t precision,
+                                  float* W0_out, void* hip_stream);
+/* Loss (host double, nullable; non-NULL waits for the stream) and its
+ * gradient (device, param_count floats). */
 cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y, const float* V,
-                            int32_t batch, int32_t M, int32_t N, double beta, float* grad_out,
-                            double* loss_out, void* workspace, size_t workspace_bytes,
-                            void* hip_stream);
+                            int32_t batch, int32_t M, int32_t N, int32_t precision, double beta,
+                            float* grad_out, double* loss_out, void* workspace,
+                            size_t workspace_bytes, void* hip_stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the fp32 master; m, v
  * are param_count floats each; step counts from 1. */
 cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int32_t step,

@@ -28,6 +28,8 @@ CPD_METHOD_ORIGINAL, CPD_METHOD_FAST, CPD_METHOD_ORIGINAL_LOWRANK = 0, 1, 2
 CPD_PREC_FP64, CPD_PREC_FP32, CPD_PREC_BF16X = 0, 1, 2
 CPD_EIG_FULL, CPD_EIG_TOPK, CPD_EIG_IMPORT = 0, 1, 2
 CPD_FLAG_NO_SORT, CPD_FLAG_NO_CULL = 1, 2
+CPDNET_BF16, CPDNET_FP32 = 0, 1
+NET_PRECISIONS = {"bf16": CPDNET_BF16, "fp32": CPDNET_FP32}
 
 METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST,
            "cpdl": CPD_METHOD_ORIGINAL_LOWRANK}
@@ -117,13 +119,15 @@ def load_library(path: str = LIB_PATH):
         "cpd_batch_destroy": ([vp], ctypes.c_int),
         "cpdnet_param_count": ([P(sz)], ctypes.c_int),
         "cpdnet_init": ([vp, ctypes.c_uint64, ctypes.c_float, vp], ctypes.c_int),
-        "cpdnet_workspace_size": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(sz)], ctypes.c_int),
-        "cpdnet_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, sz,
-                            vp], ctypes.c_int),
+        "cpdnet_workspace_size": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   P(sz)], ctypes.c_int),
+        "cpdnet_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int32, vp, vp, sz, vp], ctypes.c_int),
         "cpdnet_forward_noalloc": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                    vp, vp], ctypes.c_int),
+                                    ctypes.c_int32, vp, vp], ctypes.c_int),
         "cpdnet_loss_grad": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                              ctypes.c_double, vp, P(ctypes.c_double), vp, sz, vp], ctypes.c_int),
+                              ctypes.c_int32, ctypes.c_double, vp, P(ctypes.c_double), vp, sz,
+                              vp], ctypes.c_int),
         "cpdnet_adam": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp], ctypes.c_int),
         "cpdnet_synth": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp],
@@ -342,10 +346,12 @@ class BatchRegistration:
 # ------------------------------------------------------------ warm start
 class WarmStartNet:
     """The warm-start point-set network: fp32 master parameters, Adam state
-    and a workspace sized for (batch, M, N)."""
+    and a workspace sized for (batch, M, N).  precision "bf16" (default) or
+    "fp32" selects the storage of activations and weight copies."""
 
-    def __init__(self, seed=0, out_scale=1e-3, device="cuda"):
+    def __init__(self, seed=0, out_scale=1e-3, device="cuda", precision="bf16"):
         import torch
+        self.precision = NET_PRECISIONS[precision]
         n = ctypes.c_size_t(0)
         _check(load_library().cpdnet_param_count(ctypes.byref(n)))
         self.count = n.value
@@ -362,10 +368,11 @@ class WarmStartNet:
 
     def _workspace(self, batch, M, N):
         import torch
-        key = (batch, M, N)
+        key = (batch, M, N, self.precision)
         if self._ws_key != key:
             n = ctypes.c_size_t(0)
-            _check(load_library().cpdnet_workspace_size(batch, M, N, ctypes.byref(n)))
+            _check(load_library().cpdnet_workspace_size(batch, M, N, self.precision,
+                                                        ctypes.byref(n)))
             self._ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=self.device)
             self._ws_key = key
         return self._ws
@@ -377,7 +384,8 @@ class WarmStartNet:
         W0 = torch.empty(B, M, 3, dtype=torch.float32, device=X.device)
         ws = self._workspace(B, M, N)
         _check(load_library().cpdnet_forward(_ptr(self.params), _ptr(X), _ptr(Y), B, M, N,
-                                             _ptr(W0), _ptr(ws), ws.numel(), _stream_ptr()))
+                                             self.precision, _ptr(W0), _ptr(ws), ws.numel(),
+                                             _stream_ptr()))
         return W0
 
     def forward_noalloc(self, X, Y):
@@ -387,21 +395,24 @@ class WarmStartNet:
         B, M, N = X.shape[0], X.shape[1], Y.shape[1]
         W0 = torch.empty(B, M, 3, dtype=torch.float32, device=X.device)
         _check(load_library().cpdnet_forward_noalloc(_ptr(self.params), _ptr(X), _ptr(Y), B, M,
-                                                     N, _ptr(W0), _stream_ptr()))
+                                                     N, self.precision, _ptr(W0),
+                                                     _stream_ptr()))
         return W0
 
-    def loss_grad(self, X, Y, V, beta):
+    def loss_grad(self, X, Y, V, beta, want_loss=True):
+        """Gradient into self.grad; the loss (a host scalar, which waits for
+        the stream) when want_loss, else None."""
         B, M, N = X.shape[0], X.shape[1], Y.shape[1]
         ws = self._workspace(B, M, N)
         loss = ctypes.c_double(0)
         _check(load_library().cpdnet_loss_grad(_ptr(self.params), _ptr(X), _ptr(Y), _ptr(V), B,
-                                               M, N, float(beta), _ptr(self.grad),
-                                               ctypes.byref(loss), _ptr(ws), ws.numel(),
-                                               _stream_ptr()))
-        return loss.value
+                                               M, N, self.precision, float(beta), _ptr(self.grad),
+                                               ctypes.byref(loss) if want_loss else None,
+                                               _ptr(ws), ws.numel(), _stream_ptr()))
+        return loss.value if want_loss else None
 
-    def train_step(self, X, Y, V, beta, lr=1e-3):
-        loss = self.loss_grad(X, Y, V, beta)
+    def train_step(self, X, Y, V, beta, lr=1e-3, want_loss=True):
+        loss = self.loss_grad(X, Y, V, beta, want_loss)
         self.step_no += 1
         _check(load_library().cpdnet_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v),
                                           _ptr(self.grad), self.step_no, float(lr),

@@ -1364,33 +1364,36 @@ cpd_status cpdnet_init(float* params, uint64_t seed, float out_scale, void* stre
   return CPD_OK;
 }
 
-static cpd_status net_dims(int32_t batch, int32_t M, int32_t N) {
+static cpd_status net_dims(int32_t batch, int32_t M, int32_t N, int32_t precision) {
   if (batch < 1 || M < 1 || N < 1 || (int64_t)batch * std::max(M, N) > (1 << 24))
     return fail(nullptr, CPD_E_ARG, "batch, M, N must be >= 1 with batch * max(M, N) <= 2^24");
+  if (precision != CPDNET_BF16 && precision != CPDNET_FP32)
+    return fail(nullptr, CPD_E_ARG, "network precision must be CPDNET_BF16 or CPDNET_FP32");
   return CPD_OK;
 }
 
-cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, size_t* bytes) {
+cpd_status cpdnet_workspace_size(int32_t batch, int32_t M, int32_t N, int32_t precision,
+                                 size_t* bytes) {
   if (!bytes) return fail(nullptr, CPD_E_ARG, "bytes is NULL");
-  const cpd_status v = net_dims(batch, M, N);
+  const cpd_status v = net_dims(batch, M, N, precision);
   if (v != CPD_OK) return v;
-  *bytes = net_ws_layout(batch, M, N).end;
+  *bytes = net_ws_layout(batch, M, N, precision).end;
   return CPD_OK;
 }
 
 cpd_status cpdnet_forward(const float* params, const float* X, const float* Y, int32_t batch,
-                          int32_t M, int32_t N, float* W0_out, void* ws, size_t bytes,
-                          void* stream) {
-  const cpd_status v = net_dims(batch, M, N);
+                          int32_t M, int32_t N, int32_t precision, float* W0_out, void* ws,
+                          size_t bytes, void* stream) {
+  const cpd_status v = net_dims(batch, M, N, precision);
   if (v != CPD_OK) return v;
   if (!params || !X || !Y || !W0_out) return fail(nullptr, CPD_E_ARG, "NULL array");
-  const NetWs L = net_ws_layout(batch, M, N);
+  const NetWs L = net_ws_layout(batch, M, N, precision);
   if (!ws || bytes < L.end || reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(nullptr, CPD_E_WORKSPACE, "network workspace missing, misaligned or too small");
   const cpd_status d = check_device(nullptr);
   if (d != CPD_OK) return d;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L, st);
+  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L, precision, st);
   HIPCHK(nullptr, hipGetLastError());
   return CPD_OK;
 }
@@ -1427,12 +1430,12 @@ cpd_status scratch_address(void** out) {
 extern "C" {
 
 cpd_status cpdnet_forward_noalloc(const float* params, const float* X, const float* Y,
-                                  int32_t batch, int32_t M, int32_t N, float* W0_out,
-                                  void* stream) {
-  const cpd_status v = net_dims(batch, M, N);
+                                  int32_t batch, int32_t M, int32_t N, int32_t precision,
+                                  float* W0_out, void* stream) {
+  const cpd_status v = net_dims(batch, M, N, precision);
   if (v != CPD_OK) return v;
   if (!params || !X || !Y || !W0_out) return fail(nullptr, CPD_E_ARG, "NULL array");
-  const NetWs L = net_ws_layout(batch, M, N);
+  const NetWs L = net_ws_layout(batch, M, N, precision);
   if (L.end > kNoAllocScratchBytes)
     return fail(nullptr, CPD_E_WORKSPACE,
                 "batch, M, N need " + std::to_string(L.end) + " bytes of network workspace; "
@@ -1442,20 +1445,21 @@ cpd_status cpdnet_forward_noalloc(const float* params, const float* X, const flo
   void* ws = nullptr;
   const cpd_status a = scratch_address(&ws);
   if (a != CPD_OK) return a;
-  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L,
+  net_forward_launch(params, X, Y, batch, M, N, W0_out, static_cast<char*>(ws), L, precision,
                      static_cast<hipStream_t>(stream));
   HIPCHK(nullptr, hipGetLastError());
   return CPD_OK;
 }
 
 cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y, const float* V,
-                            int32_t batch, int32_t M, int32_t N, double beta, float* grad_out,
-                            double* loss_out, void* ws, size_t bytes, void* stream) {
-  const cpd_status v = net_dims(batch, M, N);
+                            int32_t batch, int32_t M, int32_t N, int32_t precision, double beta,
+                            float* grad_out, double* loss_out, void* ws, size_t bytes,
+                            void* stream) {
+  const cpd_status v = net_dims(batch, M, N, precision);
   if (v != CPD_OK) return v;
   if (!params || !X || !Y || !V || !grad_out) return fail(nullptr, CPD_E_ARG, "NULL array");
   if (!(beta > 0.0)) return fail(nullptr, CPD_E_ARG, "beta must be > 0");
-  const NetWs L = net_ws_layout(batch, M, N);
+  const NetWs L = net_ws_layout(batch, M, N, precision);
   if (!ws || bytes < L.end || reinterpret_cast<uintptr_t>(ws) % 256)
     return fail(nullptr, CPD_E_WORKSPACE, "network workspace missing, misaligned or too small");
   const cpd_status d = check_device(nullptr);
@@ -1463,7 +1467,7 @@ cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y,
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   double* ldev = reinterpret_cast<double*>(w + L.loss);
-  net_loss_grad_launch(params, X, Y, V, batch, M, N, beta, grad_out, ldev, w, L, st);
+  net_loss_grad_launch(params, X, Y, V, batch, M, N, beta, grad_out, ldev, w, L, precision, st);
   HIPCHK(nullptr, hipGetLastError());
   if (loss_out) {
     HIPCHK(nullptr, hipMemcpyAsync(loss_out, ldev, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1484,7 +1488,7 @@ cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int
 cpd_status cpdnet_synth(float* X, float* Y, float* V, float* Wsc, int32_t batch, int32_t M,
                         double beta, double coef, double jitter, double outlier_frac,
                         uint64_t seed0, void* stream) {
-  const cpd_status vd = net_dims(batch, M, M);
+  const cpd_status vd = net_dims(batch, M, M, CPDNET_BF16);
   if (vd != CPD_OK) return vd;
   if (!X || !Y || !V || !Wsc || !(beta > 0.0) || !(outlier_frac >= 0.0 && outlier_frac <= 1.0))
     return fail(nullptr, CPD_E_ARG, "bad synth arguments");

@@ -1,17 +1,19 @@
 // Learned warm start: a point-set network that predicts the initial
 // Gaussian-RBF coefficients W0 of the transformation f(X) = X + Phi W
-// (Section III, eq. 9-11), trained and run with bf16 matrix-core kernels.
+// (Section III, eq. 9-11), trained and run with matrix-core kernels.
 //
 //   encoder  shared per-point MLP on e = [p, flag] (flag 0 model, 1 scene):
 //            h1 = relu(e W1 + b1) (4 -> 256, VALU), h2..f = relu(h W + b)
-//            (256 -> 256, v_mfma_f32_16x16x32_bf16, fp32 accumulate, bf16 out)
+//            (256 -> 256 on the matrix cores, fp32 accumulate)
 //   pool     g_X = max over model points, g_Y = max over scene points
 //   head     z = relu(f(x_m) Wa + g_X Wb + g_Y Wc + bh), W0_m = z Wo + bo
 //   loss     |Phi W0 - V*|^2 / M per instance (Phi formed on the fly, fp32),
 //            dL/dW0 = 2 Phi (Phi W0 - V*) / M; mean over the batch.
-// Parameters: one fp32 master array in a fixed order (W stored [fan_in][fan_out]),
-// bf16 copies of the 256 x 256 matrices in both orientations for the
-// forward and backward products; Adam keeps fp32 moments.
+// Two storage precisions share every kernel: bf16 (activations, inter-layer
+// gradients and the 256 x 256 weight copies in bf16, v_mfma_f32_16x16x32_bf16)
+// and fp32 (the same in fp32, v_mfma_f32_16x16x4_f32).  Parameters are one
+// fp32 master array in a fixed order (W stored [fan_in][fan_out]); Adam keeps
+// fp32 moments.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,6 +27,7 @@ namespace fcpd {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------- layout
 NetOffsets net_offsets() {
@@ -126,238 +129,684 @@ __global__ __launch_bounds__(256) void k_synth_points(float* __restrict__ X, flo
   }
 }
 
-__global__ __launch_bounds__(256) void k_synth_field(const float* __restrict__ X,
-                                                     const float* __restrict__ Wc, int batch,
-                                                     int M, float inv2b2, uint64_t seed0,
-                                                     float outlier_frac, float* __restrict__ Y,
-                                                     float* __restrict__ V) {
-  const int lane = threadIdx.x & 63;
-  const size_t row = ((size_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+
+// Y = X + V with a fraction of rows replaced by U[-1.5, 1.5]^3 (V = Phi W*
+// already computed); one thread per point.
+__global__ __launch_bounds__(256) void k_synth_scene(const float* __restrict__ X,
+                                                     const float* __restrict__ V, int batch,
+                                                     int M, uint64_t seed0, float outlier_frac,
+                                                     float* __restrict__ Y) {
+  const size_t row = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (row >= (size_t)batch * M) return;
-  const int b = (int)(row / M);
-  const float* Xb = X + (size_t)b * M * 3;
-  const float* Wb = Wc + (size_t)b * M * 3;
-  const float* x = X + 3 * row;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-  for (int j = lane; j < M; j += 64) {
-    const float dx = x[0] - Xb[3 * j], dy = x[1] - Xb[3 * j + 1], dz = x[2] - Xb[3 * j + 2];
-    const float k = expf(-(dx * dx + dy * dy + dz * dz) * inv2b2);
-    s0 = fmaf(k, Wb[3 * j], s0);
-    s1 = fmaf(k, Wb[3 * j + 1], s1);
-    s2 = fmaf(k, Wb[3 * j + 2], s2);
-  }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (lane == 0) {
-    V[3 * row] = s0;
-    V[3 * row + 1] = s1;
-    V[3 * row + 2] = s2;
-    const uint64_t s = seed0 + (uint64_t)b;
-    const uint64_t m = row % M;
-    if (uniform_at(s, m, 14) < outlier_frac) {
-      for (int d = 0; d < 3; ++d) Y[3 * row + d] = -1.5f + 3.0f * uniform_at(s, 3 * m + d, 15);
-    } else {
-      Y[3 * row] = x[0] + s0;
-      Y[3 * row + 1] = x[1] + s1;
-      Y[3 * row + 2] = x[2] + s2;
-    }
+  const uint64_t s = seed0 + (uint64_t)(row / M);
+  const uint64_t m = row % M;
+  if (uniform_at(s, m, 14) < outlier_frac) {
+    for (int d = 0; d < 3; ++d) Y[3 * row + d] = -1.5f + 3.0f * uniform_at(s, 3 * m + d, 15);
+  } else {
+    for (int d = 0; d < 3; ++d) Y[3 * row + d] = X[3 * row + d] + V[3 * row + d];
   }
 }
 
+// ------------------------------------------------- Gram products (fp32)
+// out[r] = scale * (sum_j Phi(x_r, x_j) in[j] - sub[r]) within each instance
+// of M points, Phi_rj = exp(-|x_r - x_j|^2 / (2 beta^2)) formed on the fly
+// in base 2 with the square expanded: with c2 = log2(e) / (2 beta^2),
+//   log2 Phi_rj = (2 c2 x_j) . x_r - c2 |x_j|^2 - c2 |x_r|^2,
+// three fused multiply-adds per pair from per-point terms staged once (the
+// rounding of this exponent is 2^-24 of its terms, ~2^-22 c2 |x|^2, for
+// the unit-scale sets the network sees).  Grid (ceil(M / 128), batch): 128
+// rows per block; a thread keeps four rows (r, r + 32, r + 64, r + 96) and one
+// eighth of every 256-point tile of j staged through LDS, so each LDS read
+// feeds four rows; the eight partial sums of a row are added in a fixed
+// order.  With lossp, each block also writes the sum over its rows of
+// |sum_j Phi in - sub|^2 (before scaling).
+constexpr int kPhiRows = 128;
+__global__ __launch_bounds__(256) void k_phi_apply(const float* __restrict__ X,
+                                                   const float* __restrict__ in, int M, float c2,
+                                                   const float* __restrict__ sub, float scale,
+                                                   float* __restrict__ out,
+                                                   double* __restrict__ lossp) {
+  __shared__ float4 sx[256], sw[256];
+  __shared__ float4 part[8][kPhiRows];
+  __shared__ double sh[16];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int rl = tid & 31, q = tid >> 5;  // row lane, j eighth
+  const size_t base = (size_t)b * M;
+  float xi[4][3], ri[4], s[4][3];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = blockIdx.x * kPhiRows + rl + 32 * u;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      xi[u][d] = i < M ? X[3 * (base + i) + d] : 0.f;
+      s[u][d] = 0.f;
+    }
+    ri[u] = -c2 * (xi[u][0] * xi[u][0] + xi[u][1] * xi[u][1] + xi[u][2] * xi[u][2]);
+  }
+  for (int j0 = 0; j0 < M; j0 += 256) {
+    const int j = j0 + tid;
+    float4 px = make_float4(0.f, 0.f, 0.f, 0.f), pw = px;
+    if (j < M) {
+      const size_t o = 3 * (base + j);
+      const float x = X[o], y = X[o + 1], z = X[o + 2];
+      px = make_float4(2.f * c2 * x, 2.f * c2 * y, 2.f * c2 * z, -c2 * (x * x + y * y + z * z));
+      pw = make_float4(in[o], in[o + 1], in[o + 2], 0.f);
+    }
+    __syncthreads();
+    sx[tid] = px;
+    sw[tid] = pw;
+    __syncthreads();
+    const int n = min(256, M - j0);
+    const int t1 = min(n, (q + 1) * 32);
+    for (int t = q * 32; t < t1; ++t) {
+      const float4 p = sx[t], w = sw[t];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float e = fmaf(xi[u][0], p.x, fmaf(xi[u][1], p.y, fmaf(xi[u][2], p.z, p.w + ri[u])));
+        const float k = __builtin_amdgcn_exp2f(fminf(e, 0.f));
+        s[u][0] = fmaf(k, w.x, s[u][0]);
+        s[u][1] = fmaf(k, w.y, s[u][1]);
+        s[u][2] = fmaf(k, w.z, s[u][2]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) part[q][rl + 32 * u] = make_float4(s[u][0], s[u][1], s[u][2], 0.f);
+  __syncthreads();
+  double l = 0.0;
+  if (tid < kPhiRows) {
+    const int i = blockIdx.x * kPhiRows + tid;
+    float4 a = part[0][tid];
+#pragma unroll
+    for (int t = 1; t < 8; ++t) {
+      const float4 v = part[t][tid];
+      a.x += v.x;
+      a.y += v.y;
+      a.z += v.z;
+    }
+    if (i < M) {
+      const size_t o = 3 * (base + i);
+      if (sub) {
+        a.x -= sub[o];
+        a.y -= sub[o + 1];
+        a.z -= sub[o + 2];
+      }
+      out[o] = scale * a.x;
+      out[o + 1] = scale * a.y;
+      out[o + 2] = scale * a.z;
+      l = (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z;
+    }
+  }
+  if (lossp) {
+    const double t = block_sum_d(l, sh);
+    if (tid == 0) lossp[(size_t)b * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_d(const double* __restrict__ p, int n, double scale,
+                                               double* __restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += p[i];
+  s = block_sum_d(s, sh);
+  if (threadIdx.x == 0) out[0] = s * scale;
+}
+
+// ------------------------------------------- storage types and MFMA steps
+// The network stores activations, inter-layer gradients and the 256 x 256
+// weight copies in T: bf16 (v_mfma_f32_16x16x32_bf16) or fp32
+// (v_mfma_f32_16x16x4_f32).  Both accumulate in fp32 and share every tile
+// shape, index map and reduction order; only the contraction length of one
+// matrix instruction (KF) and the elements each lane brings to it (KPL) differ.
+//   A operand: lane l holds A[i = l % 16][k = (l / 16) KPL .. + KPL - 1]
+//   B operand: lane l holds B[k = (l / 16) KPL .. + KPL - 1][j = l % 16]
+//   result:    lane l holds C[i = 4 (l / 16) + q][j = l % 16], q = 0..3
+template <typename T> struct St;
+template <> struct St<__bf16> {
+  typedef bf16x8 frag;
+  static constexpr int VEC = 8;  // elements per 16-byte vector
+  static constexpr int KF = 32;
+  static constexpr int KPL = 8;
+};
+template <> struct St<float> {
+  typedef float frag;
+  static constexpr int VEC = 4;
+  static constexpr int KF = 4;
+  static constexpr int KPL = 1;
+};
+
+__device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ typename St<T>::frag ldfrag(const T* p) {
+  return *reinterpret_cast<const typename St<T>::frag*>(p);
+}
+
+__device__ __forceinline__ float tof(__bf16 v) { return (float)v; }
+__device__ __forceinline__ float tof(float v) { return v; }
+template <typename T> __device__ __forceinline__ T fromf(float v) { return (T)v; }
+
+// Eight consecutive values of a T row to / from fp32 (16 bytes of bf16, 32 of fp32).
+__device__ __forceinline__ void load8(const __bf16* p, float v[8]) {
+  const bf16x8 a = *reinterpret_cast<const bf16x8*>(p);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = (float)a[c];
+}
+__device__ __forceinline__ void load8(const float* p, float v[8]) {
+  const f32x4 a = *reinterpret_cast<const f32x4*>(p), b = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    v[c] = a[c];
+    v[4 + c] = b[c];
+  }
+}
+__device__ __forceinline__ void store8(__bf16* p, const float v[8]) {
+  bf16x8 a;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) a[c] = (__bf16)v[c];
+  *reinterpret_cast<bf16x8*>(p) = a;
+}
+__device__ __forceinline__ void store8(float* p, const float v[8]) {
+  *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+  *reinterpret_cast<f32x4*>(p + 4) = f32x4{v[4], v[5], v[6], v[7]};
+}
+
 // ----------------------------------------------------- weight copies
-// bf16 copies of a 256 x 256 fp32 matrix W [k][n]: Wn = W, Wt = W^T.
-__global__ __launch_bounds__(256) void k_cvt_w(const float* __restrict__ W, __bf16* __restrict__ Wn,
-                                               __bf16* __restrict__ Wt) {
+// T copies of the 256 x 256 fp32 matrices W2, W3, W4, Wa (blockIdx.y picks
+// one): Wn = W ([k][n]) and Wt = W^T ([n][k]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_cvt_w(const float* __restrict__ p, NetOffsets o,
+                                               T* __restrict__ wbuf) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= H * H) return;
+  const size_t offs[4] = {o.W2, o.W3, o.W4, o.Wa};
+  const int m = blockIdx.y;
+  const float* W = p + offs[m];
+  T* Wn = wbuf + (size_t)(2 * m) * H * H;
+  T* Wt = Wn + (size_t)H * H;
   const int k = i / H, n = i % H;
-  const __bf16 v = (__bf16)W[i];
+  const T v = fromf<T>(W[i]);
   Wn[i] = v;
   Wt[n * H + k] = v;
 }
 
 // ----------------------------------------------------- layer 1 (VALU)
+// h[r][c] = relu(p_r . W1[0..2][c] + flag W1[3][c] + b1[c]); eight columns
+// per thread.
+template <typename T>
 __global__ __launch_bounds__(256) void k_layer1(const float* __restrict__ P, int rows, float flag,
                                                 const float* __restrict__ W1,
-                                                const float* __restrict__ b1,
-                                                __bf16* __restrict__ h) {
+                                                const float* __restrict__ b1, T* __restrict__ h) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (size_t)rows * H) return;
-  const size_t r = i / H;
-  const int c = (int)(i % H);
+  if (i >= (size_t)rows * (H / 8)) return;
+  const size_t r = i / (H / 8);
+  const int c0 = (int)(i % (H / 8)) * 8;
   const float* p = P + 3 * r;
-  float v = b1[c] + p[0] * W1[c] + p[1] * W1[H + c] + p[2] * W1[2 * H + c] + flag * W1[3 * H + c];
-  h[i] = (__bf16)fmaxf(v, 0.f);
+  const float x = p[0], y = p[1], z = p[2];
+  float v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int n = c0 + c;
+    v[c] = fmaxf(b1[n] + x * W1[n] + y * W1[H + n] + z * W1[2 * H + n] + flag * W1[3 * H + n], 0.f);
+  }
+  store8(h + r * H + c0, v);
 }
 
-// ----------------------------------------------------- bf16 GEMM (MFMA)
-// C[r][n] = sum_k A[r][k] Bt[n][k] for A [rows x 256], Bt [256 x 256] (both
-// bf16, k contiguous).  64 x 64 tile per block, four waves of 32 x 32, k in
-// steps of 32 through LDS.  Epilogues:
-//   EPI_BIAS_RELU  out = relu(acc + bias[n] + gbias[r / rpg][n]) -> bf16
-//   EPI_MASK       out = acc * (mask[r][n] > 0)                  -> bf16
-//   EPI_F32        out = acc                                      -> fp32
-enum { EPI_BIAS_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
+// ------------------------------------------------ row-panel GEMM (MFMA)
+// C[r][n] = sum_k A[r][k] Bt[n][k] for A [rows x 256] and Bt [256 x 256]
+// (k contiguous in both).  Persistent and weights-stationary: a block owns
+// one half of the output columns (128 rows of Bt, held in LDS for the whole
+// launch) and walks 128-row panels of A; each of its four waves computes 32
+// rows x 128 columns (2 x 8 tiles of 16 x 16), taking its A operands straight
+// from global memory into registers: all of a panel's loads are issued at
+// once, each matrix step waits only for its own, and the next panel's are
+// issued before the current panel's epilogue.  The 1-D grid has a multiple of 16
+// blocks; block L runs on XCD L % 8, and the two blocks that share a panel
+// (one per column half) get ids with the same residue, so the panel's second
+// read comes from that XCD's L2.  Epilogues (fp32 until the store):
+//   EPI_BIAS_RELU  out = relu(acc + bias[n] + gbias[r / per][n])
+//   EPI_MASK       out = acc * (mask[r][n] > 0)
+enum { EPI_BIAS_RELU = 0, EPI_MASK = 1 };
+constexpr int GBM = 128;
 
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm(const __bf16* __restrict__ A,
-                                              const __bf16* __restrict__ Bt, int rows,
-                                              const float* __restrict__ bias,
-                                              const float* __restrict__ gbias, int rpg,
-                                              const __bf16* __restrict__ mask,
-                                              __bf16* __restrict__ outb, float* __restrict__ outf) {
-  __shared__ __align__(16) __bf16 sA[64][40];
-  __shared__ __align__(16) __bf16 sB[64][40];
+template <typename T>
+__device__ __forceinline__ typename St<T>::frag zfrag();
+template <> __device__ __forceinline__ bf16x8 zfrag<__bf16>() {
+  bf16x8 z;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) z[t] = (__bf16)0.f;
+  return z;
+}
+template <> __device__ __forceinline__ float zfrag<float>() { return 0.f; }
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(const T* __restrict__ A, const T* __restrict__ Bt,
+                                              int rows, const float* __restrict__ bias,
+                                              const float* __restrict__ gbias, int per,
+                                              const T* __restrict__ mask, T* __restrict__ out) {
+  typedef typename St<T>::frag F;
+  constexpr int VEC = St<T>::VEC, KF = St<T>::KF, KPL = St<T>::KPL;
+  constexpr int NS = H / KF;              // matrix steps over k
+  __shared__ __align__(16) T sB[128][H + VEC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  f32x4 acc[2][2];
+  const int xcd = blockIdx.x & 7, idx = blockIdx.x >> 3;
+  const int half = idx & 1;
+  const int pslot = (idx >> 1) * 8 + xcd;
+  const int pstride = gridDim.x >> 1;
+  const int npanels = (rows + GBM - 1) / GBM;
+  if (pslot >= npanels) return;  // uniform over the block
+  {  // this block's 128 rows of Bt into LDS
+    constexpr int VPR = H / VEC;
+    constexpr int NV = 128 * VPR / 256;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int t0 = 0; t0 < NV; t0 += 8) {
+      u32x4 v[8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 8;  // this thread's 16-byte load
-  for (int k0 = 0; k0 < H; k0 += 32) {
-    bf16x8 va, vb;
-    if (r0 + lr < rows)
-      va = *reinterpret_cast<const bf16x8*>(A + (size_t)(r0 + lr) * H + k0 + lk);
-    else
-      for (int t = 0; t < 8; ++t) va[t] = (__bf16)0.f;
-    vb = *reinterpret_cast<const bf16x8*>(Bt + (size_t)(n0 + lr) * H + k0 + lk);
-    *reinterpret_cast<bf16x8*>(&sA[lr][lk]) = va;
-    *reinterpret_cast<bf16x8*>(&sB[lr][lk]) = vb;
-    __syncthreads();
-    const int kk = 8 * (lane >> 4);
-    bf16x8 a[2], b[2];
+      for (int t = 0; t < 8; ++t) {
+        const int vi = tid + 256 * (t0 + t);
+        v[t] = *reinterpret_cast<const u32x4*>(Bt + (size_t)(half * 128 + vi / VPR) * H +
+                                                (vi % VPR) * VEC);
+      }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&sA[wr + 16 * i + (lane & 15)][kk]);
+      for (int t = 0; t < 8; ++t) {
+        const int vi = tid + 256 * (t0 + t);
+        *reinterpret_cast<u32x4*>(&sB[vi / VPR][(vi % VPR) * VEC]) = v[t];
+      }
+    }
+  }
+  __syncthreads();
+  auto loadA = [&](int p, F (&f)[2][NS]) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&sB[wc + 16 * j + (lane & 15)][kk]);
+    for (int i = 0; i < 2; ++i) {
+      const int row = p * GBM + wave * 32 + 16 * i + (lane & 15);
+      const T* src = A + (size_t)row * H + (lane >> 4) * KPL;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        f[i][s] = row < rows ? *reinterpret_cast<const F*>(src + s * KF) : zfrag<T>();
+    }
+  };
+  float bj[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    bj[j] = (EPI == EPI_BIAS_RELU && bias) ? bias[half * 128 + 16 * j + (lane & 15)] : 0.f;
+  F fa[2][NS];
+  loadA(pslot, fa);
+  for (int p = pslot; p < npanels; p += pstride) {
+    f32x4 acc[2][8];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
-  }
+      for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int s = 0; s < NS; ++s) {  // waits only for the operands of step s
+      F b[8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 8; ++j) b[j] = ldfrag(&sB[16 * j + (lane & 15)][s * KF + (lane >> 4) * KPL]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = mma(fa[i][s], b[j], acc[i][j]);
+      __builtin_amdgcn_sched_barrier(0);  // keep each step's LDS reads with its products
+    }
+    // the next panel's operands are in flight during this panel's epilogue
+    if (p + pstride < npanels) loadA(p + pstride, fa);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wr + 16 * i + 4 * (lane >> 4) + q;
-        const int n = n0 + wc + 16 * j + (lane & 15);
+        const int r = p * GBM + wave * 32 + 16 * i + 4 * (lane >> 4) + q;
         if (r >= rows) continue;
-        float v = acc[i][j][q];
-        const size_t o = (size_t)r * H + n;
-        if (EPI == EPI_BIAS_RELU) {
-          if (bias) v += bias[n];
-          if (gbias) v += gbias[(size_t)(r / rpg) * H + n];
-          outb[o] = (__bf16)fmaxf(v, 0.f);
-        } else if (EPI == EPI_MASK) {
-          outb[o] = (__bf16)((float)mask[o] > 0.f ? v : 0.f);
-        } else {
-          outf[o] = v;
+        const float* grow = gbias ? gbias + (size_t)(r / per) * H : nullptr;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int n = half * 128 + 16 * j + (lane & 15);
+          float v = acc[i][j][q];
+          const size_t o = (size_t)r * H + n;
+          if (EPI == EPI_BIAS_RELU) {
+            v += bj[j];
+            if (grow) v += grow[n];
+            out[o] = fromf<T>(fmaxf(v, 0.f));
+          } else {
+            out[o] = fromf<T>(tof(mask[o]) > 0.f ? v : 0.f);
+          }
         }
       }
+  }
 }
 
-// Weight gradient partials: P[split][k][n] = sum over this split's rows of
-// X[r][k] D[r][n] (X, D bf16 [rows x 256]).  The r axis is staged transposed
-// so both operands are contiguous in the contraction index.
-__global__ __launch_bounds__(256) void k_wgrad(const __bf16* __restrict__ Xa,
-                                               const __bf16* __restrict__ Da, int rows,
-                                               int rows_per_split, float* __restrict__ P) {
-  __shared__ __align__(16) __bf16 sX[64][40];  // [k][r]
-  __shared__ __align__(16) __bf16 sD[64][40];  // [n][r]
+// ------------------------------------------------ weight gradient (MFMA)
+// P[split][k][n] = sum over this split's rows r of X[r][k] D[r][n] (the
+// contraction runs over rows), and with with_bias the column sums of D over
+// the same rows in P[split][H*H + n] (the bias gradient).  A block computes a
+// 128 x 128 quarter (kt, nt) of the 256 x 256 result, four waves of 64 x 64.
+// The 1-D grid holds 4 x ceil(splits / 8) x 8 blocks; workgroups are handed
+// to the eight XCDs in turn, so block L runs on XCD L % 8, and the map below
+// gives the four quarters of one split block ids with the same residue: the
+// two that read the same half of X (or of D) share that XCD's L2.
+// Rows advance in stages of SR: threads 0-127 stage X, 128-255 stage D, each
+// loading an 8-row x VEC-column block with 16-byte row loads, transposing it
+// in registers and storing it column-major ([column][row]) so that every MFMA
+// operand is one LDS vector read.
+template <typename T>
+__global__ __launch_bounds__(256) void k_wgrad(const T* __restrict__ Xa, const T* __restrict__ Da,
+                                               int rows, int rows_per_split, int with_bias,
+                                               float* __restrict__ P) {
+  constexpr int VEC = St<T>::VEC, KF = St<T>::KF, KPL = St<T>::KPL;
+  constexpr int NCG = 128 / VEC;     // column groups of a 128-column tile
+  constexpr int SR = 8 * (128 / NCG);  // rows per stage (bf16 64, fp32 32)
+  constexpr int PT = SR + VEC;       // padded pitch of a column (elements)
+  __shared__ __align__(16) T sX[2][128][PT];
+  __shared__ __align__(16) T sD[2][128][PT];
+  __shared__ float sb[SR / 8][128];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  const int rb = blockIdx.z * rows_per_split;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int split = (slot >> 2) * 8 + xcd;
+  const int kt = (slot >> 1) & 1, nt = slot & 1;
+  const int rb = split * rows_per_split;
+  if (rb >= rows) return;  // padding of the grid to whole groups of eight splits
   const int re = min(rows, rb + rows_per_split);
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  f32x4 acc[2][2];
+  const int wk = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const bool isD = tid >= 128;
+  const int u = tid & 127, cg = u % NCG, rg = u / NCG;
+  const T* src = isD ? Da + nt * 128 + cg * VEC : Xa + kt * 128 + cg * VEC;
+  T(*dst)[128][PT] = isD ? sD : sX;
+  const bool bias = with_bias && kt == 0 && isD;
+  float bsum[VEC];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int c = 0; c < VEC; ++c) bsum[c] = 0.f;
+  f32x4 acc[4][4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 3, lc = (tid & 7) * 8;  // load row (0..31), 8 columns
-  for (int r0 = rb; r0 < re; r0 += 32) {
-    const int r = r0 + lr;
-    bf16x8 vx, vd;
-    if (r < re) {
-      vx = *reinterpret_cast<const bf16x8*>(Xa + (size_t)r * H + k0 + lc);
-      vd = *reinterpret_cast<const bf16x8*>(Da + (size_t)r * H + n0 + lc);
-    } else {
-      for (int t = 0; t < 8; ++t) vx[t] = vd[t] = (__bf16)0.f;
-    }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  u32x4 v[8];
+  auto gload = [&](int r0) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      sX[lc + t][lr] = vx[t];
-      sD[lc + t][lr] = vd[t];
+      const int r = r0 + rg * 8 + t;
+      v[t] = r < re ? *reinterpret_cast<const u32x4*>(src + (size_t)r * H)
+                    : u32x4{0u, 0u, 0u, 0u};
     }
-    __syncthreads();
-    const int kk = 8 * (lane >> 4);
-    bf16x8 a[2], b[2];
+  };
+  auto sstore = [&](int buf) {
+    if constexpr (VEC == 8) {  // bf16: 8 x 8 block, two values per dword
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&sX[wr + 16 * i + (lane & 15)][kk]);
+      for (int c = 0; c < 8; ++c) {
+        const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+        u32x4 o;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&sD[wc + 16 * j + (lane & 15)][kk]);
+        for (int p = 0; p < 4; ++p)
+          o[p] = __builtin_amdgcn_perm(v[2 * p + 1][c >> 1], v[2 * p][c >> 1], sel);
+        *reinterpret_cast<u32x4*>(&dst[buf][cg * 8 + c][rg * 8]) = o;
+        if (bias) {
+          float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+          for (int p = 0; p < 4; ++p) {
+            s += __uint_as_float(o[p] << 16);
+            s += __uint_as_float(o[p] & 0xFFFF0000u);
+          }
+          bsum[c] += s;
+        }
+      }
+    } else {  // fp32: 8 x 4 block
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+      for (int c = 0; c < 4; ++c) {
+        const u32x4 o0{v[0][c], v[1][c], v[2][c], v[3][c]};
+        const u32x4 o1{v[4][c], v[5][c], v[6][c], v[7][c]};
+        *reinterpret_cast<u32x4*>(&dst[buf][cg * 4 + c][rg * 8]) = o0;
+        *reinterpret_cast<u32x4*>(&dst[buf][cg * 4 + c][rg * 8 + 4]) = o1;
+        if (bias) {
+          float s = 0.f;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) s += __uint_as_float(v[t][c]);
+          bsum[c] += s;
+        }
+      }
+    }
+  };
+  if (rb < re) {
+    gload(rb);
+    sstore(0);
   }
-  float* out = P + (size_t)blockIdx.z * H * H;
+  __syncthreads();
+  int buf = 0;
+  for (int r0 = rb; r0 < re; r0 += SR) {
+    const bool more = r0 + SR < re;
+    if (more) gload(r0 + SR);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int s = 0; s < SR / KF; ++s) {
+      const int kk = s * KF + (lane >> 4) * KPL;
+      typename St<T>::frag a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 4; ++i) a[i] = ldfrag(&sX[buf][wk + 16 * i + (lane & 15)][kk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = ldfrag(&sD[buf][wn + 16 * j + (lane & 15)][kk]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mma(a[i], b[j], acc[i][j]);
+    }
+    if (more) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  float* out = P + (size_t)split * (H * H + H);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int k = k0 + wr + 16 * i + 4 * (lane >> 4) + q;
-        const int n = n0 + wc + 16 * j + (lane & 15);
+        const int k = kt * 128 + wk + 16 * i + 4 * (lane >> 4) + q;
+        const int n = nt * 128 + wn + 16 * j + (lane & 15);
         out[(size_t)k * H + n] = acc[i][j][q];
       }
+  if (with_bias && kt == 0) {  // uniform over the block
+    if (isD) {
+#pragma unroll
+      for (int c = 0; c < VEC; ++c) sb[rg][cg * VEC + c] = bsum[c];
+    }
+    __syncthreads();
+    if (tid < 128) {
+      float s = 0.f;
+#pragma unroll
+      for (int g = 0; g < SR / 8; ++g) s += sb[g][tid];
+      out[(size_t)H * H + nt * 128 + tid] = s;
+    }
+  }
 }
 
-// g[i] += sum over splits of P[s][i]  (fixed order)
+// g[i] += sum over splits of P[s][i], i < n; P rows are `stride` apart.
 __global__ __launch_bounds__(256) void k_reduce_add(const float* __restrict__ P, int splits,
-                                                    size_t n, float* __restrict__ g) {
+                                                    size_t stride, size_t n,
+                                                    float* __restrict__ g) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  float s = 0.f;
-  for (int k = 0; k < splits; ++k) s += P[(size_t)k * n + i];
-  g[i] += s;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int k = 0;
+  for (; k + 4 <= splits; k += 4) {
+    s0 += P[(size_t)k * stride + i];
+    s1 += P[(size_t)(k + 1) * stride + i];
+    s2 += P[(size_t)(k + 2) * stride + i];
+    s3 += P[(size_t)(k + 3) * stride + i];
+  }
+  for (; k < splits; ++k) s0 += P[(size_t)k * stride + i];
+  g[i] += (s0 + s1) + (s2 + s3);
 }
 
-// Column sums of a bf16 [rows x 256] array in row chunks: P[chunk][c].
-__global__ __launch_bounds__(256) void k_colsum_bf16(const __bf16* __restrict__ D, int rows,
-                                                     int rows_per_chunk, float* __restrict__ P) {
-  const int c = threadIdx.x;
-  const int r0 = blockIdx.x * rows_per_chunk;
-  const int r1 = min(rows, r0 + rows_per_chunk);
+// ---------------------------------------- column sums over row chunks
+// For chunk j of instance b (rows b per + j chunk .. , never crossing an
+// instance) with NE per-row weights E[r][0..NE-1]:
+//   part[ch][0][c]      = sum_r D[r][c]
+//   part[ch][1 + e][c]  = sum_r E[r][e] D[r][c]
+//   part[ch][1 + NE][e] = sum_r E[r][e]            (e < NE)
+// ch = b cpi + j; grid (cpi, batch).  256 threads: 32 groups of eight
+// columns (one 16-byte bf16 load, two fp32) x 8 row lanes taking every
+// eighth row; the lanes are added in order.
+template <typename T, int NE>
+__global__ __launch_bounds__(256) void k_colsums(const T* __restrict__ D,
+                                                 const float* __restrict__ E, int per, int chunk,
+                                                 float* __restrict__ part) {
+  constexpr int NP = NE + 1;
+  __shared__ float sh[8][NP * H + 4];
+  const int b = blockIdx.y, j = blockIdx.x, tid = threadIdx.x;
+  const int cg = tid & 31, rl = tid >> 5;
+  const size_t r0 = (size_t)b * per + (size_t)j * chunk;
+  const size_t r1 = (size_t)b * per + min(per, (j + 1) * chunk);
+  float s[NP][8], ee[NE > 0 ? NE : 1];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s[p][c] = 0.f;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) ee[e] = 0.f;
+  for (size_t r = r0 + rl; r < r1; r += 8) {
+    float d[8];
+    load8(D + r * H + cg * 8, d);
+    float w[NE > 0 ? NE : 1];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      w[e] = E[r * NE + e];
+      ee[e] += w[e];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      s[0][c] += d[c];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) s[1 + e][c] = fmaf(w[e], d[c], s[1 + e][c]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sh[rl][p * H + cg * 8 + c] = s[p][c];
+  if (cg == 0)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) sh[rl][NP * H + e] = ee[e];
+  __syncthreads();
+  float* out = part + ((size_t)b * gridDim.x + j) * (NE + 2) * H;
+  for (int o = tid; o < NP * H + NE; o += 256) {
+    float t = 0.f;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) t += sh[l][o];
+    out[o] = t;
+  }
+}
+
+// red[g][o] = sum over the chunks g cpg .. (g + 1) cpg - 1 of part[ch][o]
+// (chunk records `stride` floats apart), o < n.  Grid (ceil(n / 16), G):
+// 16 outputs x 16 lanes per block, lane l adding chunks l, l + 16, ...; the
+// lanes are then added in order.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float* __restrict__ part, int cpg,
+                                                    int stride, int n, float* __restrict__ red) {
+  __shared__ float sh[16][17];
+  const int g = blockIdx.y, t = threadIdx.x, oi = t & 15, lane = t >> 4;
+  const int o = blockIdx.x * 16 + oi;
   float s = 0.f;
-  for (int r = r0; r < r1; ++r) s += (float)D[(size_t)r * H + c];
-  P[(size_t)blockIdx.x * H + c] = s;
+  if (o < n) {
+    const float* p = part + (size_t)g * cpg * stride + o;
+#pragma unroll 4
+    for (int k = lane; k < cpg; k += 16) s += p[(size_t)k * stride];
+  }
+  sh[lane][oi] = s;
+  __syncthreads();
+  if (lane == 0 && o < n) {
+    float r = 0.f;
+#pragma unroll
+    for (int l = 0; l < 16; ++l) r += sh[l][oi];
+    red[(size_t)g * n + o] = r;
+  }
+}
+
+// Layer 1 from its summed planes (NE = 3, e = [p, flag]): gW1[e][c] for the
+// coordinates, flag * sum d for the flag input, gb1[c] = sum d.
+__global__ __launch_bounds__(256) void k_apply_w1(const float* __restrict__ red, float flag,
+                                                  float* __restrict__ gW1,
+                                                  float* __restrict__ gb1) {
+  const int c = threadIdx.x;
+  for (int e = 0; e < 3; ++e) gW1[(size_t)e * H + c] += red[(size_t)(1 + e) * H + c];
+  gW1[(size_t)3 * H + c] += flag * red[c];
+  gb1[c] += red[c];
+}
+
+// The output layer from its summed planes (D = z, E = dW0): gWo[k][d], gbo[d].
+__global__ __launch_bounds__(256) void k_apply_wo(const float* __restrict__ red,
+                                                  float* __restrict__ gWo,
+                                                  float* __restrict__ gbo) {
+  const int k = threadIdx.x;
+  for (int d = 0; d < 3; ++d) gWo[3 * k + d] += red[(size_t)(1 + d) * H + k];
+  if (k < 3) gbo[k] += red[(size_t)4 * H + k];
 }
 
 // ----------------------------------------------------- pooling and head
-// g[b][c] = max over rows of instance b, idx = the lowest arg max.
-__global__ __launch_bounds__(256) void k_maxpool(const __bf16* __restrict__ F, int per,
-                                                 float* __restrict__ g, int* __restrict__ idx) {
+// Max over rows of each instance in two steps: per chunk of rows, then over
+// the chunks in order; the lowest arg max wins ties.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool_part(const T* __restrict__ F, int per, int chunk,
+                                                   float* __restrict__ pv, int* __restrict__ pi) {
+  __shared__ float sv[8][H];
+  __shared__ int si[8][H];
+  const int b = blockIdx.y, j = blockIdx.x, tid = threadIdx.x;
+  const int cg = tid & 31, rl = tid >> 5;
+  const int rl0 = j * chunk, rl1 = min(per, rl0 + chunk);
+  const T* f = F + (size_t)b * per * H + cg * 8;
+  float best[8];
+  int bi[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    best[c] = -3.0e38f;
+    bi[c] = rl0;
+  }
+  for (int r = rl0 + rl; r < rl1; r += 8) {  // rows ascending: > keeps the lowest
+    float v[8];
+    load8(f + (size_t)r * H, v);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (v[c] > best[c]) {
+        best[c] = v[c];
+        bi[c] = r;
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    sv[rl][cg * 8 + c] = best[c];
+    si[rl][cg * 8 + c] = bi[c];
+  }
+  __syncthreads();
+  float bv = sv[0][tid];
+  int bx = si[0][tid];
+#pragma unroll
+  for (int l = 1; l < 8; ++l) {
+    const float v = sv[l][tid];
+    const int x = si[l][tid];
+    if (v > bv || (v == bv && x < bx)) {
+      bv = v;
+      bx = x;
+    }
+  }
+  const size_t o = ((size_t)b * gridDim.x + j) * H + tid;
+  pv[o] = bv;
+  pi[o] = bx;
+}
+
+__global__ __launch_bounds__(256) void k_pool_merge(const float* __restrict__ pv,
+                                                    const int* __restrict__ pi, int cpi,
+                                                    float* __restrict__ g,
+                                                    int* __restrict__ idx) {
   const int b = blockIdx.x, c = threadIdx.x;
-  const __bf16* f = F + (size_t)b * per * H;
-  float best = -1e30f;
-  int bi = 0;
-  for (int r = 0; r < per; ++r) {
-    const float v = (float)f[(size_t)r * H + c];
-    if (v > best) {
-      best = v;
-      bi = r;
+  size_t o = (size_t)b * cpi * H + c;
+  float best = pv[o];
+  int bi = pi[o];
+  for (int j = 1; j < cpi; ++j) {
+    o += H;
+    if (pv[o] > best) {
+      best = pv[o];
+      bi = pi[o];
     }
   }
   g[(size_t)b * H + c] = best;
@@ -373,13 +822,15 @@ __global__ __launch_bounds__(256) void k_head_u(const float* __restrict__ gX,
                                                 float* __restrict__ u) {
   const int b = blockIdx.x, c = threadIdx.x;
   float s = bh[c];
+#pragma unroll 8
   for (int k = 0; k < H; ++k)
     s += gX[(size_t)b * H + k] * Wb[(size_t)k * H + c] + gY[(size_t)b * H + k] * Wc[(size_t)k * H + c];
   u[(size_t)b * H + c] = s;
 }
 
 // W0[r] = z[r] Wo + bo (one wave per row).
-__global__ __launch_bounds__(256) void k_head_out(const __bf16* __restrict__ z, int rows,
+template <typename T>
+__global__ __launch_bounds__(256) void k_head_out(const T* __restrict__ z, int rows,
                                                   const float* __restrict__ Wo,
                                                   const float* __restrict__ bo,
                                                   float* __restrict__ W0) {
@@ -388,7 +839,7 @@ __global__ __launch_bounds__(256) void k_head_out(const __bf16* __restrict__ z, 
   if (r >= (size_t)rows) return;
   float s0 = 0.f, s1 = 0.f, s2 = 0.f;
   for (int k = lane; k < H; k += 64) {
-    const float v = (float)z[r * H + k];
+    const float v = tof(z[r * H + k]);
     s0 = fmaf(v, Wo[3 * k], s0);
     s1 = fmaf(v, Wo[3 * k + 1], s1);
     s2 = fmaf(v, Wo[3 * k + 2], s2);
@@ -403,104 +854,27 @@ __global__ __launch_bounds__(256) void k_head_out(const __bf16* __restrict__ z, 
   }
 }
 
-// out[r] = scale * (sum_j Phi(x_r, x_j) in[j] - sub[r]) within each instance
-// (one wave per row, fp32, Phi formed on the fly); loss partial per block of
-// sum |out|^2 / scale^2 when lossp != NULL.
-__global__ __launch_bounds__(256) void k_phi_mv(const float* __restrict__ X,
-                                                const float* __restrict__ in, int M, int rows,
-                                                float inv2b2, const float* __restrict__ sub,
-                                                float scale, float* __restrict__ out,
-                                                double* __restrict__ lossp) {
-  __shared__ double sh[16];
-  const int lane = threadIdx.x & 63;
-  const size_t r = ((size_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-  double l = 0.0;
-  if (r < (size_t)rows) {
-    const size_t b = r / M;
-    const float* Xb = X + b * M * 3;
-    const float* ib = in + b * M * 3;
-    const float* x = X + 3 * r;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int j = lane; j < M; j += 64) {
-      const float dx = x[0] - Xb[3 * j], dy = x[1] - Xb[3 * j + 1], dz = x[2] - Xb[3 * j + 2];
-      const float k = expf(-(dx * dx + dy * dy + dz * dz) * inv2b2);
-      s0 = fmaf(k, ib[3 * j], s0);
-      s1 = fmaf(k, ib[3 * j + 1], s1);
-      s2 = fmaf(k, ib[3 * j + 2], s2);
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    if (lane == 0) {
-      if (sub) {
-        s0 -= sub[3 * r];
-        s1 -= sub[3 * r + 1];
-        s2 -= sub[3 * r + 2];
-      }
-      out[3 * r] = scale * s0;
-      out[3 * r + 1] = scale * s1;
-      out[3 * r + 2] = scale * s2;
-      l = (double)s0 * s0 + (double)s1 * s1 + (double)s2 * s2;
-    }
-  }
-  if (lossp) {
-    const double t = block_sum_d(l, sh);
-    if (threadIdx.x == 0) lossp[blockIdx.x] = t;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_sum_d(const double* __restrict__ p, int n, double scale,
-                                               double* __restrict__ out) {
-  __shared__ double sh[16];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += p[i];
-  s = block_sum_d(s, sh);
-  if (threadIdx.x == 0) out[0] = s * scale;
-}
-
 // ----------------------------------------------------- head backward
-// dWo[k][d] = sum_r z[r][k] dW0[r][d]; dbo[d] = sum_r dW0[r][d]
-__global__ __launch_bounds__(256) void k_dWo(const __bf16* __restrict__ z,
-                                             const float* __restrict__ dW0, int rows,
-                                             float* __restrict__ gWo, float* __restrict__ gbo) {
-  __shared__ double sh[16];
-  const int k = blockIdx.x;  // 0..H (H: the bias)
-  double s[3] = {0, 0, 0};
-  for (int r = threadIdx.x; r < rows; r += 256) {
-    const float v = k < H ? (float)z[(size_t)r * H + k] : 1.f;
-    for (int d = 0; d < 3; ++d) s[d] += (double)v * dW0[3 * (size_t)r + d];
-  }
-  for (int d = 0; d < 3; ++d) {
-    const double t = block_sum_d(s[d], sh);
-    if (threadIdx.x == 0) {
-      if (k < H)
-        gWo[3 * k + d] += (float)t;
-      else
-        gbo[d] += (float)t;
-    }
-  }
-}
-
-// dz[r][k] = (dW0[r] . Wo[k]) * (z[r][k] > 0)
+// dz[r][k] = (dW0[r] . Wo[k]) * (z[r][k] > 0); eight columns per thread.
+template <typename T>
 __global__ __launch_bounds__(256) void k_dz(const float* __restrict__ dW0,
                                             const float* __restrict__ Wo,
-                                            const __bf16* __restrict__ z, int rows,
-                                            __bf16* __restrict__ dz) {
+                                            const T* __restrict__ z, int rows,
+                                            T* __restrict__ dz) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (size_t)rows * H) return;
-  const size_t r = i / H;
-  const int k = (int)(i % H);
-  const float v = dW0[3 * r] * Wo[3 * k] + dW0[3 * r + 1] * Wo[3 * k + 1] + dW0[3 * r + 2] * Wo[3 * k + 2];
-  dz[i] = (__bf16)((float)z[i] > 0.f ? v : 0.f);
-}
-
-// du[b][c] = sum over instance b's rows of dz; then dWb, dWc, dbh, dgX, dgY.
-__global__ __launch_bounds__(256) void k_du(const __bf16* __restrict__ dz, int M,
-                                            float* __restrict__ du) {
-  const int b = blockIdx.x, c = threadIdx.x;
-  float s = 0.f;
-  for (int r = 0; r < M; ++r) s += (float)dz[((size_t)b * M + r) * H + c];
-  du[(size_t)b * H + c] = s;
+  if (i >= (size_t)rows * (H / 8)) return;
+  const size_t r = i / (H / 8);
+  const int k0 = (int)(i % (H / 8)) * 8;
+  const float a = dW0[3 * r], b = dW0[3 * r + 1], c = dW0[3 * r + 2];
+  float zv[8], v[8];
+  load8(z + r * H + k0, zv);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int k = k0 + t;
+    const float g = a * Wo[3 * k] + b * Wo[3 * k + 1] + c * Wo[3 * k + 2];
+    v[t] = zv[t] > 0.f ? g : 0.f;
+  }
+  store8(dz + r * H + k0, v);
 }
 
 __global__ __launch_bounds__(256) void k_head_small_grads(
@@ -520,6 +894,7 @@ __global__ __launch_bounds__(256) void k_head_small_grads(
     // dg[b][k] = Wb[k] . du[b]  (threads over b)
     for (int b = c; b < batch; b += 256) {
       float a = 0.f, e = 0.f;
+#pragma unroll 8
       for (int j = 0; j < H; ++j) {
         a += Wb[(size_t)k * H + j] * du[(size_t)b * H + j];
         e += Wc[(size_t)k * H + j] * du[(size_t)b * H + j];
@@ -534,38 +909,23 @@ __global__ __launch_bounds__(256) void k_head_small_grads(
   }
 }
 
-// df[rows] (fp32, or zero when df_in is NULL) plus the max-pool scatter,
-// times the relu mask of f, to bf16.
-__global__ __launch_bounds__(256) void k_pool_back(const float* __restrict__ df_in,
-                                                   const float* __restrict__ dg,
-                                                   const int* __restrict__ idx, int per,
-                                                   int rows, const __bf16* __restrict__ f,
-                                                   __bf16* __restrict__ d) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (size_t)rows * H) return;
-  const size_t r = i / H;
-  const int c = (int)(i % H);
-  const size_t b = r / per;
-  float v = df_in ? df_in[i] : 0.f;
-  if (idx[b * H + c] == (int)(r % per)) v += dg[b * H + c];
-  d[i] = (__bf16)((float)f[i] > 0.f ? v : 0.f);
+// The max-pool's gradient: for every instance b and feature c, the pooled
+// value's gradient dg[b][c] goes to the arg max row idx[b][c] (times the relu
+// mask of f there), added to d (add != 0) or written over it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pool_scatter(const float* __restrict__ dg,
+                                                      const int* __restrict__ idx, int per,
+                                                      const T* __restrict__ f, int add,
+                                                      T* __restrict__ d) {
+  const int b = blockIdx.x, c = threadIdx.x;
+  const size_t o = ((size_t)b * per + idx[(size_t)b * H + c]) * H + c;
+  const float g = tof(f[o]) > 0.f ? dg[(size_t)b * H + c] : 0.f;
+  d[o] = fromf<T>(add ? tof(d[o]) + g : g);
 }
 
-// dW1 [4 x 256] and db1 from e = [p, flag] and d1 (bf16), added into g.
-__global__ __launch_bounds__(256) void k_dW1(const float* __restrict__ P, float flag, int rows,
-                                             const __bf16* __restrict__ d1,
-                                             float* __restrict__ gW1, float* __restrict__ gb1) {
-  const int c = threadIdx.x;
-  const int comp = blockIdx.x;  // 0..4: x, y, z, flag, bias
-  double s = 0.0;
-  for (int r = 0; r < rows; ++r) {
-    const float e = comp < 3 ? P[3 * (size_t)r + comp] : (comp == 3 ? flag : 1.f);
-    s += (double)e * (float)d1[(size_t)r * H + c];
-  }
-  if (comp < 4)
-    gW1[(size_t)comp * H + c] += (float)s;
-  else
-    gb1[c] += (float)s;
+__global__ __launch_bounds__(256) void k_zero16(u32x4* __restrict__ a, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = u32x4{0u, 0u, 0u, 0u};
 }
 
 // ----------------------------------------------------- Adam
@@ -592,10 +952,14 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ a, size_t n, f
 namespace {
 unsigned nb(size_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
-constexpr int kWgradRows = 4096;
+constexpr int kWgradRows = 1024;  // rows per weight-gradient split (a multiple of 64)
+constexpr int kChunk = 128;       // rows per column-sum / pooling chunk
+int cpi_of(int per) { return (per + kChunk - 1) / kChunk; }
 }  // namespace
 
-NetWs net_ws_layout(int batch, int M, int N) {
+size_t net_elem_bytes(int precision) { return precision == kNetFp32 ? 4 : 2; }
+
+NetWs net_ws_layout(int batch, int M, int N, int precision) {
   NetWs L;
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -604,13 +968,12 @@ NetWs net_ws_layout(int batch, int M, int N) {
     return o;
   };
   const size_t RM = (size_t)batch * M, RN = (size_t)batch * N;
-  const size_t bf = sizeof(__bf16);
-  for (int l = 0; l < 4; ++l) L.aX[l] = take(RM * H * bf);
-  for (int l = 0; l < 4; ++l) L.aY[l] = take(RN * H * bf);
-  L.z = take(RM * H * bf);
-  L.dA = take(std::max(RM, RN) * H * bf);
-  L.dB = take(std::max(RM, RN) * H * bf);
-  L.dfX = take(RM * H * sizeof(float));
+  const size_t es = net_elem_bytes(precision);
+  for (int l = 0; l < 4; ++l) L.aX[l] = take(RM * H * es);
+  for (int l = 0; l < 4; ++l) L.aY[l] = take(RN * H * es);
+  L.z = take(RM * H * es);
+  L.dA = take(std::max(RM, RN) * H * es);
+  L.dB = take(std::max(RM, RN) * H * es);
   L.gX = take((size_t)batch * H * 4);
   L.gY = take((size_t)batch * H * 4);
   L.iX = take((size_t)batch * H * 4);
@@ -622,108 +985,173 @@ NetWs net_ws_layout(int batch, int M, int N) {
   L.W0 = take(RM * 3 * 4);
   L.R = take(RM * 3 * 4);
   L.dW0 = take(RM * 3 * 4);
-  L.lossp = take((RM / 4 + 2) * sizeof(double));
+  L.lossp = take((size_t)batch * nb(M, kPhiRows) * sizeof(double));
   L.loss = take(sizeof(double));
-  const int splits = (int)((std::max(RM, RN) + kWgradRows - 1) / kWgradRows);
-  L.wsplits = splits;
-  L.part = take((size_t)std::max(splits * H * H, (int)((std::max(RM, RN) + 1023) / 1024) * H) * 4);
-  L.wbf = take((size_t)8 * H * H * bf);  // W2, W3, W4, Wa in both orientations
+  const size_t rmax = std::max(RM, RN);
+  const size_t splits = (rmax + kWgradRows - 1) / kWgradRows;
+  const size_t nchunks = (size_t)batch * cpi_of(std::max(M, N));
+  L.part = take(std::max({splits * (H * H + H), nchunks * 5 * H, 2 * nchunks * H}) * 4);
+  L.red = take((size_t)std::max(5 * H, batch * H) * 4);
+  L.wbf = take((size_t)8 * H * H * es);  // W2, W3, W4, Wa in both orientations
   L.end = off;
   return L;
 }
 
 namespace {
+template <typename T>
 struct NetRun {
   const NetOffsets o;
   const NetWs& L;
   char* ws;
   hipStream_t st;
   int batch, M, N;
-  template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  __bf16* wn(int i) const { return at<__bf16>(L.wbf) + (size_t)(2 * i) * H * H; }
-  __bf16* wt(int i) const { return at<__bf16>(L.wbf) + (size_t)(2 * i + 1) * H * H; }
+  template <typename U> U* at(size_t off) const { return reinterpret_cast<U*>(ws + off); }
+  T* act(size_t off) const { return at<T>(off); }
+  T* wn(int i) const { return at<T>(L.wbf) + (size_t)(2 * i) * H * H; }
+  T* wt(int i) const { return at<T>(L.wbf) + (size_t)(2 * i + 1) * H * H; }
+  float* part() const { return at<float>(L.part); }
 };
 
-void net_weights(const NetRun& r, const float* p) {
-  const size_t offs[4] = {r.o.W2, r.o.W3, r.o.W4, r.o.Wa};
-  for (int i = 0; i < 4; ++i)
-    hipLaunchKernelGGL(k_cvt_w, dim3(nb(H * H)), dim3(256), 0, r.st, p + offs[i], r.wn(i), r.wt(i));
+template <typename T, int EPI>
+void gemm(const NetRun<T>& r, const T* A, const T* Bt, int rows, const float* bias,
+          const float* gbias, int per, const T* mask, T* out) {
+  // two blocks per CU with bf16 weights in LDS, one with fp32
+  const int cap = sizeof(T) == 2 ? 512 : 256;
+  const int want = ((2 * (int)nb(rows, GBM) + 15) / 16) * 16;
+  hipLaunchKernelGGL((k_gemm<T, EPI>), dim3(std::min(want, cap)), dim3(256), 0, r.st, A, Bt, rows,
+                     bias, gbias, per, mask, out);
 }
 
-void gemm_bias_relu(const NetRun& r, const __bf16* A, const __bf16* Bt, int rows, const float* bias,
-                    const float* gbias, int rpg, __bf16* out) {
-  hipLaunchKernelGGL(k_gemm<EPI_BIAS_RELU>, dim3(nb(rows, 64), H / 64), dim3(256), 0, r.st, A, Bt,
-                     rows, bias, gbias, rpg, (const __bf16*)nullptr, out, (float*)nullptr);
-}
-
-void encoder(const NetRun& r, const float* p, const float* P, int rows, float flag,
+template <typename T>
+void encoder(const NetRun<T>& r, const float* p, const float* P, int rows, float flag,
              const size_t* act) {
-  hipLaunchKernelGGL(k_layer1, dim3(nb((size_t)rows * H)), dim3(256), 0, r.st, P, rows, flag,
-                     p + r.o.W1, p + r.o.b1, r.at<__bf16>(act[0]));
+  hipLaunchKernelGGL(k_layer1<T>, dim3(nb((size_t)rows * (H / 8))), dim3(256), 0, r.st, P, rows,
+                     flag,
+                     p + r.o.W1, p + r.o.b1, r.act(act[0]));
   const size_t bias[3] = {r.o.b2, r.o.b3, r.o.b4};
   for (int l = 0; l < 3; ++l)
-    gemm_bias_relu(r, r.at<__bf16>(act[l]), r.wt(l), rows, p + bias[l], nullptr, 1,
-                   r.at<__bf16>(act[l + 1]));
+    gemm<T, EPI_BIAS_RELU>(r, r.act(act[l]), r.wt(l), rows, p + bias[l], nullptr, 1, nullptr,
+                           r.act(act[l + 1]));
 }
 
-void forward_all(const NetRun& r, const float* p, const float* X, const float* Y, float* W0) {
+template <typename T>
+void maxpool(const NetRun<T>& r, const T* F, int per, float* g, int* idx) {
+  const int cpi = cpi_of(per);
+  float* pv = r.part();
+  int* pi = reinterpret_cast<int*>(pv + (size_t)r.batch * cpi * H);
+  hipLaunchKernelGGL(k_pool_part<T>, dim3(cpi, r.batch), dim3(H), 0, r.st, F, per, kChunk, pv, pi);
+  hipLaunchKernelGGL(k_pool_merge, dim3(r.batch), dim3(H), 0, r.st, pv, pi, cpi, g, idx);
+}
+
+template <typename T>
+void forward_all(const NetRun<T>& r, const float* p, const float* X, const float* Y, float* W0) {
   const int RM = r.batch * r.M, RN = r.batch * r.N;
-  net_weights(r, p);
+  hipLaunchKernelGGL(k_cvt_w<T>, dim3(nb(H * H), 4), dim3(256), 0, r.st, p, r.o, r.wn(0));
   encoder(r, p, X, RM, 0.f, r.L.aX);
   encoder(r, p, Y, RN, 1.f, r.L.aY);
-  hipLaunchKernelGGL(k_maxpool, dim3(r.batch), dim3(H), 0, r.st, r.at<__bf16>(r.L.aX[3]), r.M,
-                     r.at<float>(r.L.gX), r.at<int>(r.L.iX));
-  hipLaunchKernelGGL(k_maxpool, dim3(r.batch), dim3(H), 0, r.st, r.at<__bf16>(r.L.aY[3]), r.N,
-                     r.at<float>(r.L.gY), r.at<int>(r.L.iY));
-  hipLaunchKernelGGL(k_head_u, dim3(r.batch), dim3(H), 0, r.st, r.at<float>(r.L.gX),
-                     r.at<float>(r.L.gY), p + r.o.Wb, p + r.o.Wc, p + r.o.bh, r.at<float>(r.L.u));
+  maxpool(r, r.act(r.L.aX[3]), r.M, r.template at<float>(r.L.gX), r.template at<int>(r.L.iX));
+  maxpool(r, r.act(r.L.aY[3]), r.N, r.template at<float>(r.L.gY), r.template at<int>(r.L.iY));
+  hipLaunchKernelGGL(k_head_u, dim3(r.batch), dim3(H), 0, r.st, r.template at<float>(r.L.gX),
+                     r.template at<float>(r.L.gY), p + r.o.Wb, p + r.o.Wc, p + r.o.bh,
+                     r.template at<float>(r.L.u));
   // z = relu(f Wa + u[b])  (the per-instance row bias carries g_X Wb + g_Y Wc + bh)
-  hipLaunchKernelGGL(k_gemm<EPI_BIAS_RELU>, dim3(nb(RM, 64), H / 64), dim3(256), 0, r.st,
-                     r.at<__bf16>(r.L.aX[3]), r.wt(3), RM, (const float*)nullptr,
-                     r.at<float>(r.L.u), r.M, (const __bf16*)nullptr, r.at<__bf16>(r.L.z),
-                     (float*)nullptr);
-  hipLaunchKernelGGL(k_head_out, dim3(nb((size_t)RM * 64)), dim3(256), 0, r.st,
-                     r.at<__bf16>(r.L.z), RM, p + r.o.Wo, p + r.o.bo, W0);
+  gemm<T, EPI_BIAS_RELU>(r, r.act(r.L.aX[3]), r.wt(3), RM, nullptr, r.template at<float>(r.L.u),
+                         r.M, nullptr, r.act(r.L.z));
+  hipLaunchKernelGGL(k_head_out<T>, dim3(nb((size_t)RM * 64)), dim3(256), 0, r.st, r.act(r.L.z),
+                     RM, p + r.o.Wo, p + r.o.bo, W0);
 }
 
-void wgrad(const NetRun& r, const __bf16* Xa, const __bf16* Da, int rows, float* g) {
+// g[W] (and the bias right after it in the parameter array) += X^T D.
+template <typename T>
+void wgrad(const NetRun<T>& r, const T* Xa, const T* Da, int rows, float* g, bool with_bias) {
   const int splits = (rows + kWgradRows - 1) / kWgradRows;
-  hipLaunchKernelGGL(k_wgrad, dim3(H / 64, H / 64, splits), dim3(256), 0, r.st, Xa, Da, rows,
-                     kWgradRows, r.at<float>(r.L.part));
-  hipLaunchKernelGGL(k_reduce_add, dim3(nb(H * H)), dim3(256), 0, r.st, r.at<float>(r.L.part),
-                     splits, (size_t)H * H, g);
+  hipLaunchKernelGGL(k_wgrad<T>, dim3(4 * ((splits + 7) / 8) * 8), dim3(256), 0, r.st, Xa, Da,
+                     rows, kWgradRows, with_bias ? 1 : 0, r.part());
+  const size_t n = (size_t)H * H + (with_bias ? H : 0);
+  hipLaunchKernelGGL(k_reduce_add, dim3(nb(n)), dim3(256), 0, r.st, r.part(), splits,
+                     (size_t)H * H + H, n, g);
 }
 
-void bias_grad(const NetRun& r, const __bf16* D, int rows, float* g) {
-  const int chunks = (rows + 1023) / 1024;
-  hipLaunchKernelGGL(k_colsum_bf16, dim3(chunks), dim3(H), 0, r.st, D, rows, 1024,
-                     r.at<float>(r.L.part));
-  hipLaunchKernelGGL(k_reduce_add, dim3(1), dim3(256), 0, r.st, r.at<float>(r.L.part), chunks,
-                     (size_t)H, g);
-}
-
-// d (bf16, already masked by f > 0) back through layers 4..1 of one set.
-void encoder_back(const NetRun& r, const float* p, float* g, const float* P, int rows,
+// d (already masked by f > 0) back through layers 4..1 of one set; d sits
+// in dA on entry.
+template <typename T>
+void encoder_back(const NetRun<T>& r, const float* p, float* g, const float* P, int per,
                   float flag, const size_t* act) {
-  __bf16* dcur = r.at<__bf16>(r.L.dA);
-  __bf16* dnext = r.at<__bf16>(r.L.dB);
+  const int rows = r.batch * per;
+  T* dcur = r.act(r.L.dA);
+  T* dnext = r.act(r.L.dB);
   const size_t W[3] = {r.o.W2, r.o.W3, r.o.W4};
-  const size_t B[3] = {r.o.b2, r.o.b3, r.o.b4};
   for (int l = 2; l >= 0; --l) {  // layer l+2: input act[l], output act[l+1]
-    wgrad(r, r.at<__bf16>(act[l]), dcur, rows, g + W[l]);
-    bias_grad(r, dcur, rows, g + B[l]);
-    // d_in = (d W^T) * (act[l] > 0): B operand rows are W's rows (k_in), k = n_out
-    hipLaunchKernelGGL(k_gemm<EPI_MASK>, dim3(nb(rows, 64), H / 64), dim3(256), 0, r.st, dcur,
-                       r.wn(l), rows, (const float*)nullptr, (const float*)nullptr, 1,
-                       r.at<__bf16>(act[l]), dnext, (float*)nullptr);
-    __bf16* t = dcur;
+    wgrad(r, r.act(act[l]), dcur, rows, g + W[l], true);
+    // d_in = (d W^T) * (act[l] > 0): the B operand rows are W's rows (k_in)
+    gemm<T, EPI_MASK>(r, dcur, r.wn(l), rows, nullptr, nullptr, 1, r.act(act[l]), dnext);
+    T* t = dcur;
     dcur = dnext;
     dnext = t;
   }
-  hipLaunchKernelGGL(k_dW1, dim3(5), dim3(H), 0, r.st, P, flag, rows, dcur, g + r.o.W1,
-                     g + r.o.b1);
+  const int cpi = cpi_of(per);
+  hipLaunchKernelGGL((k_colsums<T, 3>), dim3(cpi, r.batch), dim3(H), 0, r.st, dcur, P, per,
+                     kChunk, r.part());
+  float* red = r.template at<float>(r.L.red);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nb(4 * H, 16), 1), dim3(256), 0, r.st, r.part(),
+                     r.batch * cpi, 5 * H, 4 * H, red);
+  hipLaunchKernelGGL(k_apply_w1, dim3(1), dim3(H), 0, r.st, red, flag, g + r.o.W1, g + r.o.b1);
 }
 
+template <typename T>
+void loss_grad_all(const NetRun<T>& r, const float* params, const float* X, const float* Y,
+                   const float* V, double beta, float* grad, double* loss_dev) {
+  const int batch = r.batch, M = r.M, N = r.N;
+  const int RM = batch * M, RN = batch * N;
+  const NetOffsets& o = r.o;
+  const NetWs& L = r.L;
+  hipStream_t st = r.st;
+  float* W0 = r.template at<float>(L.W0);
+  forward_all(r, params, X, Y, W0);
+  const float c2 = (float)(kLog2e / (2.0 * beta * beta));
+  // R = Phi W0 - V, the loss; dW0 = 2 Phi R / (B M)
+  const dim3 pg(nb(M, kPhiRows), batch);
+  hipLaunchKernelGGL(k_phi_apply, pg, dim3(256), 0, st, X, W0, M, c2, V, 1.0f,
+                     r.template at<float>(L.R), r.template at<double>(L.lossp));
+  hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(256), 0, st, r.template at<double>(L.lossp),
+                     (int)(pg.x * pg.y), 1.0 / ((double)batch * M), loss_dev);
+  hipLaunchKernelGGL(k_phi_apply, pg, dim3(256), 0, st, X, r.template at<float>(L.R), M, c2,
+                     (const float*)nullptr, (float)(2.0 / ((double)batch * M)),
+                     r.template at<float>(L.dW0), (double*)nullptr);
+  hipLaunchKernelGGL(k_fill, dim3(nb(o.count)), dim3(256), 0, st, grad, o.count, 0.f);
+  // head: gWo, gbo from z and dW0; dz; gWa; du and the pooled-feature grads
+  const float* dW0 = r.template at<float>(L.dW0);
+  const int cpm = cpi_of(M);
+  hipLaunchKernelGGL((k_colsums<T, 3>), dim3(cpm, batch), dim3(H), 0, st, r.act(L.z), dW0, M,
+                     kChunk, r.part());
+  float* red = r.template at<float>(L.red);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(nb(5 * H, 16), 1), dim3(256), 0, st, r.part(),
+                     batch * cpm, 5 * H, 5 * H, red);
+  hipLaunchKernelGGL(k_apply_wo, dim3(1), dim3(H), 0, st, red, grad + o.Wo, grad + o.bo);
+  T* dz = r.act(L.dB);
+  hipLaunchKernelGGL(k_dz<T>, dim3(nb((size_t)RM * (H / 8))), dim3(256), 0, st, dW0, params + o.Wo,
+                     r.act(L.z), RM, dz);
+  wgrad(r, r.act(L.aX[3]), dz, RM, grad + o.Wa, false);
+  hipLaunchKernelGGL((k_colsums<T, 0>), dim3(cpm, batch), dim3(H), 0, st, dz, (const float*)nullptr,
+                     M, kChunk, r.part());
+  hipLaunchKernelGGL(k_sum_chunks, dim3(H / 16, batch), dim3(256), 0, st, r.part(), cpm, 2 * H,
+                     H, r.template at<float>(L.du));
+  hipLaunchKernelGGL(k_head_small_grads, dim3(H + 1), dim3(H), 0, st, r.template at<float>(L.gX),
+                     r.template at<float>(L.gY), r.template at<float>(L.du), batch,
+                     params + o.Wb, params + o.Wc, grad + o.Wb, grad + o.Wc, grad + o.bh,
+                     r.template at<float>(L.dgX), r.template at<float>(L.dgY));
+  // model set: d_f = dz Wa^T * (f > 0) plus the max-pool scatter, then the encoder
+  gemm<T, EPI_MASK>(r, dz, r.wn(3), RM, nullptr, nullptr, 1, r.act(L.aX[3]), r.act(L.dA));
+  hipLaunchKernelGGL(k_pool_scatter<T>, dim3(batch), dim3(H), 0, st, r.template at<float>(L.dgX),
+                     r.template at<int>(L.iX), M, r.act(L.aX[3]), 1, r.act(L.dA));
+  encoder_back(r, params, grad, X, M, 0.f, L.aX);
+  // scene set: only the max-pool scatter
+  const size_t n16 = (size_t)RN * H * sizeof(T) / 16;
+  hipLaunchKernelGGL(k_zero16, dim3(nb(n16)), dim3(256), 0, st, r.template at<u32x4>(L.dA), n16);
+  hipLaunchKernelGGL(k_pool_scatter<T>, dim3(batch), dim3(H), 0, st, r.template at<float>(L.dgY),
+                     r.template at<int>(L.iY), N, r.act(L.aY[3]), 0, r.act(L.dA));
+  encoder_back(r, params, grad, Y, N, 1.f, L.aY);
+}
 }  // namespace
 
 void net_init_launch(float* params, uint64_t seed, float out_scale, hipStream_t st) {
@@ -737,61 +1165,35 @@ void net_synth_launch(float* X, float* Y, float* V, float* Wscratch, int batch, 
   const size_t rows = (size_t)batch * M;
   hipLaunchKernelGGL(k_synth_points, dim3(nb(rows)), dim3(256), 0, st, X, Wscratch, batch, M,
                      seed0, (float)coef, (float)jitter);
-  hipLaunchKernelGGL(k_synth_field, dim3(nb(rows * 64)), dim3(256), 0, st, X, Wscratch, batch, M,
-                     (float)(1.0 / (2.0 * beta * beta)), seed0, (float)outlier_frac, Y, V);
+  hipLaunchKernelGGL(k_phi_apply, dim3(nb(M, kPhiRows), batch), dim3(256), 0, st, X, Wscratch, M,
+                     (float)(kLog2e / (2.0 * beta * beta)), (const float*)nullptr, 1.0f, V,
+                     (double*)nullptr);
+  hipLaunchKernelGGL(k_synth_scene, dim3(nb(rows)), dim3(256), 0, st, X, V, batch, M, seed0,
+                     (float)outlier_frac, Y);
 }
 
 void net_forward_launch(const float* params, const float* X, const float* Y, int batch, int M,
-                        int N, float* W0, char* ws, const NetWs& L, hipStream_t st) {
-  NetRun r{net_offsets(), L, ws, st, batch, M, N};
-  forward_all(r, params, X, Y, W0);
+                        int N, float* W0, char* ws, const NetWs& L, int precision,
+                        hipStream_t st) {
+  if (precision == kNetFp32) {
+    NetRun<float> r{net_offsets(), L, ws, st, batch, M, N};
+    forward_all(r, params, X, Y, W0);
+  } else {
+    NetRun<__bf16> r{net_offsets(), L, ws, st, batch, M, N};
+    forward_all(r, params, X, Y, W0);
+  }
 }
 
 void net_loss_grad_launch(const float* params, const float* X, const float* Y, const float* V,
                           int batch, int M, int N, double beta, float* grad, double* loss_dev,
-                          char* ws, const NetWs& L, hipStream_t st) {
-  NetRun r{net_offsets(), L, ws, st, batch, M, N};
-  const int RM = batch * M, RN = batch * N;
-  const NetOffsets& o = r.o;
-  float* W0 = r.at<float>(L.W0);
-  forward_all(r, params, X, Y, W0);
-  const float inv2b2 = (float)(1.0 / (2.0 * beta * beta));
-  // R = Phi W0 - V, loss; dW0 = 2 Phi R / (B M)
-  hipLaunchKernelGGL(k_phi_mv, dim3(nb((size_t)RM * 64)), dim3(256), 0, st, X, W0, M, RM, inv2b2,
-                     V, 1.0f, r.at<float>(L.R), r.at<double>(L.lossp));
-  hipLaunchKernelGGL(k_sum_d, dim3(1), dim3(256), 0, st, r.at<double>(L.lossp),
-                     (int)nb((size_t)RM * 64), 1.0 / ((double)batch * M), loss_dev);
-  hipLaunchKernelGGL(k_phi_mv, dim3(nb((size_t)RM * 64)), dim3(256), 0, st, X, r.at<float>(L.R), M,
-                     RM, inv2b2, (const float*)nullptr, (float)(2.0 / ((double)batch * M)),
-                     r.at<float>(L.dW0), (double*)nullptr);
-  hipLaunchKernelGGL(k_fill, dim3(nb(o.count)), dim3(256), 0, st, grad, o.count, 0.f);
-  // head
-  const float* dW0 = r.at<float>(L.dW0);
-  hipLaunchKernelGGL(k_dWo, dim3(H + 1), dim3(256), 0, st, r.at<__bf16>(L.z), dW0, RM,
-                     grad + o.Wo, grad + o.bo);
-  hipLaunchKernelGGL(k_dz, dim3(nb((size_t)RM * H)), dim3(256), 0, st, dW0, params + o.Wo,
-                     r.at<__bf16>(L.z), RM, r.at<__bf16>(L.dB));
-  const __bf16* dz = r.at<__bf16>(L.dB);
-  wgrad(r, r.at<__bf16>(L.aX[3]), dz, RM, grad + o.Wa);
-  hipLaunchKernelGGL(k_du, dim3(batch), dim3(H), 0, st, dz, M, r.at<float>(L.du));
-  hipLaunchKernelGGL(k_head_small_grads, dim3(H + 1), dim3(H), 0, st, r.at<float>(L.gX),
-                     r.at<float>(L.gY), r.at<float>(L.du), batch, params + o.Wb, params + o.Wc,
-                     grad + o.Wb, grad + o.Wc, grad + o.bh, r.at<float>(L.dgX),
-                     r.at<float>(L.dgY));
-  // df_X = dz Wa^T (fp32)
-  hipLaunchKernelGGL(k_gemm<EPI_F32>, dim3(nb(RM, 64), H / 64), dim3(256), 0, st, dz, r.wn(3), RM,
-                     (const float*)nullptr, (const float*)nullptr, 1, (const __bf16*)nullptr,
-                     (__bf16*)nullptr, r.at<float>(L.dfX));
-  // model set: (df_X + pool scatter) * (f > 0), then back through the encoder
-  hipLaunchKernelGGL(k_pool_back, dim3(nb((size_t)RM * H)), dim3(256), 0, st,
-                     r.at<float>(L.dfX), r.at<float>(L.dgX), r.at<int>(L.iX), M, RM,
-                     r.at<__bf16>(L.aX[3]), r.at<__bf16>(L.dA));
-  encoder_back(r, params, grad, X, RM, 0.f, L.aX);
-  // scene set: only the pool scatter
-  hipLaunchKernelGGL(k_pool_back, dim3(nb((size_t)RN * H)), dim3(256), 0, st,
-                     (const float*)nullptr, r.at<float>(L.dgY), r.at<int>(L.iY), N, RN,
-                     r.at<__bf16>(L.aY[3]), r.at<__bf16>(L.dA));
-  encoder_back(r, params, grad, Y, RN, 1.f, L.aY);
+                          char* ws, const NetWs& L, int precision, hipStream_t st) {
+  if (precision == kNetFp32) {
+    NetRun<float> r{net_offsets(), L, ws, st, batch, M, N};
+    loss_grad_all(r, params, X, Y, V, beta, grad, loss_dev);
+  } else {
+    NetRun<__bf16> r{net_offsets(), L, ws, st, batch, M, N};
+    loss_grad_all(r, params, X, Y, V, beta, grad, loss_dev);
+  }
 }
 
 void net_adam_launch(float* params, float* m, float* v, const float* grad, int step, float lr,

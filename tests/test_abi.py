@@ -131,3 +131,13 @@ def test_no_device_is_reported():
 def test_status_strings():
     for s in (fc.CPD_OK, fc.CPD_E_ARG, fc.CPD_E_NUMERIC, fc.CPD_E_UNSUPPORTED):
         assert fc.status_name(s).startswith("CPD_")
+
+
+def test_network_workspace_depends_on_precision_and_rejects_unknown_ones():
+    lib = fc.load_library()
+    n16, n32 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.cpdnet_workspace_size(2, 300, 200, fc.CPDNET_BF16, ctypes.byref(n16)) == fc.CPD_OK
+    assert lib.cpdnet_workspace_size(2, 300, 200, fc.CPDNET_FP32, ctypes.byref(n32)) == fc.CPD_OK
+    assert n32.value > n16.value > 0
+    assert lib.cpdnet_workspace_size(2, 300, 200, 7, ctypes.byref(n16)) == fc.CPD_E_ARG
+    assert lib.cpdnet_forward(None, None, None, 1, 10, 10, 7, None, None, 0, None) == fc.CPD_E_ARG

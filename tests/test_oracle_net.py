@@ -83,3 +83,31 @@ def test_bf16_mode_is_close_to_float64():
     L, G = net64.loss_grad(batch, p, 1.0)
     Lb, Gb = net64.loss_grad(batch, p, 1.0, bf16_storage=True)
     assert Lb == pytest.approx(L, rel=3e-2)
+
+
+def test_bf16_weights_alone_move_the_float64_gradients_by_percents():
+    # The bf16 mode's distance from float64 is a property of bf16 storage, not
+    # of any kernel: rounding only the four 256 x 256 weight matrices to
+    # bfloat16, everything else float64, already moves the gradient by a
+    # few percent (8 instances of one model and one scene point).
+    p = net64.init_params(7, out_scale=0.5)
+    rng = np.random.default_rng(8)
+    for n in p:
+        if n.startswith("b"):
+            p[n] = 0.02 * rng.normal(size=p[n].shape)
+    batch = []
+    for _ in range(8):
+        x = rng.normal(size=(1, 3))
+        x /= np.linalg.norm(x)
+        batch.append((x, x + 0.3, 0.2 + 0.05 * rng.normal(size=(1, 3))))
+    q = dict(p)
+    for n in ("W2", "W3", "W4", "Wa"):
+        q[n] = net64.bf16(p[n])
+    L, G = net64.loss_grad(batch, p, 2.0)
+    Lq, Gq = net64.loss_grad(batch, q, 2.0)
+    g, gq = net64.pack(G), net64.pack(Gq)
+    rel = np.linalg.norm(gq - g) / np.linalg.norm(g)
+    assert 5e-3 < rel < 5e-2
+    # the deepest encoder block moves most
+    relW1 = np.linalg.norm(Gq["W1"] - G["W1"]) / np.linalg.norm(G["W1"])
+    assert relW1 > rel

@@ -38,7 +38,8 @@ def test_noalloc_forward_refuses_sizes_beyond_the_scratch(lib):
     import torch
     net = lib.WarmStartNet(seed=5)
     n = ctypes.c_size_t(0)
-    lib._check(lib.load_library().cpdnet_workspace_size(8, 2000, 2000, ctypes.byref(n)))
+    lib._check(lib.load_library().cpdnet_workspace_size(8, 2000, 2000, lib.CPDNET_BF16,
+                                                        ctypes.byref(n)))
     assert n.value > 64 << 20
     X = torch.zeros(8, 2000, 3, device="cuda")
     with pytest.raises(lib.FastCPDError) as e:
