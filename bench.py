@@ -464,7 +464,7 @@ def main():
                          "reference for hardware byte counters)")
     ap.add_argument("--workload", default="surface50k",
                     choices=["surface50k", "batch256", "warm2000", "warmtrain", "table4",
-                             "converge07"],
+                             "converge07", "plain50k"],
                     help="batch256 / warm2000 / table4 / converge07 (surface50k at the "
                          "paper's w = 0.7, eigen-prep and one run to tolerance): that leg "
                          "alone, one JSON line of its own")
@@ -525,6 +525,31 @@ def main():
                           "config": {"workload": "warm2000 training: batch 32 pairs, M=N=2000, "
                                                  "sphere recipe drawn on the device"},
                           "roofline": b["roofline"], "train": b}), flush=True)
+        return
+
+    if args.workload == "plain50k":
+        pair = synth.workload("surface50k")
+        X = torch.as_tensor(pair.X, dtype=torch.float32).cuda().contiguous()
+        Y = torch.as_tensor(pair.Y, dtype=torch.float32).cuda().contiguous()
+        reg = fc.Registration(X, Y, precision="fp32", method="original", beta=pair.beta,
+                              lam=pair.lam, w=pair.w, tol=0.0, max_iter=1000)
+        reg.prepare()
+        k = reg.time_kernels(reps=args.steps)
+        flop = pair.M ** 3 / 3.0
+        log(f"plain50k: {k}")
+        print(json.dumps({"metric": "original CPD (eq. 21) EM iterations/s at M=N=50k",
+                          "value": 1000.0 / k["iteration"], "unit": "EM iters/s", "n_gpus": 1,
+                          "steps": args.steps, "ms_per_step": k["iteration"],
+                          "higher_is_better": True, "dtype": "f64 solve, f32 E-step",
+                          "data": "synthetic",
+                          "config": {"workload": "surface50k, original CPD, FP64 Cholesky"},
+                          "roofline": {"bound": "mfma", "kernel": "M-step (Cholesky, solves, "
+                                                                  "Phi W)",
+                                       "achieved": flop / (k["mstep"] * 1e-3) / 1e12,
+                                       "peak": 78.6, "unit": "TFLOP/s",
+                                       "frac": flop / (k["mstep"] * 1e-3) / 1e12 / 78.6,
+                                       "traffic": None, "flop_model": "M^3 / 3 per iteration"},
+                          "kernels_ms": k}), flush=True)
         return
 
     if args.workload == "converge07":

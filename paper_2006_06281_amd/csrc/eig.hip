@@ -89,7 +89,7 @@ EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start) {
     L.R = take(std::max(nn, nblk * kCholNB * kCholNB * sizeof(double)));
     L.V = take(nn);
     L.phi = take(nn);  // the n x n Rayleigh-Ritz / Gram matrix
-    L.chol = take((size_t)n * kCholNB * sizeof(double));
+    L.chol = take((size_t)n * kCholPanel * sizeof(double));
     L.ritz = take((size_t)n * sizeof(double));
     L.misc = take(((size_t)n * sizeof(int) + 64) + (65 + 8 * (size_t)(n / 2 + 1)) * sizeof(double));
   }

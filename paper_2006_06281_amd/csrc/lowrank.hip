@@ -43,7 +43,7 @@ LowRankLayout lowrank_layout(int M, int K, size_t start) {
   L.S = take((size_t)K * K * sizeof(double));
   L.gpart = take(gram_partial_doubles(M, K) * sizeof(double));
   L.Linv = take((size_t)nblk * kCholBlock * kCholBlock * sizeof(double));
-  L.pan = take((size_t)K * kCholBlock * sizeof(double));
+  L.pan = take((size_t)K * kCholPanel * sizeof(double));
   L.q = take((size_t)K * 4 * sizeof(double));
   L.qchunks = (M + kQRows - 1) / kQRows;
   L.qpart = take((size_t)L.qchunks * K * 4 * sizeof(double));

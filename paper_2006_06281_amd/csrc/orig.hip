@@ -10,12 +10,18 @@
 // beyond FP32's 1/eps, where an FP32 Cholesky breaks down (and iterative
 // refinement from an FP32 factor diverges).
 //
-// Per block column k (width NB = 128):
+// Two-level blocking: panels of NP = 256 columns, each factored as two
+// blocks of NB = 128.  Per block k of a panel:
 //   diag   factor the NB x NB diagonal block in LDS, keep L_kk^-1
-//   panel  P = A[below, k] L_kk^-T             (FP64 tile GEMM)
-//   syrk   A[below, below] -= P P^T, lower tiles only (FP64, 8 x 8 per thread)
-//   store  P back into A's panel
-// then the two triangular solves reuse the saved L_kk^-1 blocks.
+//   panel  P[:, k] = A[below, k] L_kk^-T     (FP64, into the panel buffer)
+//   store  P[:, k] back into A
+//   inner  after the first block: A[below, second block] -= P1 P1^T (the
+//          panel's own second block columns, FP64 matrix cores)
+// then one trailing update with the whole 256-wide panel,
+//   syrk   A[below panel, below panel] -= P P^T, lower tiles only,
+// which re-reads and rewrites the trailing triangle once per 256 columns
+// instead of once per 128.  The two triangular solves reuse the saved
+// L_kk^-1 blocks.
 #include <algorithm>
 
 #include "common.hpp"
@@ -43,7 +49,7 @@ OrigLayout orig_layout(int M, int elem_bytes, size_t start) {
   L.phi = take((size_t)M * M * sizeof(double));
   L.A = take((size_t)M * M * sizeof(double));
   L.rhs = take((size_t)M * 4 * sizeof(double) * 2);     // rhs (z) and w
-  L.misc = take((size_t)M * NB * sizeof(double));       // panel P
+  L.misc = take((size_t)M * kCholPanel * sizeof(double));  // panel P
   L.info = take((size_t)nblk * NB * NB * sizeof(double) + 256);  // L_kk^-1 blocks
   L.end = off;
   return L;
@@ -177,8 +183,8 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
 // through the cache (four threads share a row).
 __global__ __launch_bounds__(256) void k_panel(const double* __restrict__ A, int lda, int k0,
                                                int nb, int rows, const double* __restrict__ Linv,
-                                               double* __restrict__ P, const int* chol_fail,
-                                               const int* done) {
+                                               double* __restrict__ P, int ldp,
+                                               const int* chol_fail, const int* done) {
   __shared__ double sL[NB][NB + 1];  // sL[t][c] = Linv[c][t]
   if (done && *done) return;
   if (*chol_fail) return;
@@ -204,31 +210,41 @@ __global__ __launch_bounds__(256) void k_panel(const double* __restrict__ A, int
 #pragma unroll
   for (int j = 0; j < NB / 4; ++j) {
     const int c = cg + 4 * j;
-    if (c < nb) P[(size_t)gr * NB + c] = acc[j];
+    if (c < nb) P[(size_t)gr * ldp + c] = acc[j];
   }
 }
 
-// Trailing update A[k1+i][k1+j] -= sum_t P[i][t] P[j][t] for i >= j, on the
-// FP64 matrix cores: tiles of 128 x 128 on or below the diagonal, four waves
-// of 64 x 64 (4 x 4 v_mfma_f64_16x16x4f64 accumulators each), the panel rows
-// staged in LDS 16 k at a time.  MFMA operands: A lane l = row l%16, k l/16;
-// B lane l = column l%16, k l/16; D lane l, register r = row 4r + l/16,
-// column l%16.
+// Update A[k1+i][k1+j] -= sum_t P[i][t] P[j][t], t < nb, for i >= j, on the
+// FP64 matrix cores (P row i at P + i ldp).  Tiles of 128 x 128; in the
+// triangle mode (cols = 0) the grid walks the tiles on or below the diagonal
+// of the R x R trailing matrix, in the column mode (cols > 0) the tiles of
+// the first `cols` columns of its R rows (one column tile).  Four waves of
+// 64 x 64 (4 x 4 v_mfma_f64_16x16x4f64 accumulators each); the panel rows
+// are staged in LDS 16 k at a time, double-buffered, the next stage's loads
+// in flight during the current stage's products.  MFMA operands: A lane l =
+// row l%16, k l/16; B lane l = column l%16, k l/16; D lane l, register r =
+// row 4r + l/16, column l%16.
 constexpr int ST = 128, SK = 16;
 typedef double dbl4_t __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256, 2) void k_syrk(double* __restrict__ A, int lda, int k1, int R,
-                                                 const double* __restrict__ P, int nb,
-                                                 const int* chol_fail, const int* done) {
-  __shared__ double sa[SK][ST + 2];
-  __shared__ double sb[SK][ST + 2];
+                                                 int cols, const double* __restrict__ P, int ldp,
+                                                 int nb, const int* chol_fail, const int* done) {
+  __shared__ double sa[2][SK][ST + 2];
+  __shared__ double sb[2][SK][ST + 2];
   if (done && *done) return;
   if (*chol_fail) return;
-  // decode the lower-triangular tile index
-  const int t = blockIdx.x;
-  int bi = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-  while (bi * (bi + 1) / 2 > t) --bi;
-  const int bj = t - bi * (bi + 1) / 2;
+  int bi, bj;
+  if (cols > 0) {
+    bi = blockIdx.x;
+    bj = 0;
+  } else {  // decode the lower-triangular tile index
+    const int t = blockIdx.x;
+    bi = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    while (bi * (bi + 1) / 2 > t) --bi;
+    bj = t - bi * (bi + 1) / 2;
+  }
+  const int ncol = cols > 0 ? cols : R;
   const int i0 = bi * ST, j0 = bj * ST;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -238,26 +254,42 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double* __restrict__ A, int lda
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = dbl4_t{0.0, 0.0, 0.0, 0.0};
-  for (int kk = 0; kk < nb; kk += SK) {
-    // 128 rows x 16 k of each operand: 2048 values, 8 per thread
+  // 128 rows x 16 k of each operand per stage: 2048 values, 8 per thread
+  double va[8], vb[8];
+  auto gload = [&](int kk) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + 256 * q;
       const int r = e >> 4, k = e & 15;
       const int gk = kk + k;
       const int ri = i0 + r, rj = j0 + r;
-      sa[k][r] = (ri < R && gk < nb) ? P[(size_t)ri * NB + gk] : 0.0;
-      sb[k][r] = (rj < R && gk < nb) ? P[(size_t)rj * NB + gk] : 0.0;
+      va[q] = (ri < R && gk < nb) ? P[(size_t)ri * ldp + gk] : 0.0;
+      vb[q] = (rj < ncol && gk < nb) ? P[(size_t)rj * ldp + gk] : 0.0;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      sa[buf][e & 15][e >> 4] = va[q];
+      sb[buf][e & 15][e >> 4] = vb[q];
+    }
+  };
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kk = 0; kk < nb; kk += SK) {
+    const bool more = kk + SK < nb;
+    if (more) gload(kk + SK);
 #pragma unroll
     for (int ks = 0; ks < SK / 4; ++ks) {
       const int k = 4 * ks + lk;
       double x[4], y[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        x[q] = sa[k][wr + 16 * q + li];
-        y[q] = sb[k][wc + 16 * q + li];
+        x[q] = sa[buf][k][wr + 16 * q + li];
+        y[q] = sb[buf][k][wc + 16 * q + li];
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -265,7 +297,9 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double* __restrict__ A, int lda
         for (int b = 0; b < 4; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], acc[a][b], 0, 0, 0);
     }
+    if (more) sstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -276,21 +310,21 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double* __restrict__ A, int lda
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int j = j0 + wc + 16 * b + li;
-        if (j <= i) A[(size_t)(k1 + i) * lda + k1 + j] -= acc[a][b][r];
+        if (j <= i && j < ncol) A[(size_t)(k1 + i) * lda + k1 + j] -= acc[a][b][r];
       }
     }
 }
 
 __global__ __launch_bounds__(256) void k_store_panel(double* __restrict__ A, int lda, int k0,
                                                      int nb, int rows,
-                                                     const double* __restrict__ P,
+                                                     const double* __restrict__ P, int ldp,
                                                      const int* chol_fail, const int* done) {
   if (done && *done) return;
   if (*chol_fail) return;
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)rows * nb) return;
   const int r = (int)(e / nb), c = (int)(e % nb);
-  A[(size_t)(k0 + nb + r) * lda + k0 + c] = P[(size_t)r * NB + c];
+  A[(size_t)(k0 + nb + r) * lda + k0 + c] = P[(size_t)r * ldp + c];
 }
 
 // ------------------------------------------------------- triangular solves
@@ -439,23 +473,35 @@ void orig_prepare(const P4<T>* X, int M, double beta, char* ws, const OrigLayout
 
 void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int* chol_fail,
                          const int* done, hipStream_t st) {
-  const int nblk = (n + NB - 1) / NB;
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int k0 = kb * NB;
-    const int nb = std::min(NB, n - k0);
-    double* Li = Linv + (size_t)kb * NB * NB;
-    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, st, A, lda, k0, nb, Li, chol_fail,
-                       done);
-    const int R = n - k0 - nb;
-    if (R <= 0) continue;
-    hipLaunchKernelGGL(k_panel, dim3((R + 63) / 64), dim3(256), 0, st, A, lda, k0, nb, R, Li, P,
-                       chol_fail, done);
-    const int T_ = (R + ST - 1) / ST;
-    hipLaunchKernelGGL(k_syrk, dim3(T_ * (T_ + 1) / 2), dim3(256), 0, st, A, lda, k0 + nb, R, P,
-                       nb, chol_fail, done);
-    const size_t cnt = (size_t)R * nb;
-    hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, A,
-                       lda, k0, nb, R, P, chol_fail, done);
+  constexpr int NP = kCholPanel;
+  for (int K0 = 0; K0 < n; K0 += NP) {
+    const int w = std::min(NP, n - K0);
+    // P row r holds row K0 + NB + r of the factor's panel columns
+    for (int k0 = K0; k0 < K0 + w; k0 += NB) {
+      const int kb = k0 / NB;
+      const int nb = std::min(NB, K0 + w - k0);
+      double* Li = Linv + (size_t)kb * NB * NB;
+      hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, st, A, lda, k0, nb, Li, chol_fail,
+                         done);
+      const int R = n - k0 - nb;
+      if (R <= 0) break;
+      double* Pk = P + (size_t)(k0 - K0) * NP + (k0 - K0);  // rows from k0 + nb, columns k0 - K0
+      hipLaunchKernelGGL(k_panel, dim3((R + 63) / 64), dim3(256), 0, st, A, lda, k0, nb, R, Li,
+                         Pk, NP, chol_fail, done);
+      const size_t cnt = (size_t)R * nb;
+      hipLaunchKernelGGL(k_store_panel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, A,
+                         lda, k0, nb, R, Pk, NP, chol_fail, done);
+      const int rest = K0 + w - (k0 + nb);  // columns of this panel still to factor
+      if (rest > 0)
+        hipLaunchKernelGGL(k_syrk, dim3((R + ST - 1) / ST), dim3(256), 0, st, A, lda, k0 + nb, R,
+                           rest, Pk, NP, nb, chol_fail, done);
+    }
+    const int R2 = n - K0 - w;
+    if (R2 <= 0) continue;
+    const int T_ = (R2 + ST - 1) / ST;
+    const double* Pt = P + (size_t)(w - NB) * NP;  // rows from K0 + w
+    hipLaunchKernelGGL(k_syrk, dim3(T_ * (T_ + 1) / 2), dim3(256), 0, st, A, lda, K0 + w, R2, 0,
+                       Pt, NP, w, chol_fail, done);
   }
 }
 

@@ -7,6 +7,7 @@
 namespace fcpd {
 
 constexpr int kCholBlock = 128;
+constexpr int kCholPanel = 2 * kCholBlock;  // panel width of the two-level blocking
 
 struct OrigLayout {
   size_t end = 0;
@@ -28,10 +29,11 @@ template <typename T> struct OrigArgs {
   P4<T>* Xnew;
   P4<T>* W;
 };
-// Blocked right-looking Cholesky (block width kCholBlock) of the lower
-// triangle of the n x n FP64 matrix A (row stride lda), in place.  Linv
-// receives the inverses of the diagonal blocks (ceil(n / NB) blocks of
-// NB x NB, row-major, lower), P is panel scratch of n x NB doubles.  A pivot
+// Blocked right-looking Cholesky (panels of kCholPanel columns, each factored
+// as blocks of kCholBlock) of the lower triangle of the n x n FP64 matrix A
+// (row stride lda), in place.  Linv receives the inverses of the diagonal
+// blocks (ceil(n / NB) blocks of NB x NB, row-major, lower), P is panel
+// scratch of n x kCholPanel doubles.  A pivot
 // that is not positive sets *chol_fail and the remaining launches return at
 // once; with done != NULL nothing runs while *done is set.
 void chol_blocked_launch(double* A, int lda, int n, double* Linv, double* P, int* chol_fail,
