@@ -96,6 +96,20 @@ def roofline_of(kern, pairs, precision):
             "stages": out}
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count()}
+
+
 def cpu_baseline(pair, K, rows=20000):
     """The FP64 oracle as it stands, timed on this host on a bounded sample:
     the E-step and the sigma^2 pass on `rows` model rows against all scene
@@ -117,7 +131,9 @@ def cpu_baseline(pair, K, rows=20000):
     t_m = time.perf_counter() - t0
     per_iter = t_pairs + t_m
     return {"value": 1.0 / per_iter, "unit": "EM iters/s", "cores": cpd64.threads(),
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
+            "threads_note": "oracle thread pool = min(16, host CPUs); the GPU box allots 16 "
+                            "host cores to one GPU",
             "sample": f"E-step + sigma^2 pass on {rows} of {M} model rows x {N} scene "
                       f"points scaled to M x N, plus one full Fast M-step (K={K}); "
                       f"{per_iter:.2f} s per iteration extrapolated"}
@@ -139,6 +155,77 @@ def converge_run(reg, pair, t_eig):
             "t_o_s": out.t_o, "rmse_eq22": rmse}
 
 
+PEAK_HBM_GBPS = 8000.0
+
+
+def mstep_roofline(kern, M, K, elem=4):
+    """The Fast M-step reads U (M x K) twice per iteration (U^T R, then
+    U (h o T)); its algorithmic bytes are 2 M K elem, against HBM."""
+    t = kern["mstep"] * 1e-3
+    ach = 2.0 * M * K * elem / t / 1e9
+    return {"bound": "hbm", "kernel": "Fast M-step (U^T R, U (h o T))", "achieved": ach,
+            "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBPS,
+            "traffic": None, "bytes_model": "2 M K x 4 B (U read twice)", "avg_us": t * 1e6}
+
+
+def fast_full_leg(fc, torch, X, Y, pair, precision):
+    """Fast CPD with every eigenpair that is not round-off (FULL mode, eq. 17)
+    at 50k: eigen-prep, per-iteration rate, and time-to-converge as configured
+    (w = 0.2) and at the paper's w = 0.7 (the eigenpairs imported, not
+    recomputed)."""
+    kw = dict(precision=precision, beta=pair.beta, lam=pair.lam, w=pair.w, eig_mode="full",
+              tol=1e-8, max_iter=1000)
+    reg = fc.Registration(X, Y, **kw)
+    _, _, s2_0 = reg.state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reg.prepare()
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    K = reg.K
+    log(f"fast full 50k: eigen-prep {t_eig:.3f}s K={K} truncated={reg.eig_truncated}")
+    reg.time_kernels(reps=5)
+    reg.set_state(X, s2_0)
+    kern = reg.time_kernels(reps=10)
+    reg.set_state(X, s2_0)
+    out = {"K": K, "truncated": reg.eig_truncated, "t_eig_s": t_eig, "kernels_ms": kern,
+           "em_iters_per_s": 1000.0 / kern["iteration"],
+           "mstep_roofline": mstep_roofline(kern, pair.M, K)}
+    out["converge_w0.2"] = converge_run(reg, pair, t_eig)
+    U, lam = reg.export_eig()
+    reg.close()
+    reg7 = fc.Registration(X, Y, **dict(kw, w=0.7, eig_mode="import", K=K))
+    reg7.prepare(U=U, lam=lam)
+    out["converge_w0.7"] = converge_run(reg7, pair, t_eig)
+    reg7.close()
+    del U, lam
+    torch.cuda.empty_cache()
+    log(f"fast full 50k: {out['converge_w0.2']} / {out['converge_w0.7']}")
+    return out
+
+
+def train_net(fc, torch, M=2000, batch=32, triples=100_000, beta=2.0):
+    """The warm-start network trained on the device's sphere recipe (cfg5:
+    unit-sphere model + N(0, 0.01^2) jitter, RBF field with coefficients
+    N(0, s^2), s = 0.3 sqrt(500 / M), 10% uniform outliers), bf16 kernels,
+    Adam with a stepped learning rate."""
+    coef = 0.3 * np.sqrt(500.0 / M)
+    net = fc.WarmStartNet(seed=1)
+    steps = -(-triples // batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(steps):
+        lr = 1e-3 if step < 0.6 * steps else (3e-4 if step < 0.85 * steps else 1e-4)
+        X, Y, V = fc.synth_pairs(batch, M, beta=beta, coef=coef, seed0=10_000_000 + batch * step)
+        last = step == steps - 1 or step % 500 == 0
+        loss = net.train_step(X, Y, V, beta=beta, lr=lr, want_loss=last)
+        if last:
+            log(f"warm: train step {step}/{steps} loss {loss:.4f}")
+    torch.cuda.synchronize()
+    return net, {"train_triples": steps * batch, "train_batch": batch,
+                 "train_s": time.perf_counter() - t0, "train_loss_last": loss}
+
+
 def plain_cpd_legs(fc, torch, X, Y, pair, kw, fast_ms_step):
     """The original CPD M-step (eq. 21) on the same GPU.
 
@@ -158,6 +245,13 @@ def plain_cpd_legs(fc, torch, X, Y, pair, kw, fast_ms_step):
     out["surface50k_mstep_ms"] = k["mstep"]
     out["surface50k_em_iters_per_s"] = 1000.0 / k["iteration"]
     out["fast_over_plain_iter_rate"] = k["iteration"] / fast_ms_step
+    flop = pair.M ** 3 / 3.0
+    ach = flop / (k["mstep"] * 1e-3) / 1e12
+    out["mstep_roofline"] = {"bound": "mfma", "kernel": "original M-step (FP64 Cholesky, "
+                                                         "solves, Phi W)",
+                             "achieved": ach, "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": ach / 78.6, "traffic": None,
+                             "flop_model": "M^3 / 3 per iteration (the factorisation)"}
     reg.close()
     del reg
     torch.cuda.empty_cache()
@@ -284,19 +378,7 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
     and from the network's W0.  RMSE is against the true position x_m + v_m
     of every model point."""
     coef = 0.3 * np.sqrt(500.0 / M)
-    net = fc.WarmStartNet(seed=1)
-    steps = -(-triples // batch)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss = float("nan")
-    for step in range(steps):
-        lr = 1e-3 if step < 0.6 * steps else (3e-4 if step < 0.85 * steps else 1e-4)
-        X, Y, V = fc.synth_pairs(batch, M, beta=beta, coef=coef, seed0=10_000_000 + batch * step)
-        loss = net.train_step(X, Y, V, beta=beta, lr=lr)
-        if step % 250 == 0 or step == steps - 1:
-            log(f"warm: train step {step}/{steps} loss {loss:.3f}")
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    net, tr = train_net(fc, torch, M=M, batch=batch, triples=triples, beta=beta)
     acc = {k: [] for k in ("it0", "itw", "cv0", "cvw", "r0", "rw", "i0", "iw")}
     t_run0 = t_runw = t_net = t_prep = 0.0
     for c0 in range(0, held_out, chunk):
@@ -342,8 +424,7 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
             "workload": f"warm{M}: M=N={M}, D=3, unit sphere + N(0,0.01^2), RBF field beta={beta:g} "
                         f"coef N(0,{coef:.4f}^2), 10% outliers; lambda={lam:g}, w={w:g}; "
                         f"Fast CPD FULL eig, FP32, tol 1e-8",
-            "train_triples": steps * batch, "train_batch": batch, "train_s": t_train,
-            "train_loss_last": loss, "held_out": held_out,
+            **tr, "held_out": held_out,
             "net_forward_s": t_net, "prepare_s": t_prep,
             "iters_mean_w0": float(a["it0"].mean()), "iters_mean_net": float(a["itw"].mean()),
             "iters_median_w0": float(np.median(a["it0"])),
@@ -459,6 +540,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-converge", action="store_true", help="skip time-to-converge")
     ap.add_argument("--no-plain", action="store_true", help="skip the original-CPD comparator")
+    ap.add_argument("--no-full", action="store_true", help="skip Fast CPD with all eigenpairs")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run two 256 MiB device-to-device copies first (a known-size "
                          "reference for hardware byte counters)")
@@ -482,10 +565,19 @@ def main():
     if args.workload == "batch256":
         b = batch_leg(fc, torch)
         log(f"batch: {b}")
+        slots = SLOTS[("fp32", "passA")] + SLOTS[("fp32", "passB")]
+        ach = b["pair_updates_per_s"] * slots * 2.0 / 1e12
         print(json.dumps({"metric": "batched Fast CPD: instance EM iterations/s",
                           "value": b["instance_iters_per_s"], "unit": "instance EM iters/s",
                           "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
                           "data": "synthetic", "config": {"workload": b["workload"]},
+                          "roofline": {"bound": "alu", "kernel": "whole batched run (E-step "
+                                                                 "passes dominate)",
+                                       "achieved": ach, "peak": PEAK_VALU_FP32_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": ach / PEAK_VALU_FP32_TFLOPS,
+                                       "traffic": None,
+                                       "flop_model": f"{slots} FP32 vector slots per pair and "
+                                                     "EM iteration (pass A + pass B, exp = 4)"},
                           "batch": b}), flush=True)
         return
 
@@ -506,11 +598,18 @@ def main():
     if args.workload == "warm2000":
         b = warm_leg(fc, torch)
         log(f"warm: {b}")
+        ach = net_gemm_flop(2000, 2000) * b["train_triples"] / b["train_s"] / 1e12
         print(json.dumps({"metric": "learned warm start: mean EM iterations to tolerance, "
                                     "held-out pairs",
                           "value": b["iters_mean_net"], "unit": "EM iterations",
                           "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 net, f32 EM",
                           "data": "synthetic", "config": {"workload": b["workload"]},
+                          "roofline": {"bound": "mfma", "kernel": "network training (all "
+                                                                  "kernels of a step)",
+                                       "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS,
+                                       "traffic": None,
+                                       "flop_model": "3 x (3 (M + N) + M) x 2 x 256^2 per pair"},
                           "warm_start": b}), flush=True)
         return
 
@@ -653,6 +752,62 @@ def main():
     pairs = pair.M * pair.N
     roofline = roofline_of(kern, pairs, args.precision)
 
+    full = None
+    if not args.no_full:
+        full = fast_full_leg(fc, torch, X, Y, pair, args.precision)
+
+    warm = None
+    if not args.no_warm:
+        net, tr = train_net(fc, torch)
+        warm = {"train": tr, "at_50k": warm_at_50k(fc, torch, net, 2000, 2.0)}
+        del net
+        torch.cuda.empty_cache()
+
+    # The metric's four rows at M = N = 50k, one GPU.  Time-to-converge is
+    # t_eig + the run to |dsigma^2| < 1e-8 (null when 1000 iterations do not
+    # get there); "w=0.7" is the same inputs at the paper's outlier weight.
+    def _ttc(c):
+        return None if c is None else c["time_to_converge_s"]
+    modes = {
+        "fast_topk": {"K": K, "em_iters_per_s": 1000.0 / ms_step,
+                      "time_to_converge_s": {w: _ttc(c) for w, c in (conv or {}).items()},
+                      "iters": {w: c["iters"] for w, c in (conv or {}).items()},
+                      "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit",
+                                                            "frac")},
+                      "mstep_roofline": mstep_roofline(kern, pair.M, K)},
+    }
+    if full:
+        modes["fast_full"] = {
+            "K": full["K"], "truncated": full["truncated"],
+            "em_iters_per_s": full["em_iters_per_s"],
+            "time_to_converge_s": {"w=0.2": _ttc(full["converge_w0.2"]),
+                                   "w=0.7": _ttc(full["converge_w0.7"])},
+            "iters": {"w=0.2": full["converge_w0.2"]["iters"],
+                      "w=0.7": full["converge_w0.7"]["iters"]},
+            "roofline": roofline_of(full["kernels_ms"], pairs, args.precision)["stages"]["passB"],
+            "mstep_roofline": full["mstep_roofline"]}
+    if warm:
+        s7 = warm["at_50k"]["surface50k_w0.7"]
+        modes["warm_start"] = {
+            "em_iters_per_s": 1000.0 / ms_step,
+            "time_to_converge_s": {"w=0.7": s7["net"]["time_to_converge_s"],
+                                   "w=0.7 from W=0": s7["w0"]["time_to_converge_s"]},
+            "iters": {"w=0.7": s7["net"]["iters"], "w=0.7 from W=0": s7["w0"]["iters"]},
+            "net_forward_s": s7["net_forward_s"],
+            "note": "network trained on the sphere recipe at M=N=2000 (out of distribution "
+                    "here); the in-distribution 50k case is in warm_start.at_50k.sphere50k",
+            "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac")}}
+    if plain:
+        it7 = (conv or {}).get("w=0.7", {}).get("iters")
+        modes["plain_cpd"] = {
+            "em_iters_per_s": plain["surface50k_em_iters_per_s"],
+            "time_to_converge_s": {"w=0.7 (extrapolated)":
+                                   None if it7 is None else it7 * plain["surface50k_ms_per_iter"] / 1e3},
+            "extrapolation": "per-iteration time of original CPD at 50k x the iteration count "
+                             "of Fast CPD top-K on the same inputs at w=0.7 (at 10k the oracle "
+                             "takes 81 iterations for original CPD and 86 for Fast CPD)",
+            "roofline": plain["mstep_roofline"]}
+
     cpu = None
     if not args.no_cpu:
         t0 = time.perf_counter()
@@ -670,7 +825,8 @@ def main():
                    "M": pair.M, "N": pair.N, "D": 3, "K": K, "method": "fast-topk",
                    "precision": args.precision, "parallelism": "single-gpu"},
         "converge": conv, "kernels_ms": kern, "roofline": roofline, "cpu_baseline": cpu,
-        "plain_cpd": plain,
+        "modes": modes, "plain_cpd": plain, "fast_full": full, "warm_start": warm,
+        "host": host_cpu(),
     }
     print(json.dumps(rec), flush=True)
 

@@ -141,7 +141,12 @@ cpd_status cpd_init(cpd_handle* h, const cpd_params* p, const void* X,
 /* One-time preparation before the iterations (Section III, eq. 16 and 19).
  *   FAST + FULL   all eigenpairs of Phi (Jacobi on the dense Phi up to 1024
  *                 points; above that, randomized subspace iteration whose width
- *                 grows until the trailing Ritz value is round-off of lam_1).
+ *                 grows until the trailing Ritz value is round-off of lam_1,
+ *                 at most 2048 columns: when even that basis ends above
+ *                 round-off (slow spectral decay: small beta, many points)
+ *                 the call returns CPD_NOT_CONVERGED, keeps the top 2016
+ *                 pairs (the handle is usable, eq. 19 instead of eq. 16) and
+ *                 cpd_last_error names the trailing Ritz value).
  *   FAST + TOPK   the K largest eigenpairs: randomized range finder with
  *                 power_iters subspace iterations and a Rayleigh-Ritz step on
  *                 K + oversample columns.  omega (device, M x (K+oversample)

@@ -210,8 +210,10 @@ def cpd_init(p: cpd_params, X, Y, workspace, stream=None):
     return h
 
 
-def cpd_eig_prepare(h, U=None, lam=None, omega=None):
-    _check(load_library().cpd_eig_prepare(h, _ptr(U), _ptr(lam), _ptr(omega)), h)
+def cpd_eig_prepare(h, U=None, lam=None, omega=None) -> int:
+    """CPD_OK, or CPD_NOT_CONVERGED for a FULL decomposition cut at its cap."""
+    return _check(load_library().cpd_eig_prepare(h, _ptr(U), _ptr(lam), _ptr(omega)), h,
+                  ok=(CPD_OK, CPD_NOT_CONVERGED))
 
 
 def cpd_eig_count(h) -> int:
@@ -467,7 +469,14 @@ class Registration:
         self.device = X.device
 
     def prepare(self, U=None, lam=None, omega=None):
-        cpd_eig_prepare(self.h, U, lam, omega)
+        """Eigen-prep.  A FULL decomposition cut at its width cap (status
+        CPD_NOT_CONVERGED) sets eig_truncated and eig_message and warns."""
+        st = cpd_eig_prepare(self.h, U, lam, omega)
+        self.eig_truncated = st == CPD_NOT_CONVERGED
+        self.eig_message = last_error(self.h) if self.eig_truncated else ""
+        if self.eig_truncated:
+            import warnings
+            warnings.warn(self.eig_message)
         return self
 
     @property

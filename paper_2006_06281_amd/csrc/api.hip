@@ -597,10 +597,18 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     int K = 0;
     std::string msg;
     const int rc = eig_prepare_run(r, &K, &msg);
-    if (rc != 0)
+    if (rc != 0 && rc != 4)
       return fail(h, rc == 1 ? CPD_E_NUMERIC : (rc == 3 ? CPD_E_UNSUPPORTED : CPD_E_DEVICE), msg);
     h->K = K;
     convert_u_launch<T>(h->at<double>(L.U64), h->at<T>(L.U), (size_t)h->p.M * K, h->st);
+    if (rc == 4) {  // usable, but truncated: reported, not hidden
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipStreamSynchronize(h->st));
+      h->t_eig = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      h->stage = Stage::Prepared;
+      fail(h, CPD_NOT_CONVERGED, msg);
+      return CPD_NOT_CONVERGED;
+    }
   }
   HIPCHK(h, hipGetLastError());
   HIPCHK(h, hipStreamSynchronize(h->st));

@@ -1115,7 +1115,16 @@ int run(const EigRun& r, int* K_out, std::string* msg) {
       (void)hipMemcpyAsync(&v[1], c.r.lam + (K - 1), sizeof(double), hipMemcpyDeviceToHost, c.st);
       (void)hipStreamSynchronize(c.st);
       *K_out = K;
-      if (std::fabs(v[1]) <= 1e-14 * std::fabs(v[0]) || n >= nmax) return 0;
+      if (std::fabs(v[1]) <= 1e-14 * std::fabs(v[0])) return 0;
+      if (n >= nmax) {  // the widest basis did not reach round-off: truncated
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "FULL eigen-prep stopped at its %d-pair cap with the trailing Ritz value at "
+                      "%.3g of lam_1 (not round-off): the decomposition is truncated",
+                      K, std::fabs(v[1]) / std::fabs(v[0]));
+        *msg = buf;
+        return 4;
+      }
       n = std::min(nmax, 2 * n);
     }
   }

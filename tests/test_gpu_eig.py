@@ -146,3 +146,26 @@ def test_full_mode_above_dense_limit(lib):
     err = cpd64.rel_rms(host(out.Xt), ref.Xt)
     say("rel_rms", err)
     assert err < 1e-5
+
+
+def test_full_mode_reports_a_truncated_decomposition(lib):
+    """Above 1024 points FULL mode widens its randomized basis up to 2048
+    columns.  With a narrow kernel (beta = 0.05 on 3000 unit-sphere points)
+    Phi's spectrum decays slowly and even that basis ends far above
+    round-off: the call must say so (CPD_NOT_CONVERGED, a message naming the
+    trailing Ritz value) and leave a usable top-2016 decomposition
+    (orthonormal vectors, eigenvalues descending within Phi's trace)."""
+    import torch
+    p = synth.sphere_pair(M=3000, seed=21)
+    say("truncated FULL, M", p.M, "beta 0.05")
+    r = lib.Registration(dev(p.X, torch.float64), dev(p.Y, torch.float64), precision="fp64",
+                         beta=0.05, lam=p.lam, w=p.w, eig_mode="full", tol=0.0, max_iter=2)
+    with pytest.warns(UserWarning, match="truncated"):
+        r.prepare()
+    assert r.eig_truncated and "trailing Ritz value" in r.eig_message
+    U, lam = (host(t) for t in r.export_eig())
+    assert U.shape[1] == r.K == 2016
+    assert lam[-1] > 1e-6 * lam[0]
+    assert np.all(np.diff(lam) <= 0) and lam.sum() <= p.M
+    assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-10
+    r.step()  # still usable
