@@ -83,8 +83,8 @@ typedef enum {
    per-point array in its own order; the permutation is internal) and the
    E-step skips tile pairs (64-point tiles in FP32 / FP64, 16-point tiles in
    BF16X) whose exponentials all underflow to +0, which leaves every result
-   bit-identical to the unskipped computation on the same order.  Batched
-   instances never reorder or skip. */
+   bit-identical to the unskipped computation on the same order.  Batch
+   members do the same per instance. */
 #define CPD_FLAG_NO_SORT 1       /* keep the caller's order (implies NO_CULL)   */
 #define CPD_FLAG_NO_CULL 2       /* sort, but evaluate every tile               */
 
@@ -270,12 +270,14 @@ cpd_status cpd_batch_prepare(cpd_batch hb, int32_t tune);
 /* Iterate all instances from their start state until each has converged or
  * reached its max_iter.  W0_packed (device, nullable, sum M_i x 3) starts
  * instance i at Xt = X + Phi W0_i with the standard sigma^2 start at that Xt
- * (warm start); NULL starts at Xt = X.  X_out_packed (device, nullable)
- * receives every Xt;
+ * (warm start); NULL starts at Xt = X.  sigma2_start (host, nullable, B
+ * values) overrides the start of sigma^2 for every instance whose entry is
+ * > 0 (a warm start that knows its expected error); entries <= 0 keep the
+ * default.  X_out_packed (device, nullable) receives every Xt;
  * res (host, nullable, B entries) gets per-instance iterations, convergence
  * and sigma^2, with t_eig per instance and t_o = the whole batched run. */
-cpd_status cpd_batch_register(cpd_batch hb, const float* W0_packed, float* X_out_packed,
-                              cpd_result* res);
+cpd_status cpd_batch_register(cpd_batch hb, const float* W0_packed, const double* sigma2_start,
+                              float* X_out_packed, cpd_result* res);
 
 /* The split length the tuner chose and the per-candidate iteration times
  * (ms, candidates 1024, 2048, 512, 4096; 0 when not tuned). */
@@ -333,14 +335,18 @@ cpd_status cpdnet_loss_grad(const float* params, const float* X, const float* Y,
  * are param_count floats each; step counts from 1. */
 cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int32_t step,
                        float lr, void* hip_stream);
-/* Training pairs on the device from the 500-point sphere recipe at any M:
- * X = unit-sphere directions + N(0, jitter^2), W* ~ N(0, coef^2),
+/* Training pairs on the device at any M: model points on the unit sphere
+ * (CPDNET_SHAPE_SPHERE, the 500-point recipe) or on a surface without
+ * symmetries, r(u) = 1 + six Gaussian bumps of random centre and height
+ * N(0, 0.25^2) (CPDNET_SHAPE_BUMPS), plus N(0, jitter^2); W* ~ N(0, coef^2),
  * V* = Phi W* (displacement of every model point), Y = X + V* with a
  * fraction outlier_frac of rows replaced by U[-1.5, 1.5]^3 (N = M).
  * Instance b draws from counter-based stream seed0 + b.  W_scratch holds W*. */
+#define CPDNET_SHAPE_SPHERE 0
+#define CPDNET_SHAPE_BUMPS 1
 cpd_status cpdnet_synth(float* X, float* Y, float* V, float* W_scratch, int32_t batch, int32_t M,
-                        double beta, double coef, double jitter, double outlier_frac,
-                        uint64_t seed0, void* hip_stream);
+                        int32_t shape, double beta, double coef, double jitter,
+                        double outlier_frac, uint64_t seed0, void* hip_stream);
 
 const char* cpd_status_str(cpd_status s);
 const char* cpd_last_error(cpd_handle h);   /* h may be NULL: global message */

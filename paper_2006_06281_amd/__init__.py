@@ -29,6 +29,8 @@ CPD_PREC_FP64, CPD_PREC_FP32, CPD_PREC_BF16X = 0, 1, 2
 CPD_EIG_FULL, CPD_EIG_TOPK, CPD_EIG_IMPORT = 0, 1, 2
 CPD_FLAG_NO_SORT, CPD_FLAG_NO_CULL = 1, 2
 CPDNET_BF16, CPDNET_FP32 = 0, 1
+CPDNET_SHAPE_SPHERE, CPDNET_SHAPE_BUMPS = 0, 1
+SHAPES = {"sphere": CPDNET_SHAPE_SPHERE, "bumps": CPDNET_SHAPE_BUMPS}
 NET_PRECISIONS = {"bf16": CPDNET_BF16, "fp32": CPDNET_FP32}
 
 METHODS = {"original": CPD_METHOD_ORIGINAL, "fast": CPD_METHOD_FAST,
@@ -114,7 +116,7 @@ def load_library(path: str = LIB_PATH):
         "cpd_batch_init": ([P(vp), ctypes.c_int32, P(cpd_params), vp, vp, P(ctypes.c_int64),
                             P(ctypes.c_int64), vp, sz, vp], ctypes.c_int),
         "cpd_batch_prepare": ([vp, ctypes.c_int32], ctypes.c_int),
-        "cpd_batch_register": ([vp, vp, vp, P(cpd_result)], ctypes.c_int),
+        "cpd_batch_register": ([vp, vp, vp, vp, P(cpd_result)], ctypes.c_int),
         "cpd_batch_info": ([vp, P(ctypes.c_int32), P(ctypes.c_double)], ctypes.c_int),
         "cpd_batch_destroy": ([vp], ctypes.c_int),
         "cpdnet_param_count": ([P(sz)], ctypes.c_int),
@@ -129,9 +131,9 @@ def load_library(path: str = LIB_PATH):
                               ctypes.c_int32, ctypes.c_double, vp, P(ctypes.c_double), vp, sz,
                               vp], ctypes.c_int),
         "cpdnet_adam": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp], ctypes.c_int),
-        "cpdnet_synth": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, vp],
-                         ctypes.c_int),
+        "cpdnet_synth": ([vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_uint64, vp], ctypes.c_int),
         "cpd_status_str": ([ctypes.c_int], ctypes.c_char_p),
         "cpd_last_error": ([vp], ctypes.c_char_p),
         "cpd_abi_version": ([], ctypes.c_int32),
@@ -322,13 +324,15 @@ class BatchRegistration:
         _check(load_library().cpd_batch_info(self.h, ctypes.byref(c), t))
         return c.value, dict(zip((1024, 2048, 512, 4096), list(t)))
 
-    def register(self, W0=None):
+    def register(self, W0=None, sigma2=None):
         """W0: optional packed (sum M_i x 3) float32 CUDA tensor of warm-start
-        coefficients."""
+        coefficients; sigma2: optional per-instance starting sigma^2 (values
+        <= 0 keep the default start)."""
         import torch
         out = torch.empty_like(self.Xp)
         res = (cpd_result * self.B)()
-        _check(load_library().cpd_batch_register(self.h, _ptr(W0), _ptr(out), res),
+        s2 = None if sigma2 is None else (ctypes.c_double * self.B)(*[float(v) for v in sigma2])
+        _check(load_library().cpd_batch_register(self.h, _ptr(W0), s2, _ptr(out), res),
                ok=(CPD_OK, CPD_NOT_CONVERGED))
         Xt = [out[self._xo[i]:self._xo[i + 1]] for i in range(self.B)]
         return Xt, list(res)
@@ -423,14 +427,16 @@ class WarmStartNet:
 
 
 def synth_pairs(batch, M, beta=2.0, coef=0.15, jitter=0.01, outlier_frac=0.10, seed0=0,
-                device="cuda"):
-    """Training pairs drawn on the device (see cpdnet_synth): X, Y, V (batch, M, 3)."""
+                device="cuda", shape="sphere"):
+    """Training pairs drawn on the device (see cpdnet_synth): X, Y, V (batch, M, 3);
+    shape "sphere" or "bumps"."""
     import torch
     X = torch.empty(batch, M, 3, dtype=torch.float32, device=device)
     Y = torch.empty_like(X)
     V = torch.empty_like(X)
     W = torch.empty_like(X)
-    _check(load_library().cpdnet_synth(_ptr(X), _ptr(Y), _ptr(V), _ptr(W), batch, M, float(beta),
+    _check(load_library().cpdnet_synth(_ptr(X), _ptr(Y), _ptr(V), _ptr(W), batch, M,
+                                       SHAPES[shape], float(beta),
                                        float(coef), float(jitter), float(outlier_frac),
                                        int(seed0), _stream_ptr()))
     return X, Y, V

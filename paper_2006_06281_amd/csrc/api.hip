@@ -116,8 +116,8 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   // sigma^2 partials: per 256 rows (k_sig_part) or per 64 (fused into the M-step)
   add(L, L.sigpart, 2 * (size_t)std::max(sigma2_blocks<T>(p.M), (p.M + 63) / 64) * sizeof(double));
   add(L, L.initpart, 8 * (size_t)init_blocks(p.M, p.N) * sizeof(double));
-  // Single handles keep their points in Hilbert order (batch members do not).
-  L.sorted = batch_chunk == 0 && !(p.flags & CPD_FLAG_NO_SORT);
+  // Points are kept in Hilbert order (single handles and batch members alike).
+  L.sorted = !(p.flags & CPD_FLAG_NO_SORT);
   L.cull = L.sorted && !(p.flags & CPD_FLAG_NO_CULL);
   if (L.sorted) {
     size_t n2 = 1;
@@ -1045,6 +1045,8 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
     D.tpart = h->at<float>(L.tpart);
     D.GT = h->at<P4<float>>(L.GT);
     D.HT = h->at<P4<float>>(L.HT);
+    D.boxX = L.cull ? h->at<P4<float>>(L.boxX) : nullptr;
+    D.boxY = L.cull ? h->at<P4<float>>(L.boxY) : nullptr;
     D.sc = h->sc();
     D.M = h->p.M;
     D.N = h->p.N;
@@ -1058,7 +1060,9 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
     D.llblocks = (D.N + 255) / 256;
     D.w = h->p.w;
     D.lmbda = h->p.lambda;
-    for (int x = 0; x < (D.M + D.N + 255) / 256; ++x) pre.push_back(make_int4(i, x, 0, 0));
+    // with boxes the model part is padded to whole 64-point tiles
+    const int pre_thr = (D.boxX ? ((D.M + 63) & ~63) : D.M) + D.N;
+    for (int x = 0; x < (pre_thr + 255) / 256; ++x) pre.push_back(make_int4(i, x, 0, 0));
     for (int t = 0; t < (D.N + 1023) / 1024; ++t)
       for (int s = 0; s < D.splitsA; ++s) cs.push_back(make_int4(i, t, s, 0));
     for (int x = 0; x < (D.N + 255) / 256; ++x) cm.push_back(make_int4(i, x, 0, 0));
@@ -1220,6 +1224,7 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
         h->st = sts[t];
         rc[i] = prepare_impl<float>(h, nullptr, nullptr, nullptr);
         h->st = b->st;
+        if (rc[i] == CPD_NOT_CONVERGED) rc[i] = CPD_OK;  // a truncated FULL basis is usable
         if (rc[i] != CPD_OK) break;
       }
     });
@@ -1272,10 +1277,14 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   return CPD_OK;
 }
 
-cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_packed,
-                              cpd_result* res) {
+cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, const double* sigma2_start,
+                              float* X_out_packed, cpd_result* res) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
   if (!b->prepared) return bfail(b, CPD_E_STATE, "cpd_batch_prepare must run first");
+  if (sigma2_start)
+    for (int i = 0; i < b->B; ++i)
+      if (!std::isfinite(sigma2_start[i]))
+        return bfail(b, CPD_E_ARG, "sigma2_start entries must be finite");
   // order after the caller's stream; every event is released on every return
   EventGuard g0, g1, gt0, gt1;
   HIPCHK(nullptr, hipEventCreate(&g0.e));
@@ -1287,18 +1296,28 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
   HIPCHK(nullptr, hipStreamWaitEvent(b->st, ev0, 0));
   const cpd_status rs = batch_restart(b);
   if (rs != CPD_OK) return rs;
-  if (W0_packed) {
-    for (int i = 0; i < b->B; ++i) {
-      cpd_ctx* h = b->inst[i];
-      phi_apply_launch<float>(h->at<P4<float>>(h->L.X), W0_packed + 3 * b->x_off[i],
-                              h->at<P4<float>>(h->L.Xt), h->p.M, 3, h->p.beta, b->st);
-      if (!(h->p.sigma2_init > 0.0))
-        reset_sigma2_launch<float>(h->at<P4<float>>(h->L.Xt), h->at<P4<float>>(h->L.Y), h->p.M,
-                                   h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st,
-                                   kS2Warm);
+  for (int i = 0; i < b->B; ++i) {
+    cpd_ctx* h = b->inst[i];
+    if (W0_packed) {
+      const float* w0 = W0_packed + 3 * b->x_off[i];
+      if (h->permX()) {  // into the instance's internal order (Xnew is free here)
+        float* tmp = h->at<float>(h->L.Xnew);
+        gather_rows_launch<float>(w0, tmp, h->permX(), h->p.M, 3, b->st);
+        w0 = tmp;
+      }
+      phi_apply_launch<float>(h->at<P4<float>>(h->L.X), w0, h->at<P4<float>>(h->L.Xt), h->p.M, 3,
+                              h->p.beta, b->st);
     }
-    HIPCHK(nullptr, hipGetLastError());
+    if (sigma2_start && sigma2_start[i] > 0.0)
+      reset_sigma2_launch<float>(h->at<P4<float>>(h->L.Xt), h->at<P4<float>>(h->L.Y), h->p.M,
+                                 h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st,
+                                 kS2Given, sigma2_start[i]);
+    else if (W0_packed && !(h->p.sigma2_init > 0.0))
+      reset_sigma2_launch<float>(h->at<P4<float>>(h->L.Xt), h->at<P4<float>>(h->L.Y), h->p.M,
+                                 h->p.N, 3, h->sc(), h->at<double>(h->L.initpart), b->st,
+                                 kS2Warm);
   }
+  HIPCHK(nullptr, hipGetLastError());
   int max_iter = 1;
   for (auto& q : b->p) max_iter = std::max(max_iter, q.max_iter);
   (void)hipEventRecord(t0, b->st);
@@ -1319,7 +1338,8 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, float* X_out_
     cpd_ctx* h = b->inst[i];
     HIPCHK(nullptr, hipMemcpyAsync(&s[i], h->sc(), sizeof(DevScalars), hipMemcpyDeviceToHost, b->st));
     if (X_out_packed)
-      unpack_launch<float>(h->at<P4<float>>(h->L.Xt), X_out_packed + 3 * b->x_off[i], h->p.M, 3, b->st);
+      unpack_launch<float>(h->at<P4<float>>(h->L.Xt), X_out_packed + 3 * b->x_off[i], h->p.M, 3,
+                           b->st, h->permX(), h->origin());
   }
   HIPCHK(nullptr, hipGetLastError());
   (void)hipEventRecord(ev1, b->st);
@@ -1494,13 +1514,14 @@ cpd_status cpdnet_adam(float* params, float* m, float* v, const float* grad, int
 }
 
 cpd_status cpdnet_synth(float* X, float* Y, float* V, float* Wsc, int32_t batch, int32_t M,
-                        double beta, double coef, double jitter, double outlier_frac,
-                        uint64_t seed0, void* stream) {
+                        int32_t shape, double beta, double coef, double jitter,
+                        double outlier_frac, uint64_t seed0, void* stream) {
   const cpd_status vd = net_dims(batch, M, M, CPDNET_BF16);
   if (vd != CPD_OK) return vd;
-  if (!X || !Y || !V || !Wsc || !(beta > 0.0) || !(outlier_frac >= 0.0 && outlier_frac <= 1.0))
+  if (!X || !Y || !V || !Wsc || !(beta > 0.0) || !(outlier_frac >= 0.0 && outlier_frac <= 1.0) ||
+      (shape != CPDNET_SHAPE_SPHERE && shape != CPDNET_SHAPE_BUMPS))
     return fail(nullptr, CPD_E_ARG, "bad synth arguments");
-  net_synth_launch(X, Y, V, Wsc, batch, M, beta, coef, jitter, outlier_frac, seed0,
+  net_synth_launch(X, Y, V, Wsc, batch, M, shape, beta, coef, jitter, outlier_frac, seed0,
                    static_cast<hipStream_t>(stream));
   HIPCHK(nullptr, hipGetLastError());
   return CPD_OK;

@@ -74,16 +74,16 @@ __device__ __forceinline__ T wave_min(T v) {
 // model and scene.  Threads [0, M64) cover the model (M64 = M rounded up to
 // 64), the rest the scene, so every wave sits inside one tile.
 template <typename T>
-__global__ __launch_bounds__(256) void k_prescale_box(const P4<T>* __restrict__ Xt,
-                                                      const P4<T>* __restrict__ Y,
-                                                      P4<T>* __restrict__ xs,
-                                                      P4<T>* __restrict__ ys, int M, int N,
-                                                      DevScalars* sc, int gate,
-                                                      P4<T>* __restrict__ boxX,
-                                                      P4<T>* __restrict__ boxY) {
+__device__ __forceinline__ void prescale_box_body(const P4<T>* __restrict__ Xt,
+                                                  const P4<T>* __restrict__ Y,
+                                                  P4<T>* __restrict__ xs,
+                                                  P4<T>* __restrict__ ys, int M, int N,
+                                                  DevScalars* sc, int gate,
+                                                  P4<T>* __restrict__ boxX,
+                                                  P4<T>* __restrict__ boxY, int bx_) {
   if (gate && sc->done) return;
   const T s = (T)sqrt(kappa_of(sc->sigma2));
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx_ * blockDim.x + threadIdx.x;
   const int M64 = (M + 63) & ~63;
   const bool isX = i < M64;
   const int k = isX ? i : i - M64;
@@ -114,6 +114,17 @@ __global__ __launch_bounds__(256) void k_prescale_box(const P4<T>* __restrict__ 
     box[2 * t] = P4<T>{lx, ly, lz, (T)0};
     box[2 * t + 1] = P4<T>{hx, hy, hz, n2};
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prescale_box(const P4<T>* __restrict__ Xt,
+                                                      const P4<T>* __restrict__ Y,
+                                                      P4<T>* __restrict__ xs,
+                                                      P4<T>* __restrict__ ys, int M, int N,
+                                                      DevScalars* sc, int gate,
+                                                      P4<T>* __restrict__ boxX,
+                                                      P4<T>* __restrict__ boxY) {
+  prescale_box_body<T>(Xt, Y, xs, ys, M, N, sc, gate, boxX, boxY, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ pass A
@@ -644,28 +655,31 @@ __global__ __launch_bounds__(256) void kb_prescale(const InstDesc* __restrict__ 
                                                    const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  prescale_body<float>(D.Xt, D.Y, D.xs, D.ys, D.M, D.N, D.sc, 1, it.y, 0, 0);
+  if (D.boxX)
+    prescale_box_body<float>(D.Xt, D.Y, D.xs, D.ys, D.M, D.N, D.sc, 1, D.boxX, D.boxY, it.y);
+  else
+    prescale_body<float>(D.Xt, D.Y, D.xs, D.ys, D.M, D.N, D.sc, 1, it.y, 0, 0);
 }
 __global__ __launch_bounds__(256) void kb_colsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsA, D.sc, D.w, D.partA,
-                           (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
+  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsA, D.sc, D.w, D.partA, D.boxX, D.boxY,
+                           1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ d,
                                                    const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
-                       D.llpart, (P4<float>*)nullptr, 6, (__bf16*)nullptr, D.xs, 1, it.y, 0, 0);
+                       D.llpart, D.boxY, 6, (__bf16*)nullptr, D.xs, 1, it.y, 0, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsB, D.sc, D.partB,
-                           (const P4<float>*)nullptr, (const P4<float>*)nullptr, 1, it.y, it.z, 0);
+  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsB, D.sc, D.partB, D.boxX, D.boxY, 1,
+                           it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ d,
                                                    const int4* __restrict__ items) {

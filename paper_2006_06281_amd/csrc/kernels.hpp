@@ -126,12 +126,13 @@ void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int 
                  hipStream_t st, double floor_rel = 0.0);
 int init_blocks(int M, int N);
 // Start of a new run: kS2Warm sets sigma^2 to the closed form at Xt (a warm
-// start Xt = X + Phi W0), kS2Start back to the value set at init; both keep
-// the data's part of the floor (kS2Init is cpd_init's own mode).
-enum { kS2Init = 0, kS2Warm = 1, kS2Start = 2 };
+// start Xt = X + Phi W0), kS2Start back to the value set at init, kS2Given to
+// `given`; all keep the data's part of the floor (kS2Init is cpd_init's own
+// mode).
+enum { kS2Init = 0, kS2Warm = 1, kS2Start = 2, kS2Given = 3 };
 template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
-                         double* part, hipStream_t st, int mode);
+                         double* part, hipStream_t st, int mode, double given = -1.0);
 // sigma^2 floor of the BF16X mode, relative to D times the data's closed-form
 // sigma^2_0: keeps its worst-case exponent error (2^-21 3 kappa R^2 base-2
 // units, R the extent of the points) to tens of units, far from where an
@@ -226,6 +227,8 @@ struct InstDesc {
   float* tpart;
   P4<float>* GT;
   P4<float>* HT;
+  P4<float>* boxX;  // 64-point tile boxes of the prescaled points (NULL: no culling)
+  P4<float>* boxY;
   DevScalars* sc;
   int M, N, K;
   int splitsA, chunkA, splitsB, chunkB;

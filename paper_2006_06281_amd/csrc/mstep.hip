@@ -597,7 +597,8 @@ __global__ __launch_bounds__(256) void k_s2init_part(const P4<T>* __restrict__ X
 //                  also kept as sigma2_start, the start of a run from X
 //   mode kS2Warm   a run from a warm start Xt = X + Phi W0: sigma^2 = the
 //                  closed form at Xt (sigma2_start is left alone)
-//   mode kS2Start  a run with a caller-given start: sigma^2 = sigma2_start
+//   mode kS2Start  a run from the start state: sigma^2 = sigma2_start
+//   mode kS2Given  a run with a caller-given start: sigma^2 = given (> 0)
 __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__ part, int blocks,
                                                       int M, int N, int D, double given,
                                                       double tol, int max_iter, int mode,
@@ -624,7 +625,7 @@ __global__ __launch_bounds__(256) void k_s2init_final(const double* __restrict__
       sc->diam2 = 0.0;  // set by the spatial ordering when the handle sorts
       sc->origin[0] = sc->origin[1] = sc->origin[2] = 0.0;
     } else {
-      s2 = mode == kS2Warm ? s2closed : sc->sigma2_start;
+      s2 = mode == kS2Warm ? s2closed : (mode == kS2Given ? given : sc->sigma2_start);
     }
     sc->sigma2 = s2;
     sc->sigma2_floor = fmax(1e-10 * s2, sc->floor_data);
@@ -654,11 +655,11 @@ void init_launch(const T* Xin, const T* Yin, P4<T>* X, P4<T>* Xt, P4<T>* Y, int 
 
 template <typename T>
 void reset_sigma2_launch(const P4<T>* Xt, const P4<T>* Y, int M, int N, int D, DevScalars* sc,
-                         double* part, hipStream_t st, int mode) {
+                         double* part, hipStream_t st, int mode, double given) {
   const int blocks = mode == kS2Warm ? init_blocks(M, N) : 0;
   if (blocks > 0)
     hipLaunchKernelGGL(k_s2init_part<T>, dim3(blocks), dim3(256), 0, st, Xt, Y, M, N, part);
-  hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D, -1.0, 0.0,
+  hipLaunchKernelGGL(k_s2init_final, dim3(1), dim3(256), 0, st, part, blocks, M, N, D, given, 0.0,
                      0, mode, sc, 0.0);
 }
 
@@ -812,7 +813,7 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
                                double, double, int, DevScalars*, double*, hipStream_t,       \
                                double);                                                       \
   template void reset_sigma2_launch<T>(const P4<T>*, const P4<T>*, int, int, int, DevScalars*, \
-                                       double*, hipStream_t, int);                            \
+                                       double*, hipStream_t, int, double);                            \
   template void unpack_launch<T>(const P4<T>*, T*, int, int, hipStream_t, const int*,       \
                                  const double*);                                              \
   template void pack_launch<T>(const T*, P4<T>*, int, int, hipStream_t, const int*,        \

@@ -107,13 +107,15 @@ __global__ __launch_bounds__(256) void k_net_init(float* __restrict__ p, NetOffs
 }
 
 // ----------------------------------------------------- training pairs
-// The 500-point sphere recipe at any size: X = unit-sphere directions +
-// N(0, jitter^2), W* ~ N(0, coef^2), V* = Phi(X, X) W* (the true displacement
-// of every model point), Y = X + V* with a fraction of rows replaced by
-// U[-1.5, 1.5]^3.  Instance b uses stream seed0 + b.  One thread per point
-// and stage.
+// Model sets: unit-sphere directions u, either on the sphere itself (shape 0)
+// or on a surface without symmetries (shape 1): r(u) = 1 + sum_{i<6} a_i
+// exp(3 (u . c_i - 1)), six bumps with per-instance centres c_i (uniform on
+// the sphere) and heights a_i ~ N(0, 0.25^2); plus N(0, jitter^2) per
+// coordinate.  W* ~ N(0, coef^2); V* = Phi(X, X) W* (the true displacement of
+// every model point), Y = X + V* with a fraction of rows replaced by
+// U[-1.5, 1.5]^3.  Instance b uses stream seed0 + b.  One thread per point.
 __global__ __launch_bounds__(256) void k_synth_points(float* __restrict__ X, float* __restrict__ Wc,
-                                                      int batch, int M, uint64_t seed0,
+                                                      int batch, int M, int shape, uint64_t seed0,
                                                       float coef, float jitter) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (size_t)batch * M) return;
@@ -123,12 +125,22 @@ __global__ __launch_bounds__(256) void k_synth_points(float* __restrict__ X, flo
   float v[3];
   for (int d = 0; d < 3; ++d) v[d] = normal_at(s, 3 * m + d, 11);
   const float inv = rsqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + 1e-30f);
+  for (int d = 0; d < 3; ++d) v[d] *= inv;
+  float r = 1.f;
+  if (shape == 1) {
+    for (int k = 0; k < 6; ++k) {
+      float c[3];
+      for (int d = 0; d < 3; ++d) c[d] = normal_at(s, 3 * k + d, 16);
+      const float ic = rsqrtf(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + 1e-30f);
+      const float cosang = (v[0] * c[0] + v[1] * c[1] + v[2] * c[2]) * ic;
+      r += 0.25f * normal_at(s, k, 17) * expf(3.f * (cosang - 1.f));
+    }
+  }
   for (int d = 0; d < 3; ++d) {
-    X[3 * i + d] = v[d] * inv + jitter * normal_at(s, 3 * m + d, 12);
+    X[3 * i + d] = r * v[d] + jitter * normal_at(s, 3 * m + d, 12);
     Wc[3 * i + d] = coef * normal_at(s, 3 * m + d, 13);
   }
 }
-
 
 // Y = X + V with a fraction of rows replaced by U[-1.5, 1.5]^3 (V = Phi W*
 // already computed); one thread per point.
@@ -1159,12 +1171,12 @@ void net_init_launch(float* params, uint64_t seed, float out_scale, hipStream_t 
   hipLaunchKernelGGL(k_net_init, dim3(nb(o.count)), dim3(256), 0, st, params, o, seed, out_scale);
 }
 
-void net_synth_launch(float* X, float* Y, float* V, float* Wscratch, int batch, int M, double beta,
-                      double coef, double jitter, double outlier_frac, uint64_t seed0,
-                      hipStream_t st) {
+void net_synth_launch(float* X, float* Y, float* V, float* Wscratch, int batch, int M, int shape,
+                      double beta, double coef, double jitter, double outlier_frac,
+                      uint64_t seed0, hipStream_t st) {
   const size_t rows = (size_t)batch * M;
   hipLaunchKernelGGL(k_synth_points, dim3(nb(rows)), dim3(256), 0, st, X, Wscratch, batch, M,
-                     seed0, (float)coef, (float)jitter);
+                     shape, seed0, (float)coef, (float)jitter);
   hipLaunchKernelGGL(k_phi_apply, dim3(nb(M, kPhiRows), batch), dim3(256), 0, st, X, Wscratch, M,
                      (float)(kLog2e / (2.0 * beta * beta)), (const float*)nullptr, 1.0f, V,
                      (double*)nullptr);

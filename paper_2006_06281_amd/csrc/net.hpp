@@ -25,9 +25,9 @@ struct NetWs {
 NetWs net_ws_layout(int batch, int M, int N, int precision);
 
 void net_init_launch(float* params, uint64_t seed, float out_scale, hipStream_t st);
-void net_synth_launch(float* X, float* Y, float* V, float* Wscratch, int batch, int M, double beta,
-                      double coef, double jitter, double outlier_frac, uint64_t seed0,
-                      hipStream_t st);
+void net_synth_launch(float* X, float* Y, float* V, float* Wscratch, int batch, int M, int shape,
+                      double beta, double coef, double jitter, double outlier_frac,
+                      uint64_t seed0, hipStream_t st);
 void net_forward_launch(const float* params, const float* X, const float* Y, int batch, int M,
                         int N, float* W0, char* ws, const NetWs& L, int precision,
                         hipStream_t st);

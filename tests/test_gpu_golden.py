@@ -111,3 +111,66 @@ def test_surface10k_to_convergence_matches_the_oracle(lib, name):
     say("surface10k", name, "tolerance stop: GPU", out.iters, "oracle", iters)
     assert out.converged and abs(out.iters - iters) <= max(3, 0.1 * iters)
     r.close()
+
+
+# -------------------------------------------------------------- surface50k
+def _surface50k_handle(lib, precision, meta, **kw):
+    import torch
+    p = synth.workload("surface50k")
+    X, Y = _f32(p.X), _f32(p.Y)
+    omega = dev(synth.gaussian_matrix(meta["M"], meta["K"] + meta["oversample"], 0), torch.float64)
+    r = lib.Registration(dev(X, torch.float32), dev(Y, torch.float32), precision=precision,
+                         beta=meta["beta"], lam=meta["lam"], w=meta["w"], eig_mode="topk",
+                         K=meta["K"], oversample=meta["oversample"],
+                         power_iters=meta["power_iters"], **kw)
+    r.prepare(omega=omega)
+    del omega
+    return r
+
+
+def test_surface50k_topk_eigenpairs_match_the_oracle(lib):
+    """The randomized top-300 eigensolver at 50k (eq. 19) on the same Gaussian
+    test matrix as the oracle: eigenvalues within 1e-11 lam_1, and the two
+    basis-invariant operators the method uses, the rank-K Gram U Lam U^T
+    (within 1e-9) and the Fast M-step's U diag(lam / (lam + lambda 1e-3)) U^T
+    (within 1e-6, which weighs eigenpairs down to ~1e-9 lam_1), applied to
+    three probe vectors and compared on 2048 sampled rows."""
+    z, meta = _load("surface50k")
+    say("surface50k eig, K", meta["K"])
+    r = _surface50k_handle(lib, "fp32", meta, tol=0.0, max_iter=1)
+    U, lam = (host(t) for t in r.export_eig())
+    r.close()
+    lam_o = z["lam"]
+    err_lam = float(np.abs(lam - lam_o).max() / lam_o[0])
+    rows = z["probe_rows"]
+    lp = np.maximum(lam, 0.0)
+    errs = []
+    for j in range(3):
+        T = U.T @ synth.gaussian_matrix(meta["M"], 3, 100 + j)
+        g = U[rows] @ (lp[:, None] * T)
+        m = U[rows] @ ((lp / (lp + meta["lam"] * 1e-3))[:, None] * T)
+        errs.append((float(np.linalg.norm(g - z["gram_probe"][j]) / np.linalg.norm(z["gram_probe"][j])),
+                     float(np.linalg.norm(m - z["mstep_probe"][j]) / np.linalg.norm(z["mstep_probe"][j]))))
+    say("lam_1", lam[0], lam_o[0], "max |dlam| / lam_1", err_lam, "probe errors", errs)
+    assert err_lam < 1e-11
+    for eg, em in errs:
+        assert eg < 1e-9 and em < 1e-6
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("bf16x", 1e-3)])
+def test_surface50k_twenty_iterations_match_the_oracle(lib, precision, bar):
+    """20 Fast CPD iterations (eq. 20, K = 300) at 50k from the closed-form
+    sigma^2_0, in the configuration the benchmark times (points in spatial
+    order, far-tile culling on), against the oracle's 20 iterations with its
+    own eigenpairs from the same test matrix."""
+    z, meta = _load("surface50k")
+    say("surface50k", precision, meta["iters"], "iterations")
+    r = _surface50k_handle(lib, precision, meta, tol=0.0, max_iter=meta["iters"])
+    out = r.register()
+    r.close()
+    err = cpd64.rel_rms(host(out.Xt), z["Xt"].astype(np.float64))
+    s2o = float(z["sigma2"][-1])
+    say("surface50k", precision, "rel_rms", err, "sigma2", out.sigma2, s2o)
+    assert out.iters == meta["iters"]
+    assert err < bar
+    assert out.sigma2 == pytest.approx(s2o, rel=bar)
