@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   // tile blockIdx.y (S = gridDim.y splits): the tiles near any scene column,
   // consecutive in the spatial order, then spread evenly over the splits
   const int S = gridDim.y, tiles = Mpad >> 4;
+  const int aoff = (lane & 15) * 32 + 8 * (lane >> 4);  // this lane's A operand slice
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   // the split layout follows the sigma^2 gate alone, so a handle without
@@ -188,17 +189,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         }
         keep = __ballot(cols != 0);
       }
-      while (keep) {
-        const int i = __builtin_ctzll(keep);
-        keep &= keep - 1;
-        const int mt = 16 * (t0 + ts * i);
-        const int cm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(cols, i, 64)) : 15;
-        const bf16x8 a = load_op(F, mt + (lane & 15), lane);
+      // kept tiles two at a time: the second tile's operand is requested
+      // before the first is evaluated (tiles still added in order)
+      auto eval = [&](int k, const bf16x8& a) {
+        const int cm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(cols, k, 64)) : 15;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (MASK && !(cm & (1 << s))) continue;  // all its terms are +0
           const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
           acc[s] += (fexp2(-d[0]) + fexp2(-d[1])) + (fexp2(-d[2]) + fexp2(-d[3]));
+        }
+      };
+      while (keep) {
+        const int k0 = __builtin_ctzll(keep);
+        keep &= keep - 1;
+        // uniform tile bases, per-lane offsets
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(F + (size_t)(16 * (t0 + ts * k0)) * 32 + aoff);
+        if (keep) {
+          const int k1 = __builtin_ctzll(keep);
+          keep &= keep - 1;
+          const bf16x8 a1 =
+              *reinterpret_cast<const bf16x8*>(F + (size_t)(16 * (t0 + ts * k1)) * 32 + aoff);
+          eval(k0, a0);
+          eval(k1, a1);
+        } else {
+          eval(k0, a0);
         }
       }
     }
@@ -247,6 +262,7 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
+  const int aoff = (lane & 15) * 32 + 8 * (lane >> 4);  // this lane's A operand slice
   // with boxes: skip 16-point scene tiles whose smallest exponent
   // |u - v|^2 + min L_n against this wave's model points reaches CullLimit
   // (the split layout follows the sigma^2 gate alone: see pass A)
@@ -286,10 +302,12 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
         keep &= keep - 1;
         const int nt = 16 * (t0 + ts * i);
         const int rm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(rows, i, 64)) : 15;
-        const bf16x8 a = load_op(G, nt + (lane & 15), lane);
+        // the tile's base is uniform, so only the lane offsets are per lane
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(G + (size_t)nt * 32 + aoff);
+        const P4<float>* yt = ys + nt;
         P4<float> yv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) yv[q] = ys[nt + rg + q];
+        for (int q = 0; q < 4; ++q) yv[q] = yt[rg + q];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (MASK && !(rm & (1 << s))) continue;  // all its terms are +0
