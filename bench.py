@@ -55,7 +55,7 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
 # of known size; valid only while the kernel source is unchanged (sha256).
 TRAFFIC = {
-    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "26a23127950d2f18f3c4008070fa8ca43de0019e53e5b151783846e6d8c1411f",
+    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "9d0946d4052620095857042be42594c668ec6d72aa186d2e7a726aafd4b6f7d9",
                      "bytes_per_dispatch": 38.49e6 + 26.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
 }
