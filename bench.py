@@ -280,7 +280,7 @@ def plain_cpd_legs(fc, torch, X, Y, pair, kw, fast_ms_step):
     return out
 
 
-def batch_leg(fc, torch, B=256, tune=True):
+def batch_leg(fc, torch, B=256, tune=True, single_n=8):
     """256 independent registrations (surface pairs, M_i, N_i ~ U{500..8000},
     beta_i ~ U[1, 3], lambda_i ~ U[1, 5], w = 0.1, 5% outliers), FULL
     eigen-prep per instance, advanced together by the batched path (FP32)."""
@@ -297,7 +297,7 @@ def batch_leg(fc, torch, B=256, tune=True):
     br.prepare(tune=tune)
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t0
-    chunk, tune_ms = br.info()
+    info = br.info()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Xt, res = br.register()
@@ -308,16 +308,72 @@ def batch_leg(fc, torch, B=256, tune=True):
     rmse = [float(np.sqrt(((x.double().cpu().numpy() - p.Y_hat) ** 2).sum(1).mean()))
             for x, p in zip(Xt, pairs)]
     br.close()
+    K = info["K"]
+    # U (M_i x K_i FP32) is streamed twice per iteration (T = U^T R, then U T)
+    u_bytes = float(sum(4 * p.M * k for p, k in zip(pairs, K)))
+    single = single_instance_rate(fc, torch, Xs, Ys, pairs, n=single_n)
+    single50 = single_50k_rate(fc, torch)
+    pair_rate = float(sum(p.M * p.N * r.iters for p, r in zip(pairs, res))) / t_run
     return {"workload": "batch256: 256 surface pairs, M_i, N_i ~ U{500..8000}, beta_i ~ U[1,3], "
                         "lambda_i ~ U[1,5], w=0.1, 5% outliers; Fast CPD FULL eig, FP32, "
                         "tol 1e-8",
             "instances": B, "sum_MN": pairs_total, "gen_s": t_gen,
-            "prepare_s": t_prep, "chunk": chunk, "tune_ms_per_iter": tune_ms,
+            "prepare_s": t_prep, "chunk": info["chunk"], "tile": info["tile"],
+            "tune_ms_per_iter": {f"{c}/{t}": v for (c, t), v in info["tune_ms"].items()},
+            "K_median": float(np.median(K)), "K_max": int(max(K)),
+            "mstep_U_bytes_per_iter": 2 * u_bytes,
             "run_s": t_run, "converged": int(sum(r.converged for r in res)),
             "iters_max": max(iters), "iters_mean": float(np.mean(iters)),
             "instance_iters_per_s": float(sum(iters)) / t_run,
-            "pair_updates_per_s": float(sum(p.M * p.N * r.iters for p, r in zip(pairs, res))) / t_run,
+            "pair_updates_per_s": pair_rate,
+            "single_instance": single,
+            "batch_vs_single_pair_rate": pair_rate / single["pair_updates_per_s"],
+            "single_50k": single50,
+            "batch_vs_single_50k_pair_rate": pair_rate / single50["pair_updates_per_s"],
             "rmse_median": float(np.median(rmse)), "rmse_max": float(np.max(rmse))}
+
+
+def single_instance_rate(fc, torch, Xs, Ys, pairs, n=8):
+    """The same registrations one at a time through single handles (FP32,
+    FULL eigen-prep, tol 1e-8) for the n largest instances: pair updates per
+    second of register() alone, the reference rate for the batched path."""
+    order = sorted(range(len(pairs)), key=lambda i: -pairs[i].M * pairs[i].N)[:n]
+    work, t = 0.0, 0.0
+    for i in order:
+        p = pairs[i]
+        r = fc.Registration(Xs[i], Ys[i], precision="fp32", beta=p.beta, lam=p.lam, w=0.1,
+                            eig_mode="full", tol=1e-8, max_iter=1000)
+        r.prepare()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = r.register()
+        torch.cuda.synchronize()
+        t += time.perf_counter() - t0
+        work += float(p.M * p.N * out.iters)
+        r.close()
+    return {"instances": len(order), "which": "the largest M_i N_i", "register_s": t,
+            "pair_updates_per_s": work / t}
+
+
+def single_50k_rate(fc, torch, iters=30):
+    """One large single-handle registration at full work for comparison: the
+    surface50k pair in FP32, top-K = 300, `iters` EM iterations from the
+    start state (culling inactive at that sigma^2), register() alone."""
+    import synth
+    p = synth.workload("surface50k")
+    X = torch.as_tensor(p.X, dtype=torch.float32).cuda()
+    Y = torch.as_tensor(p.Y, dtype=torch.float32).cuda()
+    r = fc.Registration(X, Y, precision="fp32", beta=p.beta, lam=p.lam, w=p.w, eig_mode="topk",
+                        K=300, tol=0.0, max_iter=iters)
+    r.prepare()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = r.register()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    r.close()
+    return {"workload": "surface50k FP32 top-K=300", "iters": out.iters, "register_s": t,
+            "pair_updates_per_s": float(p.M) * p.N * out.iters / t}
 
 
 def warm_at_50k(fc, torch, net, M_train, beta, M=50000):

@@ -262,9 +262,15 @@ cpd_status cpd_batch_init(cpd_batch* hb, int32_t B, const cpd_params* p,
                           void* hip_stream);
 
 /* Eigen-prep of every instance (Section III, eq. 16/19; host threads drive up
- * to four streams), then, with tune != 0, a choice of the E-step split length
- * among {512, 1024, 2048, 4096} points by timing two batched iterations of
- * each, then the graph capture.  Leaves every instance at its start state. */
+ * to four streams), then the choice of the E-step plan, then the graph
+ * capture.  Leaves every instance at its start state.  The plan is a split
+ * length among {1024, 2048, 512, 4096} points and a tile of 1024 or 512
+ * points per workgroup (the 8 candidates of cpd_batch_info):
+ *   tune == 1        time two batched iterations of every candidate, keep
+ *                    the fastest;
+ *   tune == 0        candidate 0 (split 1024, tile 1024), untimed;
+ *   2 <= tune <= 9   candidate tune - 2, untimed (tests, reproducible runs).
+ * Other values: CPD_E_ARG. */
 cpd_status cpd_batch_prepare(cpd_batch hb, int32_t tune);
 
 /* Iterate all instances from their start state until each has converged or
@@ -279,9 +285,15 @@ cpd_status cpd_batch_prepare(cpd_batch hb, int32_t tune);
 cpd_status cpd_batch_register(cpd_batch hb, const float* W0_packed, const double* sigma2_start,
                               float* X_out_packed, cpd_result* res);
 
-/* The split length the tuner chose and the per-candidate iteration times
- * (ms, candidates 1024, 2048, 512, 4096; 0 when not tuned). */
-cpd_status cpd_batch_info(cpd_batch hb, int32_t* chunk, double* tune_ms);
+/* What cpd_batch_prepare chose, every output optional (NULL skips it):
+ *   chunk    the split length of the E-step partials (points per split);
+ *   tile     the E-step tile (points per workgroup, 512 or 1024);
+ *   tune_ms  8 doubles: one batched iteration's time (ms) per candidate,
+ *            candidate c = split length {1024, 2048, 512, 4096}[c / 2] with
+ *            tile {1024, 512}[c % 2]; 0 when not tuned;
+ *   K        B int32: each instance's eigenpair count (the M-step's width). */
+cpd_status cpd_batch_info(cpd_batch hb, int32_t* chunk, int32_t* tile, double* tune_ms,
+                          int32_t* K);
 
 cpd_status cpd_batch_destroy(cpd_batch hb);
 

@@ -117,7 +117,8 @@ def load_library(path: str = LIB_PATH):
                             P(ctypes.c_int64), vp, sz, vp], ctypes.c_int),
         "cpd_batch_prepare": ([vp, ctypes.c_int32], ctypes.c_int),
         "cpd_batch_register": ([vp, vp, vp, vp, P(cpd_result)], ctypes.c_int),
-        "cpd_batch_info": ([vp, P(ctypes.c_int32), P(ctypes.c_double)], ctypes.c_int),
+        "cpd_batch_info": ([vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double),
+                            P(ctypes.c_int32)], ctypes.c_int),
         "cpd_batch_destroy": ([vp], ctypes.c_int),
         "cpdnet_param_count": ([P(sz)], ctypes.c_int),
         "cpdnet_init": ([vp, ctypes.c_uint64, ctypes.c_float, vp], ctypes.c_int),
@@ -314,15 +315,28 @@ class BatchRegistration:
             ctypes.byref(self.h), B, arr, _ptr(self.Xp), _ptr(self.Yp), self.x_off, self.y_off,
             _ptr(self.workspace), self.workspace.numel(), _stream_ptr(stream)))
 
-    def prepare(self, tune=True):
-        _check(load_library().cpd_batch_prepare(self.h, int(bool(tune))))
+    CHUNKS = (1024, 2048, 512, 4096)
+    TILES = (1024, 512)
+
+    def prepare(self, tune=True, candidate=None):
+        """tune: time every (split length, tile) candidate and keep the
+        fastest; candidate: force one (index into candidates()) untimed."""
+        code = 2 + int(candidate) if candidate is not None else int(bool(tune))
+        _check(load_library().cpd_batch_prepare(self.h, code))
         return self
 
+    @classmethod
+    def candidates(cls):
+        return [(cls.CHUNKS[c // 2], cls.TILES[c % 2]) for c in range(8)]
+
     def info(self):
-        c = ctypes.c_int32(0)
-        t = (ctypes.c_double * 4)()
-        _check(load_library().cpd_batch_info(self.h, ctypes.byref(c), t))
-        return c.value, dict(zip((1024, 2048, 512, 4096), list(t)))
+        """dict: chunk, tile, tune_ms {(chunk, tile): ms per iteration}, K per instance."""
+        c, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        ms = (ctypes.c_double * 8)()
+        K = (ctypes.c_int32 * self.B)()
+        _check(load_library().cpd_batch_info(self.h, ctypes.byref(c), ctypes.byref(t), ms, K))
+        return {"chunk": c.value, "tile": t.value,
+                "tune_ms": dict(zip(self.candidates(), list(ms))), "K": list(K)}
 
     def register(self, W0=None, sigma2=None):
         """W0: optional packed (sum M_i x 3) float32 CUDA tensor of warm-start

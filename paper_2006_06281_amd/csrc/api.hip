@@ -926,7 +926,9 @@ cpd_status cpd_time_kernels(cpd_handle h, int32_t reps, double* out_ms) {
 }  // extern "C"
 
 namespace {
-constexpr int kBatchChunks[] = {1024, 2048, 512, 4096};  // candidates; [0] sizes the partials
+constexpr int kBatchChunks[] = {1024, 2048, 512, 4096};  // split-length candidates
+constexpr int kBatchTiles[] = {4, 2};  // E-step points per thread (tiles of 256 x this)
+constexpr int kBatchCands = 8;         // chunk-major: candidate c = kBatchChunks[c / 2], kBatchTiles[c % 2]
 constexpr int kBatchSmallestChunk = 512;
 
 struct BatchHeader {
@@ -941,8 +943,8 @@ size_t batch_item_capacity(int B, const cpd_params* p) {
     const int M = p[i].M, N = p[i].N;
     const int c = kBatchSmallestChunk;
     const size_t sA = (M + c - 1) / c, sB = (N + c - 1) / c;
-    const size_t tA = (N + 1023) / 1024, tB = (M + 1023) / 1024;
-    n += (M + N + 255) / 256;                        // prescale
+    const size_t tA = (N + 511) / 512, tB = (M + 511) / 512;  // the smallest tile
+    n += (((M + 63) & ~63) + N + 255) / 256;         // prescale (model part in whole tiles)
     n += tA * sA + tB * sB;                          // colsum, rowsum
     n += (N + 255) / 256 + (M + 255) / 256;          // merges
     n += (size_t)((M + 127) / 128) * 8;              // tpart (chunks x k groups)
@@ -996,9 +998,10 @@ struct cpd_batch_ctx {
   hipGraph_t graph = nullptr;
   BatchItems items{};
   int chunk = kBatchChunks[0];
+  int nb = kBatchTiles[0];
   bool prepared = false;
   std::string err;
-  double tune_ms[4] = {0, 0, 0, 0};
+  double tune_ms[kBatchCands] = {};
   ~cpd_batch_ctx() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1016,11 +1019,17 @@ cpd_status bfail(cpd_batch_ctx* b, cpd_status s, const std::string& m) {
 }
 
 // Descriptors and work lists for split length `chunk`; uploads both.
-cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
+cpd_status batch_build(cpd_batch_ctx* b, int chunk, int nb) {
   std::vector<InstDesc> d(b->B);
-  std::vector<int4> pre, cs, cm, rs, rm, tp, tm, ap, sp, in;
-  int maxK = 1;
-  for (int i = 0; i < b->B; ++i) maxK = std::max(maxK, b->inst[i]->K);
+  std::vector<int4> pre, cs, cm, rs, rm, tp, tp4, tm, ap, ap4, sp, in;
+  int maxK = 1, maxK4 = 1;
+  for (int i = 0; i < b->B; ++i) {
+    const int K = b->inst[i]->K;
+    if (fast_mstep_vec4<float>(K))
+      maxK4 = std::max(maxK4, K);
+    else
+      maxK = std::max(maxK, K);
+  }
   const int kt = maxK <= 256 ? 1 : (maxK <= 512 ? 2 : 4);
   for (int i = 0; i < b->B; ++i) {
     cpd_ctx* h = b->inst[i];
@@ -1056,51 +1065,65 @@ cpd_status batch_build(cpd_batch_ctx* b, int chunk) {
       return bfail(b, CPD_E_WORKSPACE, "batch split plan exceeds the partial buffers");
     D.mrows = L.mrows;
     D.mchunks = L.mchunks;
-    D.sigblocks = sigma2_blocks<float>(D.M);
+    const bool vec4 = fast_mstep_vec4<float>(D.K);
+    // the 16-byte-load apply writes one sigma^2 partial per 64 rows
+    D.sigblocks = vec4 ? (D.M + 63) / 64 : sigma2_blocks<float>(D.M);
     D.llblocks = (D.N + 255) / 256;
     D.w = h->p.w;
     D.lmbda = h->p.lambda;
     // with boxes the model part is padded to whole 64-point tiles
     const int pre_thr = (D.boxX ? ((D.M + 63) & ~63) : D.M) + D.N;
     for (int x = 0; x < (pre_thr + 255) / 256; ++x) pre.push_back(make_int4(i, x, 0, 0));
-    for (int t = 0; t < (D.N + 1023) / 1024; ++t)
+    const int tile = 256 * nb;
+    for (int t = 0; t < (D.N + tile - 1) / tile; ++t)
       for (int s = 0; s < D.splitsA; ++s) cs.push_back(make_int4(i, t, s, 0));
     for (int x = 0; x < (D.N + 255) / 256; ++x) cm.push_back(make_int4(i, x, 0, 0));
-    for (int t = 0; t < (D.M + 1023) / 1024; ++t)
+    for (int t = 0; t < (D.M + tile - 1) / tile; ++t)
       for (int s = 0; s < D.splitsB; ++s) rs.push_back(make_int4(i, t, s, 0));
     for (int x = 0; x < (D.M + 255) / 256; ++x) rm.push_back(make_int4(i, x, 0, 0));
-    for (int c = 0; c < D.mchunks; ++c)
-      for (int g = 0; g < (D.K + 256 * kt - 1) / (256 * kt); ++g) tp.push_back(make_int4(i, c, g, 0));
+    if (vec4) {
+      for (int c = 0; c < D.mchunks; ++c) tp4.push_back(make_int4(i, c, 0, 0));
+    } else {
+      for (int c = 0; c < D.mchunks; ++c)
+        for (int g = 0; g < (D.K + 256 * kt - 1) / (256 * kt); ++g) tp.push_back(make_int4(i, c, g, 0));
+    }
     for (int k = 0; k < D.K; ++k) tm.push_back(make_int4(i, k, 0, 0));
-    for (int x = 0; x < (D.M + 63) / 64; ++x) ap.push_back(make_int4(i, x, 0, 0));
-    for (int x = 0; x < D.sigblocks; ++x) sp.push_back(make_int4(i, x, 0, 0));
+    for (int x = 0; x < (D.M + 63) / 64; ++x) (vec4 ? ap4 : ap).push_back(make_int4(i, x, 0, 0));
+    if (!vec4)
+      for (int x = 0; x < D.sigblocks; ++x) sp.push_back(make_int4(i, x, 0, 0));
     in.push_back(make_int4(i, 0, 0, 0));
   }
   std::vector<int4> all;
-  std::vector<const std::vector<int4>*> lists = {&pre, &cs, &cm, &rs, &rm, &tp, &tm, &ap, &sp, &in};
+  std::vector<const std::vector<int4>*> lists = {&pre, &cs, &cm, &rs, &rm, &tp, &tp4,
+                                                 &tm, &ap, &ap4, &sp, &in};
   for (auto* l : lists) all.insert(all.end(), l->begin(), l->end());
   if (all.size() > b->hd.item_cap) return bfail(b, CPD_E_WORKSPACE, "batch work list too large");
   int4* dev = reinterpret_cast<int4*>(b->ws + b->hd.items);
   size_t o = 0;
   const int4** ptrs[] = {&b->items.prescale, &b->items.colsum, &b->items.colmerge,
-                         &b->items.rowsum, &b->items.rowmerge, &b->items.tpart, &b->items.tmerge,
-                         &b->items.apply, &b->items.sigpart, &b->items.inst};
+                         &b->items.rowsum, &b->items.rowmerge, &b->items.tpart,
+                         &b->items.tpart4, &b->items.tmerge, &b->items.apply,
+                         &b->items.apply4, &b->items.sigpart, &b->items.inst};
   int* counts[] = {&b->items.n_prescale, &b->items.n_colsum, &b->items.n_colmerge,
-                   &b->items.n_rowsum, &b->items.n_rowmerge, &b->items.n_tpart, &b->items.n_tmerge,
-                   &b->items.n_apply, &b->items.n_sigpart, &b->items.n_inst};
+                   &b->items.n_rowsum, &b->items.n_rowmerge, &b->items.n_tpart,
+                   &b->items.n_tpart4, &b->items.n_tmerge, &b->items.n_apply,
+                   &b->items.n_apply4, &b->items.n_sigpart, &b->items.n_inst};
   for (size_t q = 0; q < lists.size(); ++q) {
     *ptrs[q] = dev + o;
     *counts[q] = (int)lists[q]->size();
     o += lists[q]->size();
   }
+  b->items.nb = nb;
   b->items.kt = kt;
   b->items.maxK = maxK;
+  b->items.maxK4 = maxK4;
   b->items.done_count = reinterpret_cast<int*>(b->ws + b->hd.done);
   InstDesc* dd = reinterpret_cast<InstDesc*>(b->ws + b->hd.desc);
   HIPCHK(nullptr, hipMemcpyAsync(dd, d.data(), sizeof(InstDesc) * d.size(), hipMemcpyHostToDevice, b->st));
   HIPCHK(nullptr, hipMemcpyAsync(dev, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice, b->st));
   HIPCHK(nullptr, hipStreamSynchronize(b->st));
   b->chunk = chunk;
+  b->nb = nb;
   return CPD_OK;
 }
 
@@ -1211,6 +1234,8 @@ cpd_status cpd_batch_init(cpd_batch* out, int32_t B, const cpd_params* p, const 
 
 cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
+  if (tune < 0 || tune > 1 + kBatchCands)
+    return bfail(b, CPD_E_ARG, "tune must be 0, 1 or 2 + a candidate index (0..7)");
   // per-instance eigen-prep, four host threads on streams of their own
   const int nt = std::min(4, b->B);
   std::vector<hipStream_t> sts(nt, nullptr);
@@ -1233,16 +1258,21 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   for (auto& s : sts) (void)hipStreamDestroy(s);
   for (int i = 0; i < b->B; ++i)
     if (rc[i] != CPD_OK) return bfail(b, rc[i], "instance " + std::to_string(i) + ": " + b->inst[i]->err);
-  // pick the split length: time two batched iterations per candidate
-  int best = kBatchChunks[0];
-  if (tune) {
+  // pick the split length and the E-step tile: time two batched iterations
+  // per candidate
+  int best = kBatchChunks[0], best_nb = kBatchTiles[0];
+  if (tune >= 2) {
+    best = kBatchChunks[(tune - 2) / 2];
+    best_nb = kBatchTiles[(tune - 2) % 2];
+  } else if (tune == 1) {
     float best_ms = 1e30f;
     EventGuard g0, g1;
     HIPCHK(nullptr, hipEventCreate(&g0.e));
     HIPCHK(nullptr, hipEventCreate(&g1.e));
     hipEvent_t e0 = g0.e, e1 = g1.e;
-    for (int c = 0; c < 4; ++c) {
-      const cpd_status s = batch_build(b, kBatchChunks[c]);
+    for (int c = 0; c < kBatchCands; ++c) {
+      const int ch = kBatchChunks[c / 2], nb = kBatchTiles[c % 2];
+      const cpd_status s = batch_build(b, ch, nb);
       if (s != CPD_OK) return s;
       hipLaunchKernelGGL(kb_reset, dim3((b->B + 255) / 256), dim3(256), 0, b->st, batch_desc(b), b->B, 0);
       batch_iteration_launch(batch_desc(b), b->items, b->st);  // warm
@@ -1255,11 +1285,12 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
       b->tune_ms[c] = ms / 2;
       if (ms < best_ms) {
         best_ms = ms;
-        best = kBatchChunks[c];
+        best = ch;
+        best_nb = nb;
       }
     }
   }
-  cpd_status s = batch_build(b, best);
+  cpd_status s = batch_build(b, best, best_nb);
   if (s != CPD_OK) return s;
   s = batch_restart(b);
   if (s != CPD_OK) return s;
@@ -1363,11 +1394,15 @@ cpd_status cpd_batch_register(cpd_batch b, const float* W0_packed, const double*
   return all ? CPD_OK : CPD_NOT_CONVERGED;
 }
 
-cpd_status cpd_batch_info(cpd_batch b, int32_t* chunk, double* tune_ms) {
+cpd_status cpd_batch_info(cpd_batch b, int32_t* chunk, int32_t* tile, double* tune_ms,
+                          int32_t* K) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
   if (chunk) *chunk = b->chunk;
+  if (tile) *tile = 256 * b->nb;
   if (tune_ms)
-    for (int c = 0; c < 4; ++c) tune_ms[c] = b->tune_ms[c];
+    for (int c = 0; c < kBatchCands; ++c) tune_ms[c] = b->tune_ms[c];
+  if (K)
+    for (int i = 0; i < b->B; ++i) K[i] = b->inst[i]->K;
   return CPD_OK;
 }
 

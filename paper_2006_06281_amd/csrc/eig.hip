@@ -31,6 +31,10 @@ constexpr int kFullMaxCols = 2048;   // widest basis of the adaptive FULL mode
 constexpr int kCholNB = kCholBlock;  // block width of the blocked Cholesky
 constexpr int kDenseMax = 1024;
 constexpr int kFullOversample = 32;
+// First basis width of the adaptive FULL mode (doubled until round-off):
+// surfaces with a few hundred numerically nonzero eigenvalues stop at the
+// first or second width, and each Rayleigh-Ritz Jacobi costs O(n^3).
+constexpr int kFullStart = 256;
 constexpr int kGramMaxChunks = 64;
 constexpr int kJacobiMax = kTopKMaxCols;
 constexpr int kJacobiStagedMax = 1024;  // one launch per step up to this size
@@ -1105,7 +1109,7 @@ int run(const EigRun& r, int* K_out, std::string* msg) {
     if (r.M <= kDenseMax) return dense_full<PT>(c, K_out, msg);
     // widen until the trailing Ritz value is round-off of the largest
     const int nmax = c.L.n;
-    int n = std::min(nmax, 512);
+    int n = std::min(nmax, kFullStart);
     for (;;) {
       const int p = std::min(kFullOversample, n / 4);
       const int K = n - p;

@@ -660,11 +660,13 @@ __global__ __launch_bounds__(256) void kb_prescale(const InstDesc* __restrict__ 
   else
     prescale_body<float>(D.Xt, D.Y, D.xs, D.ys, D.M, D.N, D.sc, 1, it.y, 0, 0);
 }
+// NB scene (model) points per thread: tiles of 256 NB points per block.
+template <int NB>
 __global__ __launch_bounds__(256) void kb_colsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  colsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsA, D.sc, D.w, D.partA, D.boxX, D.boxY,
+  colsum_body<float, 3, NB>(D.xs, D.ys, D.M, D.N, D.splitsA, D.sc, D.w, D.partA, D.boxX, D.boxY,
                            1, it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ d,
@@ -674,11 +676,12 @@ __global__ __launch_bounds__(256) void kb_colmerge(const InstDesc* __restrict__ 
   colmerge_body<float>(D.partA, D.splitsA, D.ys, (float*)nullptr, D.M, D.N, 3, D.sc, D.w,
                        D.llpart, D.boxY, 6, (__bf16*)nullptr, D.xs, 1, it.y, 0, 0);
 }
+template <int NB>
 __global__ __launch_bounds__(256) void kb_rowsum(const InstDesc* __restrict__ d,
                                                  const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
   const InstDesc& D = d[it.x];
-  rowsum_body<float, 3, 4>(D.xs, D.ys, D.M, D.N, D.splitsB, D.sc, D.partB, D.boxX, D.boxY, 1,
+  rowsum_body<float, 3, NB>(D.xs, D.ys, D.M, D.N, D.splitsB, D.sc, D.partB, D.boxX, D.boxY, 1,
                            it.y, it.z, 0);
 }
 __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ d,
@@ -690,9 +693,15 @@ __global__ __launch_bounds__(256) void kb_rowmerge(const InstDesc* __restrict__ 
 }
 void batch_estep_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
   hipLaunchKernelGGL(kb_prescale, dim3(it.n_prescale), dim3(256), 0, st, d, it.prescale);
-  hipLaunchKernelGGL(kb_colsum, dim3(it.n_colsum), dim3(256), 0, st, d, it.colsum);
+  if (it.nb == 2)
+    hipLaunchKernelGGL(kb_colsum<2>, dim3(it.n_colsum), dim3(256), 0, st, d, it.colsum);
+  else
+    hipLaunchKernelGGL(kb_colsum<4>, dim3(it.n_colsum), dim3(256), 0, st, d, it.colsum);
   hipLaunchKernelGGL(kb_colmerge, dim3(it.n_colmerge), dim3(256), 0, st, d, it.colmerge);
-  hipLaunchKernelGGL(kb_rowsum, dim3(it.n_rowsum), dim3(256), 0, st, d, it.rowsum);
+  if (it.nb == 2)
+    hipLaunchKernelGGL(kb_rowsum<2>, dim3(it.n_rowsum), dim3(256), 0, st, d, it.rowsum);
+  else
+    hipLaunchKernelGGL(kb_rowsum<4>, dim3(it.n_rowsum), dim3(256), 0, st, d, it.rowsum);
   hipLaunchKernelGGL(kb_rowmerge, dim3(it.n_rowmerge), dim3(256), 0, st, d, it.rowmerge);
 }
 

@@ -99,6 +99,8 @@ template <typename T> struct FastMArgs {
 };
 template <typename T> int fast_mstep_launch(const FastMArgs<T>& a, hipStream_t st);
 template <typename T> int fast_mstep_chunks(int M, int* rows_per_chunk);
+// FP32 with K % 4 == 0 and K <= 1024: the M-step takes 16-byte loads of U
+template <typename T> bool fast_mstep_vec4(int K);
 
 template <typename T> struct Sigma2Args {
   P4<T>* Xt;          // old iterate; overwritten with Xnew
@@ -239,12 +241,14 @@ struct InstDesc {
 // Work items: (instance, block index x, block index y, unused), one per
 // workgroup of the corresponding stage.
 struct BatchItems {
-  const int4 *prescale, *colsum, *colmerge, *rowsum, *rowmerge, *tpart, *tmerge, *apply,
-      *sigpart, *inst;
-  int n_prescale, n_colsum, n_colmerge, n_rowsum, n_rowmerge, n_tpart, n_tmerge, n_apply,
-      n_sigpart, n_inst;
-  int kt;             // eigenpairs per thread in k_tpart (from the largest K)
-  int maxK;
+  const int4 *prescale, *colsum, *colmerge, *rowsum, *rowmerge, *tpart, *tpart4, *tmerge, *apply,
+      *apply4, *sigpart, *inst;
+  int n_prescale, n_colsum, n_colmerge, n_rowsum, n_rowmerge, n_tpart, n_tpart4, n_tmerge,
+      n_apply, n_apply4, n_sigpart, n_inst;
+  int nb;             // points per thread in the E-step passes (tiles of 256 nb)
+  int kt;             // eigenpairs per thread in kb_tpart (from the largest K it serves)
+  int maxK;           // largest K among instances on the generic M-step kernels
+  int maxK4;          // largest K among instances on the 16-byte-load kernels
   int* done_count;    // device counter of finished instances
 };
 void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t st);

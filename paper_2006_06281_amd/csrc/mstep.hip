@@ -184,11 +184,11 @@ __global__ __launch_bounds__(256) void k_apply(const P4<T>* __restrict__ X,
 // T: the block's threads split into RP = 256 / (K/4) row lanes of K/4
 // threads; thread (r, q) accumulates k = 4q..4q+3 over rows m = m0 + r,
 // m0 + r + RP, ...; the row lanes are summed in LDS in a fixed order.
-__global__ __launch_bounds__(256) void k_tpart4(const P4<float>* __restrict__ X,
+__device__ __forceinline__ void tpart4_body(const P4<float>* __restrict__ X,
                                                 const P4<float>* __restrict__ Yt,
                                                 const float* __restrict__ U, int M, int K,
                                                 int rows, const DevScalars* __restrict__ sc,
-                                                float* __restrict__ tpart, int gate) {
+                                                float* __restrict__ tpart, int gate, int bx_) {
   __shared__ float red[256 * 12];
   if (gate && sc->done) return;
   const int KQ = K >> 2, RP = 256 / KQ;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_tpart4(const P4<float>* __restrict__ X,
   float a[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) a[i] = 0.f;
-  const int m0 = blockIdx.x * rows, m1 = min(M, m0 + rows);
+  const int m0 = bx_ * rows, m1 = min(M, m0 + rows);
   if (r < RP) {
 #pragma unroll 4
     for (int m = m0 + r; m < m1; m += RP) {
@@ -225,17 +225,25 @@ __global__ __launch_bounds__(256) void k_tpart4(const P4<float>* __restrict__ X,
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float* o = tpart + ((size_t)blockIdx.x * K + 4 * q + j) * 4;
+      float* o = tpart + ((size_t)bx_ * K + 4 * q + j) * 4;
       *reinterpret_cast<float4*>(o) = make_float4(a[3 * j], a[3 * j + 1], a[3 * j + 2], 0.f);
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_tpart4(const P4<float>* __restrict__ X,
+                                                const P4<float>* __restrict__ Yt,
+                                                const float* __restrict__ U, int M, int K,
+                                                int rows, const DevScalars* __restrict__ sc,
+                                                float* __restrict__ tpart, int gate) {
+  tpart4_body(X, Yt, U, M, K, rows, sc, tpart, gate, blockIdx.x);
 }
 
 // Xnew_m = X_m + U_m . HT, W_m = U_m . GT: sixteen lanes per row, four rows
 // per wave in flight together, 64 rows per block.  GT and HT sit in LDS as
 // six float arrays, so the four factors of a lane's float4 of U are 16-byte
 // reads that fall on distinct banks across the sixteen lanes.
-__global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
+__device__ __forceinline__ void apply4_body(const P4<float>* __restrict__ X,
                                                 const float* __restrict__ U,
                                                 const P4<float>* __restrict__ GTg,
                                                 const P4<float>* __restrict__ HTg, int M, int K,
@@ -245,7 +253,7 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
                                                 P4<float>* __restrict__ Xt,
                                                 const P4<float>* __restrict__ Yt,
                                                 const float* __restrict__ tbar,
-                                                double* __restrict__ sigpart) {
+                                                double* __restrict__ sigpart, int bx_) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[16];
   if (gate && sc->done) return;
@@ -268,7 +276,7 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
   float acc[4][6];
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
-    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+    const int m = bx_ * 64 + wave * 16 + it * 4 + sub;
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[it][c] = 0.f;
     if (m < M) {
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
     for (int c = 0; c < 6; ++c)
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) acc[it][c] += __shfl_xor(acc[it][c], o, 16);
-    const int m = blockIdx.x * 64 + wave * 16 + it * 4 + sub;
+    const int m = bx_ * 64 + wave * 16 + it * 4 + sub;
     if (l16 == 0 && m < M) {
       const P4<float> x = X[m];
       const P4<float> a{x.x + acc[it][3], x.y + acc[it][4], x.z + acc[it][5], 0.f};
@@ -311,10 +319,24 @@ __global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
   if (sigpart) {
     const double s1 = block_sum_d(v, sh);
     if (threadIdx.x == 0) {
-      sigpart[2 * blockIdx.x] = s1;
-      sigpart[2 * blockIdx.x + 1] = 0.0;
+      sigpart[2 * bx_] = s1;
+      sigpart[2 * bx_ + 1] = 0.0;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_apply4(const P4<float>* __restrict__ X,
+                                                const float* __restrict__ U,
+                                                const P4<float>* __restrict__ GTg,
+                                                const P4<float>* __restrict__ HTg, int M, int K,
+                                                const DevScalars* __restrict__ sc,
+                                                P4<float>* __restrict__ Xnew,
+                                                P4<float>* __restrict__ W, int gate,
+                                                P4<float>* __restrict__ Xt,
+                                                const P4<float>* __restrict__ Yt,
+                                                const float* __restrict__ tbar,
+                                                double* __restrict__ sigpart) {
+  apply4_body(X, U, GTg, HTg, M, K, sc, Xnew, W, gate, Xt, Yt, tbar, sigpart, blockIdx.x);
 }
 
 // T_k over the row chunks with 16-byte loads: one block of 256 threads per
@@ -758,6 +780,22 @@ __global__ __launch_bounds__(256) void kb_apply(const InstDesc* __restrict__ d,
   const InstDesc& D = d[it.x];
   apply_body<float, LDS>(D.X, D.U, D.GT, D.HT, D.M, D.K, D.sc, D.Xnew, D.W, 1, it.y, 0, 0);
 }
+// Instances whose U rows allow 16-byte loads (fast_mstep_vec4) run the
+// single-handle bodies; their apply also writes the sigma^2 partials and
+// retires the iterate, so they have no kb_sigpart items.
+__global__ __launch_bounds__(256) void kb_tpart4(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  tpart4_body(D.X, D.Yt, D.U, D.M, D.K, D.mrows, D.sc, D.tpart, 1, it.y);
+}
+__global__ __launch_bounds__(256) void kb_apply4(const InstDesc* __restrict__ d,
+                                                 const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const InstDesc& D = d[it.x];
+  apply4_body(D.X, D.U, D.GT, D.HT, D.M, D.K, D.sc, D.Xnew, D.W, 1, D.Xt, D.Yt, D.tbar,
+              D.sigpart, it.y);
+}
 __global__ __launch_bounds__(256) void kb_sigpart(const InstDesc* __restrict__ d,
                                                   const int4* __restrict__ items) {
   const int4 it = items[blockIdx.x];
@@ -782,19 +820,29 @@ __global__ __launch_bounds__(256) void kb_count_done(const InstDesc* __restrict_
 }
 
 void batch_mstep_sigma_launch(const InstDesc* d, const BatchItems& it, hipStream_t st) {
-  if (it.kt == 1)
-    hipLaunchKernelGGL(kb_tpart<1>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
-  else if (it.kt == 2)
-    hipLaunchKernelGGL(kb_tpart<2>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
-  else
-    hipLaunchKernelGGL(kb_tpart<4>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+  if (it.n_tpart > 0) {
+    if (it.kt == 1)
+      hipLaunchKernelGGL(kb_tpart<1>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+    else if (it.kt == 2)
+      hipLaunchKernelGGL(kb_tpart<2>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+    else
+      hipLaunchKernelGGL(kb_tpart<4>, dim3(it.n_tpart), dim3(256), 0, st, d, it.tpart);
+  }
+  if (it.n_tpart4 > 0)
+    hipLaunchKernelGGL(kb_tpart4, dim3(it.n_tpart4), dim3(256), 0, st, d, it.tpart4);
   hipLaunchKernelGGL(kb_tmerge, dim3(it.n_tmerge), dim3(64), 0, st, d, it.tmerge);
-  const size_t lds = 2 * (size_t)it.maxK * sizeof(P4<float>);
-  if (lds <= kApplyLdsBytes)
-    hipLaunchKernelGGL(kb_apply<true>, dim3(it.n_apply), dim3(256), lds, st, d, it.apply);
-  else
-    hipLaunchKernelGGL(kb_apply<false>, dim3(it.n_apply), dim3(256), 0, st, d, it.apply);
-  hipLaunchKernelGGL(kb_sigpart, dim3(it.n_sigpart), dim3(256), 0, st, d, it.sigpart);
+  if (it.n_apply > 0) {
+    const size_t lds = 2 * (size_t)it.maxK * sizeof(P4<float>);
+    if (lds <= kApplyLdsBytes)
+      hipLaunchKernelGGL(kb_apply<true>, dim3(it.n_apply), dim3(256), lds, st, d, it.apply);
+    else
+      hipLaunchKernelGGL(kb_apply<false>, dim3(it.n_apply), dim3(256), 0, st, d, it.apply);
+  }
+  if (it.n_apply4 > 0)
+    hipLaunchKernelGGL(kb_apply4, dim3(it.n_apply4), dim3(256), 6 * (size_t)it.maxK4 * sizeof(float),
+                       st, d, it.apply4);
+  if (it.n_sigpart > 0)
+    hipLaunchKernelGGL(kb_sigpart, dim3(it.n_sigpart), dim3(256), 0, st, d, it.sigpart);
   hipLaunchKernelGGL(kb_sigfinal, dim3(it.n_inst), dim3(256), 0, st, d, it.inst);
   hipLaunchKernelGGL(kb_count_done, dim3(1), dim3(256), 0, st, d, it.n_inst, it.done_count);
 }
@@ -807,6 +855,7 @@ void batch_iteration_launch(const InstDesc* d, const BatchItems& it, hipStream_t
 #define FCPD_INST(T)                                                                          \
   template int fast_mstep_launch<T>(const FastMArgs<T>&, hipStream_t);                       \
   template int fast_mstep_chunks<T>(int, int*);                                              \
+  template bool fast_mstep_vec4<T>(int);                                                     \
   template void sigma2_launch<T>(const Sigma2Args<T>&, hipStream_t);                         \
   template int sigma2_blocks<T>(int);                                                        \
   template void init_launch<T>(const T*, const T*, P4<T>*, P4<T>*, P4<T>*, int, int, int,     \

@@ -26,24 +26,40 @@ def _instances(B, lo, hi, seed0):
 
 
 def test_batch_matches_oracle_per_instance(lib):
+    """10 instances of 150..1800 points (dense FULL eigen-prep below 1025
+    points with K = M, some K % 4 != 0, randomized above): every plan the
+    tuner can choose (4 split lengths x 2 E-step tiles) and the tuned one
+    give the oracle's 15 iterations within 1e-5."""
     import torch
     pairs = _instances(10, 150, 1800, 500)
     say("batch vs oracle", [(p.M, p.N) for p in pairs])
     Xs = [dev(_f32(p.X), torch.float32) for p in pairs]
     Ys = [dev(_f32(p.Y), torch.float32) for p in pairs]
+    refs = []
+    for p in pairs:
+        X, Y = _f32(p.X), _f32(p.Y)
+        refs.append(cpd64.register(X, Y, p.beta, p.lam, p.w, "fast",
+                                   eig=eig64.eig_full(eig64.gram(X, p.beta)), iters=15).Xt)
     br = lib.BatchRegistration(Xs, Ys, beta=[p.beta for p in pairs], lam=[p.lam for p in pairs],
                                w=0.1, eig_mode="full", tol=0.0, max_iter=15)
-    br.prepare(tune=True)
-    chunk, tms = br.info()
-    say("tuned chunk", chunk, tms)
-    Xt, res = br.register()
-    for p, x, r in zip(pairs, Xt, res):
-        X, Y = _f32(p.X), _f32(p.Y)
-        ref = cpd64.register(X, Y, p.beta, p.lam, p.w, "fast",
-                             eig=eig64.eig_full(eig64.gram(X, p.beta)), iters=15)
-        err = cpd64.rel_rms(host(x), ref.Xt)
-        say(p.M, p.N, "iters", r.iters, "rel_rms", err)
-        assert r.iters == 15 and err < 1e-5
+    plans = [None] + list(range(8))
+    for cand in plans:
+        if cand is None:
+            br.prepare(tune=True)
+        else:
+            br.prepare(candidate=cand)
+        info = br.info()
+        say("plan", cand, "chunk", info["chunk"], "tile", info["tile"], "K", info["K"])
+        if cand is not None:
+            assert (info["chunk"], info["tile"]) == lib.BatchRegistration.candidates()[cand]
+        else:
+            assert all(v > 0 for v in info["tune_ms"].values())
+        Xt, res = br.register()
+        for p, x, r, ref in zip(pairs, Xt, res, refs):
+            err = cpd64.rel_rms(host(x), ref)
+            assert r.iters == 15 and err < 1e-5, (cand, p.M, p.N, err)
+        assert any(k % 4 for k in info["K"]) and any(k % 4 == 0 for k in info["K"])
+    br.close()
 
 
 def test_batch_instances_stop_independently(lib):
