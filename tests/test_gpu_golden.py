@@ -179,3 +179,39 @@ def test_surface50k_twenty_iterations_match_the_oracle(lib, precision, bar):
     assert out.iters == meta["iters"]
     assert err < bar
     assert out.sigma2 == pytest.approx(s2o, rel=bar)
+
+
+# ---------------------------------------------------- surface20k, w = 0.2
+def test_surface20k_w02_trace_matches_the_oracle(lib):
+    """The 50k recipe at M = N = 20 000 with its configured w = 0.2 (20%
+    uniform outliers): 250 Fast CPD iterations (eq. 20, top-300 eigenpairs
+    from the oracle's test matrix) in FP64 from the closed-form sigma^2_0,
+    stepped one at a time, against the oracle's sigma^2 and RMSE (eq. 22)
+    traces.  The oracle's run does not converge to the registration (its
+    RMSE falls to 0.14 by iteration 30, then grows to 0.62); the GPU must
+    follow the same path."""
+    import torch
+    z, meta = _load("surface20k_w02")
+    M, iters = meta["M"], meta["iters"]
+    p = synth.workload("surface50k", M=M)
+    omega = dev(synth.gaussian_matrix(M, meta["K"] + meta["oversample"], 0), torch.float64)
+    r = lib.Registration(dev(p.X, torch.float64), dev(p.Y, torch.float64), precision="fp64",
+                         beta=meta["beta"], lam=meta["lam"], w=meta["w"], eig_mode="topk",
+                         K=meta["K"], oversample=meta["oversample"],
+                         power_iters=meta["power_iters"], tol=0.0, max_iter=iters)
+    r.prepare(omega=omega)
+    Yh = dev(p.Y_hat, torch.float64)
+    s2, rm = [], []
+    for k in range(iters):
+        s2.append(r.step().sigma2)
+        Xt = r.state()[0]
+        rm.append(float(((Xt - Yh) ** 2).sum(1).mean().sqrt()))
+    r.close()
+    s2, rm = np.array(s2), np.array(rm)
+    es = np.abs(s2 / z["sigma2"] - 1.0)
+    er = np.abs(rm / z["rmse"] - 1.0)
+    say("surface20k w=0.2: sigma2", s2[[0, 99, -1]], "oracle", z["sigma2"][[0, 99, -1]])
+    say("rmse", rm[[0, 99, -1]], "oracle", z["rmse"][[0, 99, -1]])
+    say("max rel diff sigma2", es.max(), "at", int(es.argmax()), "rmse", er.max(), "at",
+        int(er.argmax()))
+    assert es.max() < 1e-6 and er.max() < 1e-6
