@@ -12,7 +12,7 @@
 //
 // Two-level blocking: panels of NP = 256 columns, each factored as two
 // blocks of NB = 128.  Per block k of a panel:
-//   diag   factor the NB x NB diagonal block in registers, keep L_kk^-1
+//   diag   factor the NB x NB diagonal block in LDS, keep L_kk^-1
 //   panel  P[:, k] = A[below, k] L_kk^-T     (FP64, into the panel buffer)
 //   store  P[:, k] back into A
 //   inner  after the first block: A[below, second block] -= P1 P1^T (the
@@ -96,139 +96,86 @@ __global__ __launch_bounds__(256) void k_build_system(const double* __restrict__
 }
 
 // ------------------------------------------------------------- diagonal
-// Factor the nb x nb diagonal block at (k0, k0) in place (lower triangle)
-// and write L_kk^-1 (NB x NB, zero-padded) to Linv; a pivot that is not
-// positive and finite sets *chol_fail.  One workgroup of 32 x 32
-// threads; thread (ty, tx) keeps the 16 elements (ty + 32 i, tx + 32 k) of
-// the block, and of its inverse, in registers.  Step j of the factorisation
-// publishes the (unscaled) column j through LDS and every thread updates its
-// own elements, s_rc -= (s_rj / d_j) s_cj; columns are scaled by sqrt(d_j)
-// at the end.  The inverse follows by forward elimination on X = I:
-// X_j. /= l_jj, then X_r. -= l_rj X_j. for r > j.  LDS holds only the
-// published column and row (double-buffered: one barrier per step).
+// Cholesky of the nb x nb diagonal block at (k0, k0), in LDS; writes L_kk back
+// (lower; the strict upper part is left as is) and Linv = L_kk^-1 (lower,
+// nb x nb, row-major with stride NB).  Breakdown sets *chol_fail.  The
+// inverse is built in the tile's free upper triangle (Linv[r][c] at s[c][r]),
+// one row per step, all columns of the row in parallel.
 __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int lda, int k0,
                                                      int nb, double* __restrict__ Linv,
                                                      int* chol_fail, const int* done) {
-  static_assert(NB == 128, "the register tiling assumes 128 x 128 blocks");
-  __shared__ double col[2][NB];
-  __shared__ double row[2][NB];
-  __shared__ double piv[NB];
+  __shared__ double s[NB][NB + 1];
+  __shared__ int fail;
   if (done && *done) return;
   if (*chol_fail) return;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  double a[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = ty + 32 * i, c = tx + 32 * k;
-      a[i][k] = (c <= r && r < nb) ? A[(size_t)(k0 + r) * lda + k0 + c] : 0.0;
-    }
-  bool fail = false;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tx = tid & 31, ty = tid >> 5;  // 32 x 32 thread grid for updates
+  for (int e = tid; e < nb * nb; e += nt) {
+    const int r = e / nb, c = e % nb;
+    s[r][c] = c <= r ? A[(size_t)(k0 + r) * lda + k0 + c] : 0.0;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  // one barrier per column: step j updates the trailing triangle with the
+  // unscaled column j (s[r][c] -= s[r][j] s[c][j] / d_j) and scales column
+  // j - 1, which no thread reads any more
+  double dprev = 1.0;
   for (int j = 0; j < nb; ++j) {
-    double* cj = col[j & 1];
-    if (tx == (j & 31)) {  // owners of column j publish rows >= j
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k == (j >> 5))
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = ty + 32 * i;
-            if (r >= j && r < nb) cj[r] = a[i][k];
-          }
-    }
-    __syncthreads();
-    const double d = cj[j];  // every thread reads the same pivot
+    const double d = s[j][j];  // every thread reads the same pivot
     if (!(d > 0.0) || !isfinite(d)) {
-      fail = true;
+      if (tid == 0) fail = 1;
       break;
     }
-    if (tid == 0) piv[j] = d;
     const double inv = 1.0 / d;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ty + 32 * i;
-      if (r > j && r < nb) {
-        const double lr = cj[r] * inv;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = tx + 32 * k;
-          if (c > j && c <= r) a[i][k] -= lr * cj[c];
-        }
-      }
+    for (int r = j + 1 + ty; r < nb; r += 32) {
+      const double lr = s[r][j] * inv;
+      for (int c = j + 1 + tx; c <= r; c += 32) s[r][c] -= lr * s[c][j];
     }
+    if (j > 0) {
+      const double piv = sqrt(dprev);
+      for (int r = j - 1 + tid; r < nb; r += nt) s[r][j - 1] = r == j - 1 ? piv : s[r][j - 1] / piv;
+    }
+    dprev = d;
+    __syncthreads();
   }
-  if (fail) {  // uniform: every thread saw the same pivot
+  __syncthreads();
+  if (fail) {
     if (tid == 0) *chol_fail = 1;
     return;
   }
-  __syncthreads();  // piv complete
-  // scale: l_rc = s_rc / sqrt(d_c), l_cc = sqrt(d_c)
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = ty + 32 * i, c = tx + 32 * k;
-      if (c <= r && r < nb) {
-        const double sq = sqrt(piv[c]);
-        a[i][k] = r == c ? sq : a[i][k] / sq;
-        A[(size_t)(k0 + r) * lda + k0 + c] = a[i][k];
+  {
+    const double piv = sqrt(dprev);
+    for (int r = nb - 1 + tid; r < nb; r += nt) s[r][nb - 1] = piv;
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += nt) {
+    const int r = e / nb, c = e % nb;
+    if (c <= r) A[(size_t)(k0 + r) * lda + k0 + c] = s[r][c];
+  }
+  // X = L^-1 row by row: X[r][c] = -(sum_{c<=k<r} L[r][k] X[k][c]) / L[r][r]
+  // for c < r, all columns at once, eight threads per column splitting the
+  // sum (X[k][c] for k > c lives at s[c][k]; X[c][c] = 1 / L[c][c])
+  {
+    const int c = tid >> 3, g = tid & 7;
+    for (int r = 1; r < nb; ++r) {
+      double v = 0.0;
+      if (c < r) {
+        if (g == 0) v = s[r][c] / s[c][c];
+        for (int k = c + 1 + g; k < r; k += 8) v = fma(s[r][k], s[c][k], v);
       }
-    }
-  // X = L^-1 by forward elimination, X starts as I
-  double x[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[i][k] = (ty + 32 * i == tx + 32 * k) ? 1.0 : 0.0;
-  for (int j = 0; j < nb; ++j) {
-    double* lj = col[j & 1];
-    double* xj = row[j & 1];
-    const double ljj = sqrt(piv[j]);
-    if (tx == (j & 31)) {  // column j of L below the diagonal
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k == (j >> 5))
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = ty + 32 * i;
-            if (r > j && r < nb) lj[r] = a[i][k];
-          }
-    }
-    if (ty == (j & 31)) {  // row j of X, scaled by 1 / l_jj
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (i == (j >> 5))
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int c = tx + 32 * k;
-            if (c <= j) {
-              x[i][k] /= ljj;
-              xj[c] = x[i][k];
-            }
-          }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = ty + 32 * i;
-      if (r > j && r < nb) {
-        const double l = lj[r];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = tx + 32 * k;
-          if (c <= j) x[i][k] -= l * xj[c];
-        }
-      }
+      v += __shfl_xor(v, 1, 8);
+      v += __shfl_xor(v, 2, 8);
+      v += __shfl_xor(v, 4, 8);
+      if (c < r && g == 0) s[c][r] = -v / s[r][r];
+      __syncthreads();
     }
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = ty + 32 * i, c = tx + 32 * k;
-      Linv[(size_t)r * NB + c] = (r < nb && c < nb && c <= r) ? x[i][k] : 0.0;
-    }
+  for (int e = tid; e < NB * NB; e += nt) {
+    const int r = e / NB, c = e % NB;
+    double v = 0.0;
+    if (r < nb && c < nb) v = r == c ? 1.0 / s[r][r] : (r > c ? s[c][r] : 0.0);
+    Linv[e] = v;
+  }
 }
 
 // P[r][c] = sum_t A[k0+nb+r][k0+t] Linv[c][t]  (P = A_panel L_kk^-T), 64 rows
