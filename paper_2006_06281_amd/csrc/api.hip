@@ -179,6 +179,7 @@ struct cpd_ctx {
   int sig_fused = 0;  // sigma^2 partials the last enqueued M-step wrote (0: none)
   double t_eig = 0.0;
   std::string err;
+  JacobiBatcher* jb = nullptr;  // set while a batch prepares: grouped Jacobi solves
   template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
   DevScalars* sc() const { return at<DevScalars>(L.sc); }
   // caller row of internal model / scene row i (NULL: same order)
@@ -594,6 +595,7 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     r.lam = h->at<double>(L.lam);
     r.Kcap = L.Kcap;
     r.st = h->st;
+    r.jb = h->jb;
     int K = 0;
     std::string msg;
     const int rc = eig_prepare_run(r, &K, &msg);
@@ -930,9 +932,12 @@ constexpr int kBatchChunks[] = {1024, 2048, 512, 4096};  // split-length candida
 constexpr int kBatchTiles[] = {4, 2};  // E-step points per thread (tiles of 256 x this)
 constexpr int kBatchCands = 8;         // chunk-major: candidate c = kBatchChunks[c / 2], kBatchTiles[c % 2]
 constexpr int kBatchSmallestChunk = 512;
+// host threads (one stream each) that run the instances' eigen-preps in
+// waves; their Jacobi solves are grouped into shared launches
+constexpr int kPrepThreads = 32;
 
 struct BatchHeader {
-  size_t desc = 0, items = 0, done = 0, end = 0;
+  size_t desc = 0, items = 0, done = 0, jac = 0, jacflags = 0, end = 0;
   size_t item_cap = 0;
 };
 
@@ -966,6 +971,8 @@ BatchHeader batch_header(int B, const cpd_params* p) {
   h.item_cap = batch_item_capacity(B, p);
   h.items = take(h.item_cap * sizeof(int4));
   h.done = take(256);
+  h.jac = take((size_t)kPrepThreads * sizeof(JacMember));
+  h.jacflags = take((size_t)kPrepThreads * sizeof(int));
   h.end = off;
   return h;
 }
@@ -1236,25 +1243,43 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
   if (!b) return fail(nullptr, CPD_E_ARG, "batch handle is NULL");
   if (tune < 0 || tune > 1 + kBatchCands)
     return bfail(b, CPD_E_ARG, "tune must be 0, 1 or 2 + a candidate index (0..7)");
-  // per-instance eigen-prep, four host threads on streams of their own
-  const int nt = std::min(4, b->B);
+  // per-instance eigen-prep in waves of up to kPrepThreads host threads, one
+  // stream each; the Jacobi solves of a wave run as grouped launches
+  const int nt = std::min(kPrepThreads, b->B);
   std::vector<hipStream_t> sts(nt, nullptr);
   for (auto& s : sts) HIPCHK(nullptr, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  JacobiBatcher jb(reinterpret_cast<JacMember*>(b->ws + b->hd.jac),
+                   reinterpret_cast<int*>(b->ws + b->hd.jacflags), kPrepThreads);
   std::vector<cpd_status> rc(b->B, CPD_OK);
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t) {
-    th.emplace_back([&, t]() {
-      for (int i = t; i < b->B; i += nt) {
+  // instances whose FULL eigen-prep is the dense Jacobi on all M points go
+  // first, widest first, so that they share waves (a wave's Jacobi launches
+  // run as many steps as its widest solve needs)
+  std::vector<int> order(b->B);
+  for (int i = 0; i < b->B; ++i) order[i] = i;
+  auto dense_n = [&](int i) {
+    const cpd_params& q = b->p[i];
+    return (q.eig_mode == CPD_EIG_FULL && eig_full_capacity(q.M) == q.M) ? q.M : 0;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return dense_n(a) > dense_n(c); });
+  for (int w0 = 0; w0 < b->B; w0 += nt) {
+    const int wn = std::min(nt, b->B - w0);
+    jb.begin(wn);
+    std::vector<std::thread> th;
+    for (int t = 0; t < wn; ++t) {
+      th.emplace_back([&, t]() {
+        const int i = order[w0 + t];
         cpd_ctx* h = b->inst[i];
         h->st = sts[t];
+        h->jb = &jb;
         rc[i] = prepare_impl<float>(h, nullptr, nullptr, nullptr);
+        jb.leave();
+        h->jb = nullptr;
         h->st = b->st;
         if (rc[i] == CPD_NOT_CONVERGED) rc[i] = CPD_OK;  // a truncated FULL basis is usable
-        if (rc[i] != CPD_OK) break;
-      }
-    });
+      });
+    }
+    for (auto& x : th) x.join();
   }
-  for (auto& x : th) x.join();
   for (auto& s : sts) (void)hipStreamDestroy(s);
   for (int i = 0; i < b->B; ++i)
     if (rc[i] != CPD_OK) return bfail(b, rc[i], "instance " + std::to_string(i) + ": " + b->inst[i]->err);

@@ -629,17 +629,17 @@ __global__ void k_jac_norm(double* __restrict__ normsq, int nparts) {
 // One step (step < 0: only the deferred columns of step `prev`).  prm holds
 // (c, s, a_pp', a_qq') per pair; prm_prev is NULL before the first step.
 // Dynamic LDS: rows p and q of A and of V (4 n doubles).
-__global__ __launch_bounds__(256) void k_jac_step(double* __restrict__ A, double* __restrict__ V,
-                                                  int n, int step, int prev,
-                                                  const double* __restrict__ prm_prev,
-                                                  double* __restrict__ prm,
-                                                  const double* __restrict__ normtot,
-                                                  int* __restrict__ rotated) {
-  extern __shared__ double rows_lds[];
+__device__ __forceinline__ void jac_step_body(double* __restrict__ A, double* __restrict__ V,
+                                              int n, int step, int prev,
+                                              const double* __restrict__ prm_prev,
+                                              double* __restrict__ prm,
+                                              const double* __restrict__ normtot,
+                                              int* __restrict__ rotated, int k,
+                                              double* rows_lds) {
   double* ra[2] = {rows_lds, rows_lds + n};
   double* rv[2] = {rows_lds + 2 * n, rows_lds + 3 * n};
   __shared__ double cs_[2];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   int p, q;
   rr_pair(k, step >= 0 ? step : 0, n, &p, &q);
   const bool two = q < n;
@@ -720,6 +720,54 @@ __global__ __launch_bounds__(256) void k_jac_step(double* __restrict__ A, double
       A[(size_t)p * n + j] = x;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_jac_step(double* __restrict__ A, double* __restrict__ V,
+                                                  int n, int step, int prev,
+                                                  const double* __restrict__ prm_prev,
+                                                  double* __restrict__ prm,
+                                                  const double* __restrict__ normtot,
+                                                  int* __restrict__ rotated) {
+  extern __shared__ double rows_lds[];
+  jac_step_body(A, V, n, step, prev, prm_prev, prm, normtot, rotated, blockIdx.x, rows_lds);
+}
+
+// The same step for a group of independent matrices (blockIdx.y = member):
+// member i runs its own round-robin schedule of steps_i = n_i - 1 (n_i even;
+// n_i for odd n_i) steps per sweep, at step t mod steps_i of the group's step
+// counter t, so members of different sizes share a launch.  Members whose
+// previous sweep rotated nothing are finished and skip.
+__global__ __launch_bounds__(256) void k_jac_step_group(const JacMember* __restrict__ g, int t,
+                                                        int final_cols) {
+  extern __shared__ double rows_lds[];
+  const JacMember& J = g[blockIdx.y];
+  const int half = ((J.n + 1) & ~1) / 2;
+  if ((int)blockIdx.x >= half || !J.state[1]) return;
+  const int steps = 2 * half - 1;
+  const int prev = t > 0 ? (t - 1) % steps : 0;
+  const double* prm_prev = t > 0 ? J.prm[(t - 1) & 1] : nullptr;
+  if (final_cols)
+    jac_step_body(J.A, J.V, J.n, -1, prev, prm_prev, nullptr, J.normtot, J.state, blockIdx.x,
+                  rows_lds);
+  else
+    jac_step_body(J.A, J.V, J.n, t % steps, prev, prm_prev, J.prm[t & 1], J.normtot, J.state,
+                  blockIdx.x, rows_lds);
+}
+
+// Start of a group sweep: state = {rotated in this sweep, still active};
+// a member stays active while its last sweep rotated something.
+__global__ void k_jac_group_sweep(const JacMember* __restrict__ g, int members, int first,
+                                  int* __restrict__ rotated_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= members) return;
+  int* st = g[i].state;
+  if (first) {
+    st[1] = 1;
+  } else {
+    rotated_out[i] = st[0];
+    st[1] = st[1] && st[0];
+  }
+  st[0] = 0;
 }
 
 // Wide matrices (n > 1024, where four staged rows per pair would leave two
@@ -994,6 +1042,20 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
     *msg = "Jacobi size exceeds its limit";
     return 3;
   }
+  if (c.r.jb && n <= kJacobiStagedMax) {  // grouped with other threads' solves
+    JacobiBatcher::Req q;
+    q.A = A;
+    q.V = V;
+    q.n = n;
+    q.vals = vals;
+    q.perm = misc_int(c);
+    q.state = misc_int(c) + n + 1;
+    q.scratch = misc_dbl(c, n);
+    q.st = c.st;
+    const int rc = c.r.jb->solve(&q);
+    if (rc) *msg = q.msg;
+    return rc;
+  }
   int* perm = misc_int(c);
   int* flag = misc_int(c) + n + 1;
   double* scratch = misc_dbl(c, n);  // [0..64): norm partials, [64] their sum, 2 x 4 per pair
@@ -1038,6 +1100,129 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
   }
   return 0;
 }
+
+// Jacobi on every request of a group (all n <= kJacobiStagedMax) on stream
+// st, with grouped launches (k_jac_step_group), then each member's
+// eigenvalues sorted descending into vals / perm.  One host synchronisation
+// per sweep reads which members still rotate.
+static void jacobi_group(const std::vector<JacobiBatcher::Req*>& reqs, JacMember* dmem,
+                         int* dflags, hipStream_t st) {
+  const int G = (int)reqs.size();
+  std::vector<JacMember> mem(G);
+  int half_max = 1, steps_max = 1, n_max = 1;
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    const int n = q->n, half = ((n + 1) & ~1) / 2;
+    double* normsq = q->scratch;
+    hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, st, q->A, q->V, n, normsq);
+    hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, st, normsq, 64);
+    JacMember& m = mem[i];
+    m.A = q->A;
+    m.V = q->V;
+    m.normtot = normsq + 64;
+    m.prm[0] = q->scratch + 65;
+    m.prm[1] = q->scratch + 65 + 4 * (size_t)half;
+    m.state = q->state;
+    m.n = n;
+    m.pad = 0;
+    half_max = std::max(half_max, half);
+    steps_max = std::max(steps_max, 2 * half - 1);
+    n_max = std::max(n_max, n);
+  }
+  hipError_t e = hipMemcpyAsync(dmem, mem.data(), sizeof(JacMember) * G, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // mem is host stack memory
+  const size_t lds = 4 * (size_t)n_max * sizeof(double);
+  const dim3 grid(half_max, G);
+  std::vector<int> rot(G, 1);
+  int t = 0, sweep = 0;
+  bool any = true;
+  hipLaunchKernelGGL(k_jac_group_sweep, dim3((G + 63) / 64), dim3(64), 0, st, dmem, G, 1, dflags);
+  for (; e == hipSuccess && sweep < kJacobiSweeps; ++sweep) {
+    for (int s = 0; s < steps_max; ++s, ++t)
+      hipLaunchKernelGGL(k_jac_step_group, grid, dim3(256), lds, st, dmem, t, 0);
+    hipLaunchKernelGGL(k_jac_group_sweep, dim3((G + 63) / 64), dim3(64), 0, st, dmem, G, 0, dflags);
+    e = hipMemcpyAsync(rot.data(), dflags, sizeof(int) * G, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    any = false;
+    for (int v : rot) any = any || v;
+    if (!any) break;
+  }
+  // members still active take the last step's column rotations
+  if (e == hipSuccess && t > 0)
+    hipLaunchKernelGGL(k_jac_step_group, grid, dim3(256), lds, st, dmem, t, 1);
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, q->A, q->n, q->perm, q->vals);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    if (e != hipSuccess) {
+      q->rc = 2;
+      q->msg = std::string("grouped Jacobi: ") + hipGetErrorString(e);
+    } else if (rot[i]) {
+      q->rc = 1;
+      q->msg = "Jacobi did not converge";
+    }
+  }
+}
+
+}  // namespace
+
+void JacobiBatcher::begin(int threads) {
+  std::lock_guard<std::mutex> lk(mu_);
+  live_ = threads;
+}
+
+void JacobiBatcher::leave() {
+  std::lock_guard<std::mutex> lk(mu_);
+  --live_;
+  if (!pending_.empty() && (int)pending_.size() >= live_) run_locked();
+}
+
+int JacobiBatcher::solve(Req* r) {
+  (void)hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
+  (void)hipEventRecord(r->ready, r->st);
+  std::unique_lock<std::mutex> lk(mu_);
+  pending_.push_back(r);
+  if ((int)pending_.size() >= live_ || (int)pending_.size() >= cap_) run_locked();
+  cv_.wait(lk, [&] { return r->done; });
+  (void)hipEventDestroy(r->ready);
+  return r->rc;
+}
+
+// Runs every pending request as one group on the stream of the first, after
+// the work each submitter queued before its request; each submitter's stream
+// then waits for the group.  Called with mu_ held.
+void JacobiBatcher::run_locked() {
+  std::vector<Req*> reqs;
+  reqs.swap(pending_);
+  hipStream_t st = reqs[0]->st;
+  for (Req* q : reqs)
+    if (q->st != st) (void)hipStreamWaitEvent(st, q->ready, 0);
+  // a group runs as many steps per sweep as its widest member needs: split
+  // the requests into size classes (widest at most twice the narrowest)
+  std::vector<Req*> by_n(reqs);
+  std::sort(by_n.begin(), by_n.end(), [](const Req* a, const Req* b) { return a->n < b->n; });
+  for (size_t g0 = 0; g0 < by_n.size();) {
+    size_t g1 = g0 + 1;
+    while (g1 < by_n.size() && by_n[g1]->n <= 2 * by_n[g0]->n) ++g1;
+    jacobi_group(std::vector<Req*>(by_n.begin() + g0, by_n.begin() + g1), dev_members_,
+                 dev_flags_, st);
+    g0 = g1;
+  }
+  hipEvent_t fin = nullptr;
+  (void)hipEventCreateWithFlags(&fin, hipEventDisableTiming);
+  (void)hipEventRecord(fin, st);
+  for (Req* q : reqs) {
+    if (q->st != st) (void)hipStreamWaitEvent(q->st, fin, 0);
+    q->done = true;
+  }
+  (void)hipEventDestroy(fin);
+  cv_.notify_all();
+}
+
+namespace {
 
 template <typename PT>
 int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64_t seed,

@@ -3,7 +3,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -22,6 +27,54 @@ int eig_topk_max_cols();
 int eig_full_capacity(int M);
 EigLayout eig_layout(int M, int mode, int K, int oversample, size_t start);
 
+// One matrix of a grouped Jacobi solve (device-visible descriptor).
+struct JacMember {
+  double* A;               // n x n symmetric, destroyed (diag -> eigenvalues)
+  double* V;               // n x n eigenvectors (rows of rotations applied)
+  const double* normtot;   // |A|_F^2
+  double* prm[2];          // per-pair rotation parameters of two steps
+  int* state;              // {rotated in this sweep, active}
+  int n;
+  int pad;
+};
+
+// Collects the Jacobi solves of eigen-preps that run in parallel host
+// threads (one stream each) and runs each collection as grouped launches:
+// a thread's solve waits until every thread still inside its eigen-prep has
+// submitted one or left; the last to arrive runs the group for all.
+class JacobiBatcher {
+ public:
+  struct Req {
+    double* A;
+    double* V;
+    int n;
+    double* vals;
+    int* perm;
+    int* state;
+    double* scratch;  // norm partials [0..64), their sum [64], two rotation buffers
+    hipStream_t st;
+    hipEvent_t ready = nullptr;
+    int rc = 0;
+    std::string msg;
+    bool done = false;
+  };
+  JacobiBatcher(JacMember* dev_members, int* dev_flags, int cap)
+      : dev_members_(dev_members), dev_flags_(dev_flags), cap_(cap) {}
+  void begin(int threads);  // threads that will each call solve() or leave()
+  void leave();             // the calling thread's eigen-prep is over
+  int solve(Req* r);        // blocks until r is solved; 0 ok, 1 no convergence, 2 device error
+
+ private:
+  void run_locked();
+  JacMember* dev_members_;
+  int* dev_flags_;
+  int cap_;
+  int live_ = 0;
+  std::vector<Req*> pending_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+};
+
 struct EigRun {
   const void* X;       // P4<float> or P4<double> model points
   bool x_is_double;
@@ -36,6 +89,7 @@ struct EigRun {
   double* lam;         // out: Kcap
   int Kcap;
   hipStream_t st;
+  JacobiBatcher* jb = nullptr;  // nullable: group the Jacobi solves with other threads'
 };
 // 0 ok, 1 numerical failure, 2 device error, 3 unsupported.
 int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg);
