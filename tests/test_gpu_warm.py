@@ -2,7 +2,7 @@
 
 Two recipes drawn by the device generator, each with a short training run
 and held-out pairs from disjoint seeds registered twice by the batched path:
-from W = 0 and from the network's W0.  Registration from W = 0 is the judge.
+from W = 0 and from the network's W0.  Registration from W = 0 is the reference.
   sphere  the cfg5 recipe (unit sphere, coefficient scale 0.3 sqrt(500/M)):
           a field so large that registration from W = 0 does not recover it;
           the warm start must start at less than half the error.
