@@ -83,3 +83,36 @@ def test_batch_instances_stop_independently(lib):
         if r.iters == out.iters:
             assert cpd64.rel_rms(host(x), host(out.Xt)) < 1e-5
     assert len(set(iters)) > 1
+
+
+def test_batch_eigen_prep_in_several_waves_matches_single_handles(lib):
+    """70 instances (three waves of the prepare's host threads, whose Jacobi
+    solves run grouped by size class: dense solves below 1025 points, the
+    256-column Rayleigh-Ritz solves above) give every instance the eigenpairs
+    a single handle computes: the same K, eigenvalues within 1e-12 lam_1 and
+    the same registration after 10 iterations (1e-5).  An unknown tuning
+    code is refused."""
+    import torch
+    pairs = _instances(70, 200, 2600, 4000)
+    Xs = [dev(_f32(p.X), torch.float32) for p in pairs]
+    Ys = [dev(_f32(p.Y), torch.float32) for p in pairs]
+    kw = dict(w=0.1, eig_mode="full", tol=0.0, max_iter=10)
+    br = lib.BatchRegistration(Xs, Ys, beta=[p.beta for p in pairs],
+                               lam=[p.lam for p in pairs], **kw)
+    with pytest.raises(lib.FastCPDError):
+        br.prepare(candidate=8)
+    br.prepare(tune=False)
+    K = br.info()["K"]
+    Xt, res = br.register()
+    br.close()
+    dense = sum(p.M <= 1024 for p in pairs)
+    say("70 instances,", dense, "dense; K range", min(K), max(K))
+    assert 0 < dense < 70
+    for i, (p, x, X, Y) in enumerate(zip(pairs, Xt, Xs, Ys)):
+        single = lib.Registration(X, Y, precision="fp32", beta=p.beta, lam=p.lam, **kw)
+        single.prepare()
+        assert single.K == K[i], (i, p.M, single.K, K[i])
+        out = single.register()
+        err = cpd64.rel_rms(host(x), host(out.Xt))
+        assert err < 1e-5, (i, p.M, err)
+        single.close()
