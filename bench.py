@@ -476,7 +476,9 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
         log(f"warm: held-out {c0 + E}/{held_out} registered")
     a = {k: np.asarray(v, dtype=np.float64) for k, v in acc.items()}
     at50k = warm_at_50k(fc, torch, net, M, beta)
-    return {"at_50k": at50k,
+    bumps = warm_bumps_leg(fc, torch, M=M)
+    log(f"warm: bumps {bumps}")
+    return {"at_50k": at50k, "bumps": bumps,
             "workload": f"warm{M}: M=N={M}, D=3, unit sphere + N(0,0.01^2), RBF field beta={beta:g} "
                         f"coef N(0,{coef:.4f}^2), 10% outliers; lambda={lam:g}, w={w:g}; "
                         f"Fast CPD FULL eig, FP32, tol 1e-8",
@@ -493,6 +495,75 @@ def warm_leg(fc, torch, M=2000, batch=32, triples=100_000, held_out=1000, chunk=
             "start_rmse_mean_w0": float(a["i0"].mean()),
             "start_rmse_mean_net": float(a["iw"].mean()),
             "run_s_w0": t_run0, "run_s_net": t_runw}
+
+
+def warm_bumps_leg(fc, torch, M=2000, batch=32, steps=6000, held_out=500, chunk=250, beta=2.0,
+                   lam=3.0, w=0.1):
+    """The warm start where registration from W = 0 succeeds: the bumps
+    recipe (unit sphere pushed out by six random Gaussian bumps, a moderate
+    RBF field, 10% outliers), a network trained on it (Adam, lr 3e-5,
+    output layer initialised at 1e-6 so training starts from W0 ~ 0), then
+    `held_out` pairs from disjoint seeds registered by the batched path from
+    W = 0 and from the network's W0; wall times include the forward pass."""
+    coef = 0.004 * np.sqrt(1000.0 / M)
+    net = fc.WarmStartNet(seed=1, out_scale=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(steps):
+        X, Y, V = fc.synth_pairs(batch, M, beta=beta, coef=coef, seed0=10_000_000 + batch * step,
+                                 shape="bumps")
+        net.train_step(X, Y, V, beta=beta, lr=3e-5, want_loss=False)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    X, Y, V = fc.synth_pairs(held_out, M, beta=beta, coef=coef, seed0=1, shape="bumps")
+    gt = (X + V).double()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W0 = net.forward(X, Y)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    start0, startw = [], []
+    for i in range(held_out):
+        x = X[i].double()
+        Phi = torch.exp(-torch.cdist(x, x).square() / (2.0 * beta * beta))
+        start0.append(float((x - gt[i]).square().sum(1).mean().sqrt()))
+        startw.append(float((x + Phi @ W0[i].double() - gt[i]).square().sum(1).mean().sqrt()))
+    acc = {t: {"it": [], "cv": 0, "rm": [], "s": 0.0} for t in ("w0", "net")}
+    for c0 in range(0, held_out, chunk):
+        E = min(chunk, held_out - c0)
+        br = fc.BatchRegistration([X[i] for i in range(c0, c0 + E)],
+                                  [Y[i] for i in range(c0, c0 + E)], beta=beta, lam=lam, w=w,
+                                  eig_mode="full", tol=1e-8, max_iter=1000)
+        br.prepare(tune=(c0 == 0))
+        for tag, w0 in (("w0", None), ("net", W0[c0:c0 + E].reshape(-1, 3).contiguous())):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Xt, res = br.register(W0=w0)
+            torch.cuda.synchronize()
+            a = acc[tag]
+            a["s"] += time.perf_counter() - t0
+            a["it"] += [r.iters for r in res]
+            a["cv"] += int(sum(r.converged for r in res))
+            a["rm"] += [float((Xt[i].double() - gt[c0 + i]).square().sum(1).mean().sqrt())
+                        for i in range(E)]
+        br.close()
+    out = {}
+    for tag, a in acc.items():
+        it, rm = np.array(a["it"], dtype=float), np.array(a["rm"])
+        out[tag] = {"iters_mean": float(it.mean()), "iters_median": float(np.median(it)),
+                    "converged": a["cv"], "rmse_mean": float(rm.mean()),
+                    "rmse_median": float(np.median(rm)),
+                    "run_s": a["s"] + (t_net if tag == "net" else 0.0)}
+    return {"workload": f"bumps{M}: M=N={M}, unit sphere + six Gaussian bumps, RBF field "
+                        f"beta={beta:g} coef N(0,{coef:.5f}^2), 10% outliers; lambda={lam:g}, "
+                        f"w={w:g}; Fast CPD FULL eig, FP32, tol 1e-8",
+            "train_steps": steps, "train_batch": batch, "train_s": t_train,
+            "held_out": held_out, "net_forward_s": t_net,
+            "start_rmse_mean_w0": float(np.mean(start0)),
+            "start_rmse_mean_net": float(np.mean(startw)),
+            "start_sq_error_vs_no_displacement": float(np.mean(np.square(startw)) /
+                                                       np.mean(np.square(start0))),
+            "from_w0": out["w0"], "from_net": out["net"]}
 
 
 PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense bf16 matrix rate of the MI355X

@@ -352,9 +352,11 @@ class BatchRegistration:
         return Xt, list(res)
 
     def close(self):
+        """Destroy the handle and release the workspace and packed inputs."""
         if getattr(self, "h", None):
             load_library().cpd_batch_destroy(self.h)
             self.h = None
+        self.workspace = self.Xp = self.Yp = None
 
     def __del__(self):
         try:
@@ -563,9 +565,12 @@ class Registration:
                                   res.t_c, res.t_eig, res.t_iter, res.t_o)
 
     def close(self):
+        """Destroy the handle and release its workspace."""
         if getattr(self, "h", None):
             cpd_destroy(self.h)
             self.h = None
+        if hasattr(self, "workspace"):
+            self.workspace = None
 
     def __del__(self):
         try:

@@ -45,6 +45,7 @@ struct Layout {
       sigpart, initpart, featX, featY;
   Region permX, permY, invY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
   bool sorted = false, cull = false;
+  bool eig_shared = false;  // batch member: U64 and eigen-prep scratch live in a shared slot
   Region U, lam, U64, tpart, GT, HT;
   EigLayout eig;
   OrigLayout orig;
@@ -141,11 +142,15 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     L.mchunks = fast_mstep_chunks<T>(p.M, &L.mrows);
     add(L, L.U, M * K * sizeof(T));
     add(L, L.lam, K * sizeof(double));
-    add(L, L.U64, M * K * sizeof(double));
+    // A batch member needs its FP64 eigenvectors and the solver's scratch
+    // only while it prepares: they come from one of the batch's per-thread
+    // slots (eig_slot_bytes) instead of the member's own workspace.
+    L.eig_shared = batch_chunk > 0 && p.eig_mode != CPD_EIG_IMPORT;
+    if (!L.eig_shared) add(L, L.U64, M * K * sizeof(double));
     add(L, L.tpart, (size_t)L.mchunks * K * 4 * sizeof(T));
     add(L, L.GT, K * p4);
     add(L, L.HT, K * p4);
-    if (p.eig_mode != CPD_EIG_IMPORT) {
+    if (p.eig_mode != CPD_EIG_IMPORT && !L.eig_shared) {
       L.eig = eig_layout(p.M, p.eig_mode, p.K, p.oversample, L.total);
       L.total = L.eig.end;
     }
@@ -160,6 +165,15 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
     L.total = L.orig.end;
   }
   return L;
+}
+
+// Bytes of a shared eigen-prep slot for one batch member: its FP64
+// eigenvectors (M x Kcap) followed by the solver's scratch.
+size_t eig_slot_u64_bytes(const cpd_params& p) {
+  return ((size_t)p.M * kcap_of(p) * sizeof(double) + 255) & ~(size_t)255;
+}
+size_t eig_slot_bytes(const cpd_params& p) {
+  return eig_layout(p.M, p.eig_mode, p.K, p.oversample, eig_slot_u64_bytes(p)).end;
 }
 
 Layout layout_for(const cpd_params& p, int batch_chunk = 0) {
@@ -180,6 +194,7 @@ struct cpd_ctx {
   double t_eig = 0.0;
   std::string err;
   JacobiBatcher* jb = nullptr;  // set while a batch prepares: grouped Jacobi solves
+  char* eig_slot = nullptr;     // set while a batch prepares: shared U64 + solver scratch
   template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
   DevScalars* sc() const { return at<DevScalars>(L.sc); }
   // caller row of internal model / scene row i (NULL: same order)
@@ -584,14 +599,26 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     r.power_iters = h->p.power_iters;
     r.seed = h->p.seed;
     r.omega = omega;
+    EigLayout slot_layout;
+    char* eig_ws = h->ws;
+    const EigLayout* el = &L.eig;
+    double* U64 = h->at<double>(L.U64);
+    if (L.eig_shared) {
+      if (!h->eig_slot) return fail(h, CPD_E_STATE, "batch member prepared outside its batch");
+      slot_layout = eig_layout(h->p.M, h->p.eig_mode, h->p.K, h->p.oversample,
+                               eig_slot_u64_bytes(h->p));
+      eig_ws = h->eig_slot;
+      el = &slot_layout;
+      U64 = reinterpret_cast<double*>(h->eig_slot);
+    }
     if (omega && h->permX()) {  // rows into internal order, in the solver's own buffer
-      double* om = reinterpret_cast<double*>(h->ws + L.eig.omega);
-      gather_rows_launch<double>(omega, om, h->permX(), h->p.M, L.eig.n, h->st);
+      double* om = reinterpret_cast<double*>(eig_ws + el->omega);
+      gather_rows_launch<double>(omega, om, h->permX(), h->p.M, el->n, h->st);
       r.omega = om;
     }
-    r.ws = h->ws;
-    r.L = &L.eig;
-    r.U64 = h->at<double>(L.U64);
+    r.ws = eig_ws;
+    r.L = el;
+    r.U64 = U64;
     r.lam = h->at<double>(L.lam);
     r.Kcap = L.Kcap;
     r.st = h->st;
@@ -602,7 +629,7 @@ cpd_status prepare_impl(cpd_ctx* h, const double* U_import, const double* lam_im
     if (rc != 0 && rc != 4)
       return fail(h, rc == 1 ? CPD_E_NUMERIC : (rc == 3 ? CPD_E_UNSUPPORTED : CPD_E_DEVICE), msg);
     h->K = K;
-    convert_u_launch<T>(h->at<double>(L.U64), h->at<T>(L.U), (size_t)h->p.M * K, h->st);
+    convert_u_launch<T>(U64, h->at<T>(L.U), (size_t)h->p.M * K, h->st);
     if (rc == 4) {  // usable, but truncated: reported, not hidden
       HIPCHK(h, hipGetLastError());
       HIPCHK(h, hipStreamSynchronize(h->st));
@@ -937,8 +964,9 @@ constexpr int kBatchSmallestChunk = 512;
 constexpr int kPrepThreads = 32;
 
 struct BatchHeader {
-  size_t desc = 0, items = 0, done = 0, jac = 0, jacflags = 0, end = 0;
+  size_t desc = 0, items = 0, done = 0, jac = 0, jacflags = 0, eigslot = 0, end = 0;
   size_t item_cap = 0;
+  size_t slot_bytes = 0;  // one prepare thread's eigen-prep slot
 };
 
 size_t batch_item_capacity(int B, const cpd_params* p) {
@@ -973,6 +1001,9 @@ BatchHeader batch_header(int B, const cpd_params* p) {
   h.done = take(256);
   h.jac = take((size_t)kPrepThreads * sizeof(JacMember));
   h.jacflags = take((size_t)kPrepThreads * sizeof(int));
+  for (int i = 0; i < B; ++i) h.slot_bytes = std::max(h.slot_bytes, eig_slot_bytes(p[i]));
+  h.slot_bytes = (h.slot_bytes + 255) & ~(size_t)255;
+  h.eigslot = take((size_t)std::min(B, kPrepThreads) * h.slot_bytes);
   h.end = off;
   return h;
 }
@@ -1271,8 +1302,10 @@ cpd_status cpd_batch_prepare(cpd_batch b, int32_t tune) {
         cpd_ctx* h = b->inst[i];
         h->st = sts[t];
         h->jb = &jb;
+        h->eig_slot = b->ws + b->hd.eigslot + (size_t)t * b->hd.slot_bytes;
         rc[i] = prepare_impl<float>(h, nullptr, nullptr, nullptr);
         jb.leave();
+        h->eig_slot = nullptr;
         h->jb = nullptr;
         h->st = b->st;
         if (rc[i] == CPD_NOT_CONVERGED) rc[i] = CPD_OK;  // a truncated FULL basis is usable
