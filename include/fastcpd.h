@@ -250,7 +250,12 @@ cpd_status cpd_destroy(cpd_handle h);
  * FP32, D = 3, FULL or TOPK eigen-prep).  Points are packed: instance i owns
  * rows x_off[i] .. x_off[i+1]-1 of X_packed (float, device, sum M_i x 3) and
  * likewise for Y with y_off (host arrays of B + 1 offsets).  One caller
- * workspace of cpd_batch_workspace_size() bytes holds everything. */
+ * workspace of cpd_batch_workspace_size() bytes holds everything: each
+ * instance's iteration state, and the eigen-prep scratch (FP64 eigenvectors,
+ * bases, Gram partials) once per preparing host thread (at most 32) rather
+ * than once per instance, since an instance needs it only while it prepares.
+ * Each instance keeps its points in Hilbert order with far-tile culling,
+ * as a single handle does (CPD_FLAG_NO_SORT / CPD_FLAG_NO_CULL per instance). */
 typedef struct cpd_batch_ctx* cpd_batch;
 
 cpd_status cpd_batch_workspace_size(int32_t B, const cpd_params* p, size_t* bytes);
