@@ -1181,13 +1181,23 @@ void JacobiBatcher::leave() {
 }
 
 int JacobiBatcher::solve(Req* r) {
-  (void)hipEventCreateWithFlags(&r->ready, hipEventDisableTiming);
-  (void)hipEventRecord(r->ready, r->st);
+  // the group runs after the work this thread queued before its request:
+  // an event on its stream, or (if none can be made) that work completed
+  if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(r->ready, r->st) != hipSuccess) {
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
+    if (hipStreamSynchronize(r->st) != hipSuccess) {  // the caller's leave() follows
+      r->rc = 2;
+      r->msg = "grouped Jacobi: the submitting stream failed";
+      return r->rc;
+    }
+  }
   std::unique_lock<std::mutex> lk(mu_);
   pending_.push_back(r);
   if ((int)pending_.size() >= live_ || (int)pending_.size() >= cap_) run_locked();
   cv_.wait(lk, [&] { return r->done; });
-  (void)hipEventDestroy(r->ready);
+  if (r->ready) (void)hipEventDestroy(r->ready);
   return r->rc;
 }
 
@@ -1199,7 +1209,7 @@ void JacobiBatcher::run_locked() {
   reqs.swap(pending_);
   hipStream_t st = reqs[0]->st;
   for (Req* q : reqs)
-    if (q->st != st) (void)hipStreamWaitEvent(st, q->ready, 0);
+    if (q->st != st && q->ready) (void)hipStreamWaitEvent(st, q->ready, 0);
   // a group runs as many steps per sweep as its widest member needs: split
   // the requests into size classes (widest at most twice the narrowest)
   std::vector<Req*> by_n(reqs);
