@@ -58,7 +58,21 @@ TRAFFIC = {
     "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "9d0946d4052620095857042be42594c668ec6d72aa186d2e7a726aafd4b6f7d9",
                      "bytes_per_dispatch": 38.49e6 + 26.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
+    # one Fast M-step at 50k, K = 300: k_tpart4 + k_tmerge4 + k_apply4
+    "fast_mstep_k300_50k": {"source": "mstep.hip",
+                            "sha256": "24d984a8e8d05c9e3f52dd2aacc18a5a025576108bbc1d099f837395345c1683",
+                            "bytes_per_dispatch": (61.69e6 + 1.877e6) + (14.99e6 + 0.019e6)
+                                                  + (62.80e6 + 2.425e6),
+                            "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
 }
+
+
+def traffic_of(key):
+    """Measured HBM bytes per dispatch, or None once the source has changed."""
+    tr = TRAFFIC.get(key)
+    if tr and _source_hash(tr["source"]) == tr["sha256"]:
+        return tr["bytes_per_dispatch"]
+    return None
 
 
 def log(*a):
@@ -85,10 +99,7 @@ def roofline_of(kern, pairs, precision):
                       "frac": ach / PEAK_VALU_FP32_TFLOPS,
                       "exp_per_s": pairs / t, "exp_frac": pairs / t / PEAK_EXP_PER_S}
     b = out["passB"]
-    traffic = None
-    tr = TRAFFIC.get(b["kernel"])
-    if tr and _source_hash(tr["source"]) == tr["sha256"]:
-        traffic = tr["bytes_per_dispatch"]
+    traffic = traffic_of(b["kernel"])
     return {"bound": "alu", "kernel": b["kernel"] + " (E-step pass B)",
             "achieved": b["achieved"], "peak": PEAK_VALU_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": b["frac"], "traffic": traffic,
@@ -171,12 +182,14 @@ PEAK_HBM_GBPS = 8000.0
 
 def mstep_roofline(kern, M, K, elem=4):
     """The Fast M-step reads U (M x K) twice per iteration (U^T R, then
-    U (h o T)); its algorithmic bytes are 2 M K elem, against HBM."""
+    U (h o T)); its algorithmic bytes are 2 M K elem, against HBM.  The
+    measured bytes (counters) are attached for the 50k, K = 300 FP32 case."""
     t = kern["mstep"] * 1e-3
     ach = 2.0 * M * K * elem / t / 1e9
+    traffic = traffic_of("fast_mstep_k300_50k") if (M, K, elem) == (50000, 300, 4) else None
     return {"bound": "hbm", "kernel": "Fast M-step (U^T R, U (h o T))", "achieved": ach,
             "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBPS,
-            "traffic": None, "bytes_model": "2 M K x 4 B (U read twice)", "avg_us": t * 1e6}
+            "traffic": traffic, "bytes_model": "2 M K x 4 B (U read twice)", "avg_us": t * 1e6}
 
 
 def fast_full_leg(fc, torch, X, Y, pair, precision):
