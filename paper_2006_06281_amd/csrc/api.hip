@@ -806,7 +806,10 @@ int32_t cpd_abi_version(void) { return CPD_ABI_VERSION; }
 const char* cpd_build_info(void) { return "libfastcpd abi=1 target=gfx950"; }
 
 const char* cpd_status_str(cpd_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the bits as one, not as the enum
+  int32_t v = 0;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case CPD_OK: return "CPD_OK";
     case CPD_NOT_CONVERGED: return "CPD_NOT_CONVERGED";
     case CPD_E_ARG: return "CPD_E_ARG";
