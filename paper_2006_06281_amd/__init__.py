@@ -318,12 +318,40 @@ class BatchRegistration:
     CHUNKS = (1024, 2048, 512, 4096)
     TILES = (1024, 512)
 
-    def prepare(self, tune=True, candidate=None):
+    def prepare(self, tune=True, candidate=None, cache=None):
         """tune: time every (split length, tile) candidate and keep the
-        fastest; candidate: force one (index into candidates()) untimed."""
+        fastest; candidate: force one (index into candidates()) untimed.
+        cache: a TuneCache or a JSON path; with tune, a stored plan for this
+        batch's key is forced untimed, and a newly timed choice is stored
+        (the environment variable FASTCPD_TUNE_CACHE names a default path)."""
+        from . import tune_cache as tc
+        if cache is None and os.environ.get("FASTCPD_TUNE_CACHE"):
+            cache = os.environ["FASTCPD_TUNE_CACHE"]
+        if isinstance(cache, str):
+            cache = tc.TuneCache(cache)
+        key = None
+        if candidate is None and tune and cache is not None:
+            key = self.tune_key()
+            hit = cache.get(key)
+            if hit is not None and 0 <= int(hit.get("candidate", -1)) < 8:
+                candidate = int(hit["candidate"])
         code = 2 + int(candidate) if candidate is not None else int(bool(tune))
         _check(load_library().cpd_batch_prepare(self.h, code))
+        if code == 1 and key is not None:
+            inf = self.info()
+            c = self.candidates().index((inf["chunk"], inf["tile"]))
+            cache.put(key, {"candidate": c, "chunk": inf["chunk"], "tile": inf["tile"],
+                            "tune_ms": [inf["tune_ms"][cd] for cd in self.candidates()]})
         return self
+
+    def tune_key(self):
+        """The autotune cache key of this batch (device arch, mean set sizes,
+        instance count, D, precision)."""
+        import torch
+        from . import tune_cache as tc
+        arch = torch.cuda.get_device_properties(self.Xp.device).gcnArchName
+        return tc.batch_key(arch, [p.M for p in self.params], [p.N for p in self.params],
+                            3, "fp32")
 
     @classmethod
     def candidates(cls):

@@ -116,3 +116,36 @@ def test_batch_eigen_prep_in_several_waves_matches_single_handles(lib):
         err = cpd64.rel_rms(host(x), host(out.Xt))
         assert err < 1e-5, (i, p.M, err)
         single.close()
+
+
+def test_batch_tune_cache_reuses_plan(lib, tmp_path):
+    """The first tuned batch stores its plan under the batch's key; a second
+    batch of the same shape forces that plan untimed and gives the same
+    result bitwise."""
+    import json
+    import torch
+    pairs = _instances(5, 300, 900, 1300)
+    Xs = [dev(_f32(p.X), torch.float32) for p in pairs]
+    Ys = [dev(_f32(p.Y), torch.float32) for p in pairs]
+    kw = dict(beta=[p.beta for p in pairs], lam=[p.lam for p in pairs], w=0.1,
+              eig_mode="full", tol=0.0, max_iter=10)
+    path = str(tmp_path / "tune.json")
+    a = lib.BatchRegistration(Xs, Ys, **kw).prepare(tune=True, cache=path)
+    ia = a.info()
+    assert all(v > 0 for v in ia["tune_ms"].values())
+    with open(path) as f:
+        stored = json.load(f)["entries"]
+    key = a.tune_key()
+    say("tune cache", key, stored[key]["chunk"], stored[key]["tile"])
+    assert key.startswith(torch.cuda.get_device_properties(0).gcnArchName + "|batch|")
+    assert (stored[key]["chunk"], stored[key]["tile"]) == (ia["chunk"], ia["tile"])
+    Xa, _ = a.register()
+    b = lib.BatchRegistration(Xs, Ys, **kw).prepare(tune=True, cache=path)
+    ib = b.info()
+    assert all(v == 0 for v in ib["tune_ms"].values())
+    assert (ib["chunk"], ib["tile"]) == (ia["chunk"], ia["tile"])
+    Xb, _ = b.register()
+    for x, y in zip(Xa, Xb):
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
