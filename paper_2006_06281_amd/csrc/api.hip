@@ -42,7 +42,7 @@ struct Region {
 struct Layout {
   size_t total = 0;
   Region sc, X, Xt, Xnew, Y, W, xs, ys, Yt, P1, tbar, partA, partB, nnY, nnX, llpart,
-      sigpart, initpart, featX, featY;
+      sigpart, initpart, featX, featY, featV;
   Region permX, permY, invY, keys, bbox, boxX, boxY, logdtmp, Xraw;  // spatial order / culling
   bool sorted = false, cull = false;
   bool eig_shared = false;  // batch member: U64 and eigen-prep scratch live in a shared slot
@@ -100,6 +100,7 @@ Layout make_layout(const cpd_params& p, int batch_chunk = 0) {
   if (p.precision == CPD_PREC_BF16X) {
     add(L, L.featX, M256 * 64);
     add(L, L.featY, N256 * 64);
+    add(L, L.featV, N256 * 64);
   }
   add(L, L.Yt, M * p4);
   add(L, L.P1, M * sizeof(T));
@@ -315,6 +316,7 @@ void enqueue_estep(cpd_ctx* h, int gate, T* logd_out, hipEvent_t* ev = nullptr) 
   a.ev = ev;
   a.featX = h->at<__bf16>(L.featX);
   a.featY = h->at<__bf16>(L.featY);
+  a.featV = h->at<__bf16>(L.featV);
   a.boxX = L.cull ? h->at<P4<T>>(L.boxX) : nullptr;
   a.boxY = L.cull ? h->at<P4<T>>(L.boxY) : nullptr;
   a.box_shift = h->p.precision == CPD_PREC_BF16X ? 4 : 6;

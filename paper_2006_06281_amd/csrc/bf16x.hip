@@ -25,7 +25,8 @@
 // Pass A: a wave keeps four 16-column scene tiles (B operands) in registers
 // and streams 16-point model tiles (A); per pair: one v_exp_f32 and one add.
 // Pass B: a wave keeps four 16-point model tiles (B) and streams scene tiles
-// (A, extra = L_n); per pair: exp, and the sums of p, p*v, p*|u - v|^2.
+// (A, extra = L_n); per pair: exp, and the sums of p, p*v, p*|u - v|^2 as a
+// second matrix product with p as its A operand.
 // Padded points carry a 3e30 offset so their exponentials are exactly 0.
 #include "bf16x_feat.hpp"
 #include "common.hpp"
@@ -36,10 +37,11 @@ namespace fcpd {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // The iteration's first kernel in this mode: prescale (xs, ys), the boxes of
-// 16-point tiles when culling is on, the model features and
-// the scene features with the pass-A reference.  Threads [0, M64) cover the
-// model rows (M64 = M rounded up to 64), the rest the scene rows up to Npad,
-// so every wave sits inside one tile.
+// 16-point tiles when culling is on, the model features,
+// the scene features with the pass-A reference and pass B's sum operands.
+// Threads [0, M64) cover the model rows (M64 = M rounded up to 64), the next
+// Npad the scene rows (so every 16-lane group sits inside one tile), the last
+// 4 Npad the sum operands (64 lanes per 16-point scene tile).
 __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restrict__ Xt,
                                                       const P4<float>* __restrict__ Y,
                                                       P4<float>* __restrict__ xs,
@@ -48,11 +50,17 @@ __global__ __launch_bounds__(256) void k_bfx_prescale(const P4<float>* __restric
                                                       int gate, P4<float>* __restrict__ boxX,
                                                       P4<float>* __restrict__ boxY,
                                                       __bf16* __restrict__ F,
-                                                      __bf16* __restrict__ G, double w, int D) {
+                                                      __bf16* __restrict__ G,
+                                                      __bf16* __restrict__ V, double w, int D) {
   if (gate && sc->done) return;
   const float s = (float)sqrt(kappa_of(sc->sigma2));
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int M64 = (M + 63) & ~63;
+  if (i >= M64 + Npad) {
+    const int j = i - (M64 + Npad);
+    if (j < 4 * Npad) sum_operand(Y, N, s, j >> 6, j & 63, V);
+    return;
+  }
   const bool isX = i < M64;
   const int k = isX ? i : i - M64;
   const bool valid = k < (isX ? M : N);
@@ -239,17 +247,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // Pass B partials: part[split][5][M] = sum over the split's scene points
 // (with culling every S-th 16-point tile, else a contiguous range) of p, p*v
 // (prescaled, absolute), p*|u - v|^2 with p = 2^-(|u - v|^2 + L_n).
+//
+// The sums run on the matrix cores as a product P V: the distance product
+// leaves lane l with p for model point l % 16 and scene points 4 (l / 16)
+// .. + 3, which is the row and k slice of the A operand of a second
+// 16x16x32 product once each p is split into a high and a low bf16 part
+// (p - hi is exact in fp32; together they keep 16 significant bits, so each
+// term carries a relative error below 2^-17).  The B operand holds, per
+// scene point, 1, the three bf16 pieces of each coordinate and of |v|^2
+// (`sum_operand`), so the accumulator's columns are sum p, sum p v and
+// sum p |v|^2, each to 24 bits.  The epilogue forms
+// sum p |u - v|^2 = sum p |v|^2 - 2 u . sum p v + |u|^2 sum p per model
+// point, in FP64.  Per pair the vector ALU spends one exponential, one
+// two-value conversion per pair of values (high parts), one dot2 per value
+// (the low part, p - hi) and one conversion per pair of values (low parts).
 __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F,
                                                     const __bf16* __restrict__ G,
-                                                    const P4<float>* __restrict__ ys, int M,
+                                                    const __bf16* __restrict__ V,
+                                                    const P4<float>* __restrict__ xs, int M,
                                                     int Npad, const DevScalars* __restrict__ sc,
                                                     float* __restrict__ part,
                                                     const P4<float>* __restrict__ boxX,
                                                     const P4<float>* __restrict__ boxY, int gate) {
   if (gate && sc->done) return;
+  __shared__ float red[4][64 * 17];  // per wave: 64 model points x 16 columns (+1 pad)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.x * 256 + wave * 64;  // this wave's 64 model columns
-  if (m0 >= M) return;  // padding only: nothing of it is stored
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[4] = {zero, zero, zero, zero};
+  if (m0 < M) {  // (a wave of padding only skips to the block's barrier)
   bf16x8 b[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
@@ -257,12 +283,15 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   // tile blockIdx.y (S = gridDim.y splits): the tiles near any model point,
   // consecutive in the spatial order, then spread evenly over the splits
   const int S = gridDim.y, tiles = Npad >> 4;
-  float r[4], px[4], py[4], pz[4], t[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) r[s] = px[s] = py[s] = pz[s] = t[s] = 0.f;
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  const int rg = 4 * (lane >> 4);  // the 4 scene rows of this lane within a tile
   const int aoff = (lane & 15) * 32 + 8 * (lane >> 4);  // this lane's A operand slice
+  // p - hi(p) for the first / second value of a bf16 pair, as a dot2 with
+  // the pair (-1, 0) or (0, -1).  Both are kept in registers: as an inline
+  // constant the compiler encodes (-1, 0) as the operand -1.0, which the
+  // hardware does not read as the bf16 pair
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  uint32_t nlo = 0x0000bf80u, nhi = 0xbf800000u;
+  asm volatile("" : "+v"(nlo), "+v"(nhi));
+  const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, nlo), neg_hi = __builtin_bit_cast(bf16x2, nhi);
   // with boxes: skip 16-point scene tiles whose smallest exponent
   // |u - v|^2 + min L_n against this wave's model points reaches CullLimit
   // (the split layout follows the sigma^2 gate alone: see pass A)
@@ -302,26 +331,22 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
         keep &= keep - 1;
         const int nt = 16 * (t0 + ts * i);
         const int rm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(rows, i, 64)) : 15;
-        // the tile's base is uniform, so only the lane offsets are per lane
+        // the tile's bases are uniform, so only the lane offsets are per lane
         const bf16x8 a = *reinterpret_cast<const bf16x8*>(G + (size_t)nt * 32 + aoff);
-        const P4<float>* yt = ys + nt;
-        P4<float> yv[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) yv[q] = yt[rg + q];
+        const bf16x8 v = *reinterpret_cast<const bf16x8*>(V + (size_t)nt * 32 + 8 * lane);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (MASK && !(rm & (1 << s))) continue;  // all its terms are +0
           const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float p = fexp2(-d[q]);
-            const float d2 = d[q] - yv[q].w;
-            r[s] += p;
-            px[s] = fmaf(p, yv[q].x, px[s]);
-            py[s] = fmaf(p, yv[q].y, py[s]);
-            pz[s] = fmaf(p, yv[q].z, pz[s]);
-            t[s] = fmaf(p, d2, t[s]);
-          }
+          const float p0 = fexp2(-d[0]), p1 = fexp2(-d[1]), p2 = fexp2(-d[2]), p3 = fexp2(-d[3]);
+          const bf16x2 h01 = {(__bf16)p0, (__bf16)p1}, h23 = {(__bf16)p2, (__bf16)p3};
+          const float l0 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_lo, p0, false);
+          const float l1 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_hi, p1, false);
+          const float l2 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_lo, p2, false);
+          const float l3 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_hi, p3, false);
+          const bf16x8 pa = {h01[0], h01[1], h23[0], h23[1],
+                             (__bf16)l0, (__bf16)l1, (__bf16)l2, (__bf16)l3};
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa, v, acc[s], 0, 0, 0);
         }
       }
     }
@@ -330,30 +355,34 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
     tiles_loop(Flag<true>{});
   else
     tiles_loop(Flag<false>{});
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-#pragma unroll
-    for (int o = 16; o <= 32; o <<= 1) {
-      r[s] += __shfl_xor(r[s], o, 64);
-      px[s] += __shfl_xor(px[s], o, 64);
-      py[s] += __shfl_xor(py[s], o, 64);
-      pz[s] += __shfl_xor(pz[s], o, 64);
-      t[s] += __shfl_xor(t[s], o, 64);
-    }
   }
-  if (lane < 16) {
-    float* base = part + (size_t)blockIdx.y * 5 * M;
+  // accumulator lane l: column l % 16 of model points 16 s + 4 (l / 16) .. + 3
+  float* r = red[wave];
+  {
+    const int f = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int m = m0 + 16 * s + lane;
-      if (m < M) {
-        base[m] = r[s];
-        base[(size_t)M + m] = px[s];
-        base[(size_t)2 * M + m] = py[s];
-        base[(size_t)3 * M + m] = pz[s];
-        base[(size_t)4 * M + m] = t[s];
-      }
-    }
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[(16 * s + 4 * g + q) * 17 + f] = acc[s][q];
+  }
+  __syncthreads();
+  const int m = m0 + lane;
+  if (m < M) {
+    const float* c = r + lane * 17;
+    const double s0 = c[0];
+    const double sx = ((double)c[3] + c[2]) + c[1];
+    const double sy = ((double)c[6] + c[5]) + c[4];
+    const double sz = ((double)c[9] + c[8]) + c[7];
+    const double s2 = ((double)c[12] + c[11]) + c[10];
+    const P4<float> u = xs[m];
+    const double ux = u.x, uy = u.y, uz = u.z;
+    const double t = s2 - 2.0 * (ux * sx + uy * sy + uz * sz) + (ux * ux + uy * uy + uz * uz) * s0;
+    float* base = part + (size_t)blockIdx.y * 5 * M;
+    base[m] = (float)s0;
+    base[(size_t)M + m] = (float)sx;
+    base[(size_t)2 * M + m] = (float)sy;
+    base[(size_t)3 * M + m] = (float)sz;
+    base[(size_t)4 * M + m] = (float)fmax(t, 0.0);  // a sum of non-negative terms
   }
 }
 
@@ -422,10 +451,10 @@ int bfx_resident_blocksB() {
 void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
   const int Mpad = (a.M + 15) & ~15, Npad = (a.N + 15) & ~15;
   const int gate = a.gate;
-  const int nthr = ((a.M + 63) & ~63) + Npad;
+  const int nthr = ((a.M + 63) & ~63) + 5 * Npad;
   hipLaunchKernelGGL(k_bfx_prescale, dim3((nthr + 255) / 256), dim3(256), 0, st, a.Xt, a.Y, a.xs,
                      a.ys, a.M, a.N, Mpad, Npad, a.sc, gate, a.boxX, a.boxY, a.featX, a.featY,
-                     a.w, a.D);
+                     a.featV, a.w, a.D);
   if (a.ev) (void)hipEventRecord(a.ev[0], st);
   hipLaunchKernelGGL(k_bfx_colsum, dim3((a.N + 255) / 256, a.splitsA), dim3(256), 0, st, a.featX,
                      a.featY, Mpad, a.N, a.sc, a.partA, a.boxX, a.boxY, a.w, a.M, gate);
@@ -433,7 +462,7 @@ void estep_bf16x_launch(const EStepArgs<float>& a, hipStream_t st) {
   colmerge_fix_launch<float>(a, st);  // also refreshes the scene features with L_n
   if (a.ev) (void)hipEventRecord(a.ev[2], st);
   hipLaunchKernelGGL(k_bfx_rowsum, dim3((a.M + 255) / 256, a.splitsB), dim3(256), 0, st, a.featX,
-                     a.featY, a.ys, a.M, Npad, a.sc, a.partB, a.boxX, a.boxY, gate);
+                     a.featY, a.featV, a.xs, a.M, Npad, a.sc, a.partB, a.boxX, a.boxY, gate);
   if (a.ev) (void)hipEventRecord(a.ev[3], st);
   rowmerge_fix_launch<float>(a, st, /*relative=*/0);
   if (a.ev) (void)hipEventRecord(a.ev[4], st);

@@ -84,4 +84,38 @@ __device__ __forceinline__ void scene_feat(const P4<float>& p, bool valid, float
   }
 }
 
+// Pass B's sum operands: for the 16-point scene tile `tile`, the 16 bytes that
+// lane `lane` of a wave feeds as the B operand of the product P V, where the
+// lane's column f = lane % 16 and its k slice covers the tile's points
+// 4 (lane / 16) .. + 3, each twice (the P operand holds their high and low
+// bf16 parts).  Columns: 1; the three bf16 pieces of each prescaled
+// coordinate (1-9); the three pieces of |y|^2 (10-12); zero (13-15).  Points
+// past N (padding) have every column 0.
+__device__ __forceinline__ void sum_operand(const P4<float>* __restrict__ Y, int N, float s,
+                                            int tile, int lane, __bf16* __restrict__ dst) {
+  const int f = lane & 15, n0 = 16 * tile + 4 * (lane >> 4);
+  bf16x8 v;
+  for (int q = 0; q < 4; ++q) {
+    const int n = n0 + q;
+    __bf16 o = (__bf16)0.0f;
+    if (n < N && f < 13) {
+      if (f == 0) {
+        o = (__bf16)1.0f;
+      } else {
+        const P4<float> p = Y[n];
+        const float x = p.x * s, y = p.y * s, z = p.z * s;  // as the prescaled scene
+        const int c = (f - 1) / 3;
+        const float u = c == 0 ? x : c == 1 ? y : c == 2 ? z : x * x + y * y + z * z;
+        __bf16 a, b, e;
+        split3(u, a, b, e);
+        const int piece = (f - 1) % 3;
+        o = piece == 0 ? a : piece == 1 ? b : e;
+      }
+    }
+    v[q] = o;
+    v[q + 4] = o;
+  }
+  *reinterpret_cast<bf16x8*>(dst + ((size_t)tile * 64 + lane) * 8) = v;
+}
+
 }  // namespace fcpd

@@ -25,6 +25,7 @@ template <typename T> struct EStepArgs {
   __bf16* featX;     // BF16X: model feature vectors (32 bf16 per point, padded)
   __bf16* featY;     // BF16X: scene feature vectors
   __bf16* featY_L;   // BF16X: featY, refreshed with L_n by the column merge (else NULL)
+  __bf16* featV;     // BF16X: scene sum operands of pass B (32 bf16 per point, padded)
   // Far-tile culling (nullable: no culling).  Per tile of 2^box_shift
   // prescaled points (64 in the FP32 / FP64 passes, 16 in BF16X), box[2t] =
   // lower corner, box[2t + 1] = upper corner; boxY[2t].w receives min L_n
