@@ -55,11 +55,12 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a device copy
 # of known size; valid only while the kernel source is unchanged (sha256).
 TRAFFIC = {
-    "k_bfx_rowsum": {"source": "bf16x.hip", "sha256": "9d0946d4052620095857042be42594c668ec6d72aa186d2e7a726aafd4b6f7d9",
-                     "bytes_per_dispatch": 38.49e6 + 26.00e6,
+    "k_bfx_rowsum": {"sources": ["bf16x.hip", "bf16x_feat.hpp"],
+                     "sha256": "4aa1bb204bce7ff7c0f555b6aa0232f4fe376a3247e0297ceb75ac8812d61ef6",
+                     "bytes_per_dispatch": 59.30e6 + 26.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
     # one Fast M-step at 50k, K = 300: k_tpart4 + k_tmerge4 + k_apply4
-    "fast_mstep_k300_50k": {"source": "mstep.hip",
+    "fast_mstep_k300_50k": {"sources": ["mstep.hip"],
                             "sha256": "24d984a8e8d05c9e3f52dd2aacc18a5a025576108bbc1d099f837395345c1683",
                             "bytes_per_dispatch": (61.69e6 + 1.877e6) + (14.99e6 + 0.019e6)
                                                   + (62.80e6 + 2.425e6),
@@ -70,7 +71,7 @@ TRAFFIC = {
 def traffic_of(key):
     """Measured HBM bytes per dispatch, or None once the source has changed."""
     tr = TRAFFIC.get(key)
-    if tr and _source_hash(tr["source"]) == tr["sha256"]:
+    if tr and _source_hash(tr["sources"]) == tr["sha256"]:
         return tr["bytes_per_dispatch"]
     return None
 
@@ -79,11 +80,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def _source_hash(name):
+def _source_hash(names):
+    """sha256 over the concatenated bytes of the named csrc files, in order."""
     import hashlib
-    p = os.path.join(ROOT, "paper_2006_06281_amd", "csrc", name)
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    m = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_2006_06281_amd", "csrc", name), "rb") as f:
+            m.update(f.read())
+    return m.hexdigest()
 
 
 def roofline_of(kern, pairs, precision):

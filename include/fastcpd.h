@@ -66,7 +66,10 @@ typedef enum {
   CPD_PREC_FP64 = 0,       /* everything in double                             */
   CPD_PREC_FP32 = 1,       /* E-step and M-step in float; eig and sigma^2 FP64 */
   CPD_PREC_BF16X = 2       /* E-step squared distances from bf16 products on
-                              the matrix cores, fp32 accumulate and exp; its
+                              the matrix cores, fp32 accumulate and exp; the
+                              row sums (P1, P Y) are a second bf16 product
+                              with each posterior value split into two bf16
+                              parts (16 significant bits); its
                               exponent error grows as 1/sigma^2, so sigma^2 is
                               not lowered below 1e-7 D times the data's
                               closed-form sigma^2_0 in this mode              */
