@@ -607,6 +607,17 @@ def net_gemm_flop(M, N, H=256):
     return 3 * rows * 2 * H * H
 
 
+def net_gemm_bytes(M, N, H=256):
+    """Algorithmic HBM bytes of the same GEMMs for one pair, bf16 storage:
+    each layer's forward reads its input and writes its output (R x H
+    each), the input gradient reads dY and writes dX, the weight gradient
+    reads X and dY: 3 x 2 x R x H x 2 bytes for R rows.  Their arithmetic
+    intensity, H / 2 = 128 FLOP per byte at H = 256, is below the bf16
+    ridge (2.5 PFLOP/s / 8 TB/s = 312), so HBM bounds them."""
+    rows = 3 * (M + N) + M
+    return 3 * 2 * rows * H * 2
+
+
 def warm_train_leg(fc, torch, steps, warmup, M=2000, batch=32, beta=2.0):
     """Training throughput of the warm-start network alone: `warmup` then
     `steps` Adam steps of `batch` device-drawn pairs at M = N = 2000 (pair
@@ -632,13 +643,19 @@ def warm_train_leg(fc, torch, steps, warmup, M=2000, batch=32, beta=2.0):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     flop = net_gemm_flop(M, M) * batch
+    nbytes = net_gemm_bytes(M, M) * batch
     ach = flop / (ms * 1e-3) / 1e12
+    bw = nbytes / (ms * 1e-3) / 1e9
     return {"ms_per_step": ms, "pairs_per_s": batch / (ms * 1e-3), "batch": batch, "M": M,
-            "N": M, "gemm_flop_per_step": flop,
-            "roofline": {"bound": "mfma", "kernel": "whole training step (all kernels)",
-                         "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ach / PEAK_BF16_MFMA_TFLOPS, "traffic": None,
-                         "flop_model": "3 x (3 (M + N) + M) x 2 x 256^2 per pair"}}
+            "N": M, "gemm_flop_per_step": flop, "gemm_bytes_per_step": nbytes,
+            "roofline": {"bound": "hbm", "kernel": "whole training step (all kernels)",
+                         "achieved": bw, "peak": 8000.0, "unit": "GB/s", "frac": bw / 8000.0,
+                         "traffic": None,
+                         "bytes_model": "3 x 2 x (3 (M + N) + M) x 256 x 2 B per pair (bf16 "
+                                        "GEMM operands; 128 FLOP/B, below the bf16 ridge)"},
+            "mfma_view": {"achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach / PEAK_BF16_MFMA_TFLOPS,
+                          "flop_model": "3 x (3 (M + N) + M) x 2 x 256^2 per pair"}}
 
 
 def table4_leg(fc, torch, sizes=(4000, 8000, 12000, 16000, 20000, 24000), iters=50):
@@ -755,17 +772,20 @@ def main():
         b = warm_leg(fc, torch)
         log(f"warm: {b}")
         ach = net_gemm_flop(2000, 2000) * b["train_triples"] / b["train_s"] / 1e12
+        bw = net_gemm_bytes(2000, 2000) * b["train_triples"] / b["train_s"] / 1e9
         print(json.dumps({"metric": "learned warm start: mean EM iterations to tolerance, "
                                     "held-out pairs",
                           "value": b["iters_mean_net"], "unit": "EM iterations",
                           "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 net, f32 EM",
                           "data": "synthetic", "config": {"workload": b["workload"]},
-                          "roofline": {"bound": "mfma", "kernel": "network training (all "
-                                                                  "kernels of a step)",
-                                       "achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
-                                       "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS,
-                                       "traffic": None,
-                                       "flop_model": "3 x (3 (M + N) + M) x 2 x 256^2 per pair"},
+                          "roofline": {"bound": "hbm", "kernel": "network training (all "
+                                                                 "kernels of a step)",
+                                       "achieved": bw, "peak": 8000.0, "unit": "GB/s",
+                                       "frac": bw / 8000.0, "traffic": None,
+                                       "bytes_model": "3 x 2 x (3 (M + N) + M) x 256 x 2 B "
+                                                      "per pair"},
+                          "mfma_view": {"achieved": ach, "peak": PEAK_BF16_MFMA_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": ach / PEAK_BF16_MFMA_TFLOPS},
                           "warm_start": b}), flush=True)
         return
 

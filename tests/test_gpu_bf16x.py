@@ -36,6 +36,10 @@ def test_bf16x_estep(lib, M, N, w, s2):
     assert err < TOL
     np.testing.assert_allclose(host(g["logd"]), es.logd, rtol=0, atol=1e-2 * max(1, np.abs(es.logd).max()))
     np.testing.assert_allclose(host(g["P1"]), es.P1, rtol=1e-2, atol=1e-30)
+    # sum p |y - x|^2 / P1 from the row-sum product's columns (sum p |y|^2,
+    # sum p y, sum p); each term carries the exponent error of the split-bf16
+    # distance (up to ~1% here: kappa |x|^2 reaches ~1e4 at sigma^2 = 1e-3)
+    np.testing.assert_allclose(host(g["tbar"]), es.tbar, rtol=2e-2, atol=1e-3 * es.tbar.mean())
 
 
 def test_bf16x_far_rows_and_empty_columns_take_the_exact_path(lib):
@@ -72,15 +76,19 @@ def test_bf16x_matches_fp32_closely(lib):
     say("bf16x vs fp32")
     p = synth.surface_pair(M=5000, N=5200, seed=8)
     X, Y = _f32(p.X), _f32(p.Y)
-    out = {}
+    out, tb = {}, {}
     for prec in ("fp32", "bf16x"):
         r = lib.Registration(dev(X, torch.float32), dev(Y, torch.float32), precision=prec,
                              beta=p.beta, lam=p.lam, w=p.w, eig_mode="import", K=1)
         r.set_state(dev(X, torch.float32), 0.005)
-        out[prec] = host(r.estep()["Yt"])
+        g = r.estep()
+        out[prec] = host(g["Yt"])
+        tb[prec] = host(g["tbar"])
     err = cpd64.rel_rms(out["bf16x"], out["fp32"])
-    say("bf16x vs fp32", err)
+    err_t = float(np.abs(tb["bf16x"] - tb["fp32"]).max() / tb["fp32"].mean())
+    say("bf16x vs fp32", err, "tbar", err_t)
     assert err < 1e-4
+    assert err_t < 5e-3
 
 
 def test_bf16x_registration(lib):
