@@ -56,7 +56,7 @@ KERNEL_NAME = {("fp32", "passA"): "k_colsum", ("fp32", "passB"): "k_rowsum",
 # of known size; valid only while the kernel source is unchanged (sha256).
 TRAFFIC = {
     "k_bfx_rowsum": {"sources": ["bf16x.hip", "bf16x_feat.hpp"],
-                     "sha256": "4aa1bb204bce7ff7c0f555b6aa0232f4fe376a3247e0297ceb75ac8812d61ef6",
+                     "sha256": "52d80843f998d87370064ae0ad09c9558fb82ddcd7c7bb8209ed1f7aebf969b2",
                      "bytes_per_dispatch": 59.30e6 + 26.00e6,
                      "profile": "profiles/bf16x_rowsum_surface50k_traffic.md"},
     # one Fast M-step at 50k, K = 300: k_tpart4 + k_tmerge4 + k_apply4

@@ -276,85 +276,85 @@ __global__ __launch_bounds__(256) void k_bfx_rowsum(const __bf16* __restrict__ F
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   f32x4 acc[4] = {zero, zero, zero, zero};
   if (m0 < M) {  // (a wave of padding only skips to the block's barrier)
-  bf16x8 b[4];
+    bf16x8 b[4];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
-  // with culling, this split's scene tiles are every S-th 16-row tile from
-  // tile blockIdx.y (S = gridDim.y splits): the tiles near any model point,
-  // consecutive in the spatial order, then spread evenly over the splits
-  const int S = gridDim.y, tiles = Npad >> 4;
-  const int aoff = (lane & 15) * 32 + 8 * (lane >> 4);  // this lane's A operand slice
-  // p - hi(p) for the first / second value of a bf16 pair, as a dot2 with
-  // the pair (-1, 0) or (0, -1).  Both are kept in registers: as an inline
-  // constant the compiler encodes (-1, 0) as the operand -1.0, which the
-  // hardware does not read as the bf16 pair
-  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-  uint32_t nlo = 0x0000bf80u, nhi = 0xbf800000u;
-  asm volatile("" : "+v"(nlo), "+v"(nhi));
-  const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, nlo), neg_hi = __builtin_bit_cast(bf16x2, nhi);
-  // with boxes: skip 16-point scene tiles whose smallest exponent
-  // |u - v|^2 + min L_n against this wave's model points reaches CullLimit
-  // (the split layout follows the sigma^2 gate alone: see pass A)
-  const bool spread = cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
-  const bool cull = boxX != nullptr && spread;
-  // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
-  // tiles to evaluate
-  // (while culling cannot pay every tile is evaluated and consecutive tiles
-  // per split read better, so the split then takes a contiguous range)
-  const int per = (tiles + S - 1) / S;
-  const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
-  const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
-  auto tiles_loop = [&](auto masked) {
-    constexpr bool MASK = decltype(masked)::value;
-    for (int i0 = 0; i0 < tn; i0 += 64) {
-      const int t0 = tb + ts * i0;
-      const int ntiles = min(64, tn - i0);
-      uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
-      int rows = 15;  // per tile (lane): the model row tiles it is evaluated against
-      if (MASK) {
-        // the wave's four 16-row model tiles (reloaded per group): a scene
-        // tile is evaluated against each of them only where it can contribute
-        P4<float> alo[4], ahi[4];
-        wave_boxes(boxX, m0 >> 4, min(4, (M - m0 + 15) >> 4), alo, ahi);
-        rows = 0;
-        if (lane < ntiles) {
-          const int k = t0 + ts * lane;
-          const P4<float> lo = boxY[2 * k], hi = boxY[2 * k + 1];  // lo.w = min L_n
+    for (int s = 0; s < 4; ++s) b[s] = load_op(F, m0 + 16 * s + (lane & 15), lane);
+    // with culling, this split's scene tiles are every S-th 16-row tile from
+    // tile blockIdx.y (S = gridDim.y splits): the tiles near any model point,
+    // consecutive in the spatial order, then spread evenly over the splits
+    const int S = gridDim.y, tiles = Npad >> 4;
+    const int aoff = (lane & 15) * 32 + 8 * (lane >> 4);  // this lane's A operand slice
+    // p - hi(p) for the first / second value of a bf16 pair, as a dot2 with
+    // the pair (-1, 0) or (0, -1).  Both are kept in registers: as an inline
+    // constant the compiler encodes (-1, 0) as the operand -1.0, which the
+    // hardware does not read as the bf16 pair
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    uint32_t nlo = 0x0000bf80u, nhi = 0xbf800000u;
+    asm volatile("" : "+v"(nlo), "+v"(nhi));
+    const bf16x2 neg_lo = __builtin_bit_cast(bf16x2, nlo), neg_hi = __builtin_bit_cast(bf16x2, nhi);
+    // with boxes: skip 16-point scene tiles whose smallest exponent
+    // |u - v|^2 + min L_n against this wave's model points reaches CullLimit
+    // (the split layout follows the sigma^2 gate alone: see pass A)
+    const bool spread = cull_worthwhile(sc, 0.0, (double)CullLimit<float>::value);
+    const bool cull = boxX != nullptr && spread;
+    // in groups of 64 tiles: one lane tests one tile's box, a ballot gives the
+    // tiles to evaluate
+    // (while culling cannot pay every tile is evaluated and consecutive tiles
+    // per split read better, so the split then takes a contiguous range)
+    const int per = (tiles + S - 1) / S;
+    const int tb = spread ? (int)blockIdx.y : (int)blockIdx.y * per, ts = spread ? S : 1;
+    const int tn = spread ? (tiles - (int)blockIdx.y + S - 1) / S : min(per, tiles - tb);
+    auto tiles_loop = [&](auto masked) {
+      constexpr bool MASK = decltype(masked)::value;
+      for (int i0 = 0; i0 < tn; i0 += 64) {
+        const int t0 = tb + ts * i0;
+        const int ntiles = min(64, tn - i0);
+        uint64_t keep = ntiles == 64 ? ~0ull : ((1ull << ntiles) - 1);
+        int rows = 15;  // per tile (lane): the model row tiles it is evaluated against
+        if (MASK) {
+          // the wave's four 16-row model tiles (reloaded per group): a scene
+          // tile is evaluated against each of them only where it can contribute
+          P4<float> alo[4], ahi[4];
+          wave_boxes(boxX, m0 >> 4, min(4, (M - m0 + 15) >> 4), alo, ahi);
+          rows = 0;
+          if (lane < ntiles) {
+            const int k = t0 + ts * lane;
+            const P4<float> lo = boxY[2 * k], hi = boxY[2 * k + 1];  // lo.w = min L_n
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            rows |= (box_gap2(alo[j], ahi[j], lo, hi) + lo.w < CullLimit<float>::value) << j;
+            for (int j = 0; j < 4; ++j)
+              rows |= (box_gap2(alo[j], ahi[j], lo, hi) + lo.w < CullLimit<float>::value) << j;
+          }
+          keep = __ballot(rows != 0);
         }
-        keep = __ballot(rows != 0);
-      }
-      while (keep) {
-        const int i = __builtin_ctzll(keep);
-        keep &= keep - 1;
-        const int nt = 16 * (t0 + ts * i);
-        const int rm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(rows, i, 64)) : 15;
-        // the tile's bases are uniform, so only the lane offsets are per lane
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(G + (size_t)nt * 32 + aoff);
-        const bf16x8 v = *reinterpret_cast<const bf16x8*>(V + (size_t)nt * 32 + 8 * lane);
+        while (keep) {
+          const int i = __builtin_ctzll(keep);
+          keep &= keep - 1;
+          const int nt = 16 * (t0 + ts * i);
+          const int rm = MASK ? __builtin_amdgcn_readfirstlane(__shfl(rows, i, 64)) : 15;
+          // the tile's bases are uniform, so only the lane offsets are per lane
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(G + (size_t)nt * 32 + aoff);
+          const bf16x8 v = *reinterpret_cast<const bf16x8*>(V + (size_t)nt * 32 + 8 * lane);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          if (MASK && !(rm & (1 << s))) continue;  // all its terms are +0
-          const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
-          const float p0 = fexp2(-d[0]), p1 = fexp2(-d[1]), p2 = fexp2(-d[2]), p3 = fexp2(-d[3]);
-          const bf16x2 h01 = {(__bf16)p0, (__bf16)p1}, h23 = {(__bf16)p2, (__bf16)p3};
-          const float l0 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_lo, p0, false);
-          const float l1 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_hi, p1, false);
-          const float l2 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_lo, p2, false);
-          const float l3 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_hi, p3, false);
-          const bf16x8 pa = {h01[0], h01[1], h23[0], h23[1],
-                             (__bf16)l0, (__bf16)l1, (__bf16)l2, (__bf16)l3};
-          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa, v, acc[s], 0, 0, 0);
+          for (int s = 0; s < 4; ++s) {
+            if (MASK && !(rm & (1 << s))) continue;  // all its terms are +0
+            const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s], zero, 0, 0, 0);
+            const float p0 = fexp2(-d[0]), p1 = fexp2(-d[1]), p2 = fexp2(-d[2]), p3 = fexp2(-d[3]);
+            const bf16x2 h01 = {(__bf16)p0, (__bf16)p1}, h23 = {(__bf16)p2, (__bf16)p3};
+            const float l0 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_lo, p0, false);
+            const float l1 = __builtin_amdgcn_fdot2_f32_bf16(h01, neg_hi, p1, false);
+            const float l2 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_lo, p2, false);
+            const float l3 = __builtin_amdgcn_fdot2_f32_bf16(h23, neg_hi, p3, false);
+            const bf16x8 pa = {h01[0], h01[1], h23[0], h23[1],
+                               (__bf16)l0, (__bf16)l1, (__bf16)l2, (__bf16)l3};
+            acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pa, v, acc[s], 0, 0, 0);
+          }
         }
       }
-    }
-  };
-  if (cull)
-    tiles_loop(Flag<true>{});
-  else
-    tiles_loop(Flag<false>{});
+    };
+    if (cull)
+      tiles_loop(Flag<true>{});
+    else
+      tiles_loop(Flag<false>{});
   }
   // accumulator lane l: column l % 16 of model points 16 s + 4 (l / 16) .. + 3
   float* r = red[wave];
