@@ -3,7 +3,7 @@
 // The paper decomposes the Gram matrix once, Phi = U Lam U^T (Section III,
 // eq. 16), or keeps its K largest pairs (eq. 19).  Here:
 //   * dense Jacobi: Phi is formed explicitly and diagonalised by cyclic
-//     two-sided Jacobi rotations in one workgroup (M <= 1024);
+//     two-sided Jacobi rotations, one launch per round-robin step (M <= 1024);
 //   * randomized: the K + p dimensional dominant subspace of Phi is found by a
 //     Gaussian range finder with subspace iteration and a Rayleigh-Ritz step
 //     (Halko, Martinsson & Tropp, SIAM Review 53(2), 2011).  Every product
@@ -11,7 +11,9 @@
 //     stored), orthonormalisation is shifted CholeskyQR followed by two plain
 //     CholeskyQR passes (Fukaya, Kannan, Nakatsukasa, Zhang & Yamamoto, SIAM J.
 //     Sci. Comput. 42(1), 2020), and the small projected matrix is diagonalised
-//     by the same Jacobi kernel.  FULL mode above 1024 points widens the
+//     by the same cyclic Jacobi method (above 1024 columns in its block form:
+//     pairs of 32-column blocks, 64 x 64 subproblems in LDS, the updates as
+//     small matrix products).  FULL mode above 1024 points widens the
 //     subspace until the trailing Ritz value is round-off of the largest.
 #include <algorithm>
 #include <cmath>
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(256) void k_tri_inv_t(const double* __restrict__ G,
 // them), takes its own rotation from the now current 2 x 2 block, applies it
 // to the two rows and writes them back; V's rows p and q get step s's column
 // rotations alongside.  A final launch applies the last step's columns.
-// (Wider matrices use two launches per step; see k_jac_rows.)  A pair is
+// (Wider matrices take the block variant below; see k_bj_solve.)  A pair is
 // rotated while |a_pq| exceeds both eps sqrt(|a_pp a_qq|) (relative
 // accuracy) and 1e-16 |A|_F (entries below are round-off of the largest
 // eigenvalues).  V accumulates the rotations; on exit diag(A) holds the
@@ -770,78 +772,281 @@ __global__ void k_jac_group_sweep(const JacMember* __restrict__ g, int members, 
   st[0] = 0;
 }
 
-// Wide matrices (n > 1024, where four staged rows per pair would leave two
-// blocks per CU): a step is two launches, k_jac_rows (one block per pair:
-// rotation from the pair's current 2 x 2 block, then rows p, q of J^T A)
-// and k_jac_cols (columns p, q of A J, the 2 x 2 block set exactly, and of
-// V J), which keeps every CU busy with short independent accesses.
-__global__ __launch_bounds__(256) void k_jac_rows(double* __restrict__ A, int n, int step,
-                                                  const double* __restrict__ normtot,
-                                                  double* __restrict__ prm,
+// ------------------------------------------------------ block Jacobi
+// Above kJacobiStagedMax columns the scalar steps are bandwidth-starved (each
+// moves every row of A and V for one rotation per pair), so wide matrices
+// take a block variant of the same cyclic method.  The columns are cut into
+// blocks of kBJ (the last one ragged, plus an empty block when the count is
+// odd) and paired round-robin.  One block step:
+//   k_bj_solve    every pair's 2 kBJ x 2 kBJ principal submatrix S gets
+//                 kBJInnerSweeps sweeps of the scalar cyclic Jacobi in LDS
+//                 (same rotation rule and threshold as the scalar solver,
+//                 rotated 2 x 2 blocks set exactly), its rotations
+//                 accumulated in Q;
+//                 the diagonalised S is written back to A as is;
+//   k_bj_apply_a  every off-diagonal pair-by-pair tile X of A becomes
+//                 Q1^T X Q2 (and its mirror image), i.e. A <- G^T A G;
+//   k_bj_apply_v  V <- V G.
+// Tiles of pairs that did not rotate are left alone, so the products add
+// round-off only where the matrix moved.  A sweep is the nblk - 1 block
+// steps; the method has converged when a whole sweep rotated nothing.
+constexpr int kBJ = 32;
+constexpr int kBJ2 = 2 * kBJ;
+constexpr int kBJInnerSweeps = 1;  // one inner sweep per block step (fastest measured)
+
+__device__ __forceinline__ int bj_size(int blk, int n) {
+  const int c0 = blk * kBJ;
+  return c0 >= n ? 0 : min(kBJ, n - c0);
+}
+
+// Global column of local index t of the pair of blocks (I, J); -1 past it.
+__device__ __forceinline__ int bj_col(int I, int J, int mI, int mJ, int t) {
+  if (t < mI) return I * kBJ + t;
+  if (t < mI + mJ) return J * kBJ + (t - mI);
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void k_bj_solve(double* __restrict__ A, int n, int nblk,
+                                                  int step, const double* __restrict__ normtot,
+                                                  double* __restrict__ Qbuf,
+                                                  int* __restrict__ qflag,
                                                   int* __restrict__ rotated) {
-  __shared__ double cs_[2];
-  const int k = blockIdx.x;
-  int p, q;
-  rr_pair(k, step, n, &p, &q);
-  if (threadIdx.x == 0) {
-    double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
-    if (q < n) {
-      const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-      const double apq = A[(size_t)p * n + q];
-      const double aa = fabs(apq);
-      const double eps = 1.1102230246251565e-16;
-      if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > 1e-16 * sqrt(normtot[0])) {
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        c = 1.0 / sqrt(1.0 + t * t);
-        s = t * c;
-        dp = app - t * apq;
-        dq = aqq + t * apq;
-        rotated[0] = 1;
-      }
-    }
-    cs_[0] = c;
-    cs_[1] = s;
-    prm[4 * k + 0] = c;
-    prm[4 * k + 1] = s;
-    prm[4 * k + 2] = dp;
-    prm[4 * k + 3] = dq;
+  __shared__ double S[kBJ2][kBJ2 + 1];
+  __shared__ double Qa[kBJ2][kBJ2 + 1];
+  __shared__ double prm[kBJ2 / 2][4];  // c, s, exact a_pp', a_qq'
+  __shared__ int rot_sweep, rot_any;
+  const int tid = threadIdx.x, k = blockIdx.x;
+  int I, J;
+  rr_pair(k, step, nblk, &I, &J);
+  const int mI = bj_size(I, n), mJ = bj_size(J, n);
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int t = e / kBJ2, u = e % kBJ2;
+    const int gt = bj_col(I, J, mI, mJ, t), gu = bj_col(I, J, mI, mJ, u);
+    S[t][u] = (gt >= 0 && gu >= 0) ? A[(size_t)gt * n + gu] : 0.0;
+    Qa[t][u] = t == u ? 1.0 : 0.0;
+  }
+  if (tid == 0) {
+    rot_sweep = 0;
+    rot_any = 0;
   }
   __syncthreads();
-  const double c = cs_[0], s = cs_[1];
-  if (q >= n || s == 0.0) return;
-  for (int j = threadIdx.x; j < n; j += 256) {
-    const double ap = A[(size_t)p * n + j], aq = A[(size_t)q * n + j];
-    A[(size_t)p * n + j] = c * ap - s * aq;
-    A[(size_t)q * n + j] = s * ap + c * aq;
+  const double eps = 1.1102230246251565e-16;
+  const double tiny = 1e-16 * sqrt(normtot[0]);
+  for (int sw = 0; sw < kBJInnerSweeps; ++sw) {
+    for (int st = 0; st < kBJ2 - 1; ++st) {
+      if (tid < kBJ2 / 2) {
+        int p, q;
+        rr_pair(tid, st, kBJ2, &p, &q);
+        double c = 1.0, s = 0.0, dp = 0.0, dq = 0.0;
+        const double app = S[p][p], aqq = S[q][q], apq = S[p][q];
+        const double aa = fabs(apq);
+        if (aa > eps * sqrt(fabs(app) * fabs(aqq)) && aa > tiny) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          dp = app - t * apq;
+          dq = aqq + t * apq;
+          rot_sweep = 1;
+        }
+        prm[tid][0] = c;
+        prm[tid][1] = s;
+        prm[tid][2] = dp;
+        prm[tid][3] = dq;
+      }
+      __syncthreads();
+      // S <- J^T S J in 2 x 2 blocks (rows of pair bi, columns of pair bj),
+      // the upper triangle of blocks computed and mirrored
+      for (int e = tid; e < (kBJ2 / 2) * (kBJ2 / 2); e += 256) {
+        const int bi = e / (kBJ2 / 2), bj = e % (kBJ2 / 2);
+        if (bj < bi) continue;
+        const double c1 = prm[bi][0], s1 = prm[bi][1], c2 = prm[bj][0], s2 = prm[bj][1];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1, q1, p2, q2;
+        rr_pair(bi, st, kBJ2, &p1, &q1);
+        if (bi == bj) {  // the rotated 2 x 2 block itself: its exact values
+          S[p1][p1] = prm[bi][2];
+          S[q1][q1] = prm[bi][3];
+          S[p1][q1] = 0.0;
+          S[q1][p1] = 0.0;
+          continue;
+        }
+        rr_pair(bj, st, kBJ2, &p2, &q2);
+        const double x00 = S[p1][p2], x01 = S[p1][q2], x10 = S[q1][p2], x11 = S[q1][q2];
+        const double r00 = c1 * x00 - s1 * x10, r01 = c1 * x01 - s1 * x11;
+        const double r10 = s1 * x00 + c1 * x10, r11 = s1 * x01 + c1 * x11;
+        const double y00 = c2 * r00 - s2 * r01, y01 = s2 * r00 + c2 * r01;
+        const double y10 = c2 * r10 - s2 * r11, y11 = s2 * r10 + c2 * r11;
+        S[p1][p2] = y00;
+        S[p1][q2] = y01;
+        S[q1][p2] = y10;
+        S[q1][q2] = y11;
+        S[p2][p1] = y00;
+        S[q2][p1] = y01;
+        S[p2][q1] = y10;
+        S[q2][q1] = y11;
+      }
+      for (int e = tid; e < kBJ2 * (kBJ2 / 2); e += 256) {  // Qa <- Qa J
+        const int row = e / (kBJ2 / 2), pi = e % (kBJ2 / 2);
+        const double c = prm[pi][0], s = prm[pi][1];
+        if (s == 0.0) continue;
+        int p, q;
+        rr_pair(pi, st, kBJ2, &p, &q);
+        const double x = Qa[row][p], y = Qa[row][q];
+        Qa[row][p] = c * x - s * y;
+        Qa[row][q] = s * x + c * y;
+      }
+      __syncthreads();
+    }
+    const bool again = rot_sweep != 0;
+    __syncthreads();
+    if (tid == 0) {
+      if (again) rot_any = 1;
+      rot_sweep = 0;
+    }
+    __syncthreads();
+    if (!again) break;
+  }
+  const int any = rot_any;
+  double* Qk = Qbuf + (size_t)k * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int t = e / kBJ2, u = e % kBJ2;
+    Qk[e] = Qa[t][u];
+    if (any) {
+      const int gt = bj_col(I, J, mI, mJ, t), gu = bj_col(I, J, mI, mJ, u);
+      if (gt >= 0 && gu >= 0) A[(size_t)gt * n + gu] = S[t][u];
+    }
+  }
+  if (tid == 0) {
+    qflag[k] = any;
+    if (any) rotated[0] = 1;
   }
 }
 
-__global__ __launch_bounds__(256) void k_jac_cols(double* __restrict__ A, double* __restrict__ V,
-                                                  int n, int step,
-                                                  const double* __restrict__ prm) {
-  const int k = blockIdx.x;
-  int p, q;
-  rr_pair(k, step, n, &p, &q);
-  if (q >= n) return;
-  const double c = prm[4 * k + 0], s = prm[4 * k + 1];
-  if (s == 0.0) return;
-  const int i = blockIdx.y * 256 + threadIdx.x;
-  if (i >= n) return;
-  const double ap = A[(size_t)i * n + p], aq = A[(size_t)i * n + q];
-  if (i == p) {
-    A[(size_t)p * n + p] = prm[4 * k + 2];
-    A[(size_t)p * n + q] = 0.0;
-  } else if (i == q) {
-    A[(size_t)q * n + p] = 0.0;
-    A[(size_t)q * n + q] = prm[4 * k + 3];
-  } else {
-    A[(size_t)i * n + p] = c * ap - s * aq;
-    A[(size_t)i * n + q] = s * ap + c * aq;
+// Tile (pair P1 rows, pair P2 columns), P1 < P2, of A <- G^T A G, written
+// with its mirror image.  Grid: npairs x npairs (the lower half returns).
+__global__ __launch_bounds__(256) void k_bj_apply_a(double* __restrict__ A, int n, int nblk,
+                                                    int step, const double* __restrict__ Qbuf,
+                                                    const int* __restrict__ qflag) {
+  const int P1 = blockIdx.y, P2 = blockIdx.x;
+  if (P1 >= P2 || (!qflag[P1] && !qflag[P2])) return;
+  __shared__ double X[kBJ2][kBJ2 + 1];
+  __shared__ double Q1[kBJ2][kBJ2 + 1];
+  __shared__ double Q2[kBJ2][kBJ2 + 1];
+  const int tid = threadIdx.x;
+  int I1, J1, I2, J2;
+  rr_pair(P1, step, nblk, &I1, &J1);
+  rr_pair(P2, step, nblk, &I2, &J2);
+  const int mI1 = bj_size(I1, n), mJ1 = bj_size(J1, n), mI2 = bj_size(I2, n),
+            mJ2 = bj_size(J2, n);
+  const double* q1 = Qbuf + (size_t)P1 * kBJ2 * kBJ2;
+  const double* q2 = Qbuf + (size_t)P2 * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int t = e / kBJ2, u = e % kBJ2;
+    const int gt = bj_col(I1, J1, mI1, mJ1, t), gu = bj_col(I2, J2, mI2, mJ2, u);
+    X[t][u] = (gt >= 0 && gu >= 0) ? A[(size_t)gt * n + gu] : 0.0;
+    Q1[t][u] = q1[e];
+    Q2[t][u] = q2[e];
   }
-  const double vp = V[(size_t)i * n + p], vq = V[(size_t)i * n + q];
-  V[(size_t)i * n + p] = c * vp - s * vq;
-  V[(size_t)i * n + q] = s * vp + c * vq;
+  __syncthreads();
+  const int i0 = (tid >> 4) * 4, j0 = (tid & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int t = 0; t < kBJ2; ++t) {  // T = Q1^T X
+    double qa[4], xb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) qa[a] = Q1[t][i0 + a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xb[b] = X[t][j0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(qa[a], xb[b], acc[a][b]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) X[i0 + a][j0 + b] = acc[a][b];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int u = 0; u < kBJ2; ++u) {  // Y = T Q2
+    double ta[4], qb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ta[a] = X[i0 + a][u];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) qb[b] = Q2[u][j0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(ta[a], qb[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int gi = bj_col(I1, J1, mI1, mJ1, i0 + a);
+    if (gi < 0) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int gj = bj_col(I2, J2, mI2, mJ2, j0 + b);
+      if (gj < 0) continue;
+      A[(size_t)gi * n + gj] = acc[a][b];
+      A[(size_t)gj * n + gi] = acc[a][b];
+    }
+  }
+}
+
+// V <- V G on the columns of pair P (blockIdx.y) for 64 rows (blockIdx.x).
+__global__ __launch_bounds__(256) void k_bj_apply_v(double* __restrict__ V, int n, int nblk,
+                                                    int step, const double* __restrict__ Qbuf,
+                                                    const int* __restrict__ qflag) {
+  const int P = blockIdx.y;
+  if (!qflag[P]) return;
+  __shared__ double X[kBJ2][kBJ2 + 1];
+  __shared__ double Q[kBJ2][kBJ2 + 1];
+  const int tid = threadIdx.x, r0 = blockIdx.x * kBJ2;
+  int I, J;
+  rr_pair(P, step, nblk, &I, &J);
+  const int mI = bj_size(I, n), mJ = bj_size(J, n);
+  const double* qp = Qbuf + (size_t)P * kBJ2 * kBJ2;
+  for (int e = tid; e < kBJ2 * kBJ2; e += 256) {
+    const int r = e / kBJ2, t = e % kBJ2;
+    const int gc = bj_col(I, J, mI, mJ, t);
+    X[r][t] = (r0 + r < n && gc >= 0) ? V[(size_t)(r0 + r) * n + gc] : 0.0;
+    Q[r][t] = qp[e];
+  }
+  __syncthreads();
+  const int i0 = (tid >> 4) * 4, j0 = (tid & 15) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int t = 0; t < kBJ2; ++t) {
+    double xa[4], qb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xa[a] = X[i0 + a][t];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) qb[b] = Q[t][j0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(xa[a], qb[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (r0 + i0 + a >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int gc = bj_col(I, J, mI, mJ, j0 + b);
+      if (gc >= 0) V[(size_t)(r0 + i0 + a) * n + gc] = acc[a][b];
+    }
+  }
 }
 
 __global__ void k_flag_clear(int* f) {
@@ -1037,11 +1242,52 @@ int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg, bool full 
 
 // Jacobi on the n x n symmetric matrix in A (destroyed), V gets eigenvectors;
 // eigenvalues sorted descending into vals, permutation into perm.
+// The block variant for wide matrices (see k_bj_solve).  Scratch: Q of every
+// pair and its rotated flag in the Rayleigh-Ritz output buffer (L.R, n x n
+// doubles, idle until the solve returns; npairs x (2 kBJ)^2 <= n^2 here).
+int block_jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals,
+                        std::string* msg) {
+  int* perm = misc_int(c);
+  int* flag = misc_int(c) + n + 1;
+  double* normsq = misc_dbl(c, n);  // [0..64): norm partials, [64] their sum
+  int nblk = (n + kBJ - 1) / kBJ;
+  nblk += nblk & 1;  // an empty block when the count is odd
+  const int npairs = nblk / 2;
+  double* Qbuf = c.at(c.L.R);
+  int* qflag = reinterpret_cast<int*>(Qbuf + (size_t)npairs * kBJ2 * kBJ2);
+  hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
+  hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, c.st, normsq, 64);
+  const double* normtot = normsq + 64;
+  int sweep = 0;
+  for (; sweep < kJacobiSweeps; ++sweep) {
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c.st, flag);
+    for (int step = 0; step < nblk - 1; ++step) {
+      hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(256), 0, c.st, A, n, nblk, step, normtot,
+                         Qbuf, qflag, flag);
+      hipLaunchKernelGGL(k_bj_apply_a, dim3(npairs, npairs), dim3(256), 0, c.st, A, n, nblk, step,
+                         (const double*)Qbuf, (const int*)qflag);
+      hipLaunchKernelGGL(k_bj_apply_v, dim3((n + kBJ2 - 1) / kBJ2, npairs), dim3(256), 0, c.st, V,
+                         n, nblk, step, (const double*)Qbuf, (const int*)qflag);
+    }
+    int h = 0;
+    (void)hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, c.st);
+    (void)hipStreamSynchronize(c.st);
+    if (!h) break;
+  }
+  hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);
+  if (sweep >= kJacobiSweeps) {
+    *msg = "Jacobi did not converge";
+    return 1;
+  }
+  return 0;
+}
+
 int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::string* msg) {
   if (n > kJacobiMax) {
     *msg = "Jacobi size exceeds its limit";
     return 3;
   }
+  if (n > kJacobiStagedMax) return block_jacobi_sorted(c, A, V, n, vals, msg);
   if (c.r.jb && n <= kJacobiStagedMax) {  // grouped with other threads' solves
     JacobiBatcher::Req q;
     q.A = A;
@@ -1065,7 +1311,6 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
   hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
   hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, c.st, normsq, 64);
   const double* normtot = normsq + 64;
-  const bool staged = n <= kJacobiStagedMax;
   const size_t lds = 4 * (size_t)n * sizeof(double);
   int sweep = 0, prev = 0, launched = 0;
   const double* prm_prev = nullptr;
@@ -1073,15 +1318,8 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
     hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c.st, flag);
     for (int step = 0; step < 2 * half - 1; ++step) {
       double* prm = prm_buf[launched++ & 1];
-      if (staged) {
-        hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, step, prev,
-                           prm_prev, prm, normtot, flag);
-      } else {
-        hipLaunchKernelGGL(k_jac_rows, dim3(half), dim3(256), 0, c.st, A, n, step, normtot, prm,
-                           flag);
-        hipLaunchKernelGGL(k_jac_cols, dim3(half, (n + 255) / 256), dim3(256), 0, c.st, A, V, n,
-                           step, prm);
-      }
+      hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, step, prev,
+                         prm_prev, prm, normtot, flag);
       prev = step;
       prm_prev = prm;
     }
@@ -1090,7 +1328,7 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::
     (void)hipStreamSynchronize(c.st);
     if (!h) break;
   }
-  if (staged && prm_prev)  // the last step's column rotations
+  if (prm_prev)  // the last step's column rotations
     hipLaunchKernelGGL(k_jac_step, dim3(half), dim3(256), lds, c.st, A, V, n, -1, prev, prm_prev,
                        (double*)nullptr, normtot, flag);
   hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, c.st, A, n, perm, vals);

@@ -112,6 +112,35 @@ def test_randomized_topk_wide_tiles(lib, M, K, over, precision):
     assert np.abs(res).max() < 1e-9 * lam[0]
 
 
+def test_randomized_topk_wide_rayleigh_ritz(lib):
+    """K + p = 1220 > 1024: the Rayleigh-Ritz matrix takes the block Jacobi
+    (39 blocks of 32 columns, the last ragged, plus an empty one to pair
+    with).  Eigenvalues against the oracle's eig_topk with the same test
+    matrix, orthonormal vectors and residuals on sampled rows of Phi."""
+    import torch
+    say("randomized topk wide Rayleigh-Ritz")
+    p = synth.surface_pair(M=2600, N=2600, seed=13, beta=1.5, lam=2.0, w=0.2)
+    X = _f32(p.X)
+    K, over, q = 1200, 20, 2
+    Om = synth.gaussian_matrix(p.M, K + over, seed=14)
+    Uo, lo = eig64.eig_topk(X, p.beta, K, Om, power_iters=q)
+    r = lib.Registration(dev(X, torch.float64), dev(_f32(p.Y), torch.float64), precision="fp64",
+                         beta=p.beta, lam=p.lam, w=p.w, eig_mode="topk", K=K, oversample=over,
+                         power_iters=q, seed=5, tol=0.0, max_iter=3)
+    out = r.prepare(omega=dev(Om, torch.float64)).register()
+    U, lam = (host(t) for t in r.export_eig())
+    err = np.abs(lam - lo).max() / lo[0]
+    say("max |lam - lam_oracle| / lam_1", err, "t_eig", out.t_eig)
+    np.testing.assert_allclose(lam, lo, rtol=0, atol=1e-11 * lo[0])
+    assert np.all(np.diff(lam) <= 0)
+    np.testing.assert_allclose(U.T @ U, np.eye(K), atol=1e-10)
+    rows = np.random.default_rng(2).choice(p.M, 40, replace=False)
+    Phr = np.exp(-cpd64.sqdist(X[rows], X) / (2 * p.beta ** 2))
+    big = lam > 1e-8 * lam[0]
+    res = Phr @ U[:, big] - U[rows][:, big] * lam[big]
+    assert np.abs(res).max() < 1e-9 * lam[0]
+
+
 def test_randomized_topk_tiny(lib):
     """40 points, K + p = 12: a single output tile and a single block."""
     import torch
