@@ -459,7 +459,10 @@ __global__ __launch_bounds__(256) void k_phi_fix(double* __restrict__ C, int M, 
 // A[m][a] B[m][b]; A, B are M x n row-major.
 __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
                                                    const double* __restrict__ B, int M, int n,
-                                                   int rows_per_chunk, double* __restrict__ P) {
+                                                   int rows_per_chunk, double* __restrict__ P,
+                                                   int upper) {
+  // upper (A == B, a symmetric Gram): only the tiles on and above the diagonal
+  if (upper && blockIdx.y > blockIdx.x) return;
   __shared__ double sA[TJ][TI + 2];  // sA[m][a]
   __shared__ double sB[TJ][TC + 2];  // sB[m][b]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -498,12 +501,20 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ A,
       }
 }
 
-// G = sum of chunk partials, symmetrised: G = (S + S^T)/2.
+// G = sum of chunk partials, symmetrised: G = (S + S^T)/2; with upper (only
+// the upper tiles computed) the upper triangle's sum, mirrored.
 __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ P, int chunks,
-                                                     int n, double* __restrict__ G) {
+                                                     int n, double* __restrict__ G, int upper) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n * n) return;
   const int a = (int)(idx / n), b = (int)(idx % n);
+  if (upper) {
+    const size_t e = (size_t)min(a, b) * n + max(a, b);
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += P[(size_t)c * n * n + e];
+    G[idx] = s;
+    return;
+  }
   double s = 0.0, t = 0.0;
   for (int c = 0; c < chunks; ++c) {
     s += P[(size_t)c * n * n + (size_t)a * n + b];
@@ -1163,9 +1174,10 @@ void gram(const Ctx& c, const double* A, const double* B, int n, double* G) {
   const int nch = (M + rows - 1) / rows;
   dim3 grid((n + TC - 1) / TC, (n + TI - 1) / TI, nch);
   double* P = c.at(c.L.G);
-  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, c.st, A, B, M, n, rows, P);
+  const int upper = A == B;
+  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, c.st, A, B, M, n, rows, P, upper);
   hipLaunchKernelGGL(k_gram_reduce, dim3(blocks_for((size_t)n * n)), dim3(256), 0, c.st, P, nch,
-                     n, G);
+                     n, G, upper);
 }
 
 int* misc_int(const Ctx& c) { return reinterpret_cast<int*>(c.ws + c.L.misc); }
@@ -1590,9 +1602,9 @@ void gram_sym_launch(const double* A, const double* B, int M, int n, double* G, 
   const int rows = (M + chunks - 1) / chunks;
   const int nch = (M + rows - 1) / rows;
   dim3 grid((n + TC - 1) / TC, (n + TI - 1) / TI, nch);
-  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, st, A, B, M, n, rows, partials);
+  hipLaunchKernelGGL(k_gram_part, grid, dim3(256), 0, st, A, B, M, n, rows, partials, 0);
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(((size_t)n * n + 255) / 256)), dim3(256), 0, st,
-                     partials, nch, n, G);
+                     partials, nch, n, G, 0);
 }
 
 int eig_prepare_run(const EigRun& r, int* K_out, std::string* msg) {
