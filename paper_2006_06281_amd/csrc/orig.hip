@@ -154,7 +154,10 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
   }
   // X = L^-1 row by row: X[r][c] = -(sum_{c<=k<r} L[r][k] X[k][c]) / L[r][r]
   // for c < r, all columns at once, eight threads per column splitting the
-  // sum (X[k][c] for k > c lives at s[c][k]; X[c][c] = 1 / L[c][c])
+  // sum (X[k][c] for k > c lives at s[c][k]; X[c][c] = 1 / L[c][c]).  A
+  // column's eight threads sit in one wave and read only L (fixed now) and
+  // their own column's earlier X, and a wave's LDS accesses complete in
+  // program order, so the rows need no workgroup barrier between them.
   {
     const int c = tid >> 3, g = tid & 7;
     for (int r = 1; r < nb; ++r) {
@@ -167,8 +170,9 @@ __global__ __launch_bounds__(1024) void k_potrf_diag(double* __restrict__ A, int
       v += __shfl_xor(v, 2, 8);
       v += __shfl_xor(v, 4, 8);
       if (c < r && g == 0) s[c][r] = -v / s[r][r];
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
   }
   for (int e = tid; e < NB * NB; e += nt) {
     const int r = e / NB, c = e % NB;
