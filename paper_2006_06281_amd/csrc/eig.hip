@@ -40,6 +40,7 @@ constexpr int kFullStart = 256;
 constexpr int kGramMaxChunks = 64;
 constexpr int kJacobiMax = kTopKMaxCols;
 constexpr int kJacobiStagedMax = 1024;  // one launch per step up to this size
+constexpr int kBlockJacobiMin = 256;    // block variant above this (single solves)
 // Graded spectra (Gaussian Gram matrices reach round-off within a few
 // hundred eigenvalues) need 20-30 sweeps before no rotation is left.
 constexpr int kJacobiSweeps = 100;
@@ -1254,18 +1255,19 @@ int orth(const Ctx& c, double* Z, double* Q, int n, std::string* msg, bool full 
 
 // Jacobi on the n x n symmetric matrix in A (destroyed), V gets eigenvectors;
 // eigenvalues sorted descending into vals, permutation into perm.
-// The block variant for wide matrices (see k_bj_solve).  Scratch: Q of every
-// pair and its rotated flag in the Rayleigh-Ritz output buffer (L.R, n x n
-// doubles, idle until the solve returns; npairs x (2 kBJ)^2 <= n^2 here).
+// The block variant (see k_bj_solve).  qscratch: room for Q of every pair
+// and its rotated flag, npairs x (2 kBJ)^2 doubles + npairs ints (the
+// Rayleigh-Ritz output buffer, n x n doubles, idle until the solve returns,
+// is enough for n > 2 kBJ).
 int block_jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals,
-                        std::string* msg) {
+                        double* qscratch, std::string* msg) {
   int* perm = misc_int(c);
   int* flag = misc_int(c) + n + 1;
   double* normsq = misc_dbl(c, n);  // [0..64): norm partials, [64] their sum
   int nblk = (n + kBJ - 1) / kBJ;
   nblk += nblk & 1;  // an empty block when the count is odd
   const int npairs = nblk / 2;
-  double* Qbuf = c.at(c.L.R);
+  double* Qbuf = qscratch;
   int* qflag = reinterpret_cast<int*>(Qbuf + (size_t)npairs * kBJ2 * kBJ2);
   hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, c.st, A, V, n, normsq);
   hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, c.st, normsq, 64);
@@ -1294,12 +1296,22 @@ int block_jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals,
   return 0;
 }
 
-int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, std::string* msg) {
+// qscratch: the block variant's scratch (see block_jacobi_sorted), NULL
+// where the caller has none (the dense path, n <= kJacobiStagedMax).  A solve
+// above kBlockJacobiMin columns that is not grouped with other threads'
+// takes the block variant (at 320 columns 4 ms less than the scalar steps).
+int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, double* qscratch,
+                  std::string* msg) {
   if (n > kJacobiMax) {
     *msg = "Jacobi size exceeds its limit";
     return 3;
   }
-  if (n > kJacobiStagedMax) return block_jacobi_sorted(c, A, V, n, vals, msg);
+  if (qscratch && (n > kJacobiStagedMax || (n > kBlockJacobiMin && !c.r.jb)))
+    return block_jacobi_sorted(c, A, V, n, vals, qscratch, msg);
+  if (n > kJacobiStagedMax) {
+    *msg = "Jacobi above the staged size needs its block scratch";
+    return 3;
+  }
   if (c.r.jb && n <= kJacobiStagedMax) {  // grouped with other threads' solves
     JacobiBatcher::Req q;
     q.A = A;
@@ -1511,7 +1523,7 @@ int randomized(const Ctx& c, int n, int K, int q, const double* omega_in, uint64
   }
   phi_times<PT>(c, Q, Z, n, Om);  // Z = Phi Q
   gram(c, Q, Z, n, B);        // B = Q^T Phi Q (symmetrised)
-  if (const int rc = jacobi_sorted(c, B, V, n, vals, msg)) return rc;
+  if (const int rc = jacobi_sorted(c, B, V, n, vals, c.at(c.L.R), msg)) return rc;
   hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)n * K)), dim3(256), 0, c.st, V, n,
                      misc_int(c), K, S);
   gemm_nn(c, Q, n, S, K, c.r.U64, K, M, n, K);
@@ -1538,7 +1550,7 @@ int dense_full(const Ctx& c, int* K_out, std::string* msg) {
   double* vals = c.at(c.L.ritz);
   hipLaunchKernelGGL(k_phi_dense<PT>, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st,
                      static_cast<const P4<PT>*>(c.r.X), M, 1.0 / (2.0 * c.r.beta * c.r.beta), Phi);
-  if (const int rc = jacobi_sorted(c, Phi, V, M, vals, msg)) return rc;
+  if (const int rc = jacobi_sorted(c, Phi, V, M, vals, nullptr, msg)) return rc;
   hipLaunchKernelGGL(k_gather_cols, dim3(blocks_for((size_t)M * M)), dim3(256), 0, c.st, V, M,
                      misc_int(c), M, c.r.U64);
   hipLaunchKernelGGL(k_copy_lam, dim3(blocks_for(M)), dim3(256), 0, c.st, vals, M, c.r.lam);
