@@ -41,6 +41,7 @@ constexpr int kGramMaxChunks = 64;
 constexpr int kJacobiMax = kTopKMaxCols;
 constexpr int kJacobiStagedMax = 1024;  // one launch per step up to this size
 constexpr int kBlockJacobiMin = 256;    // block variant above this (single solves)
+constexpr int kBlockGroupMin = 128;     // and above this in grouped solves
 // Graded spectra (Gaussian Gram matrices reach round-off within a few
 // hundred eigenvalues) need 20-30 sweeps before no rotation is left.
 constexpr int kJacobiSweeps = 100;
@@ -818,16 +819,15 @@ __device__ __forceinline__ int bj_col(int I, int J, int mI, int mJ, int t) {
   return -1;
 }
 
-__global__ __launch_bounds__(256) void k_bj_solve(double* __restrict__ A, int n, int nblk,
-                                                  int step, const double* __restrict__ normtot,
-                                                  double* __restrict__ Qbuf,
-                                                  int* __restrict__ qflag,
-                                                  int* __restrict__ rotated) {
+__device__ __forceinline__ void bj_solve_body(double* __restrict__ A, int n, int nblk, int step,
+                                              const double* __restrict__ normtot,
+                                              double* __restrict__ Qbuf, int* __restrict__ qflag,
+                                              int* __restrict__ rotated, int k) {
   __shared__ double S[kBJ2][kBJ2 + 1];
   __shared__ double Qa[kBJ2][kBJ2 + 1];
   __shared__ double prm[kBJ2 / 2][4];  // c, s, exact a_pp', a_qq'
   __shared__ int rot_sweep, rot_any;
-  const int tid = threadIdx.x, k = blockIdx.x;
+  const int tid = threadIdx.x;
   int I, J;
   rr_pair(k, step, nblk, &I, &J);
   const int mI = bj_size(I, n), mJ = bj_size(J, n);
@@ -935,12 +935,19 @@ __global__ __launch_bounds__(256) void k_bj_solve(double* __restrict__ A, int n,
   }
 }
 
+__global__ __launch_bounds__(256) void k_bj_solve(double* __restrict__ A, int n, int nblk,
+                                                  int step, const double* __restrict__ normtot,
+                                                  double* __restrict__ Qbuf,
+                                                  int* __restrict__ qflag,
+                                                  int* __restrict__ rotated) {
+  bj_solve_body(A, n, nblk, step, normtot, Qbuf, qflag, rotated, blockIdx.x);
+}
+
 // Tile (pair P1 rows, pair P2 columns), P1 < P2, of A <- G^T A G, written
 // with its mirror image.  Grid: npairs x npairs (the lower half returns).
-__global__ __launch_bounds__(256) void k_bj_apply_a(double* __restrict__ A, int n, int nblk,
-                                                    int step, const double* __restrict__ Qbuf,
-                                                    const int* __restrict__ qflag) {
-  const int P1 = blockIdx.y, P2 = blockIdx.x;
+__device__ __forceinline__ void bj_apply_a_body(double* __restrict__ A, int n, int nblk,
+                                                int step, const double* __restrict__ Qbuf,
+                                                const int* __restrict__ qflag, int P1, int P2) {
   if (P1 >= P2 || (!qflag[P1] && !qflag[P2])) return;
   __shared__ double X[kBJ2][kBJ2 + 1];
   __shared__ double Q1[kBJ2][kBJ2 + 1];
@@ -1013,15 +1020,20 @@ __global__ __launch_bounds__(256) void k_bj_apply_a(double* __restrict__ A, int 
   }
 }
 
-// V <- V G on the columns of pair P (blockIdx.y) for 64 rows (blockIdx.x).
-__global__ __launch_bounds__(256) void k_bj_apply_v(double* __restrict__ V, int n, int nblk,
+__global__ __launch_bounds__(256) void k_bj_apply_a(double* __restrict__ A, int n, int nblk,
                                                     int step, const double* __restrict__ Qbuf,
                                                     const int* __restrict__ qflag) {
-  const int P = blockIdx.y;
+  bj_apply_a_body(A, n, nblk, step, Qbuf, qflag, blockIdx.y, blockIdx.x);
+}
+
+// V <- V G on the columns of pair P (blockIdx.y) for 64 rows (blockIdx.x).
+__device__ __forceinline__ void bj_apply_v_body(double* __restrict__ V, int n, int nblk,
+                                                int step, const double* __restrict__ Qbuf,
+                                                const int* __restrict__ qflag, int P, int chunk) {
   if (!qflag[P]) return;
   __shared__ double X[kBJ2][kBJ2 + 1];
   __shared__ double Q[kBJ2][kBJ2 + 1];
-  const int tid = threadIdx.x, r0 = blockIdx.x * kBJ2;
+  const int tid = threadIdx.x, r0 = chunk * kBJ2;
   int I, J;
   rr_pair(P, step, nblk, &I, &J);
   const int mI = bj_size(I, n), mJ = bj_size(J, n);
@@ -1059,6 +1071,37 @@ __global__ __launch_bounds__(256) void k_bj_apply_v(double* __restrict__ V, int 
       if (gc >= 0) V[(size_t)(r0 + i0 + a) * n + gc] = acc[a][b];
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_bj_apply_v(double* __restrict__ V, int n, int nblk,
+                                                    int step, const double* __restrict__ Qbuf,
+                                                    const int* __restrict__ qflag) {
+  bj_apply_v_body(V, n, nblk, step, Qbuf, qflag, blockIdx.y, blockIdx.x);
+}
+
+// The three block steps for a group of matrices (blockIdx.z = member), each
+// member on its own round-robin schedule (step t mod (nblk - 1)); members
+// whose last sweep rotated nothing skip, as in k_jac_step_group.
+__global__ __launch_bounds__(256) void k_bj_solve_group(const JacMember* __restrict__ g, int t) {
+  const JacMember& J = g[blockIdx.z];
+  if (!J.state[1] || (int)blockIdx.x >= J.nblk / 2) return;
+  bj_solve_body(J.A, J.n, J.nblk, t % (J.nblk - 1), J.normtot, J.q, J.qflag, J.state,
+                blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_bj_apply_a_group(const JacMember* __restrict__ g,
+                                                          int t) {
+  const JacMember& J = g[blockIdx.z];
+  const int np = J.nblk / 2;
+  if (!J.state[1] || (int)blockIdx.x >= np || (int)blockIdx.y >= np) return;
+  bj_apply_a_body(J.A, J.n, J.nblk, t % (J.nblk - 1), J.q, J.qflag, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_bj_apply_v_group(const JacMember* __restrict__ g,
+                                                          int t) {
+  const JacMember& J = g[blockIdx.z];
+  if (!J.state[1] || (int)blockIdx.y >= J.nblk / 2 || (int)blockIdx.x * kBJ2 >= J.n) return;
+  bj_apply_v_body(J.V, J.n, J.nblk, t % (J.nblk - 1), J.q, J.qflag, blockIdx.y, blockIdx.x);
 }
 
 __global__ void k_flag_clear(int* f) {
@@ -1321,6 +1364,7 @@ int jacobi_sorted(const Ctx& c, double* A, double* V, int n, double* vals, doubl
     q.perm = misc_int(c);
     q.state = misc_int(c) + n + 1;
     q.scratch = misc_dbl(c, n);
+    q.qscratch = qscratch;
     q.st = c.st;
     const int rc = c.r.jb->solve(&q);
     if (rc) *msg = q.msg;
@@ -1386,7 +1430,9 @@ static void jacobi_group(const std::vector<JacobiBatcher::Req*>& reqs, JacMember
     m.prm[1] = q->scratch + 65 + 4 * (size_t)half;
     m.state = q->state;
     m.n = n;
-    m.pad = 0;
+    m.nblk = 0;
+    m.q = nullptr;
+    m.qflag = nullptr;
     half_max = std::max(half_max, half);
     steps_max = std::max(steps_max, 2 * half - 1);
     n_max = std::max(n_max, n);
@@ -1422,6 +1468,76 @@ static void jacobi_group(const std::vector<JacobiBatcher::Req*>& reqs, JacMember
     if (e != hipSuccess) {
       q->rc = 2;
       q->msg = std::string("grouped Jacobi: ") + hipGetErrorString(e);
+    } else if (rot[i]) {
+      q->rc = 1;
+      q->msg = "Jacobi did not converge";
+    }
+  }
+}
+
+// The block variant for a group whose members all brought its scratch
+// (randomized Rayleigh-Ritz solves): grouped launches of the three block
+// steps, one host synchronisation per sweep, then each member's eigenvalues
+// sorted descending.
+static void block_jacobi_group(const std::vector<JacobiBatcher::Req*>& reqs, JacMember* dmem,
+                               int* dflags, hipStream_t st) {
+  const int G = (int)reqs.size();
+  std::vector<JacMember> mem(G);
+  int np_max = 1, steps_max = 1, chunks_max = 1;
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    const int n = q->n;
+    int nblk = (n + kBJ - 1) / kBJ;
+    nblk += nblk & 1;
+    const int np = nblk / 2;
+    double* normsq = q->scratch;
+    hipLaunchKernelGGL(k_jac_init, dim3(64), dim3(256), 0, st, q->A, q->V, n, normsq);
+    hipLaunchKernelGGL(k_jac_norm, dim3(1), dim3(64), 0, st, normsq, 64);
+    JacMember& m = mem[i];
+    m.A = q->A;
+    m.V = q->V;
+    m.normtot = normsq + 64;
+    m.prm[0] = m.prm[1] = nullptr;
+    m.state = q->state;
+    m.n = n;
+    m.nblk = nblk;
+    m.q = q->qscratch;
+    m.qflag = reinterpret_cast<int*>(q->qscratch + (size_t)np * kBJ2 * kBJ2);
+    np_max = std::max(np_max, np);
+    steps_max = std::max(steps_max, nblk - 1);
+    chunks_max = std::max(chunks_max, (n + kBJ2 - 1) / kBJ2);
+  }
+  hipError_t e = hipMemcpyAsync(dmem, mem.data(), sizeof(JacMember) * G, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // mem is host stack memory
+  std::vector<int> rot(G, 1);
+  int t = 0, sweep = 0;
+  hipLaunchKernelGGL(k_jac_group_sweep, dim3((G + 63) / 64), dim3(64), 0, st, dmem, G, 1, dflags);
+  for (; e == hipSuccess && sweep < kJacobiSweeps; ++sweep) {
+    for (int s = 0; s < steps_max; ++s, ++t) {
+      hipLaunchKernelGGL(k_bj_solve_group, dim3(np_max, 1, G), dim3(256), 0, st,
+                         (const JacMember*)dmem, t);
+      hipLaunchKernelGGL(k_bj_apply_a_group, dim3(np_max, np_max, G), dim3(256), 0, st,
+                         (const JacMember*)dmem, t);
+      hipLaunchKernelGGL(k_bj_apply_v_group, dim3(chunks_max, np_max, G), dim3(256), 0, st,
+                         (const JacMember*)dmem, t);
+    }
+    hipLaunchKernelGGL(k_jac_group_sweep, dim3((G + 63) / 64), dim3(64), 0, st, dmem, G, 0, dflags);
+    e = hipMemcpyAsync(rot.data(), dflags, sizeof(int) * G, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    bool any = false;
+    for (int v : rot) any = any || v;
+    if (!any) break;
+  }
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    hipLaunchKernelGGL(k_sort_desc, dim3(1), dim3(1024), 0, st, q->A, q->n, q->perm, q->vals);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  for (int i = 0; i < G; ++i) {
+    JacobiBatcher::Req* q = reqs[i];
+    if (e != hipSuccess) {
+      q->rc = 2;
+      q->msg = std::string("grouped block Jacobi: ") + hipGetErrorString(e);
     } else if (rot[i]) {
       q->rc = 1;
       q->msg = "Jacobi did not converge";
@@ -1474,14 +1590,23 @@ void JacobiBatcher::run_locked() {
     if (q->st != st && q->ready) (void)hipStreamWaitEvent(st, q->ready, 0);
   // a group runs as many steps per sweep as its widest member needs: split
   // the requests into size classes (widest at most twice the narrowest)
-  std::vector<Req*> by_n(reqs);
-  std::sort(by_n.begin(), by_n.end(), [](const Req* a, const Req* b) { return a->n < b->n; });
-  for (size_t g0 = 0; g0 < by_n.size();) {
-    size_t g1 = g0 + 1;
-    while (g1 < by_n.size() && by_n[g1]->n <= 2 * by_n[g0]->n) ++g1;
-    jacobi_group(std::vector<Req*>(by_n.begin() + g0, by_n.begin() + g1), dev_members_,
-                 dev_flags_, st);
-    g0 = g1;
+  // (solves that brought the block variant's scratch take it, above
+  // kBlockGroupMin columns; the others the grouped scalar steps)
+  for (int blk = 0; blk < 2; ++blk) {
+    std::vector<Req*> by_n;
+    for (Req* q : reqs)
+      if ((q->qscratch && q->n > kBlockGroupMin) == (blk == 1)) by_n.push_back(q);
+    std::sort(by_n.begin(), by_n.end(), [](const Req* a, const Req* b) { return a->n < b->n; });
+    for (size_t g0 = 0; g0 < by_n.size();) {
+      size_t g1 = g0 + 1;
+      while (g1 < by_n.size() && by_n[g1]->n <= 2 * by_n[g0]->n) ++g1;
+      const std::vector<Req*> grp(by_n.begin() + g0, by_n.begin() + g1);
+      if (blk)
+        block_jacobi_group(grp, dev_members_, dev_flags_, st);
+      else
+        jacobi_group(grp, dev_members_, dev_flags_, st);
+      g0 = g1;
+    }
   }
   hipEvent_t fin = nullptr;
   (void)hipEventCreateWithFlags(&fin, hipEventDisableTiming);

@@ -35,7 +35,9 @@ struct JacMember {
   double* prm[2];          // per-pair rotation parameters of two steps
   int* state;              // {rotated in this sweep, active}
   int n;
-  int pad;
+  int nblk;                // block Jacobi: column blocks (even), else 0
+  double* q;               // block Jacobi: Q of every pair (nblk / 2 x 64 x 64)
+  int* qflag;              // block Jacobi: pairs that rotated in the step
 };
 
 // Collects the Jacobi solves of eigen-preps that run in parallel host
@@ -52,6 +54,7 @@ class JacobiBatcher {
     int* perm;
     int* state;
     double* scratch;  // norm partials [0..64), their sum [64], two rotation buffers
+    double* qscratch = nullptr;  // the block variant's scratch, if the caller has one
     hipStream_t st;
     hipEvent_t ready = nullptr;
     int rc = 0;
