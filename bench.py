@@ -147,8 +147,8 @@ def cpu_baseline(pair, K, rows=20000):
     per_iter = t_pairs + t_m
     return {"value": 1.0 / per_iter, "unit": "EM iters/s", "cores": cpd64.threads(),
             "kind": "oracle", **host_cpu(),
-            "threads_note": "oracle thread pool = min(16, host CPUs); the GPU box allots 16 "
-                            "host cores to one GPU",
+            "threads_note": "oracle thread pool = min(16, host CPUs): the host share of "
+                            "one GPU is 16 cores",
             "sample": f"E-step + sigma^2 pass on {rows} of {M} model rows x {N} scene "
                       f"points scaled to M x N, plus one full Fast M-step (K={K}); "
                       f"{per_iter:.2f} s per iteration extrapolated"}
@@ -726,7 +726,7 @@ def main():
                          "alone, one JSON line of its own")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: this implementation has no multi-GPU path "
               "(each GPU would register its own instances).", file=sys.stderr)
         sys.exit(2)
 

@@ -143,6 +143,6 @@ int main(void) {
   }
 
   if (fails) fprintf(stderr, "%d checks failed\n", fails);
-  else printf("host ABI driver: all checks passed\n");
+  else printf("host ABI check: all checks passed\n");
   return fails ? 1 : 0;
 }

@@ -2,7 +2,7 @@
 
 Every HIP source of the library is compiled with the sanitizers on its host
 pass only (each ``-fsanitize=`` behind ``-Xarch_host``; the gfx950 device code
-is built as usual), linked with ``host_abi_driver.c`` and run.  The driver
+is built as usual), linked with ``host_abi_check.c`` and run.  The program
 calls only host code: argument validation, workspace sizing for every
 method/precision/mode, the batched and warm-start layouts, status strings
 (including codes outside the enum) and the no-device path of ``cpd_init``.
@@ -19,7 +19,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2006_06281_amd", "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-DRIVER = os.path.join(ROOT, "tests", "host_abi_driver.c")
+CHECK_SRC = os.path.join(ROOT, "tests", "host_abi_check.c")
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
 
@@ -35,7 +35,7 @@ HIP_FLAGS = ["-O1", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
 def _inputs():
     files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                    if f.endswith((".hip", ".hpp")))
-    return files + [os.path.join(INCLUDE, "fastcpd.h"), DRIVER]
+    return files + [os.path.join(INCLUDE, "fastcpd.h"), CHECK_SRC]
 
 
 def _digest():
@@ -65,21 +65,21 @@ def _build(out):
 
     with ThreadPoolExecutor(8) as ex:
         objs = list(ex.map(comp, srcs))
-    drv = os.path.join(out, "driver.o")
+    chk = os.path.join(out, "check.o")
     _run([CLANG, "-O1", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
-          "-fno-omit-frame-pointer", "-I", INCLUDE, "-c", DRIVER, "-o", drv], out)
-    exe = os.path.join(out, "host_abi_driver")
-    _run([HIPCC, "--offload-arch=gfx950", *SAN_HOST, drv, *objs, "-o", exe], out)
+          "-fno-omit-frame-pointer", "-I", INCLUDE, "-c", CHECK_SRC, "-o", chk], out)
+    exe = os.path.join(out, "host_abi_check")
+    _run([HIPCC, "--offload-arch=gfx950", *SAN_HOST, chk, *objs, "-o", exe], out)
     return exe
 
 
 @pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)),
                     reason="ROCm hipcc/clang not installed")
 @pytest.mark.skipif(os.path.exists("/dev/kfd"),
-                    reason="the driver's no-device case needs a machine without a GPU")
+                    reason="the program's no-device case needs a machine without a GPU")
 def test_host_paths_clean_under_asan_ubsan():
     out = os.path.join("/tmp", "fastcpd_host_sanitizers", _digest())
-    exe = os.path.join(out, "host_abi_driver")
+    exe = os.path.join(out, "host_abi_check")
     if not os.path.exists(exe):
         shutil.rmtree(out, ignore_errors=True)
         exe = _build(out)
