@@ -196,6 +196,10 @@ struct cpd_ctx {
   std::string err;
   JacobiBatcher* jb = nullptr;  // set while a batch prepares: grouped Jacobi solves
   char* eig_slot = nullptr;     // set while a batch prepares: shared U64 + solver scratch
+  DevScalars* host_sc = nullptr;  // pinned host copies of the scalars (two slots), lazily made
+  ~cpd_ctx() {
+    if (host_sc) (void)hipHostFree(host_sc);
+  }
   template <typename U> U* at(const Region& r) const { return reinterpret_cast<U*>(ws + r.off); }
   DevScalars* sc() const { return at<DevScalars>(L.sc); }
   // caller row of internal model / scene row i (NULL: same order)
@@ -486,34 +490,59 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
   }
   hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 1);
   HIPCHK(h, hipGetLastError());
-  // Iterations are enqueued in batches; after convergence the remaining
-  // launches of a batch see sc->done and return at once.
+  if (!h->host_sc) {
+    void* p = nullptr;
+    HIPCHK(h, hipHostMalloc(&p, 2 * sizeof(DevScalars), hipHostMallocDefault));
+    h->host_sc = static_cast<DevScalars*>(p);
+  }
+  // Iterations are enqueued in batches, each followed by a copy of the
+  // scalars into its pinned slot.  Two batches are in flight: the host
+  // enqueues the next batch before it waits for the previous one's copy, so
+  // the device does not idle through the host's round trip.  After
+  // convergence the launches still queued see sc->done and return at once.
   const int batch = 8;
-  std::vector<EventGuard> guards(res ? 4 * batch : 0);
-  std::vector<PhaseEvents> evs(res ? batch : 0);
+  std::vector<EventGuard> guards(res ? 2 * 4 * batch : 0);
+  std::vector<PhaseEvents> evs(res ? 2 * batch : 0);
   for (int i = 0; i < (int)guards.size(); ++i) {
     HIPCHK(h, hipEventCreate(&guards[i].e));
     evs[i / 4].e[i % 4] = guards[i].e;
   }
+  EventGuard copied[2];
+  for (auto& g : copied) HIPCHK(h, hipEventCreateWithFlags(&g.e, hipEventDisableTiming));
   double t_c = 0, t_it = 0;
   DevScalars s{};
   cpd_status status = CPD_OK;
-  for (int done_iters = 0; done_iters < h->p.max_iter;) {
-    const int nb = std::min(batch, h->p.max_iter - done_iters);
-    for (int i = 0; i < nb; ++i) enqueue_step<T>(h, 1, res ? &evs[i] : nullptr);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(&s, h->sc(), sizeof(s), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(h, hipStreamSynchronize(h->st));
+  int nbs[2] = {0, 0};
+  int head = 0, inflight = 0, enqueued = 0;
+  for (;;) {
+    while (inflight < 2 && enqueued < h->p.max_iter) {
+      const int slot = (head + inflight) & 1;
+      const int nb = std::min(batch, h->p.max_iter - enqueued);
+      for (int i = 0; i < nb; ++i)
+        enqueue_step<T>(h, 1, res ? &evs[slot * batch + i] : nullptr);
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(&h->host_sc[slot], h->sc(), sizeof(DevScalars),
+                               hipMemcpyDeviceToHost, h->st));
+      HIPCHK(h, hipEventRecord(copied[slot].e, h->st));
+      nbs[slot] = nb;
+      enqueued += nb;
+      ++inflight;
+    }
+    if (inflight == 0) break;
+    HIPCHK(h, hipEventSynchronize(copied[head].e));
+    s = h->host_sc[head];
     if (res) {
-      for (int i = 0; i < nb; ++i) {
+      for (int i = 0; i < nbs[head]; ++i) {
+        const PhaseEvents& e = evs[head * batch + i];
         float a = 0, b = 0;
-        (void)hipEventElapsedTime(&a, evs[i].e[0], evs[i].e[1]);
-        (void)hipEventElapsedTime(&b, evs[i].e[1], evs[i].e[2]);
+        (void)hipEventElapsedTime(&a, e.e[0], e.e[1]);
+        (void)hipEventElapsedTime(&b, e.e[1], e.e[2]);
         t_c += a * 1e-3;
         t_it += b * 1e-3;
       }
     }
-    done_iters += nb;
+    head ^= 1;
+    --inflight;
     if (s.done) break;
   }
   if (s.nonfinite == 2) status = fail(h, CPD_E_NUMERIC, "Cholesky factorisation broke down");
