@@ -214,6 +214,11 @@ struct cpd_ctx {
 
 namespace {
 
+// Events that only time work on the handle's stream: recorded without the
+// system-scope fence (an L2 write-back and invalidation), which would make the
+// kernel after each event start from a cold cache and slow the timed run.
+constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
+
 // A HIP event released when the guard leaves scope.
 struct EventGuard {
   hipEvent_t e = nullptr;
@@ -420,8 +425,9 @@ void enqueue_sigma2(cpd_ctx* h, int gate) {
   sigma2_launch<T>(a, h->st);
 }
 
+// E-step start, M-step start, M-step end (the paper's t_c and t_iter).
 struct PhaseEvents {
-  hipEvent_t e[4];
+  hipEvent_t e[3];
 };
 
 template <typename T>
@@ -432,7 +438,6 @@ void enqueue_step(cpd_ctx* h, int gate, PhaseEvents* ev) {
   enqueue_mstep<T>(h, gate);
   if (ev) (void)hipEventRecord(ev->e[2], h->st);
   enqueue_sigma2<T>(h, gate);
-  if (ev) (void)hipEventRecord(ev->e[3], h->st);
 }
 
 __global__ void k_arm(DevScalars* sc, int reset_iter) {
@@ -501,11 +506,11 @@ cpd_status register_impl(cpd_ctx* h, const void* W0, void* X_out, void* W_out, c
   // the device does not idle through the host's round trip.  After
   // convergence the launches still queued see sc->done and return at once.
   const int batch = 8;
-  std::vector<EventGuard> guards(res ? 2 * 4 * batch : 0);
+  std::vector<EventGuard> guards(res ? 2 * 3 * batch : 0);
   std::vector<PhaseEvents> evs(res ? 2 * batch : 0);
   for (int i = 0; i < (int)guards.size(); ++i) {
-    HIPCHK(h, hipEventCreate(&guards[i].e));
-    evs[i / 4].e[i % 4] = guards[i].e;
+    HIPCHK(h, hipEventCreateWithFlags(&guards[i].e, kTimingEventFlags));
+    evs[i / 3].e[i % 3] = guards[i].e;
   }
   EventGuard copied[2];
   for (auto& g : copied) HIPCHK(h, hipEventCreateWithFlags(&g.e, hipEventDisableTiming));
@@ -790,7 +795,7 @@ cpd_status time_impl(cpd_ctx* h, int reps, double* out) {
   EventGuard g[8];
   hipEvent_t e[8];
   for (int i = 0; i < 8; ++i) {
-    HIPCHK(h, hipEventCreate(&g[i].e));
+    HIPCHK(h, hipEventCreateWithFlags(&g[i].e, kTimingEventFlags));
     e[i] = g[i].e;
   }
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
