@@ -21,9 +21,11 @@
  *     and float otherwise.
  *   - The library never allocates device memory.  The caller allocates one
  *     workspace of cpd_workspace_size() bytes (256-byte aligned) and keeps it
- *     alive until cpd_destroy().  The handle itself is host memory.  The one
- *     exception is a fixed 64 MiB device array per device, part of the
- *     library's code object, that only cpdnet_forward_noalloc uses.
+ *     alive until cpd_destroy().  The handle itself is host memory, as is
+ *     the small pinned buffer (two copies of the iteration scalars) that
+ *     the first cpd_register on a handle allocates and cpd_destroy frees.
+ *     The one exception is a fixed 64 MiB device array per device, part of
+ *     the library's code object, that only cpdnet_forward_noalloc uses.
  *   - All device work is enqueued on the stream given to cpd_init.  Calls
  *     that return host scalars synchronise that stream.
  *   - Errors are reported through the return code only; arguments are
