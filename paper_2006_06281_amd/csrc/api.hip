@@ -457,7 +457,8 @@ cpd_status ready_for_steps(cpd_ctx* h) {
 
 template <typename T>
 cpd_status step_impl(cpd_ctx* h, cpd_step_info* info) {
-  hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, h->st, h->sc(), 0);
+  // ungated: every kernel of the step runs whatever sc->done holds (only
+  // cpd_register reads that flag, and it re-arms it), so nothing is reset
   enqueue_step<T>(h, 0, nullptr);
   HIPCHK(h, hipGetLastError());
   if (!info) return CPD_OK;
